@@ -1,0 +1,205 @@
+/*
+ * kmg.h -- C ABI of libkmg: the data-parallel hot path of KISS-Matcher
+ * (arXiv 2409.15615) on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem: two voxelized
+ * clouds (Section III-A) are turned into Faster-PFH descriptors (Section
+ * III-C, Appendix A: Algorithm 1 and Eq. A1-A5) and matched by the mutual
+ * nearest-neighbour (reciprocity) test of Section III-C.  Pruning (Eq. 3,
+ * k-core) and the pose solver are not part of this library.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller, unless a
+ *    parameter is documented as a host pointer.  The library never allocates
+ *    device memory: scratch space comes from the caller's workspace `ws` of
+ *    `ws_bytes` bytes, sized by kmg_workspace_bytes().  `ws` must be
+ *    256-byte aligned.
+ *  - Point clouds are float32 structure-of-arrays: x[0..n), y[0..n),
+ *    z[0..n) stored back to back (3*n floats, row stride n).
+ *  - Descriptors are row-major float32, 3*H values per point (H = n_bins).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; calls that return a count through a host
+ *    pointer synchronise that stream before returning.
+ *  - Indices are int32 and refer to the kept (voxelized) cloud, except
+ *    kept_idx, which maps kept points back to raw input indices.
+ *  - Errors are returned as kmg_status; no call aborts or throws.  On
+ *    KMG_ERR_CAPACITY the required size is written to the count pointer and
+ *    the other outputs are unspecified.
+ *  - Determinism: identical inputs give bit-identical integer outputs and
+ *    bit-identical floating-point outputs on every call.
+ */
+#ifndef KMG_H
+#define KMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KMG_OK = 0,
+    KMG_ERR_ARG = -1,      /* invalid argument (null pointer, bad size or parameter) */
+    KMG_ERR_CAPACITY = -2, /* an output buffer is too small; required size reported */
+    KMG_ERR_DEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+    KMG_ERR_RANGE = -4,    /* input outside the supported range (see each call) */
+    KMG_ERR_WORKSPACE = -5 /* ws_bytes smaller than kmg_workspace_bytes() */
+} kmg_status;
+
+typedef enum { KMG_FP32 = 0, KMG_BF16 = 1, KMG_FP16 = 2 } kmg_precision;
+
+/* Faster-PFH parameters.  Section IV-B states them in units of the voxel
+ * size v: r_normal = 3.5 v, r_FPFH = 5 v, tau_num = 3, tau_lin = 0.99.
+ * Requirements: voxel > 0; 0 < r_normal <= r_fpfh (Section III-C relies on
+ * r_normal <= r_FPFH to subsample the normal neighbourhood from the single
+ * r_FPFH search); tau_num >= 1; 0 < tau_lin <= 1; 1 <= n_bins <= 32.
+ * viewpoint: the normals are oriented so that n . (viewpoint - a_q) >= 0. */
+typedef struct {
+    double voxel;
+    double r_normal;
+    double r_fpfh;
+    double tau_lin;
+    int32_t tau_num;
+    int32_t n_bins;
+    double viewpoint[3];
+} kmg_params;
+
+/* Operation codes for kmg_workspace_bytes(). */
+enum {
+    KMG_OP_VOXELIZE = 0, /* n0 = raw points */
+    KMG_OP_NORMALS = 1,  /* n0 = kept points m */
+    KMG_OP_FPFH = 2,     /* n0 = kept points m */
+    KMG_OP_MATCH = 3     /* n0 = rows of P (np), n1 = rows of Q (nq) */
+};
+
+/* Workspace size in bytes needed by `op` for the given sizes (a host call;
+ * touches no device).  For KMG_OP_MATCH the descriptor length is
+ * 3 * p->n_bins (33 when p is NULL); a workspace sized for a longer
+ * descriptor also serves a shorter one.  Returns 0 for an unknown op or
+ * invalid sizes. */
+size_t kmg_workspace_bytes(int32_t op, int64_t n0, int64_t n1, const kmg_params* p);
+
+/* Human-readable name of a status code (static storage). */
+const char* kmg_status_string(int32_t status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t kmg_version(void);
+
+/*
+ * Diagnostics: per-stage device time.  kmg_timing_enable(1) resets the
+ * totals and makes every later call bracket its kernel launches with HIP
+ * events on its stream; the elapsed times are added to process-wide
+ * per-stage totals when the call completes (each call then also waits for
+ * its stream).  Not thread-safe: for single-threaded profiling runs.
+ * kmg_timing_enable(0) stops timing.  Returns 0, or -1 if events could not
+ * be created.  kmg_timing_read copies up to n stage totals (milliseconds and
+ * number of bracketed launches; the match_topk stage is bracketed once per
+ * direction, i.e. per kernel launch) and returns the number of stages;
+ * kmg_stage_name(i) names stage i (static storage).
+ */
+int32_t kmg_timing_enable(int32_t on);
+int32_t kmg_timing_read(double* ms, int64_t* launches, int32_t n);
+const char* kmg_stage_name(int32_t stage);
+
+/*
+ * kmg_voxelize -- voxel downsampling of a raw cloud (Section III-A: the
+ * method takes clouds voxelized with voxel size v).
+ *
+ * Every finite point i gets the key (floor(x_i / v), floor(y_i / v),
+ * floor(z_i / v)), evaluated in FP64.  For each occupied voxel the point of
+ * lowest input index is kept; kept points are written in ascending input
+ * index.  Non-finite points are dropped.
+ *   xyz       [in]  SoA 3 x n float32.
+ *   n         [in]  number of raw points (0 <= n < 2^31).
+ *   voxel     [in]  voxel size v > 0.
+ *   kept_idx  [out] int32[cap]: raw index of each kept point.
+ *   kept_xyz  [out] float32[3 * cap]: kept points as a packed SoA 3 x m block
+ *                   (row stride m = *n_kept, not cap).
+ *   cap       [in]  capacity in points of kept_idx and kept_xyz.
+ *   n_kept    [out, HOST] number of kept points m.
+ * Errors: KMG_ERR_RANGE if a key does not fit in [-2^20, 2^20) per axis.
+ */
+kmg_status kmg_voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz,
+                        int64_t cap, int64_t* n_kept, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kmg_normals -- Algorithm 1, Step 1: one radius search per point at
+ * r_FPFH (Eq. A1: N(q) = { s : ||a_s - a_q|| < r_FPFH }, the query
+ * included), the r_normal subset P_normal(q) taken from it, the
+ * cardinality tests |N(q)| >= tau_num and |P_normal(q)| >= tau_num, the
+ * PCA normal (unit eigenvector of the smallest covariance eigenvalue of
+ * P_normal) and the linearity p_lin = (l1 - l2) / l1 with the test
+ * p_lin < tau_lin.
+ *   xyz       [in]  SoA 3 x m float32, a voxelized cloud.
+ *   normals   [out] SoA 3 x m float32; zero where no normal was estimated.
+ *   flags     [out] uint8[m]; bit 0 = B[q] (a reliable normal after Step 1).
+ *   nbr_off   [out] int32[m + 1]: CSR offsets of N(q).
+ *   nbr_idx   [out] int32[nbr_cap]: N(q) for every q, each list ascending.
+ *   nbr_cap   [in]  capacity of nbr_idx.
+ *   nnz       [out, HOST] total number of neighbour entries.
+ *   n_normal  [out, optional] int32[m]: |P_normal(q)|, or NULL.
+ * Distances are decided exactly as the FP64 expression
+ * ((dx*dx) + dy*dy) + dz*dz < r*r with dx = (double)x_s - (double)x_q.
+ * Errors: KMG_ERR_CAPACITY (nnz > nbr_cap); KMG_ERR_RANGE if some |N(q)|
+ * exceeds 8192 or nnz exceeds 2^31 - 1, or a cell key overflows.
+ */
+kmg_status kmg_normals(const float* xyz, int64_t m, const kmg_params* p, float* normals, uint8_t* flags,
+                       int32_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nnz, int32_t* n_normal,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kmg_fpfh -- Algorithm 1, Step 2 and Eq. A2-A5.
+ * M[q] = { k in N(q) : B[k] }; J = { q : B[q] and |M[q]| >= tau_num }.
+ * For every q with B[q], SPFH(q) (Eq. A4) histograms the Darboux-frame
+ * features (Eq. A2) of the pairs (q, k), k in M[q] \ {q}, into H bins per
+ * feature (Eq. A3, bounds [-pi, pi], [-1, 1], [-1, 1]), normalised to 100
+ * by P_q = |M[q]| - 1.  For q in J, FPFH(q) = SPFH(q) + (1 / P_q) *
+ * sum_{k in M[q] \ {q}} SPFH(k) / ||a_k - a_q|| (Eq. A5).
+ *   xyz, normals, nbr_off, nbr_idx [in] as produced by kmg_normals.
+ *   flags     [in/out] bit 0 = B (read); bit 1 = q in J (written).
+ *   spfh      [out, optional] float32[m * 3H] or NULL; zero rows where not B.
+ *   fpfh      [out] float32[m * 3H]; zero rows outside J.
+ *   j_idx     [out] int32[m]: the points of J in ascending order.
+ *   n_j       [out, HOST] |J|.
+ *   stats     [out, optional HOST] int64[2] or NULL: number of pair
+ *             features decided in FP64 near a bin edge or a selection tie,
+ *             and the number within 1e-9 of a bin edge in FP64.
+ */
+kmg_status kmg_fpfh(const float* xyz, const float* normals, uint8_t* flags, const int32_t* nbr_off,
+                    const int32_t* nbr_idx, int64_t m, const kmg_params* p, float* spfh, float* fpfh,
+                    int32_t* j_idx, int64_t* n_j, int64_t* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kmg_match -- mutual nearest-neighbour matching (the reciprocity test of
+ * Section III-C) between descriptor rows of P and Q.
+ * Distance D(i, j) = sum_t ((double)x_it - (double)y_jt)^2 in dimension
+ * order (squared L2).  NN_Q(i) = argmin_j D(i, j), ties to the smaller j;
+ * NN_P(j) likewise.  (i, j) is a correspondence iff NN_Q(i) = j and
+ * NN_P(j) = i.  Candidates are found on matrix cores (precision `prec`)
+ * and every reported decision is re-scored exactly in FP64; rows whose
+ * candidate set cannot be certified are re-scanned exactly.
+ *   desc_p    [in]  float32 row-major, rows addressed through rows_p.
+ *   rows_p    [in]  int32[np]: row of desc_p for each P entry, or NULL for
+ *                   rows 0..np-1.  The same for desc_q / rows_q / nq.
+ *   dim       [in]  descriptor length (1 <= dim <= 64).
+ *   prec      [in]  KMG_FP32 (KMG_BF16 / KMG_FP16: candidate generation in
+ *                   16-bit with FP32 accumulation; same exact result).
+ *   pairs     [out] int32[cap * 2]: (rows_p[i], rows_q[j]) sorted by i.
+ *   d1, d2    [out] float32[cap]: sqrt of the smallest and second-smallest
+ *                   D over row i (d2 = +inf if nq < 2).
+ *   n_pairs   [out, HOST] number of correspondences.
+ *   n_fallback[out, optional HOST] rows (both directions) re-scanned exactly.
+ * Descriptors must be finite and non-negative (FPFH rows are).
+ */
+kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, const float* desc_q,
+                     const int32_t* rows_q, int64_t nq, int32_t dim, int32_t prec, int32_t* pairs, float* d1,
+                     float* d2, int64_t cap, int64_t* n_pairs, int64_t* n_fallback, void* ws, size_t ws_bytes,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KMG_H */

@@ -1,0 +1,109 @@
+// extern "C" entry points of libkmg: argument validation, workspace checks and
+// dispatch to the kernels.  No call aborts; every failure is a kmg_status.
+#include <math.h>
+
+#include "kmg_internal.h"
+
+namespace {
+
+bool params_ok(const kmg_params* p) {
+    if (!p) return false;
+    if (!(p->voxel > 0.0) || !isfinite(p->voxel)) return false;
+    if (!(p->r_normal > 0.0) || !(p->r_fpfh > 0.0) || !isfinite(p->r_fpfh)) return false;
+    if (p->r_normal > p->r_fpfh) return false;  // the normal subset is taken from the r_FPFH search
+    if (p->tau_num < 1) return false;
+    if (!(p->tau_lin > 0.0) || p->tau_lin > 1.0) return false;
+    if (p->n_bins < 1 || p->n_bins > kmg::kMaxBins) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!isfinite(p->viewpoint[c])) return false;
+    return true;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+#define KMG_EXPORT __attribute__((visibility("default")))
+
+extern "C" {
+
+KMG_EXPORT int32_t kmg_version(void) { return 10000; }
+
+KMG_EXPORT const char* kmg_status_string(int32_t status) {
+    switch (status) {
+        case KMG_OK: return "ok";
+        case KMG_ERR_ARG: return "invalid argument";
+        case KMG_ERR_CAPACITY: return "output capacity too small";
+        case KMG_ERR_DEVICE: return "HIP device error";
+        case KMG_ERR_RANGE: return "input outside the supported range";
+        case KMG_ERR_WORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+KMG_EXPORT size_t kmg_workspace_bytes(int32_t op, int64_t n0, int64_t n1, const kmg_params* p) {
+    if (n0 < 0 || n1 < 0 || n0 > INT32_MAX || n1 > INT32_MAX) return 0;
+    switch (op) {
+        case KMG_OP_VOXELIZE: return kmg::voxelize_ws(n0);
+        case KMG_OP_NORMALS: return kmg::normals_ws(n0);
+        case KMG_OP_FPFH: return kmg::fpfh_ws(n0, p ? p->n_bins : 11);
+        case KMG_OP_MATCH: return kmg::match_ws(n0, n1, p ? 3 * p->n_bins : 33);
+        default: return 0;
+    }
+}
+
+KMG_EXPORT int32_t kmg_timing_enable(int32_t on) { return kmg::timer_enable(on); }
+
+KMG_EXPORT int32_t kmg_timing_read(double* ms, int64_t* launches, int32_t n) {
+    return kmg::timer_read(ms, launches, n);
+}
+
+KMG_EXPORT const char* kmg_stage_name(int32_t stage) { return kmg::stage_name(stage); }
+
+KMG_EXPORT kmg_status kmg_voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz,
+                        int64_t cap, int64_t* n_kept, void* ws, size_t ws_bytes, void* stream) {
+    if (!n_kept || n < 0 || n > INT32_MAX - 1 || cap < 0) return KMG_ERR_ARG;
+    if (!(voxel > 0.0) || !isfinite(voxel)) return KMG_ERR_ARG;
+    if (n > 0 && (!xyz || !kept_idx || !kept_xyz)) return KMG_ERR_ARG;
+    if (!ws) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::voxelize_ws(n)) return KMG_ERR_WORKSPACE;
+    return kmg::voxelize(xyz, n, voxel, kept_idx, kept_xyz, cap, n_kept, ws, ws_bytes, as_stream(stream));
+}
+
+KMG_EXPORT kmg_status kmg_normals(const float* xyz, int64_t m, const kmg_params* p, float* normals, uint8_t* flags,
+                       int32_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nnz, int32_t* n_normal,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!params_ok(p) || !nnz || m < 0 || m > INT32_MAX - 1 || nbr_cap < 0) return KMG_ERR_ARG;
+    if (!nbr_off || !ws) return KMG_ERR_ARG;
+    if (m > 0 && (!xyz || !normals || !flags)) return KMG_ERR_ARG;
+    if (nbr_cap > 0 && !nbr_idx) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::normals_ws(m)) return KMG_ERR_WORKSPACE;
+    return kmg::normals(xyz, m, *p, normals, flags, nbr_off, nbr_idx, nbr_cap, nnz, n_normal, ws, ws_bytes,
+                        as_stream(stream));
+}
+
+KMG_EXPORT kmg_status kmg_fpfh(const float* xyz, const float* normals, uint8_t* flags, const int32_t* nbr_off,
+                    const int32_t* nbr_idx, int64_t m, const kmg_params* p, float* spfh, float* fpfh,
+                    int32_t* j_idx, int64_t* n_j, int64_t* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (!params_ok(p) || !n_j || m < 0 || m > INT32_MAX - 1 || !ws) return KMG_ERR_ARG;
+    if (m > 0 && (!xyz || !normals || !flags || !nbr_off || !nbr_idx || !fpfh || !j_idx)) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::fpfh_ws(m, p->n_bins)) return KMG_ERR_WORKSPACE;
+    return kmg::fpfh(xyz, normals, flags, nbr_off, nbr_idx, m, *p, spfh, fpfh, j_idx, n_j, stats, ws, ws_bytes,
+                     as_stream(stream));
+}
+
+KMG_EXPORT kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, const float* desc_q,
+                     const int32_t* rows_q, int64_t nq, int32_t dim, int32_t prec, int32_t* pairs, float* d1,
+                     float* d2, int64_t cap, int64_t* n_pairs, int64_t* n_fallback, void* ws, size_t ws_bytes,
+                     void* stream) {
+    if (!n_pairs || np < 0 || nq < 0 || np > INT32_MAX / 2 || nq > INT32_MAX / 2 || cap < 0) return KMG_ERR_ARG;
+    if (dim < 1 || dim > 64 || !ws) return KMG_ERR_ARG;
+    if (prec != KMG_FP32 && prec != KMG_BF16 && prec != KMG_FP16) return KMG_ERR_ARG;
+    if ((np > 0 && !desc_p) || (nq > 0 && !desc_q)) return KMG_ERR_ARG;
+    if (cap > 0 && (!pairs || !d1 || !d2)) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::match_ws(np, nq, dim)) return KMG_ERR_WORKSPACE;
+    return kmg::match(desc_p, rows_p, np, desc_q, rows_q, nq, dim, prec, pairs, d1, d2, cap, n_pairs, n_fallback,
+                      ws, ws_bytes, as_stream(stream));
+}
+
+}  // extern "C"

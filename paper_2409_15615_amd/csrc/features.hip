@@ -1,0 +1,355 @@
+// Algorithm 1 Step 2, Darboux-frame pair features (Eq. A2), bins (Eq. A3),
+// SPFH (Eq. A4) and FPFH (Eq. A5).
+//
+// SPFH: one wavefront per point q; lanes take the neighbours k of q, 64 at a
+// time.  Each lane computes the three features of (q, k) in FP32 and bins
+// them; a feature set that lies within a guard band of a bin edge, of the
+// a/b selection tie, or of an ill-conditioned frame is recomputed in FP64
+// with the operation order of the plain definition, so the bins equal the
+// FP64 definition's.  Bin counts are formed with one ballot + popcount per
+// (feature, bin): no atomics, deterministic.  SPFH values 100 * c / P_q are
+// kept in FP64 for the FPFH pass.
+//
+// FPFH: one wavefront per point q in J; lanes first compute the weights
+// 1 / ||a_k - a_q|| of a chunk of neighbours (FP64) and compact them into
+// LDS, then each lane owns descriptor bins and accumulates
+// (1 / w_k) * SPFH(k) over the chunk in ascending k, in FP64.
+#include <math.h>
+
+#include "kmg_device.h"
+
+namespace kmg {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+
+struct V3f {
+    float x, y, z;
+};
+
+__device__ __forceinline__ V3f sub(V3f a, V3f b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ float dotf(V3f a, V3f b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3f crossf(V3f a, V3f b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ V3f scalef(V3f a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+
+// FP32 features and bins.  Returns false when any decision is too close to
+// call in FP32: the a/b tie (|n_q.d0| vs |n_k.d0| within 1e-5 ||d0||), a
+// short frame axis (||d x u|| < 0.2), a near-degenerate f1 argument
+// (|(w.n_b, u.n_b)| < 0.2), or a scaled feature within 2e-4 of an integer.
+// The FP32 error of the scaled features is below 2e-5 outside those cases.
+__device__ __forceinline__ bool bins_f32(V3f pq, V3f nq, V3f pk, V3f nk, int H, int bins[3]) {
+    const V3f d0 = sub(pk, pq);
+    const float aq = fabsf(dotf(nq, d0));
+    const float ak = fabsf(dotf(nk, d0));
+    const float dl = sqrtf(dotf(d0, d0));
+    if (fabsf(aq - ak) <= 1e-5f * dl) return false;
+    const bool qa = aq >= ak;
+    const V3f u = qa ? nq : nk;
+    const V3f nb = qa ? nk : nq;
+    const V3f d = scalef(d0, (qa ? 1.0f : -1.0f) / dl);
+    V3f v = crossf(d, u);
+    const float vl = sqrtf(dotf(v, v));
+    if (vl < 0.2f) return false;
+    v = scalef(v, 1.0f / vl);
+    const V3f w = crossf(u, v);
+    const float y = dotf(w, nb), x = dotf(u, nb);
+    if (x * x + y * y < 0.04f) return false;
+    const float f[3] = {atan2f(y, x), dotf(v, nb), dotf(u, d)};
+    const float lo[3] = {-3.14159265358979323846f, -1.0f, -1.0f};
+    const float sc[3] = {H / 6.28318530717958647692f, 0.5f * H, 0.5f * H};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const float s = (f[l] - lo[l]) * sc[l];
+        if (fabsf(s - rintf(s)) < 2e-4f) return false;
+        bins[l] = min(max(static_cast<int>(floorf(s)), 0), H - 1);
+    }
+    return true;
+}
+
+__device__ __forceinline__ double dotd(const double a[3], const double b[3]) {
+#pragma clang fp contract(off)
+    double s = a[0] * b[0];
+    s = s + a[1] * b[1];
+    s = s + a[2] * b[2];
+    return s;
+}
+
+__device__ __forceinline__ void crossd(const double a[3], const double b[3], double o[3]) {
+#pragma clang fp contract(off)
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// FP64 features and bins by the plain definition: a/b by the unsigned
+// angle, d = (a_b - a_a) / ||.||, u = n_a, v = d x u normalised, w = u x v,
+// f = (atan2(w.n_b, u.n_b), v.n_b, u.d); f = (0, 0, u.d) when d x u = 0.
+// Bin h = floor(H (f - lo) / (hi - lo)) clamped to [0, H-1].
+__device__ void bins_f64(V3f pq32, V3f nq32, V3f pk32, V3f nk32, int H, int bins[3], bool& edge) {
+#pragma clang fp contract(off)
+    const double pq[3] = {pq32.x, pq32.y, pq32.z}, nq[3] = {nq32.x, nq32.y, nq32.z};
+    const double pk[3] = {pk32.x, pk32.y, pk32.z}, nk[3] = {nk32.x, nk32.y, nk32.z};
+    const double d0[3] = {pk[0] - pq[0], pk[1] - pq[1], pk[2] - pq[2]};
+    const bool qa = fabs(dotd(nq, d0)) >= fabs(dotd(nk, d0));
+    const double* pa = qa ? pq : pk;
+    const double* pb = qa ? pk : pq;
+    const double* u = qa ? nq : nk;
+    const double* nb = qa ? nk : nq;
+    double d[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+    const double dl = sqrt(dotd(d, d));
+    for (int c = 0; c < 3; ++c) d[c] = d[c] / dl;
+    double v[3];
+    crossd(d, u, v);
+    const double vl = sqrt(dotd(v, v));
+    double f[3];
+    if (vl == 0.0) {
+        f[0] = 0.0;
+        f[1] = 0.0;
+        f[2] = dotd(u, d);
+    } else {
+        for (int c = 0; c < 3; ++c) v[c] = v[c] / vl;
+        double w[3];
+        crossd(u, v, w);
+        f[0] = atan2(dotd(w, nb) + 0.0, dotd(u, nb));
+        f[1] = dotd(v, nb);
+        f[2] = dotd(u, d);
+    }
+    const double lo[3] = {-M_PI, -1.0, -1.0};
+    const double hi[3] = {M_PI, 1.0, 1.0};
+    for (int l = 0; l < 3; ++l) {
+        const double s = (static_cast<double>(H) * (f[l] - lo[l])) / (hi[l] - lo[l]);
+        const double fl = floor(s);
+        if (fabs(s - fl) < 1e-9 || fabs(s - (fl + 1.0)) < 1e-9) edge = true;
+        bins[l] = min(max(static_cast<int>(fl), 0), H - 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void spfh_kernel(const float* __restrict__ xyz, const float* __restrict__ nrm,
+                                                      const uint8_t* __restrict__ flags,
+                                                      const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ nbr, int m, int H, int tau_num,
+                                                      double* __restrict__ spfh64, float* __restrict__ spfh_out,
+                                                      int32_t* __restrict__ Pq, int32_t* __restrict__ jflag,
+                                                      DevStatus* st) {
+    const int lane = lane_id();
+    const int q = blockIdx.x * kWaves + threadIdx.x / kWave;
+    if (q >= m) return;
+    const int D = 3 * H;
+    const int64_t m2 = 2 * static_cast<int64_t>(m);
+    double* row = spfh64 + static_cast<int64_t>(q) * D;
+    if (!(flags[q] & 1)) {
+        for (int t = lane; t < D; t += kWave) {
+            row[t] = 0.0;
+            if (spfh_out) spfh_out[static_cast<int64_t>(q) * D + t] = 0.0f;
+        }
+        if (lane == 0) {
+            Pq[q] = 0;
+            jflag[q] = 0;
+        }
+        return;
+    }
+    const V3f pq = {xyz[q], xyz[m + q], xyz[m2 + q]};
+    const V3f nq = {nrm[q], nrm[m + q], nrm[m2 + q]};
+    const int b = off[q], e = off[q + 1];
+    int n_valid = 0;
+    // lane h holds the counts of bin h for the three features
+    int c0 = 0, c1 = 0, c2 = 0;
+    uint32_t n64 = 0, nedge = 0;
+    for (int base = b; base < e; base += kWave) {
+        const int t = base + lane;
+        bool valid = false;
+        int bn[3] = {-1, -1, -1};
+        if (t < e) {
+            const int k = nbr[t];
+            valid = (flags[k] & 1) != 0;
+            if (valid && k != q) {
+                const V3f pk = {xyz[k], xyz[m + k], xyz[m2 + k]};
+                const V3f nk = {nrm[k], nrm[m + k], nrm[m2 + k]};
+                if (!bins_f32(pq, nq, pk, nk, H, bn)) {
+                    bool edge = false;
+                    bins_f64(pq, nq, pk, nk, H, bn, edge);
+                    ++n64;
+                    nedge += edge ? 1u : 0u;
+                }
+            }
+        }
+        n_valid += __popcll(ballot(valid));
+        for (int h = 0; h < H; ++h) {
+            const int a0 = __popcll(ballot(bn[0] == h));
+            const int a1 = __popcll(ballot(bn[1] == h));
+            const int a2 = __popcll(ballot(bn[2] == h));
+            if (lane == h) {
+                c0 += a0;
+                c1 += a1;
+                c2 += a2;
+            }
+        }
+    }
+    n64 = wave_sum(n64);
+    nedge = wave_sum(nedge);
+    const int P = n_valid - 1;
+    if (lane < H) {
+        const int cs[3] = {c0, c1, c2};
+        for (int l = 0; l < 3; ++l) {
+            const double val = (P > 0) ? (100.0 * static_cast<double>(cs[l])) / static_cast<double>(P) : 0.0;
+            row[l * H + lane] = val;
+            if (spfh_out) spfh_out[static_cast<int64_t>(q) * D + l * H + lane] = static_cast<float>(val);
+        }
+    }
+    if (lane == 0) {
+        Pq[q] = P;
+        jflag[q] = (n_valid >= tau_num) ? 1 : 0;
+        if (n64) atomicAdd(&st->feat_fp64, n64);
+        if (nedge) atomicAdd(&st->feat_edge, nedge);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ xyz,
+                                                      const uint8_t* __restrict__ flags,
+                                                      const int32_t* __restrict__ jflag,
+                                                      const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ nbr, int m, int H,
+                                                      const double* __restrict__ spfh64,
+                                                      const int32_t* __restrict__ Pq, float* __restrict__ fpfh) {
+#pragma clang fp contract(off)
+    __shared__ int32_t s_k[kWaves][kWave];
+    __shared__ double s_w[kWaves][kWave];
+    const int wv = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int q = blockIdx.x * kWaves + wv;
+    if (q >= m) return;
+    const int D = 3 * H;
+    float* out = fpfh + static_cast<int64_t>(q) * D;
+    if (!jflag[q]) {
+        for (int t = lane; t < D; t += kWave) out[t] = 0.0f;
+        return;
+    }
+    const int64_t m2 = 2 * static_cast<int64_t>(m);
+    const float qx = xyz[q], qy = xyz[m + q], qz = xyz[m2 + q];
+    const int b = off[q], e = off[q + 1];
+    double acc0 = 0.0, acc1 = 0.0;  // bins lane and lane + 64
+    for (int base = b; base < e; base += kWave) {
+        const int t = base + lane;
+        bool use = false;
+        int k = 0;
+        double w = 0.0;
+        if (t < e) {
+            k = nbr[t];
+            use = (k != q) && (flags[k] & 1);
+            if (use) w = 1.0 / sqrt(d2_exact(qx, qy, qz, xyz[k], xyz[m + k], xyz[m2 + k]));
+        }
+        const uint64_t bm = ballot(use);
+        if (use) {
+            const int at = lanes_below(bm);
+            s_k[wv][at] = k;
+            s_w[wv][at] = w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int nuse = __popcll(bm);
+        for (int j = 0; j < nuse; ++j) {
+            const double wj = s_w[wv][j];
+            const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j]) * D;
+            if (lane < D) acc0 = acc0 + wj * sk[lane];
+            if (lane + kWave < D) acc1 = acc1 + wj * sk[lane + kWave];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int P = Pq[q];
+    const double* sq = spfh64 + static_cast<int64_t>(q) * D;
+    if (P == 0) {
+        if (lane < D) out[lane] = static_cast<float>(sq[lane]);
+        if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave]);
+        return;
+    }
+    const double inv = 1.0 / static_cast<double>(P);
+    if (lane < D) out[lane] = static_cast<float>(sq[lane] + inv * acc0);
+    if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave] + inv * acc1);
+}
+
+__global__ __launch_bounds__(kBlock) void j_emit(const int32_t* __restrict__ jflag, const int32_t* __restrict__ pos,
+                                                 int m, uint8_t* __restrict__ flags, int32_t* __restrict__ j_idx) {
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= m) return;
+    const int j = jflag[q];
+    flags[q] = static_cast<uint8_t>((flags[q] & 1) | (j << 1));
+    if (j) j_idx[pos[q]] = q;
+}
+
+struct FeatWs {
+    DevStatus* st;
+    double* spfh64;
+    int32_t* Pq;
+    int32_t* jflag;
+    int32_t* pos;
+    int64_t* total;
+    int64_t* scan_tmp;
+};
+
+FeatWs carve(Carver& c, int64_t m, int H) {
+    FeatWs w;
+    w.st = c.take<DevStatus>(1);
+    w.spfh64 = c.take<double>(static_cast<size_t>(m) * 3 * H);
+    w.Pq = c.take<int32_t>(static_cast<size_t>(m));
+    w.jflag = c.take<int32_t>(static_cast<size_t>(m));
+    w.pos = c.take<int32_t>(static_cast<size_t>(m));
+    w.total = c.take<int64_t>(2);
+    w.scan_tmp = c.take<int64_t>(scan_temp_elems(m));
+    return w;
+}
+
+}  // namespace
+
+size_t fpfh_ws(int64_t m, int H) {
+    Carver c(nullptr, 0);
+    carve(c, m, H);
+    return c.off;
+}
+
+kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_t* off, const int32_t* nbr,
+                int64_t m, const kmg_params& p, float* spfh_out, float* fpfh_out, int32_t* j_idx, int64_t* n_j_host,
+                int64_t* stats_host, void* ws, size_t ws_bytes, hipStream_t s) {
+    const int H = p.n_bins;
+    Carver c(ws, ws_bytes);
+    FeatWs w = carve(c, m, H);
+    if (!c.fits()) return KMG_ERR_WORKSPACE;
+    const int mi = static_cast<int>(m);
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.st), 0u, sizeof(DevStatus) / 4, s));
+    if (m > 0) {
+        {
+        StageScope sc(ST_SPFH, s);
+        spfh_kernel<<<grid_for(m, kWaves), kBlock, 0, s>>>(xyz, nrm, flags, off, nbr, mi, H, p.tau_num, w.spfh64,
+                                                          spfh_out, w.Pq, w.jflag, w.st);
+        KMG_TRY(launch_status());
+        }
+        StageScope sc(ST_FPFH, s);
+        fpfh_kernel<<<grid_for(m, kWaves), kBlock, 0, s>>>(xyz, flags, w.jflag, off, nbr, mi, H, w.spfh64, w.Pq,
+                                                          fpfh_out);
+        KMG_TRY(launch_status());
+    }
+    {
+    StageScope sc(ST_J_COMPACT, s);
+    KMG_TRY(scan_exclusive(w.jflag, w.pos, m, w.total, w.scan_tmp, s));
+    if (m > 0) {
+        j_emit<<<grid_for(m, kBlock), kBlock, 0, s>>>(w.jflag, w.pos, mi, flags, j_idx);
+        KMG_TRY(launch_status());
+    }
+    }
+    int64_t nj = 0;
+    DevStatus st;
+    KMG_TRY_HIP(hipMemcpyAsync(&nj, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    KMG_TRY_HIP(hipMemcpyAsync(&st, w.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    KMG_TRY_HIP(hipStreamSynchronize(s));
+    timer_collect();
+    *n_j_host = nj;
+    if (stats_host) {
+        stats_host[0] = st.feat_fp64;
+        stats_host[1] = st.feat_edge;
+    }
+    return KMG_OK;
+}
+
+}  // namespace kmg

@@ -1,0 +1,299 @@
+"""Thin Python binding of libkmg (argument marshalling only).
+
+Every step of the hot path runs in the HIP library; this module only checks
+tensor placement and dtypes, allocates outputs and workspace with torch on
+the current device, and passes raw pointers and the current HIP stream to the
+C ABI declared in include/kmg.h.  There is no fallback: if libkmg.so is
+missing, importing the binding raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkmg.so")
+
+KMG_OK = 0
+KMG_ERR_ARG = -1
+KMG_ERR_CAPACITY = -2
+KMG_ERR_DEVICE = -3
+KMG_ERR_RANGE = -4
+KMG_ERR_WORKSPACE = -5
+
+KMG_FP32, KMG_BF16, KMG_FP16 = 0, 1, 2
+OP_VOXELIZE, OP_NORMALS, OP_FPFH, OP_MATCH = 0, 1, 2, 3
+PRECISIONS = {"fp32": KMG_FP32, "bf16": KMG_BF16, "fp16": KMG_FP16}
+
+
+class KmgParams(C.Structure):
+    _fields_ = [
+        ("voxel", C.c_double),
+        ("r_normal", C.c_double),
+        ("r_fpfh", C.c_double),
+        ("tau_lin", C.c_double),
+        ("tau_num", C.c_int32),
+        ("n_bins", C.c_int32),
+        ("viewpoint", C.c_double * 3),
+    ]
+
+
+class KmgError(RuntimeError):
+    def __init__(self, fn: str, status: int, lib):
+        self.status = status
+        msg = lib.kmg_status_string(status).decode() if lib is not None else str(status)
+        super().__init__(f"{fn} failed: {msg} ({status})")
+
+
+_lib = None
+
+
+def load():
+    """Loads libkmg.so (built in-tree by paper_2409_15615_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libkmg.so is not built ({_LIB_PATH}); run: python -m paper_2409_15615_amd.build")
+    lib = C.CDLL(_LIB_PATH)
+    vp, i64, i32, dbl, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_size_t
+    pp = C.POINTER(KmgParams)
+    i64p = C.POINTER(C.c_int64)
+    lib.kmg_version.restype = i32
+    lib.kmg_status_string.argtypes = [i32]
+    lib.kmg_status_string.restype = C.c_char_p
+    lib.kmg_workspace_bytes.argtypes = [i32, i64, i64, pp]
+    lib.kmg_workspace_bytes.restype = sz
+    lib.kmg_voxelize.argtypes = [vp, i64, dbl, vp, vp, i64, i64p, vp, sz, vp]
+    lib.kmg_voxelize.restype = i32
+    lib.kmg_normals.argtypes = [vp, i64, pp, vp, vp, vp, vp, i64, i64p, vp, vp, sz, vp]
+    lib.kmg_normals.restype = i32
+    lib.kmg_fpfh.argtypes = [vp, vp, vp, vp, vp, i64, pp, vp, vp, vp, i64p, i64p, vp, sz, vp]
+    lib.kmg_fpfh.restype = i32
+    lib.kmg_match.argtypes = [vp, vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, i64, i64p, i64p, vp, sz, vp]
+    lib.kmg_match.restype = i32
+    _lib = lib
+    return lib
+
+
+def make_params(voxel, r_normal, r_fpfh, tau_num=3, tau_lin=0.99, n_bins=11, viewpoint=(0.0, 0.0, 0.0)):
+    p = KmgParams()
+    p.voxel, p.r_normal, p.r_fpfh, p.tau_lin = float(voxel), float(r_normal), float(r_fpfh), float(tau_lin)
+    p.tau_num, p.n_bins = int(tau_num), int(n_bins)
+    for c in range(3):
+        p.viewpoint[c] = float(viewpoint[c])
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _raise(fn, st):
+    if st != KMG_OK:
+        raise KmgError(fn, st, _lib)
+
+
+class Workspace:
+    """Caller-owned device scratch, grown on demand and reused across calls."""
+
+    def __init__(self, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.buf = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes * 1.25) + 4096, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws(ws):
+    if ws is not None:
+        return ws
+    dev = torch.cuda.current_device()
+    if dev not in _default_ws:
+        _default_ws[dev] = Workspace()
+    return _default_ws[dev]
+
+
+def workspace_bytes(op, n0, n1=0, params=None):
+    lib = load()
+    return int(lib.kmg_workspace_bytes(op, int(n0), int(n1), C.byref(params) if params is not None else None))
+
+
+def voxelize(xyz, voxel, ws=None):
+    """kmg_voxelize.  xyz: (3, n) float32 device SoA.  Returns (kept_idx int32 [m],
+    kept_xyz float32 (3, m))."""
+    lib = load()
+    _check_dev(xyz, torch.float32, "xyz")
+    n = xyz.shape[1]
+    kept_idx = torch.empty(max(n, 1), dtype=torch.int32, device=xyz.device)
+    kept_xyz = torch.empty(3 * max(n, 1), dtype=torch.float32, device=xyz.device)
+    w = _ws(ws).get(workspace_bytes(OP_VOXELIZE, n))
+    m = C.c_int64(0)
+    st = lib.kmg_voxelize(_ptr(xyz), n, float(voxel), _ptr(kept_idx), _ptr(kept_xyz), n, C.byref(m), _ptr(w),
+                          w.numel(), _stream())
+    _raise("kmg_voxelize", st)
+    m = m.value
+    return kept_idx[:m], kept_xyz[: 3 * m].view(3, m)
+
+
+@dataclass
+class NormalsOut:
+    normals: torch.Tensor
+    flags: torch.Tensor
+    off: torch.Tensor
+    idx: torch.Tensor
+    n_normal: torch.Tensor
+
+
+_nbr_cap_hint = {}
+
+
+def normals(xyz, params, ws=None, want_n_normal=True):
+    """kmg_normals (Algorithm 1, Step 1).  xyz: (3, m) float32 device SoA."""
+    lib = load()
+    _check_dev(xyz, torch.float32, "xyz")
+    m = xyz.shape[1]
+    dev = xyz.device
+    nrm = torch.empty(3 * max(m, 1), dtype=torch.float32, device=dev)
+    flags = torch.empty(max(m, 1), dtype=torch.uint8, device=dev)
+    off = torch.empty(m + 1, dtype=torch.int32, device=dev)
+    n_normal = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if want_n_normal else None
+    w = _ws(ws).get(workspace_bytes(OP_NORMALS, m, 0, params))
+    cap = max(_nbr_cap_hint.get(dev.index, 0), 64 * m, 1)
+    for _ in range(2):
+        idx = torch.empty(cap, dtype=torch.int32, device=dev)
+        nnz = C.c_int64(0)
+        st = lib.kmg_normals(_ptr(xyz), m, C.byref(params), _ptr(nrm), _ptr(flags), _ptr(off), _ptr(idx), cap,
+                             C.byref(nnz), _ptr(n_normal), _ptr(w), w.numel(), _stream())
+        if st == KMG_ERR_CAPACITY:
+            cap = int(nnz.value)
+            _nbr_cap_hint[dev.index] = cap
+            continue
+        _raise("kmg_normals", st)
+        break
+    nnz = nnz.value
+    return NormalsOut(nrm[: 3 * m].view(3, m), flags[:m], off, idx[:nnz],
+                      n_normal[:m] if n_normal is not None else None)
+
+
+@dataclass
+class FpfhOut:
+    fpfh: torch.Tensor
+    spfh: torch.Tensor
+    j_idx: torch.Tensor
+    flags: torch.Tensor
+    stats: tuple
+
+
+def fpfh(xyz, nrm, flags, off, idx, params, ws=None, want_spfh=False):
+    """kmg_fpfh (Algorithm 1, Step 2; Eq. A2-A5).  `flags` is updated in place
+    (bit 1 = J)."""
+    lib = load()
+    for t, nm, dt in ((xyz, "xyz", torch.float32), (nrm, "normals", torch.float32), (flags, "flags", torch.uint8),
+                      (off, "off", torch.int32), (idx, "idx", torch.int32)):
+        _check_dev(t, dt, nm)
+    m = xyz.shape[1]
+    D = 3 * params.n_bins
+    dev = xyz.device
+    out = torch.empty((max(m, 1), D), dtype=torch.float32, device=dev)
+    sp = torch.empty((max(m, 1), D), dtype=torch.float32, device=dev) if want_spfh else None
+    j_idx = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    idx_arg = idx if idx.numel() else torch.empty(1, dtype=torch.int32, device=dev)
+    w = _ws(ws).get(workspace_bytes(OP_FPFH, m, 0, params))
+    nj = C.c_int64(0)
+    stats = (C.c_int64 * 2)()
+    st = lib.kmg_fpfh(_ptr(xyz), _ptr(nrm), _ptr(flags), _ptr(off), _ptr(idx_arg), m, C.byref(params), _ptr(sp),
+                      _ptr(out), _ptr(j_idx), C.byref(nj), stats, _ptr(w), w.numel(), _stream())
+    _raise("kmg_fpfh", st)
+    return FpfhOut(out[:m], sp[:m] if sp is not None else None, j_idx[: nj.value], flags, (stats[0], stats[1]))
+
+
+@dataclass
+class MatchOut:
+    pairs: torch.Tensor
+    d1: torch.Tensor
+    d2: torch.Tensor
+    n_fallback: int
+
+
+def match(desc_p, desc_q, rows_p=None, rows_q=None, prec="fp32", ws=None):
+    """kmg_match (mutual NN).  desc_*: (n, dim) float32 device; rows_*: optional
+    int32 row lists.  Returns pairs (k, 2) int32 of row ids, d1, d2."""
+    lib = load()
+    _check_dev(desc_p, torch.float32, "desc_p")
+    _check_dev(desc_q, torch.float32, "desc_q")
+    dim = desc_p.shape[1]
+    if desc_q.shape[1] != dim:
+        raise ValueError("descriptor lengths differ")
+    for r, nm in ((rows_p, "rows_p"), (rows_q, "rows_q")):
+        if r is not None:
+            _check_dev(r, torch.int32, nm)
+    np_ = rows_p.numel() if rows_p is not None else desc_p.shape[0]
+    nq = rows_q.numel() if rows_q is not None else desc_q.shape[0]
+    dev = desc_p.device
+    cap = max(min(np_, nq), 1)
+    pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    d1 = torch.empty(cap, dtype=torch.float32, device=dev)
+    d2 = torch.empty(cap, dtype=torch.float32, device=dev)
+    w = _ws(ws).get(_match_ws_dim(np_, nq, dim))
+    npairs = C.c_int64(0)
+    nfb = C.c_int64(0)
+    st = lib.kmg_match(_ptr(desc_p), _ptr(rows_p), np_, _ptr(desc_q), _ptr(rows_q), nq, dim, PRECISIONS[prec],
+                       _ptr(pairs), _ptr(d1), _ptr(d2), cap, C.byref(npairs), C.byref(nfb), _ptr(w), w.numel(),
+                       _stream())
+    _raise("kmg_match", st)
+    k = npairs.value
+    return MatchOut(pairs[:k], d1[:k], d2[:k], nfb.value)
+
+
+def _match_ws_dim(np_, nq, dim):
+    # the match workspace is sized for descriptors of length 3 * n_bins >= dim
+    p = make_params(1.0, 1.0, 1.0, n_bins=(dim + 2) // 3)
+    return int(load().kmg_workspace_bytes(OP_MATCH, np_, nq, C.byref(p)))
+
+
+@dataclass
+class CloudOut:
+    kept_idx: torch.Tensor
+    xyz: torch.Tensor
+    normals: NormalsOut
+    feats: FpfhOut
+
+
+def faster_pfh(raw_xyz, params, ws=None):
+    """voxelize -> normals -> fpfh for one raw cloud (3, n)."""
+    kept_idx, xyz = voxelize(raw_xyz, params.voxel, ws)
+    xyz = xyz.contiguous()
+    nr = normals(xyz, params, ws)
+    ft = fpfh(xyz, nr.normals, nr.flags, nr.off, nr.idx, params, ws)
+    return CloudOut(kept_idx, xyz, nr, ft)
+
+
+def register_pair(src_raw, tgt_raw, params_src, params_tgt, prec="fp32", ws=None):
+    """The whole hot path for one pair: Faster-PFH on both clouds, then mutual
+    matching of the J descriptors.  Pairs are kept-cloud indices."""
+    a = faster_pfh(src_raw, params_src, ws)
+    b = faster_pfh(tgt_raw, params_tgt, ws)
+    mt = match(a.feats.fpfh, b.feats.fpfh, a.feats.j_idx, b.feats.j_idx, prec=prec, ws=ws)
+    return a, b, mt

@@ -1,0 +1,310 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (from the method's discrete/continuous outputs):
+  - voxel kept set, kept coordinates, neighbour CSR, |P_normal|, B and J flags,
+    J lists and correspondence sets: bit-exact;
+  - normals: angle to the oracle normal <= 1e-5 rad wherever the relative
+    eigen-gap (l2 - l3) / l1 is >= 1e-6 (ill-conditioned points are counted);
+  - SPFH: |delta| <= 1e-4 per bin; FPFH: |delta| <= 1e-4 * S_q / 100 per bin,
+    S_q being the sub-histogram sum (FPFH rows are rescaled sums of SPFH rows
+    weighted by 1 / distance, so the bar is stated per unit of S_q / 100);
+  - d1, d2: the FP32 rounding of the oracle's FP64 values.
+The histogram step is compared on shared inputs: both sides take the oracle's
+CSR, B flags and the oracle's normals rounded to float32.
+"""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_15615_amd import kmg
+
+    kmg.load()
+    torch.cuda.set_device(0)
+    return kmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def kparams(K, p, vp):
+    return K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, vp)
+
+
+_cache = {}
+
+
+def oracle_pair(orc, name):
+    if name not in _cache:
+        d = synth.c0_pair(0) if name == "c0" else synth.c1_pair(0)
+        _cache[name] = (d, orc.run_pair(d["src"], d["tgt"], d["params"], d["vp_src"], d["vp_tgt"]))
+    return _cache[name]
+
+
+# ---------------------------------------------------------------- voxelize --
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_voxelize_bit_exact(K, orc, name):
+    d, ref = oracle_pair(orc, name)
+    for tag in ("src", "tgt"):
+        raw = d[tag]
+        kept, xyz = K.voxelize(dev(raw), d["params"].voxel)
+        np.testing.assert_array_equal(host(kept), ref[tag]["kept"])
+        np.testing.assert_array_equal(host(xyz), raw[:, ref[tag]["kept"]])
+
+
+def test_voxelize_edge_cases(K, orc):
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(-2, 2, (3, 5000)).astype(np.float32)
+    pts[:, 17] = np.nan
+    pts[1, 99] = np.inf
+    pts[:, 2000:2100] = pts[:, 2000:2001]  # one voxel, 100 copies
+    kept, xyz = K.voxelize(dev(pts), 0.05)
+    ref, _ = orc.voxelize(pts, 0.05)
+    np.testing.assert_array_equal(host(kept), ref)
+    kept, xyz = K.voxelize(dev(np.zeros((3, 0), np.float32)), 0.1)
+    assert kept.numel() == 0 and xyz.shape == (3, 0)
+    one = np.array([[1.0], [2.0], [3.0]], np.float32)
+    kept, _ = K.voxelize(dev(one), 0.1)
+    assert host(kept).tolist() == [0]
+    far = np.array([[1e6], [0.0], [0.0]], np.float32)
+    with pytest.raises(K.KmgError) as e:
+        K.voxelize(dev(far), 0.01)
+    assert e.value.status == K.KMG_ERR_RANGE
+
+
+# ----------------------------------------------------------------- normals --
+
+def check_normals(K, xyz, p, vp, ref_csr=None):
+    import oracle as orc
+
+    off_r, idx_r = ref_csr if ref_csr is not None else orc.radius_search(xyz, p.r_fpfh)
+    nr_r = orc.normals(xyz, off_r, idx_r, p.r_normal, p.tau_num, p.tau_lin, vp)
+    out = K.normals(dev(xyz), kparams(K, p, vp))
+    np.testing.assert_array_equal(host(out.off).astype(np.int64), off_r)
+    np.testing.assert_array_equal(host(out.idx), idx_r)
+    np.testing.assert_array_equal(host(out.n_normal), nr_r["n_normal"])
+    np.testing.assert_array_equal(host(out.flags) & 1, nr_r["B"])
+    has = nr_r["B"] == 1
+    g = host(out.normals).astype(np.float64)
+    cosang = np.clip(np.sum(g[:, has] * nr_r["normals"][:, has], axis=0), -1.0, 1.0)
+    ang = np.arccos(cosang)
+    well = nr_r["gap"][has] >= 1e-6
+    assert np.all(ang[well] <= 1e-5), (ang[well].max(), int((ang[well] > 1e-5).sum()))
+    return out, nr_r, int((~well).sum())
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_normals_and_csr(K, orc, name):
+    d, ref = oracle_pair(orc, name)
+    for tag in ("src", "tgt"):
+        r = ref[tag]
+        _, _, ill = check_normals(K, r["xyz"], d["params"], d["vp_src" if tag == "src" else "vp_tgt"],
+                                  (r["off"], r["idx"]))
+        print(f"{name}/{tag}: m={r['xyz'].shape[1]} nnz={len(r['idx'])} ill-conditioned normals: {ill}")
+
+
+def test_normals_edge_cases(K, orc):
+    p = synth.Params(voxel=0.05, r_normal=0.1, r_fpfh=0.25)
+    line = np.zeros((3, 200), np.float32)
+    line[0] = np.linspace(0, 4, 200)
+    out, nr_r, _ = check_normals(K, line, p, np.array([0, 0, 1.0]))
+    assert host(out.flags).sum() == 0  # collinear: linearity 1, no reliable normal
+    sparse = (np.arange(3 * 50, dtype=np.float32).reshape(3, 50) * 10).copy()
+    out, _, _ = check_normals(K, sparse, p, np.zeros(3))
+    assert host(out.flags).sum() == 0  # isolated points: too few neighbours
+    out = K.normals(dev(np.zeros((3, 0), np.float32)), kparams(K, p, np.zeros(3)))
+    assert out.idx.numel() == 0 and host(out.off).tolist() == [0]
+    # a dense cube: many neighbours per query (long lists, rank sort across several rounds)
+    g = (np.arange(12) * 0.05).astype(np.float32)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    cube = np.stack([X.ravel(), Y.ravel(), Z.ravel()]).astype(np.float32)
+    cube = np.ascontiguousarray(cube[:, np.random.default_rng(0).permutation(cube.shape[1])])
+    check_normals(K, cube, synth.Params(voxel=0.05, r_normal=0.12, r_fpfh=0.3), np.array([5.0, 4.0, 3.0]))
+
+
+def test_dense_neighbourhoods_over_1024(K, orc):
+    """|N(q)| above 1024 takes the single-wave pass with the large LDS list."""
+    g = (np.arange(16) * 0.05).astype(np.float32)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    cube = np.ascontiguousarray(np.stack([X.ravel(), Y.ravel(), Z.ravel()]).astype(np.float32))
+    p = synth.Params(voxel=0.05, r_normal=0.1, r_fpfh=0.36)
+    out, _, _ = check_normals(K, cube, p, np.array([5.0, 4.0, 3.0]))
+    assert np.diff(host(out.off)).max() > 1024
+
+
+# ------------------------------------------------------------ SPFH / FPFH --
+
+def check_features(K, orc, xyz, p, vp, csr=None):
+    off, idx = csr if csr is not None else orc.radius_search(xyz, p.r_fpfh)
+    nr = orc.normals(xyz, off, idx, p.r_normal, p.tau_num, p.tau_lin, vp)
+    n32 = nr["normals"].astype(np.float32)
+    sp = orc.spfh(xyz, n32.astype(np.float64), off, idx, nr["B"], p.tau_num, p.n_bins)
+    fp = orc.fpfh(xyz, off, idx, nr["B"], sp["J"], sp["spfh"], sp["Pq"], p.n_bins)
+    flags = dev(nr["B"].astype(np.uint8))
+    out = K.fpfh(dev(xyz), dev(n32), flags, dev(off.astype(np.int32)), dev(idx if len(idx) else np.zeros(1, np.int32)),
+                 kparams(K, p, vp), want_spfh=True)
+    gflags = host(out.flags)
+    np.testing.assert_array_equal(gflags & 1, nr["B"])
+    np.testing.assert_array_equal((gflags >> 1) & 1, sp["J"])
+    np.testing.assert_array_equal(host(out.j_idx), np.nonzero(sp["J"])[0])
+    gs = host(out.spfh).astype(np.float64)
+    assert np.abs(gs - sp["spfh"]).max() <= 1e-4
+    gf = host(out.fpfh).astype(np.float64)
+    H = p.n_bins
+    S = np.maximum(fp[:, :H].sum(1, keepdims=True), 100.0)
+    rel = np.abs(gf - fp) / (S / 100.0)
+    assert rel.max() <= 1e-4, rel.max()
+    exact = np.mean(gf.astype(np.float32) == fp.astype(np.float32))
+    return out, sp, fp, exact
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_features_on_shared_inputs(K, orc, name):
+    d, ref = oracle_pair(orc, name)
+    for tag in ("src", "tgt"):
+        r = ref[tag]
+        out, sp, fp, exact = check_features(K, orc, r["xyz"], d["params"],
+                                            d["vp_src" if tag == "src" else "vp_tgt"], (r["off"], r["idx"]))
+        print(f"{name}/{tag}: |J|={out.j_idx.numel()} FPFH values equal in float32: {exact:.6f}; "
+              f"FP64 feature recomputes {out.stats[0]}, FP64 edge events {out.stats[1]}")
+
+
+def test_features_closed_forms(K, orc):
+    """Plane: every SPFH is 100 at bins 5, 16, 27; four-point golden FPFH."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "four_points.json")))
+    pts = np.array(g["points"], np.float32).T.copy()
+    p = synth.Params(voxel=1.0, r_normal=g["r_normal"], r_fpfh=g["r_fpfh"], tau_num=g["tau_num"], tau_lin=g["tau_lin"])
+    out, sp, fp, _ = check_features(K, orc, pts, p, np.array(g["viewpoint"]))
+    f = host(out.fpfh)
+    for q in range(4):
+        np.testing.assert_allclose(f[q, g["spfh_support"]], g["fpfh_support_value"][q], rtol=1e-6)
+        assert np.count_nonzero(f[q]) == 3
+
+
+# ---------------------------------------------------------------- matching --
+
+def check_match(K, orc, X, Y, prec="fp32"):
+    mm = orc.mutual_match(X, Y)
+    out = K.match(dev(X), dev(Y), prec=prec)
+    np.testing.assert_array_equal(host(out.pairs), mm["pairs"])
+    np.testing.assert_array_equal(host(out.d1), mm["d1"].astype(np.float32))
+    np.testing.assert_array_equal(host(out.d2), mm["d2"].astype(np.float32))
+    return out, mm
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_match_on_oracle_descriptors(K, orc, name):
+    d, ref = oracle_pair(orc, name)
+    X = ref["src"]["fpfh"][ref["src"]["j_idx"]].astype(np.float32)
+    Y = ref["tgt"]["fpfh"][ref["tgt"]["j_idx"]].astype(np.float32)
+    out, mm = check_match(K, orc, X, Y)
+    print(f"{name}: {X.shape[0]} x {Y.shape[0]} -> {len(mm['pairs'])} pairs, exact re-scans {out.n_fallback}")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 5), (5, 1), (3, 3), (31, 33), (257, 255), (1000, 777), (4097, 300)])
+def test_match_ragged_sizes(K, orc, shape):
+    X, Y, _ = synth.synthetic_descriptors(shape[0], shape[1], item=shape[0] * 7 + shape[1])
+    check_match(K, orc, X, Y)
+
+
+def test_match_ties_and_self_match(K, orc):
+    rng = np.random.default_rng(9)
+    X = rng.integers(0, 4, (700, 33)).astype(np.float32)
+    Y = rng.integers(0, 4, (650, 33)).astype(np.float32)
+    check_match(K, orc, X, Y)
+    Z = rng.uniform(0, 50, (500, 33)).astype(np.float32)
+    Z[100:120] = Z[7]
+    out, mm = check_match(K, orc, Z, Z)
+    expect = [i for i in range(500) if not (100 <= i < 120)]
+    assert host(out.pairs)[:, 0].tolist() == expect
+
+
+@pytest.mark.parametrize("dim", [1, 8, 34, 64])
+def test_match_other_lengths(K, orc, dim):
+    rng = np.random.default_rng(dim)
+    X = rng.gamma(0.7, 10.0, (600, dim)).astype(np.float32)
+    Y = np.concatenate([X[:300] * (1 + 0.01 * rng.standard_normal((300, dim))),
+                        rng.gamma(0.7, 10.0, (200, dim))]).astype(np.float32)
+    Y = np.abs(Y)
+    check_match(K, orc, X, Y)
+
+
+def test_match_rows_and_capacity(K, orc):
+    X, Y, _ = synth.synthetic_descriptors(900, 800, item=5)
+    rows_p = np.arange(0, 900, 2, dtype=np.int32)
+    rows_q = np.arange(1, 800, 2, dtype=np.int32)
+    mm = orc.mutual_match(X[rows_p], Y[rows_q])
+    out = K.match(dev(X), dev(Y), dev(rows_p), dev(rows_q))
+    expect = np.stack([rows_p[mm["pairs"][:, 0]], rows_q[mm["pairs"][:, 1]]], 1)
+    np.testing.assert_array_equal(host(out.pairs), expect)
+    # too small an output buffer: KMG_ERR_CAPACITY with the required count
+    lib = K.load()
+    n = C.c_int64(0)
+    ws = torch.empty(K.workspace_bytes(K.OP_MATCH, 900, 800, K.make_params(1, 1, 1)), dtype=torch.uint8,
+                     device="cuda")
+    buf = torch.empty(16, dtype=torch.int32, device="cuda")
+    f = torch.empty(16, dtype=torch.float32, device="cuda")
+    dx, dy = dev(X), dev(Y)
+    st = lib.kmg_match(C.c_void_p(dx.data_ptr()), None, 900, C.c_void_p(dy.data_ptr()), None, 800, 33, 0,
+                       C.c_void_p(buf.data_ptr()), C.c_void_p(f.data_ptr()), C.c_void_p(f.data_ptr()), 2,
+                       C.byref(n), None, C.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert st == K.KMG_ERR_CAPACITY and n.value == len(orc.mutual_match(X, Y)["pairs"])
+
+
+def test_match_empty(K):
+    X = torch.zeros((0, 33), dtype=torch.float32, device="cuda")
+    Y = torch.ones((10, 33), dtype=torch.float32, device="cuda")
+    assert K.match(X, Y).pairs.shape[0] == 0
+    assert K.match(Y, X).pairs.shape[0] == 0
+
+
+# -------------------------------------------------------------- end to end --
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_end_to_end(K, orc, name):
+    d, ref = oracle_pair(orc, name)
+    p = d["params"]
+    a, b, mt = K.register_pair(dev(d["src"]), dev(d["tgt"]), kparams(K, p, d["vp_src"]), kparams(K, p, d["vp_tgt"]))
+    for tag, g in (("src", a), ("tgt", b)):
+        np.testing.assert_array_equal(host(g.kept_idx), ref[tag]["kept"])
+        np.testing.assert_array_equal(host(g.normals.idx), ref[tag]["idx"])
+        np.testing.assert_array_equal(host(g.feats.flags) & 1, ref[tag]["B"])
+        np.testing.assert_array_equal(host(g.feats.j_idx), ref[tag]["j_idx"])
+    gp = {tuple(x) for x in host(mt.pairs).tolist()}
+    rp = {tuple(x) for x in ref["pairs"].tolist()}
+    jac = len(gp & rp) / max(1, len(gp | rp))
+    print(f"{name}: correspondences GPU {len(gp)} oracle {len(rp)} Jaccard {jac:.6f} equal {gp == rp}")
+    assert gp == rp
+
+
+def test_determinism(K, orc):
+    d, _ = oracle_pair(orc, "c1")
+    p = d["params"]
+    outs = []
+    for _ in range(2):
+        a, b, mt = K.register_pair(dev(d["src"]), dev(d["tgt"]), kparams(K, p, d["vp_src"]),
+                                   kparams(K, p, d["vp_tgt"]))
+        outs.append([host(x).copy() for x in (a.normals.normals, a.feats.fpfh, b.feats.fpfh, mt.pairs, mt.d1, mt.d2)])
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
