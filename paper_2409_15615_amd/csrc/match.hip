@@ -2,24 +2,29 @@
 // Section III-C) on gfx950 matrix cores, with exact FP64 decisions.
 //
 // Candidate generation.  For a query row y and swept rows x_i, the NN ranks
-// D(i) = ||x_i||^2 + ||y||^2 - 2 x_i.y by s_i = ||x_i||^2 - 2 x_i.y.  Rows are
-// packed k-major in 32-row chunks with the squared norm appended as an extra
-// "dimension" (A = [x, ||x||^2]); queries use B = [-2 y, 1].  One
-// v_mfma_f32_32x32x2_f32 chain of ceil((dim+1)/2) steps yields a 32x32 tile of
-// s; lane l owns query column l % 32 and 16 of the 32 rows, and keeps a
-// running top-4 of s in registers.  A wave holds 64 query columns (two
-// chains), a block of four waves 256, and the swept rows are split into S
-// segments; block b takes segment b % S (S is a multiple of 8 when possible,
-// so each of the eight XCDs streams one eighth of the rows through its L2).
+// D(i) = ||x_i||^2 + ||y||^2 - 2 x_i.y by t_i = ||x_i||^2 - 2 x_i.y.  FPFH rows
+// cluster tightly (nearest-neighbour distances are often 1e-5 of the squared
+// norms), so this expanded form is evaluated on FP64 matrix cores: rows are
+// packed k-major in 16-row chunks with the squared norm appended as an extra
+// "dimension" (A = [x, ||x||^2]), queries use B = [-2 y, 1], and one
+// v_mfma_f64_16x16x4_f64 chain of ceil((dim+1)/4) steps yields a 16x16 tile
+// of t.  Lane l owns query column l % 16 and tile rows l / 16 + {0, 4, 8, 12}
+// (result register r holds row 4 r + l / 16), and keeps a running top-4 of t
+// in registers.  A wave holds 64 query
+// columns (four chains), a block of four waves 256, and the swept rows are
+// split into S segments; block b takes segment b % S (S is a multiple of 8
+// when possible, so each of the eight XCDs streams one eighth of the rows
+// through its own L2).
 //
 // Exact decision.  The per-segment top-4 lists are merged, the four
 // candidates are re-scored with the plain FP64 sum of squared differences in
 // dimension order, and the result is certified: every non-candidate has
-// s >= s_4 (the 4th candidate's score), and |s - exact| <= E with
-// E = 256 u (max ||x||^2 + ||y||^2) (u = 2^-24; the FP32 dot-product bound is
-// (dim+2) u times the same sum).  If the exact second-best distance is
-// below s_4 + ||y||^2 - E, the exact best and second-best over all rows are
-// among the candidates.  Otherwise the query is re-scanned exactly in FP64.
+// t >= t_4 (the 4th candidate's value) and |t - exact| <= E with
+// E = 128 u (2 max ||x||^2 + 2 ||y||^2), u = 2^-53 (the dot-product rounding
+// bound is (dim + 2) u times ||x||^2 + 2 x.y <= 2 ||x||^2 + ||y||^2).  If the
+// exact second-best distance is below t_4 + ||y||^2 - E, the exact best and
+// second-best over all rows are among the candidates; otherwise the query is
+// re-scanned exactly in FP64.
 #include <math.h>
 
 #include "kmg_device.h"
@@ -28,19 +33,21 @@ namespace kmg {
 
 namespace {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTileRows = 32;
-constexpr int kColsPerWave = 64;
+constexpr int kTileRows = 16;     // rows per packed chunk (MFMA M)
+constexpr int kTileCols = 16;     // query columns per MFMA tile (MFMA N)
+constexpr int kTilesPerWave = 4;  // 64 query columns per wave
+constexpr int kColsPerWave = kTileCols * kTilesPerWave;
 constexpr int kWavesPerBlock = 4;
 constexpr int kColsPerBlock = kColsPerWave * kWavesPerBlock;
 constexpr int kBlock = 256;
 
 struct Packed {
-    const float* pk;  // [chunks][Kp][32]
-    int n;            // rows
+    const double* pk;  // [chunks][kp][16]
+    int n;             // rows
     int chunks;
-    int kp;           // packed depth (even)
+    int kp;            // packed depth (multiple of 4)
 };
 
 // ---------------------------------------------------------------- packing --
@@ -63,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void row_norms(const float* __restrict__ de
 
 __global__ __launch_bounds__(kBlock) void pack_rows(const float* __restrict__ desc, const int32_t* __restrict__ rows,
                                                     int n, int dim, int kp, int chunks,
-                                                    const double* __restrict__ nrm2, float* __restrict__ pk) {
+                                                    const double* __restrict__ nrm2, double* __restrict__ pk) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t total = static_cast<int64_t>(chunks) * kp * kTileRows;
     if (t >= total) return;
@@ -71,10 +78,10 @@ __global__ __launch_bounds__(kBlock) void pack_rows(const float* __restrict__ de
     const int k = static_cast<int>((t / kTileRows) % kp);
     const int c = static_cast<int>(t / (static_cast<int64_t>(kTileRows) * kp));
     const int i = c * kTileRows + ii;
-    float v = 0.0f;
+    double v = 0.0;
     if (i < n) {
         if (k < dim) v = desc[static_cast<int64_t>(rows ? rows[i] : i) * dim + k];
-        else if (k == dim) v = static_cast<float>(nrm2[i]);
+        else if (k == dim) v = nrm2[i];
     } else if (k == dim) {
         v = INFINITY;  // padding rows never enter a top-k list
     }
@@ -84,13 +91,13 @@ __global__ __launch_bounds__(kBlock) void pack_rows(const float* __restrict__ de
 // ----------------------------------------------------------- top-4 passes --
 
 struct Top4 {
-    float v0, v1, v2, v3;
+    double v0, v1, v2, v3;
     int i0, i1, i2, i3;
     __device__ void init() {
         v0 = v1 = v2 = v3 = INFINITY;
         i0 = i1 = i2 = i3 = -1;
     }
-    __device__ __forceinline__ void push(float v, int i) {
+    __device__ __forceinline__ void push(double v, int i) {
         if (!(v < v3)) return;
         if (v < v2) {
             v3 = v2;
@@ -119,12 +126,12 @@ struct Top4 {
 };
 
 // (value, index) order used wherever lists are merged: deterministic.
-__device__ __forceinline__ bool before(float va, int ia, float vb, int ib) {
+__device__ __forceinline__ bool before(double va, int ia, double vb, int ib) {
     return va < vb || (va == vb && static_cast<unsigned>(ia) < static_cast<unsigned>(ib));
 }
 
 // Insertion into a sorted Top4 under the (value, index) order.
-__device__ __forceinline__ void push_ordered(Top4& t, float v, int ix) {
+__device__ __forceinline__ void push_ordered(Top4& t, double v, int ix) {
     if (!before(v, ix, t.v3, t.i3)) return;
     if (before(v, ix, t.v2, t.i2)) {
         t.v3 = t.v2;
@@ -151,86 +158,89 @@ __device__ __forceinline__ void push_ordered(Top4& t, float v, int ix) {
     }
 }
 
+// Merges the top-4 list of lane l ^ d into this lane's list.
+__device__ __forceinline__ void merge_lanes(Top4& t, int d) {
+    const double v0 = __shfl_xor(t.v0, d, kWave), v1 = __shfl_xor(t.v1, d, kWave);
+    const double v2 = __shfl_xor(t.v2, d, kWave), v3 = __shfl_xor(t.v3, d, kWave);
+    const int i0 = __shfl_xor(t.i0, d, kWave), i1 = __shfl_xor(t.i1, d, kWave);
+    const int i2 = __shfl_xor(t.i2, d, kWave), i3 = __shfl_xor(t.i3, d, kWave);
+    push_ordered(t, v0, i0);
+    push_ordered(t, v1, i1);
+    push_ordered(t, v2, i2);
+    push_ordered(t, v3, i3);
+}
+
 template <int KS>
 __global__ __launch_bounds__(kBlock) void topk_pass(Packed A, Packed B, int dim, int segs, int chunks_per_seg,
-                                                    float* __restrict__ part_v, int32_t* __restrict__ part_i) {
+                                                    double* __restrict__ part_v, int32_t* __restrict__ part_i) {
     const int seg = blockIdx.x % segs;
     const int cblk = blockIdx.x / segs;
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
     if (col0 >= B.n) return;
-    const int half = lane >> 5;
-    const int l32 = lane & 31;
+    const int g = lane >> 4;   // k offset within a step for the operands; row group for the result
+    const int l16 = lane & 15;
     // query operand: B[k][j] = -2 y_j[k] (k < dim), 1 (k = dim), 0 beyond
-    float bq[2][KS];
+    double bq[kTilesPerWave][KS];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int chunk = (col0 >> 5) + t;
+    for (int t = 0; t < kTilesPerWave; ++t) {
+        const int chunk = col0 / kTileCols + t;
         const bool have = chunk < B.chunks;
-        const float* src = B.pk + static_cast<int64_t>(have ? chunk : 0) * B.kp * kTileRows;
+        const double* src = B.pk + static_cast<int64_t>(have ? chunk : 0) * B.kp * kTileRows;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const int k = 2 * s + half;
-            const float v = (have && k < B.kp) ? src[k * kTileRows + l32] : 0.0f;
-            bq[t][s] = (k < dim) ? -2.0f * v : (k == dim ? 1.0f : 0.0f);
+            const int k = 4 * s + g;
+            const double v = (have && k < B.kp) ? src[k * kTileRows + l16] : 0.0;
+            bq[t][s] = (k < dim) ? -2.0 * v : (k == dim ? 1.0 : 0.0);
         }
     }
-    Top4 top[2];
-    top[0].init();
-    top[1].init();
+    Top4 top[kTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) top[t].init();
     const int c_begin = seg * chunks_per_seg;
     const int c_end = min(c_begin + chunks_per_seg, A.chunks);
     for (int c = c_begin; c < c_end; ++c) {
-        const float* src = A.pk + static_cast<int64_t>(c) * A.kp * kTileRows;
-        float a[KS];
+        const double* src = A.pk + static_cast<int64_t>(c) * A.kp * kTileRows;
+        double a[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) a[s] = (2 * s + half < A.kp) ? src[s * 2 * kTileRows + lane] : 0.0f;
-        floatx16 acc0 = {0}, acc1 = {0};
+        for (int s = 0; s < KS; ++s) a[s] = (4 * s + g < A.kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+        doublex4 acc[kTilesPerWave];
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], bq[0][s], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], bq[1][s], acc1, 0, 0, 0);
-        }
-        const int row0 = c * kTileRows + 4 * half;
-        float mn0 = acc0[0], mn1 = acc1[0];
 #pragma unroll
-        for (int r = 1; r < 16; ++r) {
-            mn0 = fminf(mn0, acc0[r]);
-            mn1 = fminf(mn1, acc1[r]);
+            for (int t = 0; t < kTilesPerWave; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bq[t][s], acc[t], 0, 0, 0);
         }
-        if (mn0 < top[0].v3) {
+        // result register r of lane l holds tile row 4 r + l / 16, column l % 16
+        const int row0 = c * kTileRows + g;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) top[0].push(acc0[r], row0 + 8 * (r >> 2) + (r & 3));
-        }
-        if (mn1 < top[1].v3) {
+        for (int t = 0; t < kTilesPerWave; ++t) {
+            const double mn = fmin(fmin(acc[t][0], acc[t][1]), fmin(acc[t][2], acc[t][3]));
+            if (mn < top[t].v3) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) top[1].push(acc1[r], row0 + 8 * (r >> 2) + (r & 3));
+                for (int r = 0; r < 4; ++r) top[t].push(acc[t][r], row0 + 4 * r);
+            }
         }
     }
-    // merge the two row halves of every column (lanes l and l ^ 32)
+    // the four row groups of a column (lanes l, l ^ 16, l ^ 32, l ^ 48) merge their lists
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const float ov0 = __shfl_xor(top[t].v0, 32, kWave), ov1 = __shfl_xor(top[t].v1, 32, kWave);
-        const float ov2 = __shfl_xor(top[t].v2, 32, kWave), ov3 = __shfl_xor(top[t].v3, 32, kWave);
-        const int oi0 = __shfl_xor(top[t].i0, 32, kWave), oi1 = __shfl_xor(top[t].i1, 32, kWave);
-        const int oi2 = __shfl_xor(top[t].i2, 32, kWave), oi3 = __shfl_xor(top[t].i3, 32, kWave);
-        Top4 mrg = top[t];
-        push_ordered(mrg, ov0, oi0);
-        push_ordered(mrg, ov1, oi1);
-        push_ordered(mrg, ov2, oi2);
-        push_ordered(mrg, ov3, oi3);
-        const int col = col0 + 32 * t + l32;
-        if (half == 0 && col < B.n) {
+    for (int t = 0; t < kTilesPerWave; ++t) {
+        merge_lanes(top[t], 16);
+        merge_lanes(top[t], 32);
+        const int col = col0 + kTileCols * t + l16;
+        if (g == 0 && col < B.n) {
             const int64_t base = (static_cast<int64_t>(col) * segs + seg) * kTopK;
-            part_v[base + 0] = mrg.v0;
-            part_v[base + 1] = mrg.v1;
-            part_v[base + 2] = mrg.v2;
-            part_v[base + 3] = mrg.v3;
-            part_i[base + 0] = mrg.i0;
-            part_i[base + 1] = mrg.i1;
-            part_i[base + 2] = mrg.i2;
-            part_i[base + 3] = mrg.i3;
+            part_v[base + 0] = top[t].v0;
+            part_v[base + 1] = top[t].v1;
+            part_v[base + 2] = top[t].v2;
+            part_v[base + 3] = top[t].v3;
+            part_i[base + 0] = top[t].i0;
+            part_i[base + 1] = top[t].i1;
+            part_i[base + 2] = top[t].i2;
+            part_i[base + 3] = top[t].i3;
         }
     }
 }
@@ -259,7 +269,7 @@ struct Side {
 // One thread per query: merge the S x 4 partial candidates, re-score the best
 // four exactly, certify or queue the query for an exact scan.
 __global__ __launch_bounds__(kBlock) void rescore(Side X, Side Y, int dim, int segs,
-                                                  const float* __restrict__ part_v, const int32_t* __restrict__ part_i,
+                                                  const double* __restrict__ part_v, const int32_t* __restrict__ part_i,
                                                   const double* __restrict__ ny2,
                                                   const unsigned long long* __restrict__ max_x_bits,
                                                   int32_t* __restrict__ nn, double* __restrict__ best,
@@ -271,9 +281,9 @@ __global__ __launch_bounds__(kBlock) void rescore(Side X, Side Y, int dim, int s
     t.init();
     const int64_t base = static_cast<int64_t>(j) * segs * kTopK;
     for (int e = 0; e < segs * kTopK; ++e) {
-        const float v = part_v[base + e];
+        const double v = part_v[base + e];
         const int ix = part_i[base + e];
-        if (ix < 0) continue;
+        if (ix < 0 || ix >= X.n) continue;  // only real rows are ever candidates
         push_ordered(t, v, ix);
     }
     const float* y = Y.row(j, dim);
@@ -299,8 +309,8 @@ __global__ __launch_bounds__(kBlock) void rescore(Side X, Side Y, int dim, int s
         ok = true;  // every row was a candidate
     } else {
         const double mx = __longlong_as_double(static_cast<long long>(*max_x_bits));
-        const double E = 256.0 * 5.9604644775390625e-8 * (mx + ny2[j]) + 1e-30;
-        const double bound = static_cast<double>(t.v3) + ny2[j] - E;
+        const double E = 128.0 * 1.1102230246251565e-16 * (2.0 * mx + 2.0 * ny2[j]) + 1e-300;
+        const double bound = t.v3 + ny2[j] - E;
         ok = ncand == 4 && b2 < bound;
     }
     if (ok) {
@@ -392,7 +402,7 @@ int choose_segments(int chunks_a, int n_queries) {
 
 struct Dir {
     int segs;
-    float* part_v;
+    double* part_v;
     int32_t* part_i;
     int32_t* nn;
     double* best;
@@ -403,8 +413,8 @@ struct Dir {
 
 struct MatchWs {
     DevStatus* st;
-    float* pk_p;
-    float* pk_q;
+    double* pk_p;
+    double* pk_q;
     double* n2_p;
     double* n2_q;
     unsigned long long* max_bits;  // [0] P, [1] Q
@@ -418,12 +428,12 @@ struct MatchWs {
 
 MatchWs carve(Carver& c, int64_t np, int64_t nq, int dim) {
     MatchWs w;
-    w.kp = (dim + 2) / 2 * 2;
+    w.kp = (dim + 1 + 3) / 4 * 4;
     w.chunks_p = static_cast<int>((np + kTileRows - 1) / kTileRows);
     w.chunks_q = static_cast<int>((nq + kTileRows - 1) / kTileRows);
     w.st = c.take<DevStatus>(1);
-    w.pk_p = c.take<float>(static_cast<size_t>(w.chunks_p) * w.kp * kTileRows);
-    w.pk_q = c.take<float>(static_cast<size_t>(w.chunks_q) * w.kp * kTileRows);
+    w.pk_p = c.take<double>(static_cast<size_t>(w.chunks_p) * w.kp * kTileRows);
+    w.pk_q = c.take<double>(static_cast<size_t>(w.chunks_q) * w.kp * kTileRows);
     w.n2_p = c.take<double>(static_cast<size_t>(np));
     w.n2_q = c.take<double>(static_cast<size_t>(nq));
     w.max_bits = c.take<unsigned long long>(2);
@@ -432,7 +442,7 @@ MatchWs carve(Carver& c, int64_t np, int64_t nq, int dim) {
     for (int d = 0; d < 2; ++d) {
         Dir& D = w.dir[d];
         D.segs = choose_segments(rows_chunks[d], static_cast<int>(nqry[d]));
-        D.part_v = c.take<float>(static_cast<size_t>(nqry[d]) * D.segs * kTopK);
+        D.part_v = c.take<double>(static_cast<size_t>(nqry[d]) * D.segs * kTopK);
         D.part_i = c.take<int32_t>(static_cast<size_t>(nqry[d]) * D.segs * kTopK);
         D.nn = c.take<int32_t>(static_cast<size_t>(nqry[d]));
         D.best = c.take<double>(static_cast<size_t>(nqry[d]));
@@ -494,16 +504,16 @@ kmg_status match(const float* dp, const int32_t* rp, int64_t np, const float* dq
     const Packed Q{w.pk_q, nqi, w.chunks_q, w.kp};
     const Side SP{dp, rp, npi}, SQ{dq, rq, nqi};
     // direction 0: queries P over rows Q; direction 1: queries Q over rows P
-    const int ks = w.kp / 2;
+    const int ks = w.kp / 4;
     for (int d = 0; d < 2; ++d) {
         const Packed& A = d == 0 ? Q : P;
         const Packed& B = d == 0 ? P : Q;
         KMG_TRY(fill_u32(w.dir[d].fb_count, 0u, 1, s));
         StageScope sc(ST_MATCH_TOPK, s);
-        if (ks <= 17) {
+        if (ks <= 9) {
+            KMG_TRY(run_pass<9>(A, B, dim, w.dir[d], s));
+        } else if (ks <= 17) {
             KMG_TRY(run_pass<17>(A, B, dim, w.dir[d], s));
-        } else if (ks <= 33) {
-            KMG_TRY(run_pass<33>(A, B, dim, w.dir[d], s));
         } else {
             return KMG_ERR_ARG;
         }

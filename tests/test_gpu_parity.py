@@ -92,6 +92,16 @@ def test_voxelize_edge_cases(K, orc):
 
 # ----------------------------------------------------------------- normals --
 
+def angle_between(a, b):
+    """Angle (rad) between columns of a and b, well conditioned near zero:
+    atan2(|a x b|, a . b) of the normalised vectors (the float32 normals are not
+    exactly unit length, which arccos of a plain dot product would read as an
+    angle of ~3e-4 rad)."""
+    a = a / np.linalg.norm(a, axis=0, keepdims=True)
+    b = b / np.linalg.norm(b, axis=0, keepdims=True)
+    return np.arctan2(np.linalg.norm(np.cross(a.T, b.T), axis=1), np.sum(a * b, axis=0))
+
+
 def check_normals(K, xyz, p, vp, ref_csr=None):
     import oracle as orc
 
@@ -103,9 +113,7 @@ def check_normals(K, xyz, p, vp, ref_csr=None):
     np.testing.assert_array_equal(host(out.n_normal), nr_r["n_normal"])
     np.testing.assert_array_equal(host(out.flags) & 1, nr_r["B"])
     has = nr_r["B"] == 1
-    g = host(out.normals).astype(np.float64)
-    cosang = np.clip(np.sum(g[:, has] * nr_r["normals"][:, has], axis=0), -1.0, 1.0)
-    ang = np.arccos(cosang)
+    ang = angle_between(host(out.normals).astype(np.float64)[:, has], nr_r["normals"][:, has])
     well = nr_r["gap"][has] >= 1e-6
     assert np.all(ang[well] <= 1e-5), (ang[well].max(), int((ang[well] > 1e-5).sum()))
     return out, nr_r, int((~well).sum())
