@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency vs plain"
-PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -136,12 +136,12 @@ def main():
         "p99_ms": round(p99, 4),
         "stages_ms_per_step": {k: round(v[0], 5) for k, v in stages.items()},
         "roofline": {
-            "kernel": "topk_pass (MFMA FP32 distance tiles + top-4 epilogue), one launch per direction",
+            "kernel": "topk_pass (FP64 MFMA distance tiles + top-4 epilogue), one launch per direction",
             "bound": "mfma",
             "achieved": round(achieved_tflops, 4),
-            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 5),
+            "frac": round(achieved_tflops / PEAK_FP64_MFMA_TFLOPS, 5),
             "traffic": None,
             "avg_launch_ms": round(topk_avg_s * 1e3, 5),
             "flops_per_launch": flops_per_launch,

@@ -19,7 +19,7 @@ constexpr int kTopK = 4;                         // candidates kept per row befo
 // Device status block carved at the start of every workspace.
 struct DevStatus {
     int32_t err_range;   // a key left the packable range
-    int32_t max_degree;  // max |N(q)|
+    int32_t dense;       // some |N(q)| exceeds the common LDS list (bit 0) or the largest one (bit 1)
     int32_t total_a;     // scan totals
     int32_t total_b;
     uint32_t amb_linearity;   // |p_lin - tau_lin| < 1e-12 (FP64)

@@ -200,11 +200,22 @@ __global__ __launch_bounds__(kBlock) void topk_pass(Packed A, Packed B, int dim,
     for (int t = 0; t < kTilesPerWave; ++t) top[t].init();
     const int c_begin = seg * chunks_per_seg;
     const int c_end = min(c_begin + chunks_per_seg, A.chunks);
+    // the A operand of chunk c + 1 is loaded while chunk c is multiplied
+    double a_next[KS];
+    if (c_begin < c_end) {
+        const double* src = A.pk + static_cast<int64_t>(c_begin) * A.kp * kTileRows;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < A.kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+    }
     for (int c = c_begin; c < c_end; ++c) {
-        const double* src = A.pk + static_cast<int64_t>(c) * A.kp * kTileRows;
         double a[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) a[s] = (4 * s + g < A.kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+        for (int s = 0; s < KS; ++s) a[s] = a_next[s];
+        if (c + 1 < c_end) {
+            const double* src = A.pk + static_cast<int64_t>(c + 1) * A.kp * kTileRows;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < A.kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+        }
         doublex4 acc[kTilesPerWave];
 #pragma unroll
         for (int t = 0; t < kTilesPerWave; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
@@ -232,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void topk_pass(Packed A, Packed B, int dim,
         merge_lanes(top[t], 32);
         const int col = col0 + kTileCols * t + l16;
         if (g == 0 && col < B.n) {
-            const int64_t base = (static_cast<int64_t>(col) * segs + seg) * kTopK;
+            const int64_t base = (static_cast<int64_t>(seg) * B.n + col) * kTopK;
             part_v[base + 0] = top[t].v0;
             part_v[base + 1] = top[t].v1;
             part_v[base + 2] = top[t].v2;
@@ -279,12 +290,15 @@ __global__ __launch_bounds__(kBlock) void rescore(Side X, Side Y, int dim, int s
     if (j >= Y.n) return;
     Top4 t;
     t.init();
-    const int64_t base = static_cast<int64_t>(j) * segs * kTopK;
-    for (int e = 0; e < segs * kTopK; ++e) {
-        const double v = part_v[base + e];
-        const int ix = part_i[base + e];
-        if (ix < 0 || ix >= X.n) continue;  // only real rows are ever candidates
-        push_ordered(t, v, ix);
+    for (int sg = 0; sg < segs; ++sg) {
+        const int64_t base = (static_cast<int64_t>(sg) * Y.n + j) * kTopK;
+#pragma unroll
+        for (int e = 0; e < kTopK; ++e) {
+            const double v = part_v[base + e];
+            const int ix = part_i[base + e];
+            if (ix < 0 || ix >= X.n) continue;  // only real rows are ever candidates
+            push_ordered(t, v, ix);
+        }
     }
     const float* y = Y.row(j, dim);
     const int cand[4] = {t.i0, t.i1, t.i2, t.i3};

@@ -141,7 +141,8 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(Grid g, int m, Ra
     if (!kFill) {
         if (lane == 0) {
             cnt[q] = found;
-            atomicMax(&st->max_degree, found);
+            // rare events only: no contended atomic per query
+            if (found > kListSmall) atomicOr(&st->dense, found > kListBig ? 3 : 1);
         }
         return;
     }
@@ -355,7 +356,7 @@ kmg_status normals(const float* xyz, int64_t m, const kmg_params& p, float* nrm,
     KMG_TRY_HIP(hipStreamSynchronize(s));
     timer_collect();
     if (st.err_range) return KMG_ERR_RANGE;
-    if (nnz > INT32_MAX || st.max_degree > kListBig) return KMG_ERR_RANGE;
+    if (nnz > INT32_MAX || (st.dense & 2)) return KMG_ERR_RANGE;
     *nnz_host = nnz;
     if (nnz > nbr_cap) return KMG_ERR_CAPACITY;
     if (m > 0) {
@@ -364,7 +365,7 @@ kmg_status normals(const float* xyz, int64_t m, const kmg_params& p, float* nrm,
         radius_search<true, kListSmall, kSearchWaves><<<grid_for(m, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
             g, mi, rf, nullptr, off, nbr, 0, w.st);
         KMG_TRY(launch_status());
-        if (st.max_degree > kListSmall) {
+        if (st.dense & 1) {
             radius_search<true, kListBig, 1><<<static_cast<unsigned>(m), kWave, 0, s>>>(g, mi, rf, nullptr, off, nbr,
                                                                                       1, w.st);
             KMG_TRY(launch_status());
