@@ -119,7 +119,7 @@ const char* kmg_stage_name(int32_t stage);
  *                   (row stride m = *n_kept, not cap).
  *   cap       [in]  capacity in points of kept_idx and kept_xyz.
  *   n_kept    [out, HOST] number of kept points m.
- * Errors: KMG_ERR_RANGE if a key does not fit in [-2^20, 2^20) per axis.
+ * Errors: KMG_ERR_RANGE if a key does not fit in [-2^17, 2^17) per axis.
  */
 kmg_status kmg_voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz,
                         int64_t cap, int64_t* n_kept, void* ws, size_t ws_bytes, void* stream);
@@ -197,6 +197,58 @@ kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, con
                      const int32_t* rows_q, int64_t nq, int32_t dim, int32_t prec, int32_t* pairs, float* d1,
                      float* d2, int64_t cap, int64_t* n_pairs, int64_t* n_fallback, void* ws, size_t ws_bytes,
                      void* stream);
+
+/*
+ * Batched registration: the whole hot path (voxelize, radius search and
+ * normals, SPFH/FPFH, mutual matching) for many pairs of raw clouds, uneven
+ * sizes allowed, each stage one kernel launch over the whole batch.
+ *
+ * Cloud 2i is the source and cloud 2i+1 the target of pair i.  Every cloud
+ * carries its own parameters (n_bins must be equal across the batch) and
+ * viewpoint.  Correspondences of pair i are written to outs[i] as
+ * (source kept index, target kept index) sorted by the source index, with
+ * d1, d2 as in kmg_match; kept indices refer to each cloud voxelized alone
+ * (ascending input index), so every result equals the result of running the
+ * pair alone through the single-cloud calls.
+ *
+ * counts [out, DEVICE] int64[8 * n_pairs]: per pair, 0 correspondences,
+ * 1 kept source points, 2 kept target points, 3 |J| source, 4 |J| target,
+ * 5 queries re-scanned exactly, 6 status (a kmg_status; KMG_ERR_WORKSPACE
+ * when the batch's neighbour entries exceed nnz_cap, KMG_ERR_CAPACITY when
+ * outs[i].cap is too small), 7 neighbour entries of the whole batch.
+ *
+ * Capacities: raw_cap >= total raw points of the batch; nnz_cap = neighbour
+ * entries reserved for the batch; at most 511 pairs.
+ *
+ * kmg_batch_upload copies the cloud and output tables into the workspace
+ * (host call; returns after the copy).  kmg_batch_run enqueues the batch on
+ * `stream` without any host synchronisation, memset or host copy, so a
+ * caller may capture it in a hipGraph and replay it after uploading a new
+ * batch with the same n_pairs, raw_cap, nnz_cap and n_bins.
+ * kmg_register_batch = upload + run.  Results are valid once the stream has
+ * completed.
+ */
+typedef struct {
+    const float* xyz;  /* device SoA 3 x n raw points (row stride n) */
+    int64_t n;
+    kmg_params params;
+} kmg_cloud;
+
+typedef struct {
+    int32_t* pairs; /* device int32[cap * 2] */
+    float* d1;      /* device float32[cap] */
+    float* d2;      /* device float32[cap] */
+    int64_t cap;
+} kmg_match_out;
+
+size_t kmg_batch_workspace_bytes(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins);
+kmg_status kmg_batch_upload(const kmg_cloud* clouds, const kmg_match_out* outs, int32_t n_pairs, int64_t raw_cap,
+                            int64_t nnz_cap, void* ws, size_t ws_bytes, void* stream);
+kmg_status kmg_batch_run(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins, int32_t prec,
+                         int64_t* counts, void* ws, size_t ws_bytes, void* stream);
+kmg_status kmg_register_batch(const kmg_cloud* clouds, const kmg_match_out* outs, int32_t n_pairs,
+                              int64_t raw_cap, int64_t nnz_cap, int32_t prec, int64_t* counts, void* ws,
+                              size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,158 @@
+// Batched registration: many uneven pairs through every stage in one launch
+// per kernel.  kmg_batch_upload copies the per-cloud table into the
+// workspace; kmg_batch_run only launches kernels (no host synchronisation,
+// no memset or host-memory copy nodes), so it can be captured in a hipGraph
+// and replayed after each new upload of equal or smaller sizes.
+#include "kmg_device.h"
+
+namespace kmg {
+
+namespace {
+
+constexpr int kCountsStride = 8;
+
+struct BatchWs {
+    DevStatus* st;
+    CloudDev* cl;
+    CloudState* cs;
+    PairOutDev* outs;
+    MatchSet* sets;
+    VoxelWs vox;
+    int32_t* kept_idx;
+    float* kept_xyz;
+    int32_t* kept_cloud;
+    SearchWs srch;
+    int32_t* off;
+    int32_t* nbr;
+    float* nrm;
+    uint8_t* flags;
+    FeatWs feat;
+    float* fpfh;
+    int32_t* jlist;
+    MatchWs match;
+};
+
+BatchWs carve_batch(Carver& c, int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H) {
+    const int C = 2 * n_pairs;
+    const size_t rc = static_cast<size_t>(std::max<int64_t>(raw_cap, 1));
+    BatchWs w;
+    w.st = c.take<DevStatus>(1);
+    w.cl = c.take<CloudDev>(C);
+    w.cs = c.take<CloudState>(C);
+    w.outs = c.take<PairOutDev>(n_pairs);
+    w.sets = c.take<MatchSet>(C);
+    w.vox = carve_voxel(c, raw_cap);
+    w.kept_idx = c.take<int32_t>(rc);
+    w.kept_xyz = c.take<float>(3 * rc);
+    w.kept_cloud = c.take<int32_t>(rc);
+    w.srch = carve_search(c, raw_cap);
+    w.off = c.take<int32_t>(rc + 1);
+    w.nbr = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz_cap, 1)));
+    w.nrm = c.take<float>(3 * rc);
+    w.flags = c.take<uint8_t>(rc);
+    w.feat = carve_feat(c, raw_cap, H);
+    w.fpfh = c.take<float>(rc * 3 * H);
+    w.jlist = c.take<int32_t>(rc);
+    w.match = carve_match(c, C, raw_cap, 3 * H);
+    return w;
+}
+
+__global__ void batch_init(DevStatus* st, const CloudDev* cl, int n_clouds) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(st);
+    for (int k = threadIdx.x; k < static_cast<int>(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) st->n_raw = static_cast<int64_t>(cl[n_clouds - 1].raw_off) + cl[n_clouds - 1].n_raw;
+}
+
+// Set c: the J rows of cloud c (global kept indices into the FPFH array),
+// written back as cloud-local kept indices.
+__global__ void build_sets(const CloudState* cs, int n_clouds, const float* fpfh, const int32_t* jlist,
+                           MatchSet* sets) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_clouds) return;
+    MatchSet s;
+    s.desc = fpfh;
+    s.rows = jlist + cs[c].j_off;
+    s.n = &cs[c].j_cnt;
+    s.row_base = cs[c].kept_off;
+    s.pad = 0;
+    sets[c] = s;
+}
+
+// counts[i * 8 + k]: 0 correspondences, 1-2 kept points, 3-4 |J|, 5 exact
+// re-scans, 6 status, 7 neighbour entries of the batch.
+__global__ void batch_counts(const CloudState* cs, int n_pairs, const PairOutDev* outs, const DevStatus* st,
+                             int64_t nnz_cap, int64_t* counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    int64_t* o = counts + static_cast<int64_t>(i) * kCountsStride;
+    o[1] = cs[2 * i].kept_cnt;
+    o[2] = cs[2 * i + 1].kept_cnt;
+    o[3] = cs[2 * i].j_cnt;
+    o[4] = cs[2 * i + 1].j_cnt;
+    o[7] = st->nnz;
+    int64_t status = KMG_OK;
+    if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
+    else if (st->err_capacity || st->nnz > nnz_cap) status = KMG_ERR_WORKSPACE;
+    else if (o[0] > outs[i].cap) status = KMG_ERR_CAPACITY;
+    o[6] = status;
+}
+
+}  // namespace
+
+size_t batch_ws(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H) {
+    Carver c(nullptr, 0);
+    carve_batch(c, n_pairs, raw_cap, nnz_cap, H);
+    return c.off;
+}
+
+kmg_status batch_upload(const kmg_cloud* clouds, const kmg_match_out* outs, int n_pairs, int64_t raw_cap,
+                        int64_t nnz_cap, int H, void* ws, size_t ws_bytes, hipStream_t s) {
+    Carver c(ws, ws_bytes);
+    BatchWs w = carve_batch(c, n_pairs, raw_cap, nnz_cap, H);
+    if (!c.fits()) return KMG_ERR_WORKSPACE;
+    const int C = 2 * n_pairs;
+    CloudDev* table = new CloudDev[C];
+    PairOutDev* otab = new PairOutDev[n_pairs];
+    int64_t off = 0;
+    for (int k = 0; k < C; ++k) {
+        table[k] = make_cloud(clouds[k].params, clouds[k].xyz, clouds[k].n, off);
+        off += clouds[k].n;
+    }
+    for (int i = 0; i < n_pairs; ++i) otab[i] = PairOutDev{outs[i].pairs, outs[i].d1, outs[i].d2, outs[i].cap};
+    hipError_t e1 = hipMemcpyAsync(w.cl, table, sizeof(CloudDev) * C, hipMemcpyHostToDevice, s);
+    hipError_t e2 = hipMemcpyAsync(w.outs, otab, sizeof(PairOutDev) * n_pairs, hipMemcpyHostToDevice, s);
+    // the tables live on the host stack of this call: wait for the copies
+    hipError_t e3 = hipStreamSynchronize(s);
+    delete[] table;
+    delete[] otab;
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return KMG_ERR_DEVICE;
+    return KMG_OK;
+}
+
+kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int prec, int64_t* counts, void* ws,
+                     size_t ws_bytes, hipStream_t s) {
+    Carver c(ws, ws_bytes);
+    BatchWs w = carve_batch(c, n_pairs, raw_cap, nnz_cap, H);
+    if (!c.fits()) return KMG_ERR_WORKSPACE;
+    const int C = 2 * n_pairs;
+    const int D = 3 * H;
+    batch_init<<<1, 64, 0, s>>>(w.st, w.cl, C);
+    KMG_TRY(launch_status());
+    KMG_TRY(fill_u64(reinterpret_cast<uint64_t*>(counts), 0ull, static_cast<size_t>(n_pairs) * kCountsStride, s));
+    KMG_TRY(voxelize_batch(w.cl, C, raw_cap, w.st, w.vox, raw_cap, raw_cap, w.kept_idx, w.kept_xyz, w.kept_cloud,
+                           w.cs, s));
+    KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s));
+    KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch, w.off,
+                              w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
+    KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, w.nbr,
+                           w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, w.cs, s));
+    build_sets<<<grid_for(C, 64), 64, 0, s>>>(w.cs, C, w.fpfh, w.jlist, w.sets);
+    KMG_TRY(launch_status());
+    KMG_TRY(match_batch(w.sets, C, D, prec, w.st, w.match, w.outs, counts, kCountsStride, s));
+    batch_counts<<<grid_for(n_pairs, 64), 64, 0, s>>>(w.cs, n_pairs, w.outs, w.st, nnz_cap, counts);
+    KMG_TRY(launch_status());
+    return KMG_OK;
+}
+
+}  // namespace kmg

@@ -92,6 +92,50 @@ KMG_EXPORT kmg_status kmg_fpfh(const float* xyz, const float* normals, uint8_t* 
                      as_stream(stream));
 }
 
+KMG_EXPORT size_t kmg_batch_workspace_bytes(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins) {
+    if (n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds || raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 ||
+        nnz_cap > INT32_MAX || n_bins < 1 || n_bins > kmg::kMaxBins)
+        return 0;
+    return kmg::batch_ws(n_pairs, raw_cap, nnz_cap, n_bins);
+}
+
+KMG_EXPORT kmg_status kmg_batch_upload(const kmg_cloud* clouds, const kmg_match_out* outs, int32_t n_pairs,
+                                       int64_t raw_cap, int64_t nnz_cap, void* ws, size_t ws_bytes, void* stream) {
+    if (!clouds || !outs || !ws || n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds) return KMG_ERR_ARG;
+    if (raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 || nnz_cap > INT32_MAX) return KMG_ERR_ARG;
+    const int H = clouds[0].params.n_bins;
+    int64_t total = 0;
+    for (int k = 0; k < 2 * n_pairs; ++k) {
+        if (!params_ok(&clouds[k].params) || clouds[k].params.n_bins != H) return KMG_ERR_ARG;
+        if (clouds[k].n < 0 || (clouds[k].n > 0 && !clouds[k].xyz)) return KMG_ERR_ARG;
+        total += clouds[k].n;
+    }
+    for (int i = 0; i < n_pairs; ++i)
+        if (outs[i].cap < 0 || (outs[i].cap > 0 && (!outs[i].pairs || !outs[i].d1 || !outs[i].d2)))
+            return KMG_ERR_ARG;
+    if (total > raw_cap) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::batch_ws(n_pairs, raw_cap, nnz_cap, H)) return KMG_ERR_WORKSPACE;
+    return kmg::batch_upload(clouds, outs, n_pairs, raw_cap, nnz_cap, H, ws, ws_bytes, as_stream(stream));
+}
+
+KMG_EXPORT kmg_status kmg_batch_run(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins,
+                                    int32_t prec, int64_t* counts, void* ws, size_t ws_bytes, void* stream) {
+    if (!counts || !ws || n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds) return KMG_ERR_ARG;
+    if (raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 || nnz_cap > INT32_MAX) return KMG_ERR_ARG;
+    if (n_bins < 1 || n_bins > kmg::kMaxBins) return KMG_ERR_ARG;
+    if (prec != KMG_FP32 && prec != KMG_BF16 && prec != KMG_FP16) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::batch_ws(n_pairs, raw_cap, nnz_cap, n_bins)) return KMG_ERR_WORKSPACE;
+    return kmg::batch_run(n_pairs, raw_cap, nnz_cap, n_bins, prec, counts, ws, ws_bytes, as_stream(stream));
+}
+
+KMG_EXPORT kmg_status kmg_register_batch(const kmg_cloud* clouds, const kmg_match_out* outs, int32_t n_pairs,
+                                         int64_t raw_cap, int64_t nnz_cap, int32_t prec, int64_t* counts, void* ws,
+                                         size_t ws_bytes, void* stream) {
+    kmg_status st = kmg_batch_upload(clouds, outs, n_pairs, raw_cap, nnz_cap, ws, ws_bytes, stream);
+    if (st != KMG_OK) return st;
+    return kmg_batch_run(n_pairs, raw_cap, nnz_cap, clouds[0].params.n_bins, prec, counts, ws, ws_bytes, stream);
+}
+
 KMG_EXPORT kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, const float* desc_q,
                      const int32_t* rows_q, int64_t nq, int32_t dim, int32_t prec, int32_t* pairs, float* d1,
                      float* d2, int64_t cap, int64_t* n_pairs, int64_t* n_fallback, void* ws, size_t ws_bytes,

@@ -1,6 +1,9 @@
 // Algorithm 1 Step 2, Darboux-frame pair features (Eq. A2), bins (Eq. A3),
 // SPFH (Eq. A4) and FPFH (Eq. A5).
 //
+// All clouds of a batch are processed by the same launches (grid-stride over
+// the kept points; each point reads its cloud's tau_num).
+//
 // SPFH: one wavefront per point q; lanes take the neighbours k of q, 64 at a
 // time.  Each lane computes the three features of (q, k) in FP32 and bins
 // them; a feature set that lies within a guard band of a bin edge, of the
@@ -128,226 +131,228 @@ __device__ void bins_f64(V3f pq32, V3f nq32, V3f pk32, V3f nk32, int H, int bins
     }
 }
 
-__global__ __launch_bounds__(kBlock) void spfh_kernel(const float* __restrict__ xyz, const float* __restrict__ nrm,
-                                                      const uint8_t* __restrict__ flags,
+__device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
+    return kept_cloud ? kept_cloud[q] : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
+                                                      int64_t stride, const int32_t* __restrict__ kept_cloud,
+                                                      int64_t m_cap, const float* __restrict__ nrm,
+                                                      int64_t nrm_stride, const uint8_t* __restrict__ flags,
                                                       const int32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ nbr, int m, int H, int tau_num,
+                                                      const int32_t* __restrict__ nbr, int H,
                                                       double* __restrict__ spfh64, float* __restrict__ spfh_out,
                                                       int32_t* __restrict__ Pq, int32_t* __restrict__ jflag,
                                                       DevStatus* st) {
     const int lane = lane_id();
-    const int q = blockIdx.x * kWaves + threadIdx.x / kWave;
-    if (q >= m) return;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     const int D = 3 * H;
-    const int64_t m2 = 2 * static_cast<int64_t>(m);
-    double* row = spfh64 + static_cast<int64_t>(q) * D;
-    if (!(flags[q] & 1)) {
-        for (int t = lane; t < D; t += kWave) {
-            row[t] = 0.0;
-            if (spfh_out) spfh_out[static_cast<int64_t>(q) * D + t] = 0.0f;
+    const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
+    for (int64_t q = global_wave(); q < m; q += wave_count()) {
+        double* row = spfh64 + q * D;
+        if (!(flags[q] & 1)) {
+            for (int t = lane; t < D; t += kWave) {
+                row[t] = 0.0;
+                if (spfh_out) spfh_out[q * D + t] = 0.0f;
+            }
+            if (lane == 0) {
+                Pq[q] = 0;
+                jflag[q] = 0;
+            }
+            continue;
         }
-        if (lane == 0) {
-            Pq[q] = 0;
-            jflag[q] = 0;
-        }
-        return;
-    }
-    const V3f pq = {xyz[q], xyz[m + q], xyz[m2 + q]};
-    const V3f nq = {nrm[q], nrm[m + q], nrm[m2 + q]};
-    const int b = off[q], e = off[q + 1];
-    int n_valid = 0;
-    // lane h holds the counts of bin h for the three features
-    int c0 = 0, c1 = 0, c2 = 0;
-    uint32_t n64 = 0, nedge = 0;
-    for (int base = b; base < e; base += kWave) {
-        const int t = base + lane;
-        bool valid = false;
-        int bn[3] = {-1, -1, -1};
-        if (t < e) {
-            const int k = nbr[t];
-            valid = (flags[k] & 1) != 0;
-            if (valid && k != q) {
-                const V3f pk = {xyz[k], xyz[m + k], xyz[m2 + k]};
-                const V3f nk = {nrm[k], nrm[m + k], nrm[m2 + k]};
-                if (!bins_f32(pq, nq, pk, nk, H, bn)) {
-                    bool edge = false;
-                    bins_f64(pq, nq, pk, nk, H, bn, edge);
-                    ++n64;
-                    nedge += edge ? 1u : 0u;
+        const V3f pq = {xyz[q], xyz[stride + q], xyz[s2 + q]};
+        const V3f nq = {nrm[q], nrm[nrm_stride + q], nrm[n2 + q]};
+        const int b = off[q], e = off[q + 1];
+        int n_valid = 0;
+        // lane h holds the counts of bin h for the three features
+        int c0 = 0, c1 = 0, c2 = 0;
+        uint32_t n64 = 0, nedge = 0;
+        for (int base = b; base < e; base += kWave) {
+            const int t = base + lane;
+            bool valid = false;
+            int bn[3] = {-1, -1, -1};
+            if (t < e) {
+                const int k = nbr[t];
+                valid = (flags[k] & 1) != 0;
+                if (valid && k != q) {
+                    const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
+                    const V3f nk = {nrm[k], nrm[nrm_stride + k], nrm[n2 + k]};
+                    if (!bins_f32(pq, nq, pk, nk, H, bn)) {
+                        bool edge = false;
+                        bins_f64(pq, nq, pk, nk, H, bn, edge);
+                        ++n64;
+                        nedge += edge ? 1u : 0u;
+                    }
+                }
+            }
+            n_valid += __popcll(ballot(valid));
+            for (int h = 0; h < H; ++h) {
+                const int a0 = __popcll(ballot(bn[0] == h));
+                const int a1 = __popcll(ballot(bn[1] == h));
+                const int a2 = __popcll(ballot(bn[2] == h));
+                if (lane == h) {
+                    c0 += a0;
+                    c1 += a1;
+                    c2 += a2;
                 }
             }
         }
-        n_valid += __popcll(ballot(valid));
-        for (int h = 0; h < H; ++h) {
-            const int a0 = __popcll(ballot(bn[0] == h));
-            const int a1 = __popcll(ballot(bn[1] == h));
-            const int a2 = __popcll(ballot(bn[2] == h));
-            if (lane == h) {
-                c0 += a0;
-                c1 += a1;
-                c2 += a2;
+        n64 = wave_sum(n64);
+        nedge = wave_sum(nedge);
+        const int P = n_valid - 1;
+        if (lane < H) {
+            const int cs[3] = {c0, c1, c2};
+            for (int l = 0; l < 3; ++l) {
+                const double val = (P > 0) ? (100.0 * static_cast<double>(cs[l])) / static_cast<double>(P) : 0.0;
+                row[l * H + lane] = val;
+                if (spfh_out) spfh_out[q * D + l * H + lane] = static_cast<float>(val);
             }
         }
-    }
-    n64 = wave_sum(n64);
-    nedge = wave_sum(nedge);
-    const int P = n_valid - 1;
-    if (lane < H) {
-        const int cs[3] = {c0, c1, c2};
-        for (int l = 0; l < 3; ++l) {
-            const double val = (P > 0) ? (100.0 * static_cast<double>(cs[l])) / static_cast<double>(P) : 0.0;
-            row[l * H + lane] = val;
-            if (spfh_out) spfh_out[static_cast<int64_t>(q) * D + l * H + lane] = static_cast<float>(val);
+        if (lane == 0) {
+            Pq[q] = P;
+            jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_num) ? 1 : 0;
+            if (n64) atomicAdd(&st->feat_fp64, n64);
+            if (nedge) atomicAdd(&st->feat_edge, nedge);
         }
-    }
-    if (lane == 0) {
-        Pq[q] = P;
-        jflag[q] = (n_valid >= tau_num) ? 1 : 0;
-        if (n64) atomicAdd(&st->feat_fp64, n64);
-        if (nedge) atomicAdd(&st->feat_edge, nedge);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ xyz,
+__global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ xyz, int64_t stride, int64_t m_cap,
                                                       const uint8_t* __restrict__ flags,
                                                       const int32_t* __restrict__ jflag,
                                                       const int32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ nbr, int m, int H,
+                                                      const int32_t* __restrict__ nbr, int H,
                                                       const double* __restrict__ spfh64,
-                                                      const int32_t* __restrict__ Pq, float* __restrict__ fpfh) {
+                                                      const int32_t* __restrict__ Pq, float* __restrict__ fpfh,
+                                                      const DevStatus* st) {
 #pragma clang fp contract(off)
     __shared__ int32_t s_k[kWaves][kWave];
     __shared__ double s_w[kWaves][kWave];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int q = blockIdx.x * kWaves + wv;
-    if (q >= m) return;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     const int D = 3 * H;
-    float* out = fpfh + static_cast<int64_t>(q) * D;
-    if (!jflag[q]) {
-        for (int t = lane; t < D; t += kWave) out[t] = 0.0f;
-        return;
-    }
-    const int64_t m2 = 2 * static_cast<int64_t>(m);
-    const float qx = xyz[q], qy = xyz[m + q], qz = xyz[m2 + q];
-    const int b = off[q], e = off[q + 1];
-    double acc0 = 0.0, acc1 = 0.0;  // bins lane and lane + 64
-    for (int base = b; base < e; base += kWave) {
-        const int t = base + lane;
-        bool use = false;
-        int k = 0;
-        double w = 0.0;
-        if (t < e) {
-            k = nbr[t];
-            use = (k != q) && (flags[k] & 1);
-            if (use) w = 1.0 / sqrt(d2_exact(qx, qy, qz, xyz[k], xyz[m + k], xyz[m2 + k]));
+    const int64_t s2 = 2 * stride;
+    for (int64_t q = global_wave(); q < m; q += wave_count()) {
+        float* out = fpfh + q * D;
+        if (!jflag[q]) {
+            for (int t = lane; t < D; t += kWave) out[t] = 0.0f;
+            continue;
         }
-        const uint64_t bm = ballot(use);
-        if (use) {
-            const int at = lanes_below(bm);
-            s_k[wv][at] = k;
-            s_w[wv][at] = w;
+        const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
+        const int b = off[q], e = off[q + 1];
+        double acc0 = 0.0, acc1 = 0.0;  // bins lane and lane + 64
+        for (int base = b; base < e; base += kWave) {
+            const int t = base + lane;
+            bool use = false;
+            int k = 0;
+            double w = 0.0;
+            if (t < e) {
+                k = nbr[t];
+                use = (k != q) && (flags[k] & 1);
+                if (use) w = 1.0 / sqrt(d2_exact(qx, qy, qz, xyz[k], xyz[stride + k], xyz[s2 + k]));
+            }
+            const uint64_t bm = ballot(use);
+            __builtin_amdgcn_wave_barrier();
+            if (use) {
+                const int at = lanes_below(bm);
+                s_k[wv][at] = k;
+                s_w[wv][at] = w;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int nuse = __popcll(bm);
+            for (int j = 0; j < nuse; ++j) {
+                const double wj = s_w[wv][j];
+                const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j]) * D;
+                if (lane < D) acc0 = acc0 + wj * sk[lane];
+                if (lane + kWave < D) acc1 = acc1 + wj * sk[lane + kWave];
+            }
         }
-        __builtin_amdgcn_wave_barrier();
-        const int nuse = __popcll(bm);
-        for (int j = 0; j < nuse; ++j) {
-            const double wj = s_w[wv][j];
-            const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j]) * D;
-            if (lane < D) acc0 = acc0 + wj * sk[lane];
-            if (lane + kWave < D) acc1 = acc1 + wj * sk[lane + kWave];
+        const int P = Pq[q];
+        const double* sq = spfh64 + q * D;
+        if (P == 0) {
+            if (lane < D) out[lane] = static_cast<float>(sq[lane]);
+            if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave]);
+            continue;
         }
-        __builtin_amdgcn_wave_barrier();
+        const double inv = 1.0 / static_cast<double>(P);
+        if (lane < D) out[lane] = static_cast<float>(sq[lane] + inv * acc0);
+        if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave] + inv * acc1);
     }
-    const int P = Pq[q];
-    const double* sq = spfh64 + static_cast<int64_t>(q) * D;
-    if (P == 0) {
-        if (lane < D) out[lane] = static_cast<float>(sq[lane]);
-        if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave]);
-        return;
-    }
-    const double inv = 1.0 / static_cast<double>(P);
-    if (lane < D) out[lane] = static_cast<float>(sq[lane] + inv * acc0);
-    if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave] + inv * acc1);
 }
 
+// flags |= J << 1; j_idx[jpos[q]] = q minus its cloud's kept offset (when cs is
+// given the J list is left in the global kept space for the matching stage).
 __global__ __launch_bounds__(kBlock) void j_emit(const int32_t* __restrict__ jflag, const int32_t* __restrict__ pos,
-                                                 int m, uint8_t* __restrict__ flags, int32_t* __restrict__ j_idx) {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= m) return;
-    const int j = jflag[q];
-    flags[q] = static_cast<uint8_t>((flags[q] & 1) | (j << 1));
-    if (j) j_idx[pos[q]] = q;
+                                                 int64_t m_cap, uint8_t* __restrict__ flags,
+                                                 int32_t* __restrict__ j_idx, const DevStatus* st) {
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < m; q += gs) {
+        const int j = jflag[q];
+        flags[q] = static_cast<uint8_t>((flags[q] & 1) | (j << 1));
+        if (j) j_idx[pos[q]] = static_cast<int32_t>(q);
+    }
 }
 
-struct FeatWs {
-    DevStatus* st;
-    double* spfh64;
-    int32_t* Pq;
-    int32_t* jflag;
-    int32_t* pos;
-    int64_t* total;
-    int64_t* scan_tmp;
-};
-
-FeatWs carve(Carver& c, int64_t m, int H) {
-    FeatWs w;
-    w.st = c.take<DevStatus>(1);
-    w.spfh64 = c.take<double>(static_cast<size_t>(m) * 3 * H);
-    w.Pq = c.take<int32_t>(static_cast<size_t>(m));
-    w.jflag = c.take<int32_t>(static_cast<size_t>(m));
-    w.pos = c.take<int32_t>(static_cast<size_t>(m));
-    w.total = c.take<int64_t>(2);
-    w.scan_tmp = c.take<int64_t>(scan_temp_elems(m));
-    return w;
+// Per-cloud J ranges from the exclusive scan at the cloud's first kept point.
+__global__ void cloud_j_ranges(int n_clouds, int64_t m_cap, const int32_t* __restrict__ pos, const DevStatus* st,
+                               CloudState* cs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_clouds) return;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    const int64_t nj = st->n_j;
+    const int64_t a = cs[c].kept_off, b = a + cs[c].kept_cnt;
+    const int64_t ja = a < m ? pos[a] : nj;
+    const int64_t jb = b < m ? pos[b] : nj;
+    cs[c].j_off = static_cast<int32_t>(ja);
+    cs[c].j_cnt = static_cast<int32_t>(jb - ja);
 }
 
 }  // namespace
 
-size_t fpfh_ws(int64_t m, int H) {
-    Carver c(nullptr, 0);
-    carve(c, m, H);
-    return c.off;
+FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
+    FeatWs w;
+    const size_t mc = static_cast<size_t>(std::max<int64_t>(m_cap, 1));
+    w.spfh64 = c.take<double>(mc * 3 * H);
+    w.Pq = c.take<int32_t>(mc);
+    w.jflag = c.take<int32_t>(mc);
+    w.pos = c.take<int32_t>(mc);
+    w.scan_tmp = c.take<int64_t>(scan_temp_elems(m_cap));
+    return w;
 }
 
-kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_t* off, const int32_t* nbr,
-                int64_t m, const kmg_params& p, float* spfh_out, float* fpfh_out, int32_t* j_idx, int64_t* n_j_host,
-                int64_t* stats_host, void* ws, size_t ws_bytes, hipStream_t s) {
-    const int H = p.n_bins;
-    Carver c(ws, ws_bytes);
-    FeatWs w = carve(c, m, H);
-    if (!c.fits()) return KMG_ERR_WORKSPACE;
-    const int mi = static_cast<int>(m);
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.st), 0u, sizeof(DevStatus) / 4, s));
-    if (m > 0) {
+kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
+                          const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
+                          const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                          uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
+                          hipStream_t s) {
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)), s));
+    if (m_cap > 0) {
         {
-        StageScope sc(ST_SPFH, s);
-        spfh_kernel<<<grid_for(m, kWaves), kBlock, 0, s>>>(xyz, nrm, flags, off, nbr, mi, H, p.tau_num, w.spfh64,
-                                                          spfh_out, w.Pq, w.jflag, w.st);
-        KMG_TRY(launch_status());
+            StageScope sc(ST_SPFH, s);
+            spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
+                                                                  nrm_stride, flags, off, nbr, H, w.spfh64,
+                                                                  spfh_out, w.Pq, w.jflag, st);
+            KMG_TRY(launch_status());
         }
         StageScope sc(ST_FPFH, s);
-        fpfh_kernel<<<grid_for(m, kWaves), kBlock, 0, s>>>(xyz, flags, w.jflag, off, nbr, mi, H, w.spfh64, w.Pq,
-                                                          fpfh_out);
+        fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, off, nbr, H,
+                                                              w.spfh64, w.Pq, fpfh_out, st);
         KMG_TRY(launch_status());
     }
-    {
     StageScope sc(ST_J_COMPACT, s);
-    KMG_TRY(scan_exclusive(w.jflag, w.pos, m, w.total, w.scan_tmp, s));
-    if (m > 0) {
-        j_emit<<<grid_for(m, kBlock), kBlock, 0, s>>>(w.jflag, w.pos, mi, flags, j_idx);
+    KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
+    if (m_cap > 0) {
+        j_emit<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st);
         KMG_TRY(launch_status());
     }
-    }
-    int64_t nj = 0;
-    DevStatus st;
-    KMG_TRY_HIP(hipMemcpyAsync(&nj, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    KMG_TRY_HIP(hipMemcpyAsync(&st, w.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    KMG_TRY_HIP(hipStreamSynchronize(s));
-    timer_collect();
-    *n_j_host = nj;
-    if (stats_host) {
-        stats_host[0] = st.feat_fp64;
-        stats_host[1] = st.feat_edge;
+    if (cs) {
+        cloud_j_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(n_clouds, m_cap, w.pos, st, cs);
+        KMG_TRY(launch_status());
     }
     return KMG_OK;
 }

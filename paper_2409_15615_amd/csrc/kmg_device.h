@@ -36,6 +36,12 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Global wave index and wave count of a grid-stride kernel.
+__device__ __forceinline__ int global_wave() {
+    return static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+}
+__device__ __forceinline__ int wave_count() { return static_cast<int>(gridDim.x * blockDim.x / kWave); }
+
 // 64-bit mixing function (the MurmurHash3 fmix64 finaliser).
 __device__ __forceinline__ uint32_t hash_key(uint64_t k) {
     k ^= k >> 33;
@@ -50,9 +56,11 @@ __device__ __forceinline__ bool key_in_range(double k) {
     return k >= -static_cast<double>(kKeyBias) && k < static_cast<double>(kKeyBias);
 }
 
-__device__ __forceinline__ uint64_t pack_key(int64_t kx, int64_t ky, int64_t kz) {
-    return (static_cast<uint64_t>(kx + kKeyBias) << 42) | (static_cast<uint64_t>(ky + kKeyBias) << 21) |
-           static_cast<uint64_t>(kz + kKeyBias);
+// 10 bits of cloud id, then 18 bits per axis.
+__device__ __forceinline__ uint64_t pack_key(int cloud, int64_t kx, int64_t ky, int64_t kz) {
+    return (static_cast<uint64_t>(cloud) << (3 * kAxisBits)) |
+           (static_cast<uint64_t>(kx + kKeyBias) << (2 * kAxisBits)) |
+           (static_cast<uint64_t>(ky + kKeyBias) << kAxisBits) | static_cast<uint64_t>(kz + kKeyBias);
 }
 
 // Open-addressing lookup; returns the slot or -1.
@@ -91,27 +99,26 @@ __device__ __forceinline__ double d2_exact(float qx, float qy, float qz, float s
     return d2;
 }
 
-// Strict radius test d2 < r^2: an FP32 screen decides everything farther than
-// a relative band of 4e-6 from the sphere (the FP32 error is below 1e-6
-// relative); inside the band the FP64 expression above decides.
-struct RadiusTest {
-    float lo2, hi2;  // FP32 band edges around r^2
-    double r2;       // r * r in FP64
-    __device__ __forceinline__ bool operator()(float qx, float qy, float qz, float sx, float sy, float sz) const {
-        float dx = sx - qx, dy = sy - qy, dz = sz - qz;
-        float d2 = dx * dx + dy * dy + dz * dz;
-        if (d2 < lo2) return true;
-        if (d2 > hi2) return false;
-        return d2_exact(qx, qy, qz, sx, sy, sz) < r2;
-    }
-};
-
-inline RadiusTest make_radius_test(double r) {
-    RadiusTest t;
-    t.r2 = r * r;
-    t.lo2 = static_cast<float>(t.r2 * (1.0 - 4e-6));
-    t.hi2 = static_cast<float>(t.r2 * (1.0 + 4e-6));
-    return t;
+__device__ __forceinline__ bool in_radius(const RadiusTest& t, float qx, float qy, float qz, float sx, float sy,
+                                          float sz) {
+    const float dx = sx - qx, dy = sy - qy, dz = sz - qz;
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    if (d2 < t.lo2) return true;
+    if (d2 > t.hi2) return false;
+    return d2_exact(qx, qy, qz, sx, sy, sz) < t.r2;
 }
+
+// Cloud of a raw index: the last cloud whose raw_off <= t.
+__device__ __forceinline__ int cloud_of_raw(const CloudDev* cl, int n_clouds, int64_t t) {
+    int lo = 0, hi = n_clouds - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cl[mid].raw_off <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t clamp_count(int64_t v, int64_t cap) { return v < cap ? v : cap; }
 
 }  // namespace kmg

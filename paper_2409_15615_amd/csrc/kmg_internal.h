@@ -1,4 +1,13 @@
 // Internal declarations shared by the libkmg translation units.
+//
+// Every kernel works on a batch of clouds laid out in flattened index
+// spaces: raw points of all clouds back to back, kept points back to back
+// (cloud order, then ascending input index), one CSR over all kept points,
+// one list of J rows.  Each point knows its cloud id; hash keys carry the
+// cloud id, so one voxel table and one cell table serve the whole batch.
+// Item counts are read from device memory and kernels loop over them with a
+// fixed grid, so a whole batch runs without host synchronisation (and can be
+// captured in a hipGraph).  The single-cloud entry points are batches of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,23 +20,104 @@ namespace kmg {
 
 constexpr int kWave = 64;
 constexpr uint64_t kEmptyKey = ~0ull;
-constexpr int64_t kKeyBias = int64_t(1) << 20;  // packed keys hold [-2^20, 2^20) per axis
-constexpr int kMaxDegree = 8192;                 // largest |N(q)| the sorted-list kernels accept
-constexpr int kMaxBins = 32;                     // largest H (3H <= 96 descriptor values)
-constexpr int kTopK = 4;                         // candidates kept per row before exact re-scoring
+constexpr int kAxisBits = 18;                                // packed keys: 18 bits per axis
+constexpr int64_t kKeyBias = int64_t(1) << (kAxisBits - 1);  // axis keys in [-2^17, 2^17)
+constexpr int kMaxClouds = 1022;                             // 10 bits of cloud id (1023 is reserved)
+constexpr int kListSmall = 1024;                             // LDS neighbour list of the common fill pass
+constexpr int kMaxDegree = 8192;                             // largest |N(q)| accepted
+constexpr int kMaxBins = 32;                                 // largest H (3H <= 96 descriptor values)
+constexpr int kTopK = 4;                                     // candidates kept per query before re-scoring
+constexpr int kPersistBlocks = 2048;                         // grid of the grid-stride kernels
+
+// Strict radius test d2 < r^2: an FP32 screen decides everything farther than
+// a relative band of 4e-6 from the sphere (the FP32 error is below 1e-6
+// relative); inside the band the exact FP64 expression decides.
+struct RadiusTest {
+    float lo2, hi2;  // FP32 band edges around r^2
+    double r2;       // r * r in FP64
+};
+
+inline RadiusTest make_radius_test(double r) {
+    RadiusTest t;
+    t.r2 = r * r;
+    t.lo2 = static_cast<float>(t.r2 * (1.0 - 4e-6));
+    t.hi2 = static_cast<float>(t.r2 * (1.0 + 4e-6));
+    return t;
+}
+
+// Per-cloud constants (uploaded once per batch).
+struct CloudDev {
+    const float* raw;  // raw SoA 3 x n_raw (row stride n_raw); unused by the single-cloud stages
+    int32_t n_raw;
+    int32_t raw_off;   // first raw index of the cloud in the batch
+    int32_t tau_num;
+    int32_t H;
+    double voxel;
+    double inv_cell;   // 1 / (r_FPFH * (1 + 1e-4)): cell edge of the search grid
+    double tau_lin;
+    double vp[3];
+    RadiusTest rf, rn;
+};
+
+// Per-cloud values produced on the device.
+struct CloudState {
+    int32_t kept_off, kept_cnt;  // range in the kept space
+    int32_t j_off, j_cnt;        // range in the J list
+};
+
+// A descriptor set for matching: rows desc[rows[i]] (or desc[i]), i < *n.
+struct MatchSet {
+    const float* desc;
+    const int32_t* rows;  // nullable
+    const int32_t* n;     // device count
+    int32_t row_base;     // subtracted from rows[i] in the output
+    int32_t pad;
+};
+
+// Per-set plan written by the device planner.
+struct SetPlan {
+    int32_t n;          // rows
+    int32_t q_off;      // first query slot in the flattened query space
+    int32_t chunk_off;  // first packed 16-row chunk
+    int32_t chunks;
+    int32_t tile_off;   // first tile of this set as the query side
+    int32_t cblocks;    // 256-query column blocks
+    int32_t segs;       // segments of the partner's rows
+    int32_t n_fb;       // queries of this set re-scanned exactly
+    int64_t part_off;   // first partial entry
+    unsigned long long max_norm_bits;  // max squared norm (FP64 bits, non-negative)
+};
+
+// Matching output of one pair (device buffers).
+struct PairOutDev {
+    int32_t* pairs;
+    float* d1;
+    float* d2;
+    int64_t cap;
+};
 
 // Device status block carved at the start of every workspace.
 struct DevStatus {
-    int32_t err_range;   // a key left the packable range
-    int32_t dense;       // some |N(q)| exceeds the common LDS list (bit 0) or the largest one (bit 1)
-    int32_t total_a;     // scan totals
-    int32_t total_b;
+    int32_t err_range;        // a key left the packable range
+    int32_t dense;            // bit 0: some |N(q)| > kListSmall; bit 1: some |N(q)| > kMaxDegree
+    int32_t err_capacity;     // a capacity bound was exceeded (CSR or partials)
+    int32_t pad0;
+    int64_t n_raw;            // raw points in the batch
+    int64_t m_kept;           // kept points
+    int64_t nnz;              // neighbour entries
+    int64_t n_j;              // J rows
+    int64_t n_cells;
     uint32_t amb_linearity;   // |p_lin - tau_lin| < 1e-12 (FP64)
     uint32_t amb_orientation; // |n . (vp - a_q)| tiny (FP64)
     uint32_t feat_fp64;       // pair features recomputed in FP64
     uint32_t feat_edge;       // FP64 features within 1e-9 of a bin edge
-    uint32_t n_fallback;      // matching columns re-scanned exactly
-    uint32_t pad[7];
+    uint32_t n_fallback;      // queries re-scanned exactly
+    int32_t total_tiles;      // matching tiles
+    uint32_t tile_next;       // persistent tile queue
+    int32_t total_queries;
+    int64_t total_chunks;
+    int64_t pairs_total;      // correspondences over the batch
+    int32_t pad1[6];
 };
 
 // Linear workspace allocator; with base == nullptr it only measures.
@@ -69,6 +159,12 @@ inline uint32_t next_pow2(uint64_t v) {
 }
 
 inline unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+inline unsigned grid_cap(int64_t n, int block) {
+    const int64_t g = (n + block - 1) / block;
+    return static_cast<unsigned>(g < 1 ? 1 : (g > kPersistBlocks ? kPersistBlocks : g));
+}
+
+CloudDev make_cloud(const kmg_params& p, const float* raw, int64_t n_raw, int64_t raw_off);
 
 // ---- timing.hip -----------------------------------------------------------
 enum Stage {
@@ -113,26 +209,115 @@ kmg_status fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 kmg_status fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 
 // ---- voxel.hip ------------------------------------------------------------
+struct VoxelWs {
+    uint64_t* keys;
+    int32_t* mins;
+    int32_t* slot;
+    int32_t* flag;
+    int32_t* pos;
+    int64_t* scan_tmp;
+    uint32_t cap_table;
+};
+VoxelWs carve_voxel(Carver& c, int64_t n_cap);
+// Voxelizes every cloud of the table (raw total on the device in st->n_raw,
+// at most n_cap).  Kept points go to kept_xyz (SoA, row stride out_stride,
+// or the kept count when out_stride == 0), their cloud-local raw index to
+// kept_idx and their cloud to kept_cloud (nullable); per-cloud ranges to cs
+// (nullable).  Nothing is written when the kept count exceeds out_cap.
+kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
+                          int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
+                          int32_t* kept_cloud, CloudState* cs, hipStream_t s);
+
+// ---- search.hip -----------------------------------------------------------
+struct SearchWs {
+    uint64_t* keys;
+    int32_t* ccount;
+    int32_t* cstart;
+    int32_t* cfill;
+    int32_t* pslot;
+    float4* pts;
+    int32_t* deg;
+    int64_t* scan_tmp;
+    uint32_t cap_table;
+};
+SearchWs carve_search(Carver& c, int64_t m_cap);
+// Grid build and the count pass over the kept points (count st->m_kept <=
+// m_cap, SoA stride `stride`, cloud ids kept_cloud (nullable = cloud 0)).
+// off receives m_cap + 1 offsets; the total goes to st->nnz.
+kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
+                              int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s);
+// Fill pass (lists ascending) and normals.  Writes nothing into nbr when
+// st->nnz > nbr_cap (device-side check; st->err_capacity is set).
+kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
+                             int64_t m_cap, int64_t nbr_cap, bool dense_pass, DevStatus* st, const SearchWs& w,
+                             const int32_t* off, int32_t* nbr, float* nrm, int64_t nrm_stride, uint8_t* flags,
+                             int32_t* n_normal, hipStream_t s);
+
+// ---- features.hip ---------------------------------------------------------
+struct FeatWs {
+    double* spfh64;
+    int32_t* Pq;
+    int32_t* jflag;
+    int32_t* pos;
+    int64_t* scan_tmp;
+};
+FeatWs carve_feat(Carver& c, int64_t m_cap, int H);
+// Step 2, SPFH, FPFH and the J list over the kept points (count st->m_kept).
+// j_idx receives kept indices minus the cloud's kept offset when cs is given.
+kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
+                          const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
+                          const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                          uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
+                          hipStream_t s);
+
+// ---- match.hip ------------------------------------------------------------
+struct MatchWs {
+    SetPlan* plan;
+    double* pk;           // packed rows
+    double* n2;           // exact squared norms per query slot
+    double* part_v;
+    int32_t* part_i;
+    int32_t* nn;
+    double* best;
+    double* second;
+    int32_t* fb_list;
+    int32_t* flag;
+    int32_t* pos;
+    int64_t* scan_tmp;
+    int64_t q_cap;        // total query slots
+    int64_t chunk_cap;    // packed chunks
+    int64_t part_cap;     // partial entries
+    int kp;
+};
+MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim);
+// Matches sets 2i and 2i+1 for every pair i (both directions, mutual check).
+// counts[i * counts_stride + 0] receives the number of correspondences of
+// pair i and [.. + 5] the number of exact re-scans of its queries.
+kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
+                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s);
+
+// ---- stages.hip: single-cloud entry points --------------------------------
 size_t voxelize_ws(int64_t n);
 kmg_status voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz, int64_t cap,
                     int64_t* n_kept_host, void* ws, size_t ws_bytes, hipStream_t s);
-
-// ---- search.hip -----------------------------------------------------------
 size_t normals_ws(int64_t m);
 kmg_status normals(const float* xyz, int64_t m, const kmg_params& p, float* nrm, uint8_t* flags, int32_t* off,
                    int32_t* nbr, int64_t nbr_cap, int64_t* nnz_host, int32_t* n_normal, void* ws, size_t ws_bytes,
                    hipStream_t s);
-
-// ---- features.hip ---------------------------------------------------------
 size_t fpfh_ws(int64_t m, int H);
 kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_t* off, const int32_t* nbr,
                 int64_t m, const kmg_params& p, float* spfh_out, float* fpfh_out, int32_t* j_idx, int64_t* n_j_host,
                 int64_t* stats_host, void* ws, size_t ws_bytes, hipStream_t s);
-
-// ---- match.hip ------------------------------------------------------------
 size_t match_ws(int64_t np, int64_t nq, int dim);
 kmg_status match(const float* dp, const int32_t* rp, int64_t np, const float* dq, const int32_t* rq, int64_t nq,
                  int dim, int prec, int32_t* pairs, float* d1, float* d2, int64_t cap, int64_t* n_pairs_host,
                  int64_t* n_fallback_host, void* ws, size_t ws_bytes, hipStream_t s);
+
+// ---- batch.hip ------------------------------------------------------------
+size_t batch_ws(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H);
+kmg_status batch_upload(const kmg_cloud* clouds, const kmg_match_out* outs, int n_pairs, int64_t raw_cap,
+                        int64_t nnz_cap, int H, void* ws, size_t ws_bytes, hipStream_t s);
+kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int prec, int64_t* counts, void* ws,
+                     size_t ws_bytes, hipStream_t s);
 
 }  // namespace kmg

@@ -1,5 +1,10 @@
 // Mutual nearest-neighbour matching of descriptor rows (reciprocity test,
-// Section III-C) on gfx950 matrix cores, with exact FP64 decisions.
+// Section III-C) on gfx950 matrix cores, with exact FP64 decisions, for every
+// pair of a batch at once.
+//
+// Sets.  Descriptor sets 2i and 2i+1 form pair i; each set is matched against
+// its partner in both directions.  Set sizes live on the device; a one-block
+// planner lays out query slots, packed chunks, tiles and candidate buffers.
 //
 // Candidate generation.  For a query row y and swept rows x_i, the NN ranks
 // D(i) = ||x_i||^2 + ||y||^2 - 2 x_i.y by t_i = ||x_i||^2 - 2 x_i.y.  FPFH rows
@@ -10,11 +15,10 @@
 // v_mfma_f64_16x16x4_f64 chain of ceil((dim+1)/4) steps yields a 16x16 tile
 // of t.  Lane l owns query column l % 16 and tile rows l / 16 + {0, 4, 8, 12}
 // (result register r holds row 4 r + l / 16), and keeps a running top-4 of t
-// in registers.  A wave holds 64 query
-// columns (four chains), a block of four waves 256, and the swept rows are
-// split into S segments; block b takes segment b % S (S is a multiple of 8
-// when possible, so each of the eight XCDs streams one eighth of the rows
-// through its own L2).
+// in registers.  A wave holds 64 query columns (four chains), a block of four
+// waves 256.  A tile is (set, 256-query block, segment of the partner's
+// rows); a persistent grid pulls tiles from an atomic queue until it is
+// empty, so uneven pairs share one launch.
 //
 // Exact decision.  The per-segment top-4 lists are merged, the four
 // candidates are re-scored with the plain FP64 sum of squared differences in
@@ -42,53 +46,164 @@ constexpr int kColsPerWave = kTileCols * kTilesPerWave;
 constexpr int kWavesPerBlock = 4;
 constexpr int kColsPerBlock = kColsPerWave * kWavesPerBlock;
 constexpr int kBlock = 256;
+constexpr int kPlanThreads = 1024;
+constexpr int kTargetTiles = 2048;  // tiles wanted per launch (8 per CU)
+constexpr int kMaxSegs = 16;
+constexpr int kTopkBlocks = 512;    // persistent grid of the tile kernel (2 blocks per CU)
 
-struct Packed {
-    const double* pk;  // [chunks][kp][16]
-    int n;             // rows
-    int chunks;
-    int kp;            // packed depth (multiple of 4)
-};
+// Set of a flattened index given non-decreasing starts (last s with start <= t).
+template <class F>
+__device__ __forceinline__ int find_set(int n_sets, int64_t t, F start) {
+    int lo = 0, hi = n_sets - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start(mid) <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
-// ---------------------------------------------------------------- packing --
+__device__ __forceinline__ const float* set_row(const MatchSet& s, int i, int dim) {
+    return s.desc + static_cast<int64_t>(s.rows ? s.rows[i] : i) * dim;
+}
 
-__global__ __launch_bounds__(kBlock) void row_norms(const float* __restrict__ desc, const int32_t* __restrict__ rows,
-                                                    int n, int dim, double* __restrict__ nrm2,
-                                                    unsigned long long* max_bits) {
+// ------------------------------------------------------------------ sets --
+
+__global__ void write_pair_sets(MatchSet* sets, int32_t* counts, MatchSet a, MatchSet b, int32_t na, int32_t nb,
+                                PairOutDev* outs, PairOutDev out) {
+    counts[0] = na;
+    counts[1] = nb;
+    a.n = counts;
+    b.n = counts + 1;
+    sets[0] = a;
+    sets[1] = b;
+    outs[0] = out;
+}
+
+// ------------------------------------------------------------------ plan --
+
+__device__ int64_t block_excl_scan64(int64_t v, int64_t* smem, int64_t& total) {
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int64_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) smem[wave] = incl;
+    __syncthreads();
+    int64_t before = 0;
+    total = 0;
+    for (int w = 0; w < kPlanThreads / kWave; ++w) {
+        const int64_t t = smem[w];
+        if (w < wave) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __restrict__ sets, int n_sets,
+                                                         int64_t part_cap, SetPlan* plan, DevStatus* st) {
+    __shared__ int64_t smem[kPlanThreads / kWave];
+    __shared__ int s_segs;
+    __shared__ int s_chunks[kPlanThreads];
+    __shared__ int s_n[kPlanThreads];
+    const int c = threadIdx.x;
+    const bool live = c < n_sets;
+    const int n = live ? *sets[c].n : 0;
+    const int chunks = (n + kTileRows - 1) / kTileRows;
+    const int cblocks = (n + kColsPerBlock - 1) / kColsPerBlock;
+    int64_t tq, tc, tb;
+    const int64_t q_off = block_excl_scan64(n, smem, tq);
+    const int64_t c_off = block_excl_scan64(chunks, smem, tc);
+    block_excl_scan64(cblocks, smem, tb);
+    s_chunks[c] = chunks;
+    s_n[c] = n;
+    if (c == 0) {
+        int S = static_cast<int>(tb > 0 ? kTargetTiles / tb : 1);
+        S = S < 1 ? 1 : (S > kMaxSegs ? kMaxSegs : S);
+        if (S >= 8) S &= ~7;  // a multiple of 8: the tiles of a column block spread over the eight XCDs
+        while (S > 1 && tq * S * kTopK > part_cap) S >>= 1;
+        s_segs = S;
+    }
+    __syncthreads();
+    // the partner's rows are split into segments (sets pair up as 2i, 2i + 1)
+    int segs = 1, tiles = 0;
+    if (live) {
+        const int p = c ^ 1;
+        const int pch = p < n_sets ? s_chunks[p] : 0;
+        const int pn = p < n_sets ? s_n[p] : 0;
+        segs = s_segs < pch ? s_segs : (pch > 0 ? pch : 1);
+        tiles = pn > 0 ? cblocks * segs : 0;
+    }
+    int64_t tt, tpart;
+    const int64_t t_off = block_excl_scan64(tiles, smem, tt);
+    const int64_t p_off = block_excl_scan64(static_cast<int64_t>(n) * segs * kTopK, smem, tpart);
+    if (live) {
+        SetPlan pl;
+        pl.n = n;
+        pl.q_off = static_cast<int32_t>(q_off);
+        pl.chunk_off = static_cast<int32_t>(c_off);
+        pl.chunks = chunks;
+        pl.tile_off = static_cast<int32_t>(t_off);
+        pl.cblocks = cblocks;
+        pl.segs = segs;
+        pl.n_fb = 0;
+        pl.part_off = p_off;
+        pl.max_norm_bits = 0ull;
+        plan[c] = pl;
+    }
+    if (c == 0) {
+        st->total_queries = static_cast<int32_t>(tq);
+        st->total_chunks = tc;
+        st->total_tiles = static_cast<int32_t>(tt);
+        st->tile_next = 0;
+        st->n_fallback = 0;
+        if (tpart > part_cap) st->err_capacity = 1;
+    }
+}
+
+// ------------------------------------------------------------- packing --
+
+__global__ __launch_bounds__(kBlock) void row_norms(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
+                                                    int dim, double* __restrict__ n2, const DevStatus* st) {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const float* x = desc + static_cast<int64_t>(rows ? rows[i] : i) * dim;
-    double acc = 0.0;
-    for (int t = 0; t < dim; ++t) {
-        const double v = x[t];
-        acc = acc + v * v;
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total; t += gs) {
+        const int c = find_set(n_sets, t, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const float* x = set_row(sets[c], static_cast<int>(t - plan[c].q_off), dim);
+        double acc = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            const double v = x[k];
+            acc = acc + v * v;
+        }
+        n2[t] = acc;
+        atomicMax(&plan[c].max_norm_bits, static_cast<unsigned long long>(__double_as_longlong(acc)));
     }
-    nrm2[i] = acc;
-    atomicMax(max_bits, static_cast<unsigned long long>(__double_as_longlong(acc)));
 }
 
-__global__ __launch_bounds__(kBlock) void pack_rows(const float* __restrict__ desc, const int32_t* __restrict__ rows,
-                                                    int n, int dim, int kp, int chunks,
-                                                    const double* __restrict__ nrm2, double* __restrict__ pk) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t total = static_cast<int64_t>(chunks) * kp * kTileRows;
-    if (t >= total) return;
-    const int ii = static_cast<int>(t % kTileRows);
-    const int k = static_cast<int>((t / kTileRows) % kp);
-    const int c = static_cast<int>(t / (static_cast<int64_t>(kTileRows) * kp));
-    const int i = c * kTileRows + ii;
-    double v = 0.0;
-    if (i < n) {
-        if (k < dim) v = desc[static_cast<int64_t>(rows ? rows[i] : i) * dim + k];
-        else if (k == dim) v = nrm2[i];
-    } else if (k == dim) {
-        v = INFINITY;  // padding rows never enter a top-k list
+__global__ __launch_bounds__(kBlock) void pack_rows(const MatchSet* __restrict__ sets,
+                                                    const SetPlan* __restrict__ plan, int n_sets, int dim, int kp,
+                                                    const double* __restrict__ n2, double* __restrict__ pk,
+                                                    const DevStatus* st) {
+    const int64_t total = st->total_chunks * kp * kTileRows;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total; t += gs) {
+        const int ii = static_cast<int>(t % kTileRows);
+        const int k = static_cast<int>((t / kTileRows) % kp);
+        const int64_t g = t / (static_cast<int64_t>(kTileRows) * kp);
+        const int c = find_set(n_sets, g, [&](int s) { return static_cast<int64_t>(plan[s].chunk_off); });
+        const int i = static_cast<int>(g - plan[c].chunk_off) * kTileRows + ii;
+        double v = 0.0;
+        if (i < plan[c].n) {
+            if (k < dim) v = set_row(sets[c], i, dim)[k];
+            else if (k == dim) v = n2[plan[c].q_off + i];
+        } else if (k == dim) {
+            v = INFINITY;  // padding rows never enter a top-k list
+        }
+        pk[t] = v;
     }
-    pk[t] = v;
 }
 
-// ----------------------------------------------------------- top-4 passes --
+// -------------------------------------------------------------- top-4 --
 
 struct Top4 {
     double v0, v1, v2, v3;
@@ -170,51 +285,47 @@ __device__ __forceinline__ void merge_lanes(Top4& t, int d) {
     push_ordered(t, v3, i3);
 }
 
+// One wave: 64 query columns of set qc (local columns col0 ..) against the
+// partner's chunks [c_begin, c_end) (partner-local chunk indices).
 template <int KS>
-__global__ __launch_bounds__(kBlock) void topk_pass(Packed A, Packed B, int dim, int segs, int chunks_per_seg,
-                                                    double* __restrict__ part_v, int32_t* __restrict__ part_i) {
-    const int seg = blockIdx.x % segs;
-    const int cblk = blockIdx.x / segs;
-    const int wv = threadIdx.x / kWave;
+__device__ __forceinline__ void tile_wave(const double* __restrict__ pk, int kp, int dim, const SetPlan& qc,
+                                          const SetPlan& pc, int col0, int c_begin, int c_end, int seg,
+                                          double* __restrict__ part_v, int32_t* __restrict__ part_i) {
     const int lane = lane_id();
-    const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
-    if (col0 >= B.n) return;
-    const int g = lane >> 4;   // k offset within a step for the operands; row group for the result
+    const int g = lane >> 4;  // k offset within a step for the operands; row group for the result
     const int l16 = lane & 15;
     // query operand: B[k][j] = -2 y_j[k] (k < dim), 1 (k = dim), 0 beyond
     double bq[kTilesPerWave][KS];
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) {
         const int chunk = col0 / kTileCols + t;
-        const bool have = chunk < B.chunks;
-        const double* src = B.pk + static_cast<int64_t>(have ? chunk : 0) * B.kp * kTileRows;
+        const bool have = chunk < qc.chunks;
+        const double* src = pk + static_cast<int64_t>(qc.chunk_off + (have ? chunk : 0)) * kp * kTileRows;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int k = 4 * s + g;
-            const double v = (have && k < B.kp) ? src[k * kTileRows + l16] : 0.0;
+            const double v = (have && k < kp) ? src[k * kTileRows + l16] : 0.0;
             bq[t][s] = (k < dim) ? -2.0 * v : (k == dim ? 1.0 : 0.0);
         }
     }
     Top4 top[kTilesPerWave];
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) top[t].init();
-    const int c_begin = seg * chunks_per_seg;
-    const int c_end = min(c_begin + chunks_per_seg, A.chunks);
     // the A operand of chunk c + 1 is loaded while chunk c is multiplied
     double a_next[KS];
     if (c_begin < c_end) {
-        const double* src = A.pk + static_cast<int64_t>(c_begin) * A.kp * kTileRows;
+        const double* src = pk + static_cast<int64_t>(pc.chunk_off + c_begin) * kp * kTileRows;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < A.kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+        for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < kp) ? src[s * 4 * kTileRows + lane] : 0.0;
     }
     for (int c = c_begin; c < c_end; ++c) {
         double a[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s) a[s] = a_next[s];
         if (c + 1 < c_end) {
-            const double* src = A.pk + static_cast<int64_t>(c + 1) * A.kp * kTileRows;
+            const double* src = pk + static_cast<int64_t>(pc.chunk_off + c + 1) * kp * kTileRows;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < A.kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+            for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < kp) ? src[s * 4 * kTileRows + lane] : 0.0;
         }
         doublex4 acc[kTilesPerWave];
 #pragma unroll
@@ -242,8 +353,8 @@ __global__ __launch_bounds__(kBlock) void topk_pass(Packed A, Packed B, int dim,
         merge_lanes(top[t], 16);
         merge_lanes(top[t], 32);
         const int col = col0 + kTileCols * t + l16;
-        if (g == 0 && col < B.n) {
-            const int64_t base = (static_cast<int64_t>(seg) * B.n + col) * kTopK;
+        if (g == 0 && col < qc.n) {
+            const int64_t base = qc.part_off + (static_cast<int64_t>(seg) * qc.n + col) * kTopK;
             part_v[base + 0] = top[t].v0;
             part_v[base + 1] = top[t].v1;
             part_v[base + 2] = top[t].v2;
@@ -253,6 +364,36 @@ __global__ __launch_bounds__(kBlock) void topk_pass(Packed A, Packed B, int dim,
             part_i[base + 2] = top[t].i2;
             part_i[base + 3] = top[t].i3;
         }
+    }
+}
+
+// Persistent tile kernel: blocks pull (set, column block, segment) tiles from
+// an atomic queue; every block leaves once the queue runs past the tile count.
+template <int KS>
+__global__ __launch_bounds__(kBlock) void topk_tiles(const SetPlan* __restrict__ plan, int n_sets,
+                                                     const double* __restrict__ pk, int kp, int dim,
+                                                     double* __restrict__ part_v, int32_t* __restrict__ part_i,
+                                                     DevStatus* st) {
+    __shared__ int s_tile;
+    const int wv = threadIdx.x / kWave;
+    const int total = st->total_tiles;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= total) break;
+        const int c = find_set(n_sets, tile, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
+        const SetPlan qc = plan[c];
+        const SetPlan pc = plan[c ^ 1];
+        const int local = tile - qc.tile_off;
+        const int seg = local % qc.segs;
+        const int cblk = local / qc.segs;
+        const int cps = (pc.chunks + qc.segs - 1) / qc.segs;
+        const int c_begin = seg * cps;
+        const int c_end = min(c_begin + cps, pc.chunks);
+        const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
+        if (col0 < qc.n) tile_wave<KS>(pk, kp, dim, qc, pc, col0, c_begin, c_end, seg, part_v, part_i);
     }
 }
 
@@ -268,303 +409,299 @@ __device__ __forceinline__ double exact_d2(const float* __restrict__ x, const fl
     return acc;
 }
 
-struct Side {
-    const float* desc;
-    const int32_t* rows;
-    int n;
-    __device__ const float* row(int i, int dim) const {
-        return desc + static_cast<int64_t>(rows ? rows[i] : i) * dim;
-    }
-};
-
-// One thread per query: merge the S x 4 partial candidates, re-score the best
+// One thread per query slot: merge the segment candidates, re-score the best
 // four exactly, certify or queue the query for an exact scan.
-__global__ __launch_bounds__(kBlock) void rescore(Side X, Side Y, int dim, int segs,
-                                                  const double* __restrict__ part_v, const int32_t* __restrict__ part_i,
-                                                  const double* __restrict__ ny2,
-                                                  const unsigned long long* __restrict__ max_x_bits,
+__global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
+                                                  int dim, const double* __restrict__ part_v,
+                                                  const int32_t* __restrict__ part_i, const double* __restrict__ n2,
                                                   int32_t* __restrict__ nn, double* __restrict__ best,
                                                   double* __restrict__ second, int32_t* __restrict__ fb_list,
-                                                  uint32_t* fb_count) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= Y.n) return;
-    Top4 t;
-    t.init();
-    for (int sg = 0; sg < segs; ++sg) {
-        const int64_t base = (static_cast<int64_t>(sg) * Y.n + j) * kTopK;
+                                                  DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const int p = c ^ 1;
+        const SetPlan qc = plan[c];
+        const int j = static_cast<int>(slot - qc.q_off);
+        const int np = p < n_sets ? plan[p].n : 0;
+        if (np == 0) {
+            nn[slot] = -1;
+            best[slot] = INFINITY;
+            second[slot] = INFINITY;
+            continue;
+        }
+        Top4 t;
+        t.init();
+        for (int sg = 0; sg < qc.segs; ++sg) {
+            const int64_t base = qc.part_off + (static_cast<int64_t>(sg) * qc.n + j) * kTopK;
 #pragma unroll
-        for (int e = 0; e < kTopK; ++e) {
-            const double v = part_v[base + e];
-            const int ix = part_i[base + e];
-            if (ix < 0 || ix >= X.n) continue;  // only real rows are ever candidates
-            push_ordered(t, v, ix);
+            for (int e = 0; e < kTopK; ++e) {
+                const double v = part_v[base + e];
+                const int ix = part_i[base + e];
+                if (ix < 0 || ix >= np) continue;  // only real rows are ever candidates
+                push_ordered(t, v, ix);
+            }
         }
-    }
-    const float* y = Y.row(j, dim);
-    const int cand[4] = {t.i0, t.i1, t.i2, t.i3};
-    double b1 = INFINITY, b2 = INFINITY;
-    int j1 = -1;
-    int ncand = 0;
-    for (int r = 0; r < 4; ++r) {
-        const int i = cand[r];
-        if (i < 0) continue;
-        ++ncand;
-        const double d = exact_d2(X.row(i, dim), y, dim);
-        if (d < b1 || (d == b1 && i < j1)) {
-            b2 = b1;
-            b1 = d;
-            j1 = i;
-        } else if (d < b2) {
-            b2 = d;
+        const float* y = set_row(sets[c], j, dim);
+        const int cand[4] = {t.i0, t.i1, t.i2, t.i3};
+        double b1 = INFINITY, b2 = INFINITY;
+        int j1 = -1;
+        int ncand = 0;
+        for (int r = 0; r < 4; ++r) {
+            const int i = cand[r];
+            if (i < 0) continue;
+            ++ncand;
+            const double d = exact_d2(set_row(sets[p], i, dim), y, dim);
+            if (d < b1 || (d == b1 && i < j1)) {
+                b2 = b1;
+                b1 = d;
+                j1 = i;
+            } else if (d < b2) {
+                b2 = d;
+            }
         }
-    }
-    bool ok;
-    if (ncand >= X.n) {
-        ok = true;  // every row was a candidate
-    } else {
-        const double mx = __longlong_as_double(static_cast<long long>(*max_x_bits));
-        const double E = 128.0 * 1.1102230246251565e-16 * (2.0 * mx + 2.0 * ny2[j]) + 1e-300;
-        const double bound = t.v3 + ny2[j] - E;
-        ok = ncand == 4 && b2 < bound;
-    }
-    if (ok) {
-        nn[j] = j1;
-        best[j] = b1;
-        second[j] = b2;
-    } else {
-        const uint32_t at = atomicAdd(fb_count, 1u);
-        fb_list[at] = j;
+        bool ok;
+        if (ncand >= np) {
+            ok = true;  // every row was a candidate
+        } else {
+            const double mx = __longlong_as_double(static_cast<long long>(plan[p].max_norm_bits));
+            const double E = 128.0 * 1.1102230246251565e-16 * (2.0 * mx + 2.0 * n2[slot]) + 1e-300;
+            const double bound = t.v3 + n2[slot] - E;
+            ok = ncand == 4 && b2 < bound;
+        }
+        if (ok) {
+            nn[slot] = j1;
+            best[slot] = b1;
+            second[slot] = b2;
+        } else {
+            const uint32_t at = atomicAdd(&st->n_fallback, 1u);
+            fb_list[at] = static_cast<int32_t>(slot);
+            atomicAdd(&plan[c].n_fb, 1);
+        }
     }
 }
 
-// One wavefront per queued query: exact FP64 scan over all rows of X.
-__global__ __launch_bounds__(kBlock) void exact_scan(Side X, Side Y, int dim, const int32_t* __restrict__ fb_list,
-                                                     const uint32_t* fb_count, int32_t* __restrict__ nn,
-                                                     double* __restrict__ best, double* __restrict__ second) {
-    const int w = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (w >= static_cast<int>(*fb_count)) return;
+// One wavefront per queued query: exact FP64 scan over all partner rows.
+__global__ __launch_bounds__(kBlock) void exact_scan(const MatchSet* __restrict__ sets,
+                                                     const SetPlan* __restrict__ plan, int n_sets, int dim,
+                                                     const int32_t* __restrict__ fb_list, const DevStatus* st,
+                                                     int32_t* __restrict__ nn, double* __restrict__ best,
+                                                     double* __restrict__ second) {
     const int lane = lane_id();
-    const int j = fb_list[w];
-    const float* y = Y.row(j, dim);
-    double b1 = INFINITY, b2 = INFINITY;
-    int j1 = INT32_MAX;
-    for (int i = lane; i < X.n; i += kWave) {  // ascending per lane
-        const double d = exact_d2(X.row(i, dim), y, dim);
-        if (d < b1) {
-            b2 = b1;
-            b1 = d;
-            j1 = i;
-        } else if (d < b2) {
-            b2 = d;
+    const int nfb = static_cast<int>(st->n_fallback);
+    for (int w = global_wave(); w < nfb; w += wave_count()) {
+        const int64_t slot = fb_list[w];
+        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const int p = c ^ 1;
+        const int j = static_cast<int>(slot - plan[c].q_off);
+        const int np = plan[p].n;
+        const float* y = set_row(sets[c], j, dim);
+        double b1 = INFINITY, b2 = INFINITY;
+        int j1 = INT32_MAX;
+        for (int i = lane; i < np; i += kWave) {  // ascending per lane
+            const double d = exact_d2(set_row(sets[p], i, dim), y, dim);
+            if (d < b1) {
+                b2 = b1;
+                b1 = d;
+                j1 = i;
+            } else if (d < b2) {
+                b2 = d;
+            }
         }
-    }
-    // combine lanes: smallest (b1, j1); second = min of the other b1s and all b2s
+        // combine lanes: smallest (b1, j1); second = min of the other b1s and all b2s
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        const double ob1 = __shfl_xor(b1, d, kWave);
-        const double ob2 = __shfl_xor(b2, d, kWave);
-        const int oj1 = __shfl_xor(j1, d, kWave);
-        const bool mine = (b1 < ob1) || (b1 == ob1 && j1 < oj1);
-        const double nb2 = mine ? fmin(b2, ob1) : fmin(ob2, b1);
-        if (!mine) {
-            b1 = ob1;
-            j1 = oj1;
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const double ob1 = __shfl_xor(b1, d, kWave);
+            const double ob2 = __shfl_xor(b2, d, kWave);
+            const int oj1 = __shfl_xor(j1, d, kWave);
+            const bool mine = (b1 < ob1) || (b1 == ob1 && j1 < oj1);
+            const double nb2 = mine ? fmin(b2, ob1) : fmin(ob2, b1);
+            if (!mine) {
+                b1 = ob1;
+                j1 = oj1;
+            }
+            b2 = nb2;
         }
-        b2 = nb2;
-    }
-    if (lane == 0) {
-        nn[j] = (j1 == INT32_MAX) ? -1 : j1;
-        best[j] = b1;
-        second[j] = b2;
+        if (lane == 0) {
+            nn[slot] = (j1 == INT32_MAX) ? -1 : j1;
+            best[slot] = b1;
+            second[slot] = b2;
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void mutual_flags(const int32_t* __restrict__ nn_pq,
-                                                       const int32_t* __restrict__ nn_qp, int np,
-                                                       int32_t* __restrict__ flag) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= np) return;
-    const int j = nn_pq[i];
-    flag[i] = (j >= 0 && nn_qp[j] == i) ? 1 : 0;
+__global__ __launch_bounds__(kBlock) void mutual_flags(const SetPlan* __restrict__ plan, int n_sets,
+                                                       const int32_t* __restrict__ nn, int64_t q_cap,
+                                                       int32_t* __restrict__ flag, const DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < q_cap; slot += gs) {
+        int f = 0;
+        if (slot < total) {
+            const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+            if (!(c & 1) && c + 1 < n_sets) {
+                const int j = nn[slot];
+                f = (j >= 0 && nn[plan[c + 1].q_off + j] == slot - plan[c].q_off) ? 1 : 0;
+            }
+        }
+        flag[slot] = f;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void emit_pairs(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
-                                                     const int32_t* __restrict__ nn_pq, const double* __restrict__ best,
+__global__ __launch_bounds__(kBlock) void emit_pairs(const MatchSet* __restrict__ sets,
+                                                     const SetPlan* __restrict__ plan, int n_sets,
+                                                     const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                                                     const int32_t* __restrict__ nn, const double* __restrict__ best,
                                                      const double* __restrict__ second,
-                                                     const int32_t* __restrict__ rows_p,
-                                                     const int32_t* __restrict__ rows_q, int np, const int64_t* total,
-                                                     int64_t cap, int32_t* __restrict__ pairs, float* __restrict__ d1,
-                                                     float* __restrict__ d2) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= np || !flag[i]) return;
-    if (*total > cap) return;
-    const int at = pos[i];
-    const int j = nn_pq[i];
-    pairs[2 * at] = rows_p ? rows_p[i] : i;
-    pairs[2 * at + 1] = rows_q ? rows_q[j] : j;
-    d1[at] = static_cast<float>(sqrt(best[i]));
-    d2[at] = static_cast<float>(sqrt(second[i]));
-}
-
-int choose_segments(int chunks_a, int n_queries) {
-    const int cblocks = (n_queries + kColsPerBlock - 1) / kColsPerBlock;
-    int s = std::max(1, 1024 / std::max(1, cblocks));
-    if (s >= 8) s &= ~7;
-    s = std::min(s, std::max(1, chunks_a));
-    return s;
-}
-
-struct Dir {
-    int segs;
-    double* part_v;
-    int32_t* part_i;
-    int32_t* nn;
-    double* best;
-    double* second;
-    int32_t* fb_list;
-    uint32_t* fb_count;
-};
-
-struct MatchWs {
-    DevStatus* st;
-    double* pk_p;
-    double* pk_q;
-    double* n2_p;
-    double* n2_q;
-    unsigned long long* max_bits;  // [0] P, [1] Q
-    Dir dir[2];                    // 0: queries P over rows Q; 1: queries Q over rows P
-    int32_t* flag;
-    int32_t* pos;
-    int64_t* total;
-    int64_t* scan_tmp;
-    int kp, chunks_p, chunks_q;
-};
-
-MatchWs carve(Carver& c, int64_t np, int64_t nq, int dim) {
-    MatchWs w;
-    w.kp = (dim + 1 + 3) / 4 * 4;
-    w.chunks_p = static_cast<int>((np + kTileRows - 1) / kTileRows);
-    w.chunks_q = static_cast<int>((nq + kTileRows - 1) / kTileRows);
-    w.st = c.take<DevStatus>(1);
-    w.pk_p = c.take<double>(static_cast<size_t>(w.chunks_p) * w.kp * kTileRows);
-    w.pk_q = c.take<double>(static_cast<size_t>(w.chunks_q) * w.kp * kTileRows);
-    w.n2_p = c.take<double>(static_cast<size_t>(np));
-    w.n2_q = c.take<double>(static_cast<size_t>(nq));
-    w.max_bits = c.take<unsigned long long>(2);
-    const int64_t nqry[2] = {np, nq};
-    const int rows_chunks[2] = {w.chunks_q, w.chunks_p};
-    for (int d = 0; d < 2; ++d) {
-        Dir& D = w.dir[d];
-        D.segs = choose_segments(rows_chunks[d], static_cast<int>(nqry[d]));
-        D.part_v = c.take<double>(static_cast<size_t>(nqry[d]) * D.segs * kTopK);
-        D.part_i = c.take<int32_t>(static_cast<size_t>(nqry[d]) * D.segs * kTopK);
-        D.nn = c.take<int32_t>(static_cast<size_t>(nqry[d]));
-        D.best = c.take<double>(static_cast<size_t>(nqry[d]));
-        D.second = c.take<double>(static_cast<size_t>(nqry[d]));
-        D.fb_list = c.take<int32_t>(static_cast<size_t>(nqry[d]));
-        D.fb_count = c.take<uint32_t>(1);
+                                                     const PairOutDev* __restrict__ outs, const DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+        if (!flag[slot]) continue;
+        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const PairOutDev o = outs[c >> 1];
+        const int64_t at = pos[slot] - pos[plan[c].q_off];
+        if (at >= o.cap) continue;
+        const int j = static_cast<int>(slot - plan[c].q_off);
+        const int i = nn[slot];
+        const MatchSet& a = sets[c];
+        const MatchSet& b = sets[c + 1];
+        o.pairs[2 * at] = (a.rows ? a.rows[j] : j) - a.row_base;
+        o.pairs[2 * at + 1] = (b.rows ? b.rows[i] : i) - b.row_base;
+        o.d1[at] = static_cast<float>(sqrt(best[slot]));
+        o.d2[at] = static_cast<float>(sqrt(second[slot]));
     }
-    w.flag = c.take<int32_t>(static_cast<size_t>(np));
-    w.pos = c.take<int32_t>(static_cast<size_t>(np));
-    w.total = c.take<int64_t>(2);
-    w.scan_tmp = c.take<int64_t>(scan_temp_elems(np));
-    return w;
 }
 
-template <int KS>
-kmg_status run_pass(const Packed& A, const Packed& B, int dim, const Dir& D, hipStream_t s) {
-    const int cps = (A.chunks + D.segs - 1) / D.segs;
-    const int cblocks = (B.n + kColsPerBlock - 1) / kColsPerBlock;
-    topk_pass<KS><<<static_cast<unsigned>(cblocks * D.segs), kBlock, 0, s>>>(A, B, dim, D.segs, cps, D.part_v,
-                                                                           D.part_i);
-    return launch_status();
+__global__ void pair_counts(const SetPlan* __restrict__ plan, int n_sets, const int32_t* __restrict__ pos,
+                            const DevStatus* st, int64_t* counts, int stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * i + 1 >= n_sets) return;
+    const int64_t total = st->total_queries;
+    const int64_t a = plan[2 * i].q_off, b = plan[2 * i + 1].q_off;
+    const int64_t pa = a < total ? pos[a] : st->pairs_total;
+    const int64_t pb = b < total ? pos[b] : st->pairs_total;
+    counts[static_cast<int64_t>(i) * stride + 0] = pb - pa;
+    counts[static_cast<int64_t>(i) * stride + 5] = plan[2 * i].n_fb + plan[2 * i + 1].n_fb;
 }
 
 }  // namespace
 
+MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim) {
+    MatchWs w;
+    w.kp = (dim + 1 + 3) / 4 * 4;
+    w.q_cap = std::max<int64_t>(q_cap, 1);
+    w.chunk_cap = q_cap / kTileRows + n_sets + 1;
+    w.part_cap = w.q_cap * kTopK * (q_cap <= 262144 ? kMaxSegs : 4);
+    w.plan = c.take<SetPlan>(static_cast<size_t>(std::max(n_sets, 1)));
+    w.pk = c.take<double>(static_cast<size_t>(w.chunk_cap) * w.kp * kTileRows);
+    w.n2 = c.take<double>(static_cast<size_t>(w.q_cap));
+    w.part_v = c.take<double>(static_cast<size_t>(w.part_cap));
+    w.part_i = c.take<int32_t>(static_cast<size_t>(w.part_cap));
+    w.nn = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.best = c.take<double>(static_cast<size_t>(w.q_cap));
+    w.second = c.take<double>(static_cast<size_t>(w.q_cap));
+    w.fb_list = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.flag = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.pos = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.scan_tmp = c.take<int64_t>(scan_temp_elems(w.q_cap));
+    return w;
+}
+
+kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
+                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s) {
+    (void)prec;
+    if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
+    const int ks = w.kp / 4;
+    {
+        StageScope sc(ST_MATCH_PACK, s);
+        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.part_cap, w.plan, st);
+        KMG_TRY(launch_status());
+        row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st);
+        KMG_TRY(launch_status());
+        pack_rows<<<grid_cap(w.chunk_cap * w.kp * kTileRows, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim,
+                                                                                     w.kp, w.n2, w.pk, st);
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_MATCH_TOPK, s);
+        if (ks <= 9) {
+            topk_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, w.kp, dim, w.part_v, w.part_i, st);
+        } else if (ks <= 17) {
+            topk_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, w.kp, dim, w.part_v, w.part_i, st);
+        } else {
+            return KMG_ERR_ARG;
+        }
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_MATCH_RESCORE, s);
+        rescore<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part_v, w.part_i, w.n2,
+                                                            w.nn, w.best, w.second, w.fb_list, st);
+        KMG_TRY(launch_status());
+        exact_scan<<<grid_cap(w.q_cap, kBlock / kWave), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, st,
+                                                                       w.nn, w.best, w.second);
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_MATCH_MUTUAL, s);
+        mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
+        KMG_TRY(launch_status());
+        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
+        emit_pairs<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best,
+                                                               w.second, outs, st);
+        KMG_TRY(launch_status());
+        pair_counts<<<grid_for(n_sets / 2, 64), 64, 0, s>>>(w.plan, n_sets, w.pos, st, counts, counts_stride);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
+// ---------------------------------------------------- single pair entry --
+
 size_t match_ws(int64_t np, int64_t nq, int dim) {
     Carver c(nullptr, 0);
-    carve(c, np, nq, dim);
+    c.take<DevStatus>(1);
+    c.take<MatchSet>(2);
+    c.take<int32_t>(2);
+    c.take<PairOutDev>(1);
+    c.take<int64_t>(8);
+    carve_match(c, 2, np + nq, dim);
     return c.off;
 }
 
 kmg_status match(const float* dp, const int32_t* rp, int64_t np, const float* dq, const int32_t* rq, int64_t nq,
                  int dim, int prec, int32_t* pairs, float* d1, float* d2, int64_t cap, int64_t* n_pairs_host,
                  int64_t* n_fallback_host, void* ws, size_t ws_bytes, hipStream_t s) {
-    if (prec != KMG_FP32) return KMG_ERR_ARG;
     Carver c(ws, ws_bytes);
-    MatchWs w = carve(c, np, nq, dim);
+    DevStatus* st = c.take<DevStatus>(1);
+    MatchSet* sets = c.take<MatchSet>(2);
+    int32_t* cnt = c.take<int32_t>(2);
+    PairOutDev* outs = c.take<PairOutDev>(1);
+    int64_t* counts = c.take<int64_t>(8);
+    MatchWs w = carve_match(c, 2, np + nq, dim);
     if (!c.fits()) return KMG_ERR_WORKSPACE;
     *n_pairs_host = 0;
     if (n_fallback_host) *n_fallback_host = 0;
     if (np == 0 || nq == 0) return KMG_OK;
-    const int npi = static_cast<int>(np), nqi = static_cast<int>(nq);
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.st), 0u, sizeof(DevStatus) / 4, s));
-    KMG_TRY(fill_u64(reinterpret_cast<uint64_t*>(w.max_bits), 0ull, 2, s));
-    {
-    StageScope sc(ST_MATCH_PACK, s);
-    row_norms<<<grid_for(np, kBlock), kBlock, 0, s>>>(dp, rp, npi, dim, w.n2_p, w.max_bits);
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(st), 0u, sizeof(DevStatus) / 4, s));
+    KMG_TRY(fill_u64(reinterpret_cast<uint64_t*>(counts), 0ull, 8, s));
+    MatchSet a{dp, rp, nullptr, 0, 0}, b{dq, rq, nullptr, 0, 0};
+    PairOutDev o{pairs, d1, d2, cap};
+    write_pair_sets<<<1, 1, 0, s>>>(sets, cnt, a, b, static_cast<int32_t>(np), static_cast<int32_t>(nq), outs, o);
     KMG_TRY(launch_status());
-    row_norms<<<grid_for(nq, kBlock), kBlock, 0, s>>>(dq, rq, nqi, dim, w.n2_q, w.max_bits + 1);
-    KMG_TRY(launch_status());
-    const int64_t tp = static_cast<int64_t>(w.chunks_p) * w.kp * kTileRows;
-    const int64_t tq = static_cast<int64_t>(w.chunks_q) * w.kp * kTileRows;
-    pack_rows<<<grid_for(tp, kBlock), kBlock, 0, s>>>(dp, rp, npi, dim, w.kp, w.chunks_p, w.n2_p, w.pk_p);
-    KMG_TRY(launch_status());
-    pack_rows<<<grid_for(tq, kBlock), kBlock, 0, s>>>(dq, rq, nqi, dim, w.kp, w.chunks_q, w.n2_q, w.pk_q);
-    KMG_TRY(launch_status());
-    }
-    const Packed P{w.pk_p, npi, w.chunks_p, w.kp};
-    const Packed Q{w.pk_q, nqi, w.chunks_q, w.kp};
-    const Side SP{dp, rp, npi}, SQ{dq, rq, nqi};
-    // direction 0: queries P over rows Q; direction 1: queries Q over rows P
-    const int ks = w.kp / 4;
-    for (int d = 0; d < 2; ++d) {
-        const Packed& A = d == 0 ? Q : P;
-        const Packed& B = d == 0 ? P : Q;
-        KMG_TRY(fill_u32(w.dir[d].fb_count, 0u, 1, s));
-        StageScope sc(ST_MATCH_TOPK, s);
-        if (ks <= 9) {
-            KMG_TRY(run_pass<9>(A, B, dim, w.dir[d], s));
-        } else if (ks <= 17) {
-            KMG_TRY(run_pass<17>(A, B, dim, w.dir[d], s));
-        } else {
-            return KMG_ERR_ARG;
-        }
-    }
-    for (int d = 0; d < 2; ++d) {
-        const Side& X = d == 0 ? SQ : SP;
-        const Side& Y = d == 0 ? SP : SQ;
-        const Dir& D = w.dir[d];
-        StageScope sc(ST_MATCH_RESCORE, s);
-        rescore<<<grid_for(Y.n, kBlock), kBlock, 0, s>>>(X, Y, dim, D.segs, D.part_v, D.part_i,
-                                                        d == 0 ? w.n2_p : w.n2_q, w.max_bits + (d == 0 ? 1 : 0),
-                                                        D.nn, D.best, D.second, D.fb_list, D.fb_count);
-        KMG_TRY(launch_status());
-        // one wave per queued query; waves beyond the queue length exit at once
-        exact_scan<<<grid_for(Y.n, kBlock / kWave), kBlock, 0, s>>>(X, Y, dim, D.fb_list, D.fb_count, D.nn,
-                                                                   D.best, D.second);
-        KMG_TRY(launch_status());
-    }
-    {
-    StageScope sc(ST_MATCH_MUTUAL, s);
-    mutual_flags<<<grid_for(np, kBlock), kBlock, 0, s>>>(w.dir[0].nn, w.dir[1].nn, npi, w.flag);
-    KMG_TRY(launch_status());
-    KMG_TRY(scan_exclusive(w.flag, w.pos, np, w.total, w.scan_tmp, s));
-    emit_pairs<<<grid_for(np, kBlock), kBlock, 0, s>>>(w.flag, w.pos, w.dir[0].nn, w.dir[0].best, w.dir[0].second,
-                                                      rp, rq, npi, w.total, cap, pairs, d1, d2);
-    KMG_TRY(launch_status());
-    }
-    int64_t npairs = 0;
-    uint32_t fb[2] = {0, 0};
-    KMG_TRY_HIP(hipMemcpyAsync(&npairs, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    KMG_TRY_HIP(hipMemcpyAsync(&fb[0], w.dir[0].fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    KMG_TRY_HIP(hipMemcpyAsync(&fb[1], w.dir[1].fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    KMG_TRY(match_batch(sets, 2, dim, prec, st, w, outs, counts, 8, s));
+    int64_t hc[8];
+    DevStatus hs;
+    KMG_TRY_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, s));
+    KMG_TRY_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     KMG_TRY_HIP(hipStreamSynchronize(s));
     timer_collect();
-    *n_pairs_host = npairs;
-    if (n_fallback_host) *n_fallback_host = static_cast<int64_t>(fb[0]) + fb[1];
-    if (npairs > cap) return KMG_ERR_CAPACITY;
+    if (hs.err_capacity) return KMG_ERR_WORKSPACE;
+    *n_pairs_host = hc[0];
+    if (n_fallback_host) *n_fallback_host = hc[5];
+    if (hc[0] > cap) return KMG_ERR_CAPACITY;
     return KMG_OK;
 }
 

@@ -28,13 +28,13 @@ void timer_begin(int stage, hipStream_t s) {
     TimerState& t = g_timer;
     if (!t.enabled || t.used >= kPairs) return;
     t.stage_of[t.used] = stage;
-    hipEventRecord(t.ev[t.used][0], s);
+    (void)hipEventRecord(t.ev[t.used][0], s);
 }
 
 void timer_end(int stage, hipStream_t s) {
     TimerState& t = g_timer;
     if (!t.enabled || t.used >= kPairs || t.stage_of[t.used] != stage) return;
-    hipEventRecord(t.ev[t.used][1], s);
+    (void)hipEventRecord(t.ev[t.used][1], s);
     ++t.used;
 }
 
@@ -43,7 +43,7 @@ void timer_collect() {
     if (!t.enabled) return;
     for (int i = 0; i < t.used; ++i) {
         float ms = 0.0f;
-        hipEventSynchronize(t.ev[i][1]);
+        (void)hipEventSynchronize(t.ev[i][1]);
         if (hipEventElapsedTime(&ms, t.ev[i][0], t.ev[i][1]) == hipSuccess) {
             t.ms[t.stage_of[i]] += ms;
             t.launches[t.stage_of[i]] += 1;
@@ -70,6 +70,7 @@ int timer_enable(int on) {
 }
 
 int timer_read(double* ms, int64_t* launches, int n) {
+    timer_collect();
     const int k = n < kStageCount ? n : kStageCount;
     for (int i = 0; i < k; ++i) {
         if (ms) ms[i] = g_timer.ms[i];

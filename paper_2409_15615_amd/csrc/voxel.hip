@@ -1,9 +1,10 @@
-// Voxel downsampling on a device hash table.
+// Voxel downsampling on a device hash table (all clouds of a batch at once).
 //
 // The method takes clouds voxelized with voxel size v (Section III-A).  Every
-// finite point gets the FP64 key floor(x / v) per axis; the voxel keeps its
-// lowest-index point (atomicMin on the table slot), and kept points are
-// compacted in ascending input index by a prefix sum over the kept flags.
+// finite point gets the FP64 key floor(x / v) per axis, tagged with its cloud;
+// each voxel keeps its lowest-index point (atomicMin on the table slot), and
+// kept points are compacted in (cloud, ascending input index) order by a
+// prefix sum over the kept flags.
 #include "kmg_device.h"
 
 namespace kmg {
@@ -12,124 +13,131 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ __launch_bounds__(kBlock) void voxel_insert(const float* __restrict__ xyz, int n, double v,
+__global__ __launch_bounds__(kBlock) void voxel_insert(const CloudDev* __restrict__ cl, int n_clouds, int64_t n_cap,
                                                        uint64_t* keys, int32_t* mins, uint32_t mask,
                                                        int32_t* __restrict__ slot, DevStatus* st) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    float x = xyz[i], y = xyz[n + i], z = xyz[2 * static_cast<int64_t>(n) + i];
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
-        slot[i] = -1;
-        return;
+    const int64_t n = clamp_count(st->n_raw, n_cap);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < n_cap; t += stride) {
+        if (t >= n) {
+            slot[t] = -1;
+            continue;
+        }
+        const int c = cloud_of_raw(cl, n_clouds, t);
+        const int64_t i = t - cl[c].raw_off;
+        const int64_t nc = cl[c].n_raw;
+        const float* raw = cl[c].raw;
+        const float x = raw[i], y = raw[nc + i], z = raw[2 * nc + i];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+            slot[t] = -1;
+            continue;
+        }
+        // IEEE FP64 division and floor: the same keys as any IEEE implementation.
+        const double v = cl[c].voxel;
+        const double kx = floor(static_cast<double>(x) / v);
+        const double ky = floor(static_cast<double>(y) / v);
+        const double kz = floor(static_cast<double>(z) / v);
+        if (!key_in_range(kx) || !key_in_range(ky) || !key_in_range(kz)) {
+            atomicOr(&st->err_range, 1);
+            slot[t] = -1;
+            continue;
+        }
+        const uint64_t key =
+            pack_key(c, static_cast<int64_t>(kx), static_cast<int64_t>(ky), static_cast<int64_t>(kz));
+        const uint32_t h = hash_insert(keys, mask, key);
+        atomicMin(mins + h, static_cast<int32_t>(t));
+        slot[t] = static_cast<int32_t>(h);
     }
-    // IEEE FP64 division and floor: the same keys as any IEEE implementation.
-    double kx = floor(static_cast<double>(x) / v);
-    double ky = floor(static_cast<double>(y) / v);
-    double kz = floor(static_cast<double>(z) / v);
-    if (!key_in_range(kx) || !key_in_range(ky) || !key_in_range(kz)) {
-        atomicOr(&st->err_range, 1);
-        slot[i] = -1;
-        return;
-    }
-    uint64_t key = pack_key(static_cast<int64_t>(kx), static_cast<int64_t>(ky), static_cast<int64_t>(kz));
-    uint32_t h = hash_insert(keys, mask, key);
-    atomicMin(mins + h, i);
-    slot[i] = static_cast<int32_t>(h);
 }
 
-__global__ __launch_bounds__(kBlock) void voxel_mark(const int32_t* __restrict__ slot, const int32_t* mins, int n,
-                                                     int32_t* __restrict__ flag) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int h = slot[i];
-    flag[i] = (h >= 0 && mins[h] == i) ? 1 : 0;
+__global__ __launch_bounds__(kBlock) void voxel_mark(const int32_t* __restrict__ slot, const int32_t* mins,
+                                                     int64_t n_cap, int32_t* __restrict__ flag) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < n_cap; t += stride) {
+        const int h = slot[t];
+        flag[t] = (h >= 0 && mins[h] == t) ? 1 : 0;
+    }
 }
 
-// Writes kept point j = pos[i] (row stride = the kept count m).
-__global__ __launch_bounds__(kBlock) void voxel_emit(const float* __restrict__ xyz, int n,
+// Kept point j = pos[t]; row stride `stride` (0: the kept count).
+__global__ __launch_bounds__(kBlock) void voxel_emit(const CloudDev* __restrict__ cl, int n_clouds, int64_t n_cap,
                                                      const int32_t* __restrict__ flag,
-                                                     const int32_t* __restrict__ pos, const int64_t* total,
-                                                     int64_t cap, int32_t* __restrict__ kept_idx,
-                                                     float* __restrict__ kept_xyz) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n || !flag[i]) return;
-    const int64_t m = *total;
-    if (m > cap) return;
-    const int64_t j = pos[i];
-    kept_idx[j] = i;
-    kept_xyz[j] = xyz[i];
-    kept_xyz[m + j] = xyz[n + i];
-    kept_xyz[2 * m + j] = xyz[2 * static_cast<int64_t>(n) + i];
+                                                     const int32_t* __restrict__ pos, const DevStatus* st,
+                                                     int64_t out_cap, int64_t out_stride,
+                                                     int32_t* __restrict__ kept_idx, float* __restrict__ kept_xyz,
+                                                     int32_t* __restrict__ kept_cloud) {
+    const int64_t n = clamp_count(st->n_raw, n_cap);
+    const int64_t m = st->m_kept;
+    if (m > out_cap) return;
+    const int64_t ks = out_stride ? out_stride : m;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < n; t += stride) {
+        if (!flag[t]) continue;
+        const int c = cloud_of_raw(cl, n_clouds, t);
+        const int64_t i = t - cl[c].raw_off;
+        const int64_t nc = cl[c].n_raw;
+        const float* raw = cl[c].raw;
+        const int64_t j = pos[t];
+        kept_idx[j] = static_cast<int32_t>(i);
+        kept_xyz[j] = raw[i];
+        kept_xyz[ks + j] = raw[nc + i];
+        kept_xyz[2 * ks + j] = raw[2 * nc + i];
+        if (kept_cloud) kept_cloud[j] = c;
+    }
 }
 
-struct VoxelWs {
-    DevStatus* st;
-    uint64_t* keys;
-    int32_t* mins;
-    int32_t* slot;
-    int32_t* flag;
-    int32_t* pos;
-    int64_t* total;
-    int64_t* scan_tmp;
-    uint32_t cap_table;
-};
-
-VoxelWs carve(Carver& c, int64_t n) {
-    VoxelWs w;
-    w.cap_table = next_pow2(static_cast<uint64_t>(std::max<int64_t>(2 * n, 64)));
-    w.st = c.take<DevStatus>(1);
-    w.keys = c.take<uint64_t>(w.cap_table);
-    w.mins = c.take<int32_t>(w.cap_table);
-    w.slot = c.take<int32_t>(static_cast<size_t>(n));
-    w.flag = c.take<int32_t>(static_cast<size_t>(n));
-    w.pos = c.take<int32_t>(static_cast<size_t>(n));
-    w.total = c.take<int64_t>(2);
-    w.scan_tmp = c.take<int64_t>(scan_temp_elems(n));
-    return w;
+// Per-cloud kept ranges: the exclusive scan at the cloud's first raw index.
+__global__ void cloud_ranges(const CloudDev* __restrict__ cl, int n_clouds, int64_t n_cap,
+                             const int32_t* __restrict__ pos, const DevStatus* st, CloudState* cs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_clouds) return;
+    const int64_t n = clamp_count(st->n_raw, n_cap);
+    const int64_t m = st->m_kept;
+    const int64_t a = cl[c].raw_off;
+    const int64_t b = a + cl[c].n_raw;
+    const int64_t ka = a < n ? pos[a] : m;
+    const int64_t kb = b < n ? pos[b] : m;
+    cs[c].kept_off = static_cast<int32_t>(ka);
+    cs[c].kept_cnt = static_cast<int32_t>(kb - ka);
 }
 
 }  // namespace
 
-size_t voxelize_ws(int64_t n) {
-    Carver c(nullptr, 0);
-    carve(c, n);
-    return c.off;
+VoxelWs carve_voxel(Carver& c, int64_t n_cap) {
+    VoxelWs w;
+    w.cap_table = next_pow2(static_cast<uint64_t>(std::max<int64_t>(2 * n_cap, 64)));
+    w.keys = c.take<uint64_t>(w.cap_table);
+    w.mins = c.take<int32_t>(w.cap_table);
+    w.slot = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(n_cap, 1)));
+    w.flag = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(n_cap, 1)));
+    w.pos = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(n_cap, 1)));
+    w.scan_tmp = c.take<int64_t>(scan_temp_elems(n_cap));
+    return w;
 }
 
-kmg_status voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz, int64_t cap,
-                    int64_t* n_kept_host, void* ws, size_t ws_bytes, hipStream_t s) {
-    Carver c(ws, ws_bytes);
-    VoxelWs w = carve(c, n);
-    if (!c.fits()) return KMG_ERR_WORKSPACE;
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.st), 0u, sizeof(DevStatus) / 4, s));
+kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
+                          int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
+                          int32_t* kept_cloud, CloudState* cs, hipStream_t s) {
+    StageScope sc(ST_VOXELIZE, s);
     KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
     KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.mins), 0x7fffffffu, w.cap_table, s));
-    const int ni = static_cast<int>(n);
-    {
-    StageScope sc(ST_VOXELIZE, s);
-    if (n > 0) {
-        voxel_insert<<<grid_for(n, kBlock), kBlock, 0, s>>>(xyz, ni, voxel, w.keys, w.mins, w.cap_table - 1,
-                                                           w.slot, w.st);
+    if (n_cap > 0) {
+        voxel_insert<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.keys, w.mins,
+                                                               w.cap_table - 1, w.slot, st);
         KMG_TRY(launch_status());
-        voxel_mark<<<grid_for(n, kBlock), kBlock, 0, s>>>(w.slot, w.mins, ni, w.flag);
+        voxel_mark<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(w.slot, w.mins, n_cap, w.flag);
         KMG_TRY(launch_status());
     }
-    KMG_TRY(scan_exclusive(w.flag, w.pos, n, w.total, w.scan_tmp, s));
-    if (n > 0) {
-        voxel_emit<<<grid_for(n, kBlock), kBlock, 0, s>>>(xyz, ni, w.flag, w.pos, w.total, cap, kept_idx,
-                                                         kept_xyz);
+    KMG_TRY(scan_exclusive(w.flag, w.pos, n_cap, &st->m_kept, w.scan_tmp, s));
+    if (n_cap > 0) {
+        voxel_emit<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.flag, w.pos, st, out_cap,
+                                                             out_stride, kept_idx, kept_xyz, kept_cloud);
         KMG_TRY(launch_status());
     }
+    if (cs) {
+        cloud_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(cl, n_clouds, n_cap, w.pos, st, cs);
+        KMG_TRY(launch_status());
     }
-    int64_t m = 0;
-    DevStatus st;
-    KMG_TRY_HIP(hipMemcpyAsync(&m, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    KMG_TRY_HIP(hipMemcpyAsync(&st, w.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    KMG_TRY_HIP(hipStreamSynchronize(s));
-    timer_collect();
-    if (st.err_range) return KMG_ERR_RANGE;
-    *n_kept_host = m;
-    if (m > cap) return KMG_ERR_CAPACITY;
     return KMG_OK;
 }
 

@@ -41,6 +41,14 @@ class KmgParams(C.Structure):
     ]
 
 
+class KmgCloud(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("n", C.c_int64), ("params", KmgParams)]
+
+
+class KmgMatchOut(C.Structure):
+    _fields_ = [("pairs", C.c_void_p), ("d1", C.c_void_p), ("d2", C.c_void_p), ("cap", C.c_int64)]
+
+
 class KmgError(RuntimeError):
     def __init__(self, fn: str, status: int, lib):
         self.status = status
@@ -75,6 +83,21 @@ def load():
     lib.kmg_fpfh.restype = i32
     lib.kmg_match.argtypes = [vp, vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, i64, i64p, i64p, vp, sz, vp]
     lib.kmg_match.restype = i32
+    cp, op = C.POINTER(KmgCloud), C.POINTER(KmgMatchOut)
+    lib.kmg_batch_workspace_bytes.argtypes = [i32, i64, i64, i32]
+    lib.kmg_batch_workspace_bytes.restype = sz
+    lib.kmg_batch_upload.argtypes = [cp, op, i32, i64, i64, vp, sz, vp]
+    lib.kmg_batch_upload.restype = i32
+    lib.kmg_batch_run.argtypes = [i32, i64, i64, i32, i32, vp, vp, sz, vp]
+    lib.kmg_batch_run.restype = i32
+    lib.kmg_register_batch.argtypes = [cp, op, i32, i64, i64, i32, vp, vp, sz, vp]
+    lib.kmg_register_batch.restype = i32
+    lib.kmg_timing_enable.argtypes = [i32]
+    lib.kmg_timing_enable.restype = i32
+    lib.kmg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+    lib.kmg_timing_read.restype = i32
+    lib.kmg_stage_name.argtypes = [i32]
+    lib.kmg_stage_name.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -297,3 +320,108 @@ def register_pair(src_raw, tgt_raw, params_src, params_tgt, prec="fp32", ws=None
     b = faster_pfh(tgt_raw, params_tgt, ws)
     mt = match(a.feats.fpfh, b.feats.fpfh, a.feats.j_idx, b.feats.j_idx, prec=prec, ws=ws)
     return a, b, mt
+
+
+# ---------------------------------------------------------------------------
+# Batched registration
+# ---------------------------------------------------------------------------
+
+COUNTS_STRIDE = 8
+
+
+@dataclass
+class PairResult:
+    pairs: torch.Tensor
+    d1: torch.Tensor
+    d2: torch.Tensor
+    kept: tuple
+    n_j: tuple
+    n_fallback: int
+    status: int
+
+
+class Batch:
+    """A reusable batch of `n_pairs` registration pairs with fixed capacities.
+
+    Owns the workspace, the per-pair output buffers and the device counts;
+    `upload` writes a new cloud table, `run` enqueues kmg_batch_run on the
+    current stream (capturable in a graph), `results` reads the counts back."""
+
+    def __init__(self, n_pairs, raw_cap, nnz_cap, n_bins=11, out_cap=None, device=None):
+        lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.n_pairs, self.raw_cap, self.nnz_cap, self.n_bins = int(n_pairs), int(raw_cap), int(nnz_cap), int(n_bins)
+        nbytes = int(lib.kmg_batch_workspace_bytes(self.n_pairs, self.raw_cap, self.nnz_cap, self.n_bins))
+        if nbytes == 0:
+            raise ValueError("invalid batch capacities")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.out_cap = int(out_cap) if out_cap is not None else max(1, self.raw_cap // 2)
+        self.pairs = torch.empty((self.n_pairs, self.out_cap, 2), dtype=torch.int32, device=self.device)
+        self.d1 = torch.empty((self.n_pairs, self.out_cap), dtype=torch.float32, device=self.device)
+        self.d2 = torch.empty((self.n_pairs, self.out_cap), dtype=torch.float32, device=self.device)
+        self.counts = torch.zeros((self.n_pairs, COUNTS_STRIDE), dtype=torch.int64, device=self.device)
+        self._keep = []
+
+    def upload(self, clouds):
+        """clouds: list of 2 * n_pairs (xyz (3, n) float32 device tensor, KmgParams)."""
+        lib = load()
+        if len(clouds) != 2 * self.n_pairs:
+            raise ValueError("need two clouds per pair")
+        ct = (KmgCloud * len(clouds))()
+        total = 0
+        for k, (xyz, prm) in enumerate(clouds):
+            _check_dev(xyz, torch.float32, "xyz")
+            ct[k].xyz = xyz.data_ptr()
+            ct[k].n = xyz.shape[1]
+            ct[k].params = prm
+            total += xyz.shape[1]
+        if total > self.raw_cap:
+            raise ValueError(f"batch has {total} raw points, capacity {self.raw_cap}")
+        ot = (KmgMatchOut * self.n_pairs)()
+        for i in range(self.n_pairs):
+            ot[i].pairs = self.pairs[i].data_ptr()
+            ot[i].d1 = self.d1[i].data_ptr()
+            ot[i].d2 = self.d2[i].data_ptr()
+            ot[i].cap = self.out_cap
+        self._keep = list(clouds)
+        _raise("kmg_batch_upload", lib.kmg_batch_upload(ct, ot, self.n_pairs, self.raw_cap, self.nnz_cap,
+                                                        _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def run(self, prec="fp32"):
+        lib = load()
+        _raise("kmg_batch_run", lib.kmg_batch_run(self.n_pairs, self.raw_cap, self.nnz_cap, self.n_bins,
+                                                  PRECISIONS[prec], _ptr(self.counts), _ptr(self.ws),
+                                                  self.ws.numel(), _stream()))
+
+    def results(self):
+        """Reads the counts (synchronises the current stream) -> list of PairResult."""
+        cnt = self.counts.cpu().numpy()
+        out = []
+        for i in range(self.n_pairs):
+            k = int(min(cnt[i, 0], self.out_cap))
+            out.append(PairResult(self.pairs[i, :k], self.d1[i, :k], self.d2[i, :k],
+                                  (int(cnt[i, 1]), int(cnt[i, 2])), (int(cnt[i, 3]), int(cnt[i, 4])),
+                                  int(cnt[i, 5]), int(cnt[i, 6])))
+        return out
+
+    def nnz(self):
+        return int(self.counts[0, 7].item())
+
+
+def register_batch(clouds, prec="fp32", nnz_per_point=48, out_cap=None):
+    """Runs the batched hot path once.  clouds: list of (xyz (3, n) device float32,
+    KmgParams), two per pair (source, target).  Grows the neighbour capacity and
+    retries once if the batch needs more.  Returns (list of PairResult, Batch)."""
+    n_pairs = len(clouds) // 2
+    raw = sum(int(x.shape[1]) for x, _ in clouds)
+    H = clouds[0][1].n_bins
+    nnz_cap = max(1024, nnz_per_point * raw)
+    for _ in range(2):
+        b = Batch(n_pairs, raw, nnz_cap, H, out_cap=out_cap)
+        b.upload(clouds)
+        b.run(prec)
+        res = b.results()
+        if all(r.status != KMG_ERR_WORKSPACE for r in res):
+            return res, b
+        nnz_cap = b.nnz() + 1024
+    raise KmgError("kmg_register_batch", KMG_ERR_WORKSPACE, _lib)
