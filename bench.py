@@ -6,12 +6,19 @@ voxelize both clouds, radius search + normals, SPFH/FPFH, and mutual
 nearest-neighbour matching of the 33-d FP32 descriptors, all in libkmg on one
 GPU, inputs already resident in device memory.
 
-Prints one JSON line.  Per-stage device times come from HIP events that the
-library records on its stream during the timed steps; the roofline entry
-reports the matching distance-tile kernel (the dominant one).  The CPU
-baseline is the FP64 oracle timed on the host for one full pair.
+Three forms of the same step are timed, each over --steps pairs:
+  plain   -- the per-stage calls (kmg_voxelize, kmg_normals, kmg_fpfh,
+             kmg_match), which return counts to the host between stages;
+  batched -- one kmg_batch_run of the pair (no host synchronisation inside),
+             then one wait for the stream;
+  graph   -- the batched run captured once in a HIP graph and replayed.
+`value` is the graph form's pairs/s; p50/p99 per-pair latency of every form
+is reported beside it.  Per-stage device times come from HIP events that the
+library records on its stream during the batched form's timed steps; the
+roofline entry reports the matching distance-tile kernel (the dominant one)
+from the same events.  The CPU baseline is the FP64 oracle on one full pair.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--prec fp32]
+Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 5] [--workload lidar|batch64]
 """
 
 from __future__ import annotations
@@ -29,13 +36,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency vs plain"
 PEAK_FP64_MFMA_TFLOPS = 78.6
-PEAK_HBM_GBS = 8000.0
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+
+
+def timed(fn, steps, sync):
+    lat = []
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        fn()
+        sync()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    t1 = time.perf_counter()
+    return t1 - t0, lat
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -47,13 +71,12 @@ def main():
               "sharding them across GPUs needs no exchange). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import synth
     from paper_2409_15615_amd import kmg
 
-    kmg.load()
+    lib = kmg.load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     d = synth.c1_pair(args.item)
@@ -62,52 +85,68 @@ def main():
     pt = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_tgt"])
     src = torch.from_numpy(d["src"]).to(dev)
     tgt = torch.from_numpy(d["tgt"]).to(dev)
-    ws = kmg.Workspace(dev)
+    sync = torch.cuda.synchronize
 
-    def step():
-        return kmg.register_pair(src, tgt, ps, pt, prec=args.prec, ws=ws)
+    # plain form
+    ws = kmg.Workspace(dev)
+    state = {}
+
+    def plain():
+        state["plain"] = kmg.register_pair(src, tgt, ps, pt, prec=args.prec, ws=ws)
 
     for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        plain()
+    t_plain, lat_plain = timed(plain, args.steps, sync)
+    a, b, mt = state["plain"]
 
-    lib = kmg.load()
-    lib.kmg_timing_enable.argtypes = [C.c_int32]
-    lib.kmg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
-    lib.kmg_stage_name.argtypes = [C.c_int32]
-    lib.kmg_stage_name.restype = C.c_char_p
+    # batched form (one pair per batch), stage timing over its timed steps
+    clouds = [(src, ps), (tgt, pt)]
+    _, probe = kmg.register_batch(clouds, prec=args.prec)
+    batch = kmg.Batch(1, probe.raw_cap, probe.nnz() + 4096, p.n_bins, device=dev)
+    batch.upload(clouds)
+
+    def batched():
+        batch.run(args.prec)
+
+    for _ in range(args.warmup):
+        batched()
     lib.kmg_timing_enable(1)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        a, b, mt = step()
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t_batch, lat_batch = timed(batched, args.steps, sync)
     nst = lib.kmg_timing_read(None, None, 0)
     ms = (C.c_double * nst)()
     ln = (C.c_int64 * nst)()
     lib.kmg_timing_read(ms, ln, nst)
     lib.kmg_timing_enable(0)
-    stages = {lib.kmg_stage_name(i).decode(): (ms[i] / args.steps, ln[i]) for i in range(nst)}
+    names = [lib.kmg_stage_name(i).decode() for i in range(nst)]
+    stages = {names[i]: round(ms[i] / args.steps, 5) for i in range(nst)}
+    res = batch.results()[0]
 
-    elapsed = t1 - t0
-    value = args.steps / elapsed
-    lat_ms = sorted(x * 1e3 for x in lat)
-    p50 = statistics.median(lat_ms)
-    p99 = lat_ms[min(len(lat_ms) - 1, int(round(0.99 * (len(lat_ms) - 1))))]
+    # graph form
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batched()
+    torch.cuda.current_stream().wait_stream(s)
+    sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batched()
+    for _ in range(args.warmup):
+        g.replay()
+    t_graph, lat_graph = timed(g.replay, args.steps, sync)
+    res_g = batch.results()[0]
 
-    nj_p, nj_q = int(a.feats.j_idx.numel()), int(b.feats.j_idx.numel())
+    same = (torch.equal(res.pairs, mt.pairs) and torch.equal(res_g.pairs, mt.pairs)
+            and torch.equal(res.d1, mt.d1) and torch.equal(res.d2, mt.d2))
+
+    nj_p, nj_q = res.n_j
     dim = 3 * p.n_bins
-    topk_ms_total = ms[[lib.kmg_stage_name(i).decode() for i in range(nst)].index("match_topk")]
-    topk_launches = ln[[lib.kmg_stage_name(i).decode() for i in range(nst)].index("match_topk")]
-    topk_avg_s = topk_ms_total / max(1, topk_launches) / 1e3
-    flops_per_launch = 2.0 * nj_p * nj_q * dim
-    achieved_tflops = flops_per_launch / topk_avg_s / 1e12 if topk_avg_s > 0 else 0.0
+    i_topk = names.index("match_topk")
+    topk_avg_s = ms[i_topk] / max(1, ln[i_topk]) / 1e3
+    flops_per_launch = 2.0 * (2.0 * nj_p * nj_q * dim)  # one persistent launch serves both directions
+    achieved = flops_per_launch / topk_avg_s / 1e12 if topk_avg_s > 0 else 0.0
 
+    value = args.steps / t_graph
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -115,7 +154,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "ms_per_step": round(1e3 * t_graph / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -126,22 +165,33 @@ def main():
                         "and moved 2-10 m with 20% outliers; voxel 0.3 m, r_normal 0.9 m, r_FPFH 1.5 m, "
                         "33-bin FP32 descriptors, mutual NN",
             "raw_points": [int(src.shape[1]), int(tgt.shape[1])],
-            "kept_points": [int(a.xyz.shape[1]), int(b.xyz.shape[1])],
+            "kept_points": list(res.kept),
             "descriptor_rows_J": [nj_p, nj_q],
-            "correspondences": int(mt.pairs.shape[0]),
-            "exact_rescans": int(mt.n_fallback),
+            "correspondences": int(res.pairs.shape[0]),
+            "exact_rescans": int(res.n_fallback),
             "precision": args.prec,
+            "form": "graph-replayed kmg_batch_run, one pair per step",
         },
-        "p50_ms": round(p50, 4),
-        "p99_ms": round(p99, 4),
-        "stages_ms_per_step": {k: round(v[0], 5) for k, v in stages.items()},
+        "p50_ms": round(statistics.median(lat_graph), 4),
+        "p99_ms": round(pct(lat_graph, 0.99), 4),
+        "forms": {
+            "plain": {"pairs_per_s": round(args.steps / t_plain, 3), "p50_ms": round(statistics.median(lat_plain), 4),
+                      "p99_ms": round(pct(lat_plain, 0.99), 4)},
+            "batched": {"pairs_per_s": round(args.steps / t_batch, 3),
+                        "p50_ms": round(statistics.median(lat_batch), 4), "p99_ms": round(pct(lat_batch, 0.99), 4)},
+            "graph": {"pairs_per_s": round(value, 3), "p50_ms": round(statistics.median(lat_graph), 4),
+                      "p99_ms": round(pct(lat_graph, 0.99), 4)},
+            "identical_correspondences": bool(same),
+        },
+        "stages_ms_per_step": stages,
         "roofline": {
-            "kernel": "topk_pass (FP64 MFMA distance tiles + top-4 epilogue), one launch per direction",
+            "kernel": "topk_tiles (FP64 MFMA distance tiles + top-4 epilogue), one persistent launch per pair "
+                      "serving both directions",
             "bound": "mfma",
-            "achieved": round(achieved_tflops, 4),
+            "achieved": round(achieved, 4),
             "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(achieved_tflops / PEAK_FP64_MFMA_TFLOPS, 5),
+            "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 5),
             "traffic": None,
             "avg_launch_ms": round(topk_avg_s * 1e3, 5),
             "flops_per_launch": flops_per_launch,
@@ -155,7 +205,7 @@ def main():
         tc0 = time.perf_counter()
         ref = oracle.run_pair(d["src"], d["tgt"], p, d["vp_src"], d["vp_tgt"])
         tc = time.perf_counter() - tc0
-        gp = {tuple(x) for x in mt.pairs.cpu().numpy().tolist()}
+        gp = {tuple(x) for x in res_g.pairs.cpu().numpy().tolist()}
         rp = {tuple(x) for x in ref["pairs"].tolist()}
         out["cpu_baseline"] = {
             "value": round(1.0 / tc, 5),

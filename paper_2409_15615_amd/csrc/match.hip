@@ -176,7 +176,22 @@ __global__ __launch_bounds__(kBlock) void row_norms(const MatchSet* __restrict__
             acc = acc + v * v;
         }
         n2[t] = acc;
-        atomicMax(&plan[c].max_norm_bits, static_cast<unsigned long long>(__double_as_longlong(acc)));
+        // one atomic per wave when the wave's rows share a set (the common case)
+        const uint64_t live = ballot(true);
+        const int c0 = __shfl(c, __ffsll(static_cast<unsigned long long>(live)) - 1, kWave);
+        const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(acc));
+        if (ballot(c == c0) == live) {
+            unsigned long long mx = bits;
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) {
+                const unsigned long long o = __shfl_xor(mx, d, kWave);
+                const bool o_live = (live >> (lane_id() ^ d)) & 1ull;
+                if (o_live && o > mx) mx = o;
+            }
+            if (lane_id() == __ffsll(static_cast<unsigned long long>(live)) - 1) atomicMax(&plan[c].max_norm_bits, mx);
+        } else {
+            atomicMax(&plan[c].max_norm_bits, bits);
+        }
     }
 }
 
@@ -286,64 +301,71 @@ __device__ __forceinline__ void merge_lanes(Top4& t, int d) {
 }
 
 // One wave: 64 query columns of set qc (local columns col0 ..) against the
-// partner's chunks [c_begin, c_end) (partner-local chunk indices).
+// partner's chunks [c_begin, c_end) (partner-local chunk indices).  The packed
+// depth is exactly 4 KS, and chunk indices are clamped rather than branched
+// on, so every operand load is unconditional and the loads of a chunk issue
+// back to back.
 template <int KS>
-__device__ __forceinline__ void tile_wave(const double* __restrict__ pk, int kp, int dim, const SetPlan& qc,
+__device__ __forceinline__ void tile_wave(const double* __restrict__ pk, int dim, const SetPlan& qc,
                                           const SetPlan& pc, int col0, int c_begin, int c_end, int seg,
                                           double* __restrict__ part_v, int32_t* __restrict__ part_i) {
+    constexpr int kp = 4 * KS;
     const int lane = lane_id();
     const int g = lane >> 4;  // k offset within a step for the operands; row group for the result
     const int l16 = lane & 15;
-    // query operand: B[k][j] = -2 y_j[k] (k < dim), 1 (k = dim), 0 beyond
+    // query operand: B[k][j] = -2 y_j[k] (k < dim), 1 (k = dim), 0 beyond.  Chunks past the
+    // set's end are clamped to its last chunk; their columns are >= n and never written.
     double bq[kTilesPerWave][KS];
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) {
-        const int chunk = col0 / kTileCols + t;
-        const bool have = chunk < qc.chunks;
-        const double* src = pk + static_cast<int64_t>(qc.chunk_off + (have ? chunk : 0)) * kp * kTileRows;
+        const int chunk = min(col0 / kTileCols + t, qc.chunks - 1);
+        const double* src = pk + static_cast<int64_t>(qc.chunk_off + chunk) * kp * kTileRows;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int k = 4 * s + g;
-            const double v = (have && k < kp) ? src[k * kTileRows + l16] : 0.0;
+            const double v = src[k * kTileRows + l16];
             bq[t][s] = (k < dim) ? -2.0 * v : (k == dim ? 1.0 : 0.0);
         }
     }
     Top4 top[kTilesPerWave];
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) top[t].init();
-    // the A operand of chunk c + 1 is loaded while chunk c is multiplied
-    double a_next[KS];
     if (c_begin < c_end) {
-        const double* src = pk + static_cast<int64_t>(pc.chunk_off + c_begin) * kp * kTileRows;
+        // the A operand of chunk c + 1 is loaded while chunk c is multiplied
+        double a_next[KS];
+        {
+            const double* src = pk + static_cast<int64_t>(pc.chunk_off + c_begin) * kp * kTileRows + lane;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < kp) ? src[s * 4 * kTileRows + lane] : 0.0;
-    }
-    for (int c = c_begin; c < c_end; ++c) {
-        double a[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) a[s] = a_next[s];
-        if (c + 1 < c_end) {
-            const double* src = pk + static_cast<int64_t>(pc.chunk_off + c + 1) * kp * kTileRows;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) a_next[s] = (4 * s + g < kp) ? src[s * 4 * kTileRows + lane] : 0.0;
+            for (int s = 0; s < KS; ++s) a_next[s] = src[s * 4 * kTileRows];
         }
-        doublex4 acc[kTilesPerWave];
+        for (int c = c_begin; c < c_end; ++c) {
+            double a[KS];
 #pragma unroll
-        for (int t = 0; t < kTilesPerWave; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+            for (int s = 0; s < KS; ++s) a[s] = a_next[s];
+            {
+                const int cn = min(c + 1, c_end - 1);
+                const double* src = pk + static_cast<int64_t>(pc.chunk_off + cn) * kp * kTileRows + lane;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+                for (int s = 0; s < KS; ++s) a_next[s] = src[s * 4 * kTileRows];
+            }
+            doublex4 acc[kTilesPerWave];
 #pragma unroll
-            for (int t = 0; t < kTilesPerWave; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bq[t][s], acc[t], 0, 0, 0);
-        }
-        // result register r of lane l holds tile row 4 r + l / 16, column l % 16
-        const int row0 = c * kTileRows + g;
+            for (int t = 0; t < kTilesPerWave; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < kTilesPerWave; ++t) {
-            const double mn = fmin(fmin(acc[t][0], acc[t][1]), fmin(acc[t][2], acc[t][3]));
-            if (mn < top[t].v3) {
+            for (int s = 0; s < KS; ++s) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) top[t].push(acc[t][r], row0 + 4 * r);
+                for (int t = 0; t < kTilesPerWave; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bq[t][s], acc[t], 0, 0, 0);
+            }
+            // result register r of lane l holds tile row 4 r + l / 16, column l % 16
+            const int row0 = c * kTileRows + g;
+#pragma unroll
+            for (int t = 0; t < kTilesPerWave; ++t) {
+                const double mn = fmin(fmin(acc[t][0], acc[t][1]), fmin(acc[t][2], acc[t][3]));
+                if (mn < top[t].v3) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) top[t].push(acc[t][r], row0 + 4 * r);
+                }
             }
         }
     }
@@ -371,7 +393,7 @@ __device__ __forceinline__ void tile_wave(const double* __restrict__ pk, int kp,
 // an atomic queue; every block leaves once the queue runs past the tile count.
 template <int KS>
 __global__ __launch_bounds__(kBlock) void topk_tiles(const SetPlan* __restrict__ plan, int n_sets,
-                                                     const double* __restrict__ pk, int kp, int dim,
+                                                     const double* __restrict__ pk, int dim,
                                                      double* __restrict__ part_v, int32_t* __restrict__ part_i,
                                                      DevStatus* st) {
     __shared__ int s_tile;
@@ -393,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void topk_tiles(const SetPlan* __restrict__
         const int c_begin = seg * cps;
         const int c_end = min(c_begin + cps, pc.chunks);
         const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
-        if (col0 < qc.n) tile_wave<KS>(pk, kp, dim, qc, pc, col0, c_begin, c_end, seg, part_v, part_i);
+        if (col0 < qc.n) tile_wave<KS>(pk, dim, qc, pc, col0, c_begin, c_end, seg, part_v, part_i);
     }
 }
 
@@ -590,7 +612,7 @@ __global__ void pair_counts(const SetPlan* __restrict__ plan, int n_sets, const 
 
 MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim) {
     MatchWs w;
-    w.kp = (dim + 1 + 3) / 4 * 4;
+    w.kp = (dim + 1 <= 36) ? 36 : 68;  // 4 KS for the two kernel instantiations (dim <= 64)
     w.q_cap = std::max<int64_t>(q_cap, 1);
     w.chunk_cap = q_cap / kTileRows + n_sets + 1;
     w.part_cap = w.q_cap * kTopK * (q_cap <= 262144 ? kMaxSegs : 4);
@@ -613,7 +635,7 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
                        const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s) {
     (void)prec;
     if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
-    const int ks = w.kp / 4;
+    const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     {
         StageScope sc(ST_MATCH_PACK, s);
         plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.part_cap, w.plan, st);
@@ -627,9 +649,9 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
     {
         StageScope sc(ST_MATCH_TOPK, s);
         if (ks <= 9) {
-            topk_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, w.kp, dim, w.part_v, w.part_i, st);
+            topk_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, dim, w.part_v, w.part_i, st);
         } else if (ks <= 17) {
-            topk_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, w.kp, dim, w.part_v, w.part_i, st);
+            topk_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, dim, w.part_v, w.part_i, st);
         } else {
             return KMG_ERR_ARG;
         }
