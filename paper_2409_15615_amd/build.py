@@ -43,6 +43,14 @@ def flags() -> list:
     ]
 
 
+# Per-source additions.  The matcher's candidate lists run min/max networks on
+# finite scores; without NaN semantics the compiler drops the quieting of each
+# operand that IEEE min/max would otherwise need.
+EXTRA = {
+    "match.hip": ["-fno-honor-nans"],
+}
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
@@ -52,7 +60,7 @@ def build(verbose: bool = False) -> str:
     for src in srcs:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [cc, *flags(), "-c", src, "-o", obj]
+        cmd = [cc, *flags(), *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

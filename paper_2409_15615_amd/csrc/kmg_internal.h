@@ -275,8 +275,7 @@ struct MatchWs {
     SetPlan* plan;
     double* pk;           // packed rows
     double* n2;           // exact squared norms per query slot
-    double* part_v;
-    int32_t* part_i;
+    double* part;         // per-segment top-4 lists of encoded scores
     int32_t* nn;
     double* best;
     double* second;

@@ -14,21 +14,23 @@
 // "dimension" (A = [x, ||x||^2]), queries use B = [-2 y, 1], and one
 // v_mfma_f64_16x16x4_f64 chain of ceil((dim+1)/4) steps yields a 16x16 tile
 // of t.  Lane l owns query column l % 16 and tile rows l / 16 + {0, 4, 8, 12}
-// (result register r holds row 4 r + l / 16), and keeps a running top-4 of t
-// in registers.  A wave holds 64 query columns (four chains), a block of four
-// waves 256.  A tile is (set, 256-query block, segment of the partner's
-// rows); a persistent grid pulls tiles from an atomic queue until it is
-// empty, so uneven pairs share one launch.
+// (result register r holds row 4 r + l / 16).  Each score carries its row
+// index in its low mantissa bits, and every lane keeps a running top-4 of
+// encoded scores with min/max networks.  A wave holds 64 query columns (four
+// chains), a block of four waves 256.  A tile is (set, 256-query block,
+// segment of the partner's rows); a persistent grid pulls tiles from an
+// atomic queue until it is empty, so uneven pairs share one launch.
 //
-// Exact decision.  The per-segment top-4 lists are merged, the four
-// candidates are re-scored with the plain FP64 sum of squared differences in
-// dimension order, and the result is certified: every non-candidate has
-// t >= t_4 (the 4th candidate's value) and |t - exact| <= E with
-// E = 128 u (2 max ||x||^2 + 2 ||y||^2), u = 2^-53 (the dot-product rounding
-// bound is (dim + 2) u times ||x||^2 + 2 x.y <= 2 ||x||^2 + ||y||^2).  If the
-// exact second-best distance is below t_4 + ||y||^2 - E, the exact best and
-// second-best over all rows are among the candidates; otherwise the query is
-// re-scanned exactly in FP64.
+// Exact decision.  The per-segment lists are merged, the four candidates are
+// re-scored with the plain FP64 sum of squared differences in dimension
+// order, and the result is certified: every non-candidate has an encoded
+// score >= t_4 (the 4th candidate's), its computed t is within 2^(bits-52)|t|
+// of the encoded one, and |t - exact| <= 128 u (2 max ||x||^2 + 2 ||y||^2),
+// u = 2^-53 (the dot-product rounding bound is (dim + 2) u times
+// ||x||^2 + 2 x.y <= 2 ||x||^2 + ||y||^2).  If the exact second-best distance
+// is below t_4 + ||y||^2 minus both bounds, the exact best and second-best
+// over all rows are among the candidates; otherwise the query is re-scanned
+// exactly in FP64.
 #include <math.h>
 
 #include "kmg_device.h"
@@ -47,9 +49,11 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kColsPerBlock = kColsPerWave * kWavesPerBlock;
 constexpr int kBlock = 256;
 constexpr int kPlanThreads = 1024;
-constexpr int kTargetTiles = 2048;  // tiles wanted per launch (8 per CU)
-constexpr int kMaxSegs = 16;
+constexpr int kTargetTiles = 4096;  // tiles wanted per launch (8 per persistent block)
+constexpr int kMaxSegs = 32;
 constexpr int kTopkBlocks = 512;    // persistent grid of the tile kernel (2 blocks per CU)
+constexpr double kPadScore = 0x1p1000;  // score of padding rows: finite, so it can carry an index
+constexpr double kNoScore = 0x1p999;    // list entries at or above this are no row
 
 // Set of a flattened index given non-decreasing starts (last s with start <= t).
 template <class F>
@@ -99,7 +103,7 @@ __device__ int64_t block_excl_scan64(int64_t v, int64_t* smem, int64_t& total) {
     return before + incl - v;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __restrict__ sets, int n_sets,
+__global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __restrict__ sets, int n_sets, int kp,
                                                          int64_t part_cap, SetPlan* plan, DevStatus* st) {
     __shared__ int64_t smem[kPlanThreads / kWave];
     __shared__ int s_segs;
@@ -116,6 +120,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     block_excl_scan64(cblocks, smem, tb);
     s_chunks[c] = chunks;
     s_n[c] = n;
+    // one buffer descriptor spans a set's packed rows: keep them below 2 GiB
+    if (static_cast<int64_t>(chunks) * kp * kTileRows * 8 > INT32_MAX) st->err_capacity = 1;
     if (c == 0) {
         int S = static_cast<int>(tb > 0 ? kTargetTiles / tb : 1);
         S = S < 1 ? 1 : (S > kMaxSegs ? kMaxSegs : S);
@@ -212,179 +218,216 @@ __global__ __launch_bounds__(kBlock) void pack_rows(const MatchSet* __restrict__
             if (k < dim) v = set_row(sets[c], i, dim)[k];
             else if (k == dim) v = n2[plan[c].q_off + i];
         } else if (k == dim) {
-            v = INFINITY;  // padding rows never enter a top-k list
+            v = kPadScore;  // padding rows never enter a top-k list
         }
         pk[t] = v;
     }
 }
 
-// -------------------------------------------------------------- top-4 --
+// ------------------------------------------------------ candidate lists --
+//
+// A candidate is a score t with its partner row index written into the low
+// `bits` mantissa bits, bits = the width of the partner's padded row count.
+// Encoded scores of distinct rows never compare equal, so a top-4 list is four
+// doubles kept ascending by min/max networks: no branches and no index
+// registers.  An encoded score differs from t by less than 2^(bits - 52) |t|,
+// which the certificate adds to its error bound.
 
-struct Top4 {
-    double v0, v1, v2, v3;
-    int i0, i1, i2, i3;
-    __device__ void init() {
-        v0 = v1 = v2 = v3 = INFINITY;
-        i0 = i1 = i2 = i3 = -1;
+__device__ __forceinline__ int row_bits(int chunks) {
+    const unsigned rows = static_cast<unsigned>(chunks) * kTileRows;  // >= 16
+    return 32 - __clz(static_cast<int>(rows - 1u));
+}
+
+__device__ __forceinline__ unsigned keep_mask(int bits) { return bits >= 32 ? 0u : ~((1u << bits) - 1u); }
+
+__device__ __forceinline__ double encode(double t, unsigned keep, unsigned row) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(t));
+    const unsigned lo = (static_cast<unsigned>(u) & keep) | row;
+    return __longlong_as_double(static_cast<long long>((u & 0xffffffff00000000ull) | lo));
+}
+
+__device__ __forceinline__ int decode_row(double v, unsigned keep) {
+    return static_cast<int>(static_cast<unsigned>(__double_as_longlong(v)) & ~keep);
+}
+
+__device__ __forceinline__ void cex(double& a, double& b) {
+    const double lo = fmin(a, b), hi = fmax(a, b);
+    a = lo;
+    b = hi;
+}
+
+// Ascending sort of four values: five compare-exchanges.
+__device__ __forceinline__ void sort4(double& a, double& b, double& c, double& d) {
+    cex(a, b);
+    cex(c, d);
+    cex(a, c);
+    cex(b, d);
+    cex(b, c);
+}
+
+// top <- the four smallest of top and w, both ascending (bitonic merge).
+__device__ __forceinline__ void merge4(double* top, double w0, double w1, double w2, double w3) {
+    double m0 = fmin(top[0], w3), m1 = fmin(top[1], w2), m2 = fmin(top[2], w1), m3 = fmin(top[3], w0);
+    cex(m0, m2);
+    cex(m1, m3);
+    cex(m0, m1);
+    cex(m2, m3);
+    top[0] = m0;
+    top[1] = m1;
+    top[2] = m2;
+    top[3] = m3;
+}
+
+// Merges the list of lane l ^ d into this lane's list.
+__device__ __forceinline__ void merge_lane(double* top, int d) {
+    const double o0 = __shfl_xor(top[0], d, kWave), o1 = __shfl_xor(top[1], d, kWave);
+    const double o2 = __shfl_xor(top[2], d, kWave), o3 = __shfl_xor(top[3], d, kWave);
+    merge4(top, o0, o1, o2, o3);
+}
+
+// Folds the four scores of one result register set (rows row0 + 4 r) into top.
+__device__ __forceinline__ void absorb(double* top, const doublex4& acc, unsigned row0, unsigned keep) {
+    double w0 = encode(acc[0], keep, row0), w1 = encode(acc[1], keep, row0 + 4u);
+    double w2 = encode(acc[2], keep, row0 + 8u), w3 = encode(acc[3], keep, row0 + 12u);
+    sort4(w0, w1, w2, w3);
+    merge4(top, w0, w1, w2, w3);
+}
+
+template <int KS>
+__device__ __forceinline__ void chunk_mfma(doublex4* acc, const double* a, const double (*bq)[KS]) {
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bq[t][s], acc[t], 0, 0, 0);
     }
-    __device__ __forceinline__ void push(double v, int i) {
-        if (!(v < v3)) return;
-        if (v < v2) {
-            v3 = v2;
-            i3 = i2;
-            if (v < v1) {
-                v2 = v1;
-                i2 = i1;
-                if (v < v0) {
-                    v1 = v0;
-                    i1 = i0;
-                    v0 = v;
-                    i0 = i;
-                } else {
-                    v1 = v;
-                    i1 = i;
-                }
-            } else {
-                v2 = v;
-                i2 = i;
-            }
-        } else {
-            v3 = v;
-            i3 = i;
+}
+
+// A packed chunk (4 KS x 16 doubles, k-major) moves through LDS in 16-byte
+// pieces: each thread of the block stages kPieces of them in registers.  The
+// loads are raw buffer loads on a descriptor that spans the partner's packed
+// rows: they keep their place before the products (plain global loads get
+// sunk to their first use), and an offset past the range reads zeros instead
+// of faulting.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr unsigned kBufferWord3 = 0x00020000u;  // raw buffer, 32-bit data format (gfx9)
+
+template <int KS>
+struct ChunkStage {
+    static constexpr int kPiecesPerChunk = 4 * KS * kTileRows / 2;
+    static constexpr int kPieces = (kPiecesPerChunk + kBlock - 1) / kBlock;
+    double2 r[kPieces];
+    // indices past the chunk are clamped: those threads load and store the last piece again
+    __device__ __forceinline__ static int piece(int e) {
+        return min(static_cast<int>(threadIdx.x) + e * kBlock, kPiecesPerChunk - 1);
+    }
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rows, int chunk) {
+#pragma unroll
+        for (int e = 0; e < kPieces; ++e) {
+            const int off = (chunk * kPiecesPerChunk + piece(e)) * 16;
+            r[e] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rows, off, 0, 0));
         }
+    }
+    __device__ __forceinline__ void store(double2* buf) const {
+#pragma unroll
+        for (int e = 0; e < kPieces; ++e) buf[piece(e)] = r[e];
     }
 };
 
-// (value, index) order used wherever lists are merged: deterministic.
-__device__ __forceinline__ bool before(double va, int ia, double vb, int ib) {
-    return va < vb || (va == vb && static_cast<unsigned>(ia) < static_cast<unsigned>(ib));
-}
-
-// Insertion into a sorted Top4 under the (value, index) order.
-__device__ __forceinline__ void push_ordered(Top4& t, double v, int ix) {
-    if (!before(v, ix, t.v3, t.i3)) return;
-    if (before(v, ix, t.v2, t.i2)) {
-        t.v3 = t.v2;
-        t.i3 = t.i2;
-        if (before(v, ix, t.v1, t.i1)) {
-            t.v2 = t.v1;
-            t.i2 = t.i1;
-            if (before(v, ix, t.v0, t.i0)) {
-                t.v1 = t.v0;
-                t.i1 = t.i0;
-                t.v0 = v;
-                t.i0 = ix;
-            } else {
-                t.v1 = v;
-                t.i1 = ix;
-            }
-        } else {
-            t.v2 = v;
-            t.i2 = ix;
-        }
-    } else {
-        t.v3 = v;
-        t.i3 = ix;
-    }
-}
-
-// Merges the top-4 list of lane l ^ d into this lane's list.
-__device__ __forceinline__ void merge_lanes(Top4& t, int d) {
-    const double v0 = __shfl_xor(t.v0, d, kWave), v1 = __shfl_xor(t.v1, d, kWave);
-    const double v2 = __shfl_xor(t.v2, d, kWave), v3 = __shfl_xor(t.v3, d, kWave);
-    const int i0 = __shfl_xor(t.i0, d, kWave), i1 = __shfl_xor(t.i1, d, kWave);
-    const int i2 = __shfl_xor(t.i2, d, kWave), i3 = __shfl_xor(t.i3, d, kWave);
-    push_ordered(t, v0, i0);
-    push_ordered(t, v1, i1);
-    push_ordered(t, v2, i2);
-    push_ordered(t, v3, i3);
-}
-
-// One wave: 64 query columns of set qc (local columns col0 ..) against the
-// partner's chunks [c_begin, c_end) (partner-local chunk indices).  The packed
-// depth is exactly 4 KS, and chunk indices are clamped rather than branched
-// on, so every operand load is unconditional and the loads of a chunk issue
-// back to back.
+// One block: four waves of 64 query columns each (set qc, local columns from
+// col0) against the partner's chunks [c_begin, c_end).  The chunk sequence is
+// shared by the four waves through a double-buffered LDS stage: the global
+// loads of chunk c + 1 issue before the products of chunk c and land in LDS
+// after them, one barrier per chunk.  The list update of chunk c - 1 is
+// independent of the products of chunk c, so it issues while the matrix core
+// works.  Query chunks past the set's end are clamped to its last chunk (their
+// columns are >= n and never written), so every wave runs the same loop.
 template <int KS>
-__device__ __forceinline__ void tile_wave(const double* __restrict__ pk, int dim, const SetPlan& qc,
-                                          const SetPlan& pc, int col0, int c_begin, int c_end, int seg,
-                                          double* __restrict__ part_v, int32_t* __restrict__ part_i) {
+__device__ __forceinline__ void tile_block(const double* __restrict__ pk, int dim, const SetPlan& qc,
+                                           const SetPlan& pc, int col0, int c_begin, int c_end, int seg,
+                                           double* __restrict__ part, double2* lds) {
     constexpr int kp = 4 * KS;
+    constexpr int kChunk = kp * kTileRows;  // doubles per packed chunk
     const int lane = lane_id();
     const int g = lane >> 4;  // k offset within a step for the operands; row group for the result
     const int l16 = lane & 15;
-    // query operand: B[k][j] = -2 y_j[k] (k < dim), 1 (k = dim), 0 beyond.  Chunks past the
-    // set's end are clamped to its last chunk; their columns are >= n and never written.
+    // query operand: B[k][j] = -2 y_j[k] (k < dim), 1 (k = dim), 0 beyond
     double bq[kTilesPerWave][KS];
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) {
         const int chunk = min(col0 / kTileCols + t, qc.chunks - 1);
-        const double* src = pk + static_cast<int64_t>(qc.chunk_off + chunk) * kp * kTileRows;
+        const double* src = pk + static_cast<int64_t>(qc.chunk_off + chunk) * kChunk;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
+            // arithmetic rather than a select, so that the load is never predicated
             const int k = 4 * s + g;
-            const double v = src[k * kTileRows + l16];
-            bq[t][s] = (k < dim) ? -2.0 * v : (k == dim ? 1.0 : 0.0);
+            const double scale = k < dim ? -2.0 : 0.0;
+            const double add = k == dim ? 1.0 : 0.0;
+            bq[t][s] = src[k * kTileRows + l16] * scale + add;
         }
     }
-    Top4 top[kTilesPerWave];
+    double top[kTilesPerWave][4];
 #pragma unroll
-    for (int t = 0; t < kTilesPerWave; ++t) top[t].init();
-    if (c_begin < c_end) {
-        // the A operand of chunk c + 1 is loaded while chunk c is multiplied
-        double a_next[KS];
-        {
-            const double* src = pk + static_cast<int64_t>(pc.chunk_off + c_begin) * kp * kTileRows + lane;
+    for (int t = 0; t < kTilesPerWave; ++t) top[t][0] = top[t][1] = top[t][2] = top[t][3] = INFINITY;
+    const unsigned keep = keep_mask(row_bits(pc.chunks));
+    if (c_begin < c_end) {  // uniform over the block
+        // the planner flags sets whose packed rows exceed 2 GiB, the reach used for one descriptor
+        const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double*>(pk + static_cast<int64_t>(pc.chunk_off) * kChunk), 0,
+            static_cast<int>(min(static_cast<int64_t>(pc.chunks) * kChunk * 8, static_cast<int64_t>(INT32_MAX))),
+            static_cast<int>(kBufferWord3));
+        constexpr int kBuf = kChunk / 2;  // double2 per LDS buffer
+        const double* lds_d = reinterpret_cast<const double*>(lds);
+        ChunkStage<KS> stage;
+        stage.load(rows, c_begin);
+        stage.store(lds);
+        __syncthreads();
+        double a[KS];
 #pragma unroll
-            for (int s = 0; s < KS; ++s) a_next[s] = src[s * 4 * kTileRows];
-        }
-        for (int c = c_begin; c < c_end; ++c) {
-            double a[KS];
+        for (int s = 0; s < KS; ++s) a[s] = lds_d[s * 4 * kTileRows + lane];
+        stage.load(rows, min(c_begin + 1, c_end - 1));
+        doublex4 prev[kTilesPerWave];
+        chunk_mfma<KS>(prev, a, bq);
+        stage.store(lds + kBuf);
+        __syncthreads();
+        for (int c = c_begin + 1; c < c_end; ++c) {
+            const int buf = (c - c_begin) & 1;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) a[s] = a_next[s];
-            {
-                const int cn = min(c + 1, c_end - 1);
-                const double* src = pk + static_cast<int64_t>(pc.chunk_off + cn) * kp * kTileRows + lane;
-#pragma unroll
-                for (int s = 0; s < KS; ++s) a_next[s] = src[s * 4 * kTileRows];
-            }
+            for (int s = 0; s < KS; ++s) a[s] = lds_d[buf * kChunk + s * 4 * kTileRows + lane];
+            stage.load(rows, min(c + 1, c_end - 1));
+            // keep the global loads ahead of the products and the LDS stores after
+            // the list update: the load latency then hides behind a whole chunk
+            __builtin_amdgcn_sched_barrier(0);
             doublex4 acc[kTilesPerWave];
-#pragma unroll
-            for (int t = 0; t < kTilesPerWave; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-#pragma unroll
-                for (int t = 0; t < kTilesPerWave; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bq[t][s], acc[t], 0, 0, 0);
-            }
+            chunk_mfma<KS>(acc, a, bq);
             // result register r of lane l holds tile row 4 r + l / 16, column l % 16
-            const int row0 = c * kTileRows + g;
+            const unsigned row0 = static_cast<unsigned>((c - 1) * kTileRows + g);
 #pragma unroll
-            for (int t = 0; t < kTilesPerWave; ++t) {
-                const double mn = fmin(fmin(acc[t][0], acc[t][1]), fmin(acc[t][2], acc[t][3]));
-                if (mn < top[t].v3) {
+            for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], prev[t], row0, keep);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) top[t].push(acc[t][r], row0 + 4 * r);
-                }
-            }
+            for (int t = 0; t < kTilesPerWave; ++t) prev[t] = acc[t];
+            __builtin_amdgcn_sched_barrier(0);
+            stage.store(lds + (buf ^ 1) * kBuf);
+            __syncthreads();
         }
+        const unsigned row0 = static_cast<unsigned>((c_end - 1) * kTileRows + g);
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], prev[t], row0, keep);
     }
     // the four row groups of a column (lanes l, l ^ 16, l ^ 32, l ^ 48) merge their lists
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) {
-        merge_lanes(top[t], 16);
-        merge_lanes(top[t], 32);
+        merge_lane(top[t], 16);
+        merge_lane(top[t], 32);
         const int col = col0 + kTileCols * t + l16;
         if (g == 0 && col < qc.n) {
-            const int64_t base = qc.part_off + (static_cast<int64_t>(seg) * qc.n + col) * kTopK;
-            part_v[base + 0] = top[t].v0;
-            part_v[base + 1] = top[t].v1;
-            part_v[base + 2] = top[t].v2;
-            part_v[base + 3] = top[t].v3;
-            part_i[base + 0] = top[t].i0;
-            part_i[base + 1] = top[t].i1;
-            part_i[base + 2] = top[t].i2;
-            part_i[base + 3] = top[t].i3;
+            double* dst = part + qc.part_off + (static_cast<int64_t>(seg) * qc.n + col) * kTopK;
+            dst[0] = top[t][0];
+            dst[1] = top[t][1];
+            dst[2] = top[t][2];
+            dst[3] = top[t][3];
         }
     }
 }
@@ -394,11 +437,11 @@ __device__ __forceinline__ void tile_wave(const double* __restrict__ pk, int dim
 template <int KS>
 __global__ __launch_bounds__(kBlock) void topk_tiles(const SetPlan* __restrict__ plan, int n_sets,
                                                      const double* __restrict__ pk, int dim,
-                                                     double* __restrict__ part_v, int32_t* __restrict__ part_i,
-                                                     DevStatus* st) {
+                                                     double* __restrict__ part, DevStatus* st) {
+    __shared__ double2 lds[2 * 4 * KS * kTileRows / 2];
     __shared__ int s_tile;
     const int wv = threadIdx.x / kWave;
-    const int total = st->total_tiles;
+    const int total = st->err_capacity ? 0 : st->total_tiles;
     while (true) {
         if (threadIdx.x == 0) s_tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
         __syncthreads();
@@ -415,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void topk_tiles(const SetPlan* __restrict__
         const int c_begin = seg * cps;
         const int c_end = min(c_begin + cps, pc.chunks);
         const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
-        if (col0 < qc.n) tile_wave<KS>(pk, dim, qc, pc, col0, c_begin, c_end, seg, part_v, part_i);
+        tile_block<KS>(pk, dim, qc, pc, col0, c_begin, c_end, seg, part, lds);
     }
 }
 
@@ -431,65 +474,85 @@ __device__ __forceinline__ double exact_d2(const float* __restrict__ x, const fl
     return acc;
 }
 
-// One thread per query slot: merge the segment candidates, re-score the best
-// four exactly, certify or queue the query for an exact scan.
+constexpr int kQuad = 4;  // lanes per query in the re-scoring kernel
+
+// Four lanes per query slot: lane q merges the segment lists q, q + 4, ..,
+// the quad merges its lists, lane q re-scores candidate q exactly, and the
+// first lane certifies the result or queues the query for an exact scan.
 __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
-                                                  int dim, const double* __restrict__ part_v,
-                                                  const int32_t* __restrict__ part_i, const double* __restrict__ n2,
-                                                  int32_t* __restrict__ nn, double* __restrict__ best,
-                                                  double* __restrict__ second, int32_t* __restrict__ fb_list,
-                                                  DevStatus* st) {
+                                                  int dim, const double* __restrict__ part,
+                                                  const double* __restrict__ n2, int32_t* __restrict__ nn,
+                                                  double* __restrict__ best, double* __restrict__ second,
+                                                  int32_t* __restrict__ fb_list, DevStatus* st) {
     const int64_t total = st->total_queries;
-    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+    const int q = lane_id() & (kQuad - 1);
+    const int quad0 = lane_id() & ~(kQuad - 1);
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * (kBlock / kQuad);
+    for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
+         slot += gs) {
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
         const int p = c ^ 1;
         const SetPlan qc = plan[c];
         const int j = static_cast<int>(slot - qc.q_off);
         const int np = p < n_sets ? plan[p].n : 0;
         if (np == 0) {
-            nn[slot] = -1;
-            best[slot] = INFINITY;
-            second[slot] = INFINITY;
+            if (q == 0) {
+                nn[slot] = -1;
+                best[slot] = INFINITY;
+                second[slot] = INFINITY;
+            }
             continue;
         }
-        Top4 t;
-        t.init();
-        for (int sg = 0; sg < qc.segs; ++sg) {
-            const int64_t base = qc.part_off + (static_cast<int64_t>(sg) * qc.n + j) * kTopK;
-#pragma unroll
-            for (int e = 0; e < kTopK; ++e) {
-                const double v = part_v[base + e];
-                const int ix = part_i[base + e];
-                if (ix < 0 || ix >= np) continue;  // only real rows are ever candidates
-                push_ordered(t, v, ix);
-            }
+        double top[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+        for (int sg = q; sg < qc.segs; sg += kQuad) {
+            const double* src = part + qc.part_off + (static_cast<int64_t>(sg) * qc.n + j) * kTopK;
+            merge4(top, src[0], src[1], src[2], src[3]);
         }
-        const float* y = set_row(sets[c], j, dim);
-        const int cand[4] = {t.i0, t.i1, t.i2, t.i3};
+        merge_lane(top, 1);
+        merge_lane(top, 2);
+        const int bits = row_bits(plan[p].chunks);
+        const double mine = q == 0 ? top[0] : (q == 1 ? top[1] : (q == 2 ? top[2] : top[3]));
+        int row = -1;
+        if (mine < kNoScore) {
+            row = decode_row(mine, keep_mask(bits));
+            if (row >= np) row = -1;  // only real rows are ever candidates
+        }
+        const double d = row >= 0 ? exact_d2(set_row(sets[p], row, dim), set_row(sets[c], j, dim), dim) : INFINITY;
+        double dq[kQuad];
+        int rq[kQuad];
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            dq[k] = __shfl(d, quad0 + k, kWave);
+            rq[k] = __shfl(row, quad0 + k, kWave);
+        }
+        if (q != 0) continue;
         double b1 = INFINITY, b2 = INFINITY;
         int j1 = -1;
         int ncand = 0;
-        for (int r = 0; r < 4; ++r) {
-            const int i = cand[r];
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const int i = rq[k];
             if (i < 0) continue;
             ++ncand;
-            const double d = exact_d2(set_row(sets[p], i, dim), y, dim);
-            if (d < b1 || (d == b1 && i < j1)) {
+            const double dk = dq[k];
+            if (dk < b1 || (dk == b1 && i < j1)) {
                 b2 = b1;
-                b1 = d;
+                b1 = dk;
                 j1 = i;
-            } else if (d < b2) {
-                b2 = d;
+            } else if (dk < b2) {
+                b2 = dk;
             }
         }
         bool ok;
         if (ncand >= np) {
             ok = true;  // every row was a candidate
         } else {
+            // MFMA error 128 u (2 max ||x||^2 + 2 ||y||^2) plus the encoding error
+            // 2^(bits - 52) |t| with |t| <= 2 ||x||^2 + ||y||^2
             const double mx = __longlong_as_double(static_cast<long long>(plan[p].max_norm_bits));
-            const double E = 128.0 * 1.1102230246251565e-16 * (2.0 * mx + 2.0 * n2[slot]) + 1e-300;
-            const double bound = t.v3 + n2[slot] - E;
+            const double rel = 0x1p-46 + ldexp(1.0, bits - 52);
+            const double E = rel * (2.0 * mx + 2.0 * n2[slot]) + 1e-300;
+            const double bound = top[3] + n2[slot] - E;
             ok = ncand == 4 && b2 < bound;
         }
         if (ok) {
@@ -615,12 +678,12 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim) {
     w.kp = (dim + 1 <= 36) ? 36 : 68;  // 4 KS for the two kernel instantiations (dim <= 64)
     w.q_cap = std::max<int64_t>(q_cap, 1);
     w.chunk_cap = q_cap / kTileRows + n_sets + 1;
-    w.part_cap = w.q_cap * kTopK * (q_cap <= 262144 ? kMaxSegs : 4);
+    // segments are chosen so that queries x segments stays near kTargetTiles x kColsPerBlock
+    w.part_cap = kTopK * (w.q_cap + 2 * static_cast<int64_t>(kTargetTiles) * kColsPerBlock);
     w.plan = c.take<SetPlan>(static_cast<size_t>(std::max(n_sets, 1)));
     w.pk = c.take<double>(static_cast<size_t>(w.chunk_cap) * w.kp * kTileRows);
     w.n2 = c.take<double>(static_cast<size_t>(w.q_cap));
-    w.part_v = c.take<double>(static_cast<size_t>(w.part_cap));
-    w.part_i = c.take<int32_t>(static_cast<size_t>(w.part_cap));
+    w.part = c.take<double>(static_cast<size_t>(w.part_cap));
     w.nn = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.best = c.take<double>(static_cast<size_t>(w.q_cap));
     w.second = c.take<double>(static_cast<size_t>(w.q_cap));
@@ -638,7 +701,7 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
     const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.part_cap, w.plan, st);
+        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st);
         KMG_TRY(launch_status());
         row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st);
         KMG_TRY(launch_status());
@@ -649,9 +712,9 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
     {
         StageScope sc(ST_MATCH_TOPK, s);
         if (ks <= 9) {
-            topk_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, dim, w.part_v, w.part_i, st);
+            topk_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, dim, w.part, st);
         } else if (ks <= 17) {
-            topk_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, dim, w.part_v, w.part_i, st);
+            topk_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, w.pk, dim, w.part, st);
         } else {
             return KMG_ERR_ARG;
         }
@@ -659,8 +722,8 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
     }
     {
         StageScope sc(ST_MATCH_RESCORE, s);
-        rescore<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part_v, w.part_i, w.n2,
-                                                            w.nn, w.best, w.second, w.fb_list, st);
+        rescore<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2, w.nn,
+                                                                    w.best, w.second, w.fb_list, st);
         KMG_TRY(launch_status());
         exact_scan<<<grid_cap(w.q_cap, kBlock / kWave), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, st,
                                                                        w.nn, w.best, w.second);
