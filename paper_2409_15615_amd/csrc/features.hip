@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+constexpr int kBatch = 8;  // SPFH rows loaded together in the FPFH sum
 
 struct V3f {
     float x, y, z;
@@ -244,17 +245,16 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
         }
         const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
         const int b = off[q], e = off[q + 1];
-        double acc0 = 0.0, acc1 = 0.0;  // bins lane and lane + 64
+        // lanes own bins lane and lane + 64; lanes past D read bin D - 1 and are never stored
+        const int lb0 = min(lane, D - 1), lb1 = min(lane + kWave, D - 1);
+        double acc0 = 0.0, acc1 = 0.0;
         for (int base = b; base < e; base += kWave) {
-            const int t = base + lane;
-            bool use = false;
-            int k = 0;
-            double w = 0.0;
-            if (t < e) {
-                k = nbr[t];
-                use = (k != q) && (flags[k] & 1);
-                if (use) w = 1.0 / sqrt(d2_exact(qx, qy, qz, xyz[k], xyz[stride + k], xyz[s2 + k]));
-            }
+            // every load is unconditional (indices clamped), the mask applies afterwards
+            const int t = min(base + lane, e - 1);
+            const int k = nbr[t];
+            const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
+            const bool use = (base + lane < e) && (k != q) && (flags[k] & 1);
+            const double w = 1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz));
             const uint64_t bm = ballot(use);
             __builtin_amdgcn_wave_barrier();
             if (use) {
@@ -264,11 +264,28 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
             }
             __builtin_amdgcn_wave_barrier();
             const int nuse = __popcll(bm);
-            for (int j = 0; j < nuse; ++j) {
+            // eight SPFH rows in flight at a time, accumulated in ascending neighbour order
+            int j = 0;
+            for (; j + kBatch <= nuse; j += kBatch) {
+                double v0[kBatch], v1[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j + u]) * D;
+                    v0[u] = sk[lb0];
+                    v1[u] = D > kWave ? sk[lb1] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const double wj = s_w[wv][j + u];
+                    acc0 = acc0 + wj * v0[u];
+                    acc1 = acc1 + wj * v1[u];
+                }
+            }
+            for (; j < nuse; ++j) {
                 const double wj = s_w[wv][j];
                 const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j]) * D;
-                if (lane < D) acc0 = acc0 + wj * sk[lane];
-                if (lane + kWave < D) acc1 = acc1 + wj * sk[lane + kWave];
+                acc0 = acc0 + wj * sk[lb0];
+                if (D > kWave) acc1 = acc1 + wj * sk[lb1];
             }
         }
         const int P = Pq[q];

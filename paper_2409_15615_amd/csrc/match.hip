@@ -338,12 +338,11 @@ struct ChunkStage {
 
 // One block: four waves of 64 query columns each (set qc, local columns from
 // col0) against the partner's chunks [c_begin, c_end).  The chunk sequence is
-// shared by the four waves through a double-buffered LDS stage: the global
-// loads of chunk c + 1 issue before the products of chunk c and land in LDS
-// after them, one barrier per chunk.  The list update of chunk c - 1 is
-// independent of the products of chunk c, so it issues while the matrix core
-// works.  Query chunks past the set's end are clamped to its last chunk (their
-// columns are >= n and never written), so every wave runs the same loop.
+// shared by the four waves through a double-buffered LDS stage: the raw
+// buffer loads of chunk c + 1 issue before the products of chunk c and land in
+// LDS after its list update, one barrier per chunk.  Query chunks past the
+// set's end are clamped to its last chunk (their columns are >= n and never
+// written), so every wave runs the same loop.
 template <int KS>
 __device__ __forceinline__ void tile_block(const double* __restrict__ pk, int dim, const SetPlan& qc,
                                            const SetPlan& pc, int col0, int c_begin, int c_end, int seg,
@@ -384,37 +383,25 @@ __device__ __forceinline__ void tile_block(const double* __restrict__ pk, int di
         stage.load(rows, c_begin);
         stage.store(lds);
         __syncthreads();
-        double a[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) a[s] = lds_d[s * 4 * kTileRows + lane];
-        stage.load(rows, min(c_begin + 1, c_end - 1));
-        doublex4 prev[kTilesPerWave];
-        chunk_mfma<KS>(prev, a, bq);
-        stage.store(lds + kBuf);
-        __syncthreads();
-        for (int c = c_begin + 1; c < c_end; ++c) {
+        for (int c = c_begin; c < c_end; ++c) {
             const int buf = (c - c_begin) & 1;
+            double a[KS];
 #pragma unroll
             for (int s = 0; s < KS; ++s) a[s] = lds_d[buf * kChunk + s * 4 * kTileRows + lane];
             stage.load(rows, min(c + 1, c_end - 1));
-            // keep the global loads ahead of the products and the LDS stores after
-            // the list update: the load latency then hides behind a whole chunk
+            // keep the loads ahead of the products and the LDS stores after the
+            // list update: the load latency then hides behind a whole chunk
             __builtin_amdgcn_sched_barrier(0);
             doublex4 acc[kTilesPerWave];
             chunk_mfma<KS>(acc, a, bq);
             // result register r of lane l holds tile row 4 r + l / 16, column l % 16
-            const unsigned row0 = static_cast<unsigned>((c - 1) * kTileRows + g);
+            const unsigned row0 = static_cast<unsigned>(c * kTileRows + g);
 #pragma unroll
-            for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], prev[t], row0, keep);
-#pragma unroll
-            for (int t = 0; t < kTilesPerWave; ++t) prev[t] = acc[t];
+            for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], acc[t], row0, keep);
             __builtin_amdgcn_sched_barrier(0);
             stage.store(lds + (buf ^ 1) * kBuf);
             __syncthreads();
         }
-        const unsigned row0 = static_cast<unsigned>((c_end - 1) * kTileRows + g);
-#pragma unroll
-        for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], prev[t], row0, keep);
     }
     // the four row groups of a column (lanes l, l ^ 16, l ^ 32, l ^ 48) merge their lists
 #pragma unroll
@@ -434,8 +421,11 @@ __device__ __forceinline__ void tile_block(const double* __restrict__ pk, int di
 
 // Persistent tile kernel: blocks pull (set, column block, segment) tiles from
 // an atomic queue; every block leaves once the queue runs past the tile count.
+// Two waves per SIMD for the 36-deep form (the second wave covers the
+// barrier, LDS and load latencies of the first); the 68-deep form needs the
+// whole register file of one.
 template <int KS>
-__global__ __launch_bounds__(kBlock) void topk_tiles(const SetPlan* __restrict__ plan, int n_sets,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 ? 2 : 1))) void topk_tiles(const SetPlan* __restrict__ plan, int n_sets,
                                                      const double* __restrict__ pk, int dim,
                                                      double* __restrict__ part, DevStatus* st) {
     __shared__ double2 lds[2 * 4 * KS * kTileRows / 2];
