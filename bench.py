@@ -37,6 +37,32 @@ sys.path.insert(0, ROOT)
 METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency vs plain"
 PEAK_FP64_MFMA_TFLOPS = 78.6
 
+# HBM bytes per launch of the distance-tile kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 14 launches on this workload),
+# each scaled by what the same counter reads for a streaming add of 256 MiB in and
+# 256 MiB out (FETCH_SIZE 131085 KiB -> x2.0, WRITE_SIZE 262144 KiB -> x1.0).  The
+# figures hold for the matcher source with this SHA-256 only; after any change to it
+# the field is reported as null until the counters are taken again.
+TILE_TRAFFIC = {
+    "source": "paper_2409_15615_amd/csrc/match.hip",
+    "sha256": "2fb470a224084a0695f57cd54d5b5a11f62d0573364e09b3a79cdb9091605f8e",
+    "fetch_kib": 91844.0,
+    "fetch_scale": 262144.0 / 131085.4,
+    "write_kib": 28549.6,
+    "write_scale": 262144.0 / 262144.0,
+}
+
+
+def tile_traffic_bytes():
+    import hashlib
+
+    path = os.path.join(ROOT, TILE_TRAFFIC["source"])
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TILE_TRAFFIC["sha256"]:
+            return None
+    t = TILE_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def pct(xs, q):
     xs = sorted(xs)
@@ -64,6 +90,9 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--item", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the JSON line, run a streaming add over MIB MiB (read MIB, write MIB) three "
+                         "times: the reference kernel for scaling HBM counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -192,7 +221,7 @@ def main():
             "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 5),
-            "traffic": None,
+            "traffic": tile_traffic_bytes(),
             "avg_launch_ms": round(topk_avg_s * 1e3, 5),
             "flops_per_launch": flops_per_launch,
         },
@@ -217,6 +246,14 @@ def main():
         }
         out["oracle_equal_correspondences"] = gp == rp
     print(json.dumps(out), flush=True)
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src_t = torch.ones(n, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            torch.add(src_t, 1.0, out=dst_t)
+        sync()
 
 
 if __name__ == "__main__":
