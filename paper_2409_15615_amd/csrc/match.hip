@@ -51,6 +51,7 @@ constexpr int kBlock = 256;
 constexpr int kPlanThreads = 1024;
 constexpr int kTargetTiles = 4096;  // tiles wanted per launch (8 per persistent block)
 constexpr int kMaxSegs = 32;
+constexpr int kSegChunks = 64;     // deepest tile (partner chunks) once a set needs more segments
 constexpr int kTopkBlocks = 512;    // persistent grid of the tile kernel (2 blocks per CU)
 constexpr double kPadScore = 0x1p1000;  // score of padding rows: finite, so it can carry an index
 constexpr double kNoScore = 0x1p999;    // list entries at or above this are no row
@@ -126,22 +127,35 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
         int S = static_cast<int>(tb > 0 ? kTargetTiles / tb : 1);
         S = S < 1 ? 1 : (S > kMaxSegs ? kMaxSegs : S);
         if (S >= 8) S &= ~7;  // a multiple of 8: the tiles of a column block spread over the eight XCDs
-        while (S > 1 && tq * S * kTopK > part_cap) S >>= 1;
         s_segs = S;
     }
     __syncthreads();
-    // the partner's rows are split into segments (sets pair up as 2i, 2i + 1)
-    int segs = 1, tiles = 0;
-    if (live) {
-        const int p = c ^ 1;
-        const int pch = p < n_sets ? s_chunks[p] : 0;
-        const int pn = p < n_sets ? s_n[p] : 0;
+    // the partner's rows are split into segments (sets pair up as 2i, 2i + 1): at least the
+    // common count, and enough that no tile sweeps more than kSegChunks chunks, so the tiles
+    // of uneven batches stay comparable in size
+    const int p = c ^ 1;
+    const int pch = (live && p < n_sets) ? s_chunks[p] : 0;
+    const int pn = (live && p < n_sets) ? s_n[p] : 0;
+    const int deep = (pch + kSegChunks - 1) / kSegChunks;
+    int segs = s_segs > deep ? s_segs : deep;
+    segs = segs < pch ? segs : (pch > 0 ? pch : 1);
+    int64_t tpart;
+    block_excl_scan64(live ? static_cast<int64_t>(n) * segs * kTopK : 0, smem, tpart);
+    if (tpart > part_cap) {
+        // too many partial lists for the buffer: one common count, halved until they fit
+        // (one segment per set always fits, the buffer holds kTopK entries per query)
+        if (c == 0) {
+            int S = s_segs;
+            while (S > 1 && tq * S * kTopK > part_cap) S >>= 1;
+            s_segs = S;
+        }
+        __syncthreads();
         segs = s_segs < pch ? s_segs : (pch > 0 ? pch : 1);
-        tiles = pn > 0 ? cblocks * segs : 0;
     }
-    int64_t tt, tpart;
+    const int tiles = (live && pn > 0) ? cblocks * segs : 0;
+    int64_t tt;
     const int64_t t_off = block_excl_scan64(tiles, smem, tt);
-    const int64_t p_off = block_excl_scan64(static_cast<int64_t>(n) * segs * kTopK, smem, tpart);
+    const int64_t p_off = block_excl_scan64(live ? static_cast<int64_t>(n) * segs * kTopK : 0, smem, tpart);
     if (live) {
         SetPlan pl;
         pl.n = n;
