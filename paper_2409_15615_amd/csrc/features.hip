@@ -6,10 +6,10 @@
 //
 // SPFH: one wavefront per point q; lanes take the neighbours k of q, 64 at a
 // time.  Each lane computes the three features of (q, k) in FP32 and bins
-// them; a feature set that lies within a guard band of a bin edge, of the
-// a/b selection tie, or of an ill-conditioned frame is recomputed in FP64
-// with the operation order of the plain definition, so the bins equal the
-// FP64 definition's.  Bin counts are formed with one ballot + popcount per
+// them; a feature set that lies within a guard band of a bin edge or of an
+// ill-conditioned frame, or near the a/b selection tie with the two role
+// assignments binning differently, is recomputed in FP64 with the operation
+// order of the plain definition, so the bins equal the FP64 definition's.  Bin counts are formed with one ballot + popcount per
 // (feature, bin): no atomics, deterministic.  SPFH values 100 * c / P_q are
 // kept in FP64 for the FPFH pass.
 //
@@ -40,18 +40,12 @@ __device__ __forceinline__ V3f crossf(V3f a, V3f b) {
 }
 __device__ __forceinline__ V3f scalef(V3f a, float s) { return {a.x * s, a.y * s, a.z * s}; }
 
-// FP32 features and bins.  Returns false when any decision is too close to
-// call in FP32: the a/b tie (|n_q.d0| vs |n_k.d0| within 1e-5 ||d0||), a
-// short frame axis (||d x u|| < 0.2), a near-degenerate f1 argument
-// (|(w.n_b, u.n_b)| < 0.2), or a scaled feature within 2e-4 of an integer.
-// The FP32 error of the scaled features is below 2e-5 outside those cases.
-__device__ __forceinline__ bool bins_f32(V3f pq, V3f nq, V3f pk, V3f nk, int H, int bins[3]) {
-    const V3f d0 = sub(pk, pq);
-    const float aq = fabsf(dotf(nq, d0));
-    const float ak = fabsf(dotf(nk, d0));
-    const float dl = sqrtf(dotf(d0, d0));
-    if (fabsf(aq - ak) <= 1e-5f * dl) return false;
-    const bool qa = aq >= ak;
+// FP32 features and bins for a given role assignment (qa: a = q, b = k).
+// Returns false when a decision is too close to call in FP32: a short frame
+// axis (||d x u|| < 0.2), a near-degenerate f1 argument (|(w.n_b, u.n_b)| <
+// 0.2), or a scaled feature within 2e-4 of an integer.  The FP32 error of the
+// scaled features is below 2e-5 outside those cases.
+__device__ __forceinline__ bool bins_f32_roles(V3f d0, float dl, V3f nq, V3f nk, bool qa, int H, int bins[3]) {
     const V3f u = qa ? nq : nk;
     const V3f nb = qa ? nk : nq;
     const V3f d = scalef(d0, (qa ? 1.0f : -1.0f) / dl);
@@ -72,6 +66,24 @@ __device__ __forceinline__ bool bins_f32(V3f pq, V3f nq, V3f pk, V3f nk, int H, 
         bins[l] = min(max(static_cast<int>(floorf(s)), 0), H - 1);
     }
     return true;
+}
+
+// FP32 features and bins.  The a/b roles follow the unsigned angle; when
+// |n_q.d0| and |n_k.d0| lie within 1e-5 ||d0|| of each other (coplanar
+// neighbours with nearly equal normals, the common case on planes) both role
+// assignments are evaluated, and if both are reliable and give the same bins,
+// the bins are those of either FP64 decision.  Returns false when the FP64
+// path has to decide.
+__device__ __forceinline__ bool bins_f32(V3f pq, V3f nq, V3f pk, V3f nk, int H, int bins[3]) {
+    const V3f d0 = sub(pk, pq);
+    const float aq = fabsf(dotf(nq, d0));
+    const float ak = fabsf(dotf(nk, d0));
+    const float dl = sqrtf(dotf(d0, d0));
+    if (fabsf(aq - ak) > 1e-5f * dl) return bins_f32_roles(d0, dl, nq, nk, aq >= ak, H, bins);
+    int other[3];
+    if (!bins_f32_roles(d0, dl, nq, nk, true, H, bins)) return false;
+    if (!bins_f32_roles(d0, dl, nq, nk, false, H, other)) return false;
+    return bins[0] == other[0] && bins[1] == other[1] && bins[2] == other[2];
 }
 
 __device__ __forceinline__ double dotd(const double a[3], const double b[3]) {

@@ -571,15 +571,30 @@ __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ s
     }
 }
 
-// One wavefront per queued query: exact FP64 scan over all partner rows.
+// Combines two (best, its index, second) triples: smallest (b1, j1) first;
+// the second is the smallest of the other best and both seconds.
+__device__ __forceinline__ void combine_best(double& b1, int& j1, double& b2, double ob1, int oj1, double ob2) {
+    const bool mine = (b1 < ob1) || (b1 == ob1 && j1 < oj1);
+    const double nb2 = mine ? fmin(b2, ob1) : fmin(ob2, b1);
+    if (!mine) {
+        b1 = ob1;
+        j1 = oj1;
+    }
+    b2 = nb2;
+}
+
+// One block per queued query: exact FP64 scan over all partner rows.
 __global__ __launch_bounds__(kBlock) void exact_scan(const MatchSet* __restrict__ sets,
                                                      const SetPlan* __restrict__ plan, int n_sets, int dim,
                                                      const int32_t* __restrict__ fb_list, const DevStatus* st,
                                                      int32_t* __restrict__ nn, double* __restrict__ best,
                                                      double* __restrict__ second) {
+    __shared__ double s_b1[kBlock / kWave], s_b2[kBlock / kWave];
+    __shared__ int s_j1[kBlock / kWave];
     const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
     const int nfb = static_cast<int>(st->n_fallback);
-    for (int w = global_wave(); w < nfb; w += wave_count()) {
+    for (int w = blockIdx.x; w < nfb; w += gridDim.x) {
         const int64_t slot = fb_list[w];
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
         const int p = c ^ 1;
@@ -588,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void exact_scan(const MatchSet* __restrict_
         const float* y = set_row(sets[c], j, dim);
         double b1 = INFINITY, b2 = INFINITY;
         int j1 = INT32_MAX;
-        for (int i = lane; i < np; i += kWave) {  // ascending per lane
+        for (int i = threadIdx.x; i < np; i += kBlock) {  // ascending per thread
             const double d = exact_d2(set_row(sets[p], i, dim), y, dim);
             if (d < b1) {
                 b2 = b1;
@@ -598,25 +613,26 @@ __global__ __launch_bounds__(kBlock) void exact_scan(const MatchSet* __restrict_
                 b2 = d;
             }
         }
-        // combine lanes: smallest (b1, j1); second = min of the other b1s and all b2s
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) {
             const double ob1 = __shfl_xor(b1, d, kWave);
             const double ob2 = __shfl_xor(b2, d, kWave);
             const int oj1 = __shfl_xor(j1, d, kWave);
-            const bool mine = (b1 < ob1) || (b1 == ob1 && j1 < oj1);
-            const double nb2 = mine ? fmin(b2, ob1) : fmin(ob2, b1);
-            if (!mine) {
-                b1 = ob1;
-                j1 = oj1;
-            }
-            b2 = nb2;
+            combine_best(b1, j1, b2, ob1, oj1, ob2);
         }
         if (lane == 0) {
+            s_b1[wv] = b1;
+            s_b2[wv] = b2;
+            s_j1[wv] = j1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int o = 1; o < kBlock / kWave; ++o) combine_best(b1, j1, b2, s_b1[o], s_j1[o], s_b2[o]);
             nn[slot] = (j1 == INT32_MAX) ? -1 : j1;
             best[slot] = b1;
             second[slot] = b2;
         }
+        __syncthreads();
     }
 }
 
@@ -729,8 +745,8 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
         rescore<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2, w.nn,
                                                                     w.best, w.second, w.fb_list, st);
         KMG_TRY(launch_status());
-        exact_scan<<<grid_cap(w.q_cap, kBlock / kWave), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, st,
-                                                                       w.nn, w.best, w.second);
+        exact_scan<<<grid_cap(w.q_cap, 1), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, st, w.nn, w.best,
+                                                          w.second);
         KMG_TRY(launch_status());
     }
     {
