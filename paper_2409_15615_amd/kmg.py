@@ -341,11 +341,13 @@ class PairResult:
 
 
 class Batch:
-    """A reusable batch of `n_pairs` registration pairs with fixed capacities.
+    """A reusable batch of up to `n_pairs` registration pairs with fixed capacities.
 
     Owns the workspace, the per-pair output buffers and the device counts;
-    `upload` writes a new cloud table, `run` enqueues kmg_batch_run on the
-    current stream (capturable in a graph), `results` reads the counts back."""
+    `upload` writes a new cloud table (any number of pairs up to `n_pairs`;
+    the workspace layout of fewer pairs fits inside that of more), `run`
+    enqueues kmg_batch_run on the current stream (capturable in a graph),
+    `results` reads the counts back."""
 
     def __init__(self, n_pairs, raw_cap, nnz_cap, n_bins=11, out_cap=None, device=None):
         lib = load()
@@ -360,13 +362,15 @@ class Batch:
         self.d1 = torch.empty((self.n_pairs, self.out_cap), dtype=torch.float32, device=self.device)
         self.d2 = torch.empty((self.n_pairs, self.out_cap), dtype=torch.float32, device=self.device)
         self.counts = torch.zeros((self.n_pairs, COUNTS_STRIDE), dtype=torch.int64, device=self.device)
+        self.n_active = self.n_pairs
         self._keep = []
 
     def upload(self, clouds):
         """clouds: list of 2 * n_pairs (xyz (3, n) float32 device tensor, KmgParams)."""
         lib = load()
-        if len(clouds) != 2 * self.n_pairs:
-            raise ValueError("need two clouds per pair")
+        if len(clouds) % 2 or not 0 < len(clouds) // 2 <= self.n_pairs:
+            raise ValueError(f"need two clouds per pair and 1..{self.n_pairs} pairs")
+        n_active = len(clouds) // 2
         ct = (KmgCloud * len(clouds))()
         total = 0
         for k, (xyz, prm) in enumerate(clouds):
@@ -377,19 +381,20 @@ class Batch:
             total += xyz.shape[1]
         if total > self.raw_cap:
             raise ValueError(f"batch has {total} raw points, capacity {self.raw_cap}")
-        ot = (KmgMatchOut * self.n_pairs)()
-        for i in range(self.n_pairs):
+        ot = (KmgMatchOut * n_active)()
+        for i in range(n_active):
             ot[i].pairs = self.pairs[i].data_ptr()
             ot[i].d1 = self.d1[i].data_ptr()
             ot[i].d2 = self.d2[i].data_ptr()
             ot[i].cap = self.out_cap
         self._keep = list(clouds)
-        _raise("kmg_batch_upload", lib.kmg_batch_upload(ct, ot, self.n_pairs, self.raw_cap, self.nnz_cap,
+        _raise("kmg_batch_upload", lib.kmg_batch_upload(ct, ot, n_active, self.raw_cap, self.nnz_cap,
                                                         _ptr(self.ws), self.ws.numel(), _stream()))
+        self.n_active = n_active
 
     def run(self, prec="fp32"):
         lib = load()
-        _raise("kmg_batch_run", lib.kmg_batch_run(self.n_pairs, self.raw_cap, self.nnz_cap, self.n_bins,
+        _raise("kmg_batch_run", lib.kmg_batch_run(self.n_active, self.raw_cap, self.nnz_cap, self.n_bins,
                                                   PRECISIONS[prec], _ptr(self.counts), _ptr(self.ws),
                                                   self.ws.numel(), _stream()))
 
@@ -397,7 +402,7 @@ class Batch:
         """Reads the counts (synchronises the current stream) -> list of PairResult."""
         cnt = self.counts.cpu().numpy()
         out = []
-        for i in range(self.n_pairs):
+        for i in range(self.n_active):
             k = int(min(cnt[i, 0], self.out_cap))
             out.append(PairResult(self.pairs[i, :k], self.d1[i, :k], self.d2[i, :k],
                                   (int(cnt[i, 1]), int(cnt[i, 2])), (int(cnt[i, 3]), int(cnt[i, 4])),

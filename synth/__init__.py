@@ -26,4 +26,6 @@ from .scenes import (  # noqa: F401
     lattice_pair,
     synthetic_descriptors,
     c4_trace,
+    c4_pool,
+    c4_requests,
 )

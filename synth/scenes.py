@@ -302,11 +302,13 @@ def _raw_for_kept(m_target, area, v):
     return int(math.ceil(-cells * math.log1p(-m_target / cells)))
 
 
-def indoor_pair(config: int, item: int, m_target: int, v: float = 0.025) -> dict:
+def indoor_pair(config: int, item: int, m_target: int, v: float = 0.025, n_raw: int = 0) -> dict:
+    """Indoor room pair; the raw count follows m_target unless n_raw is given."""
     rng = rng_for(config, item)
     _, _, area = indoor_scene(rng_for(config, item, 1), 16)  # size-probe draw of the same room
     rng_room = rng_for(config, item, 1)
-    n_raw = _raw_for_kept(m_target, area, v)
+    if n_raw <= 0:
+        n_raw = _raw_for_kept(m_target, area, v)
     src, vp, _ = indoor_scene(rng_room, n_raw)
     R = random_rotation(rng)
     t = rng.uniform(-1.0, 1.0, 3)
@@ -438,3 +440,34 @@ def c4_trace(rate: float, n_requests: int = 2000, warmup: int = 200, config: int
     sizes = np.round(np.exp(rng.uniform(math.log(1000), math.log(120000), total))).astype(int)
     kinds = rng.integers(0, 2, total)  # 0 indoor, 1 lidar
     return arrivals, sizes, kinds
+
+
+def c4_pool(n_each: int = 6, config: int = 4) -> dict:
+    """Base pairs for serving requests: n_each LiDAR pairs (64 x 1,875 rays, voxel
+    0.3 m) and n_each indoor room pairs of 120,000 raw points per cloud."""
+    return {
+        0: [indoor_pair(config, 100 + i, 0, n_raw=120000) for i in range(n_each)],
+        1: [lidar_pair(config, 200 + i, 0.3) for i in range(n_each)],
+    }
+
+
+def c4_requests(rate: float, n_requests: int = 2000, warmup: int = 200, config: int = 4, pool=None) -> list:
+    """Requests of the Poisson trace at `rate`: request i takes base pair i of its
+    kind (cycling through the pool) and keeps a seeded random subset of n_i raw
+    points of each cloud, in their original order."""
+    pool = c4_pool(config=config) if pool is None else pool
+    arrivals, sizes, kinds = c4_trace(rate, n_requests, warmup, config)
+    out = []
+    for i in range(len(arrivals)):
+        base = pool[int(kinds[i])][i % len(pool[int(kinds[i])])]
+        rng = rng_for(config, int(rate), 1 + i)
+        req = dict(arrival=float(arrivals[i]), kind=int(kinds[i]), params=base["params"],
+                   vp_src=base["vp_src"], vp_tgt=base["vp_tgt"], warmup=i < warmup)
+        for key in ("src", "tgt"):
+            n_all = base[key].shape[1]
+            n = int(min(sizes[i], n_all))
+            sel = np.sort(rng.choice(n_all, size=n, replace=False))
+            req[key] = np.ascontiguousarray(base[key][:, sel])
+        out.append(req)
+    return out
+
