@@ -71,8 +71,13 @@ enum {
     KMG_OP_VOXELIZE = 0, /* n0 = raw points */
     KMG_OP_NORMALS = 1,  /* n0 = kept points m */
     KMG_OP_FPFH = 2,     /* n0 = kept points m */
-    KMG_OP_MATCH = 3     /* n0 = rows of P (np), n1 = rows of Q (nq) */
+    KMG_OP_MATCH = 3,    /* n0 = rows of P (np), n1 = rows of Q (nq) */
+    KMG_OP_GRAPH = 4,    /* n0 = correspondences, n1 = N_tau */
+    KMG_OP_KCORE = 5     /* n0 = graph vertices */
 };
+
+/* Largest graph kmg_max_kcore accepts (its state lives in on-chip memory). */
+#define KMG_MAX_KCORE_VERTICES 8192
 
 /* Workspace size in bytes needed by `op` for the given sizes (a host call;
  * touches no device).  For KMG_OP_MATCH the descriptor length is
@@ -249,6 +254,42 @@ kmg_status kmg_batch_run(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int3
 kmg_status kmg_register_batch(const kmg_cloud* clouds, const kmg_match_out* outs, int32_t n_pairs,
                               int64_t raw_cap, int64_t nnz_cap, int32_t prec, int64_t* counts, void* ws,
                               size_t ws_bytes, void* stream);
+
+/*
+ * Downstream of matching, Section III-D: the ratio filter, the pairwise-
+ * invariant compatibility graph of Eq. (3), and its maximum k-core.
+ *
+ * kmg_corr_graph: src_xyz / tgt_xyz are the kept clouds (device float32 SoA,
+ * 3 x m_src and 3 x m_tgt); pairs (device int32[n_corr * 2]), d1 and d2
+ * (device float32[n_corr]) are a correspondence set as kmg_match writes it.
+ * The n_sel = min(n_corr, n_tau) correspondences with the lowest ratio d1/d2
+ * (computed in FP64; 0 when d1 = d2 = 0, +inf when only d2 = 0; ties by
+ * position) become the graph's vertices in that order: sel[v] (device
+ * int32[n_tau]) is the correspondence of vertex v.  Vertices u != v are
+ * adjacent iff | ||b_u - b_v|| - ||a_u - a_v|| | <= 2 beta (Eq. 3) with both
+ * norms in FP64 from the float32 coordinates, a = source point, b = target
+ * point of the correspondence.  The graph is written as CSR: off (device
+ * int32[n_tau + 1], off[n_sel] = nnz) and adj (device int32[adj_cap]), every
+ * row ascending, no self loops.  The caller owns every buffer.  *n_sel and
+ * *nnz are host pointers (the call synchronises the stream); when
+ * nnz > adj_cap, *nnz is the needed capacity, adj is untouched and the call
+ * returns KMG_ERR_CAPACITY.  Correspondence indices outside [0, m) give
+ * KMG_ERR_RANGE.  Requires 1 <= n_tau <= KMG_MAX_KCORE_VERTICES and
+ * beta > 0.
+ *
+ * kmg_max_kcore: core numbers of the graph (off, adj) on n vertices
+ * (n <= KMG_MAX_KCORE_VERTICES; adj entries in [0, n), rows need not be
+ * sorted): core (device int32[n]); members (device int32[n]) receives the
+ * vertices of the maximum k-core, ascending, *n_members (host) their count and
+ * *max_core (host) the largest core number (-1 for n = 0).  An adj entry
+ * outside [0, n) gives KMG_ERR_RANGE.  Synchronises the stream.
+ */
+kmg_status kmg_corr_graph(const float* src_xyz, int64_t m_src, const float* tgt_xyz, int64_t m_tgt,
+                          const int32_t* pairs, const float* d1, const float* d2, int64_t n_corr, int32_t n_tau,
+                          double beta, int32_t* sel, int32_t* off, int32_t* adj, int64_t adj_cap, int32_t* n_sel,
+                          int64_t* nnz, void* ws, size_t ws_bytes, void* stream);
+kmg_status kmg_max_kcore(const int32_t* off, const int32_t* adj, int32_t n, int32_t* core, int32_t* members,
+                         int32_t* n_members, int32_t* max_core, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -25,14 +25,18 @@ def ratio_filter(d1, d2, n_tau: int = 3000):
     return order[:n_tau]
 
 
+def _pair_norms(p):
+    """||p_u - p_v|| for all u, v, summed as (dx dx + dy dy) + dz dz in FP64."""
+    d = p[:, None, :] - p[None, :, :]
+    return np.sqrt((d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2])
+
+
 def compat_graph(a, b, beta: float):
     """Adjacency (boolean, no self loops) of Eq. (3):
     | ||b_j - b_j'|| - ||a_i - a_i'|| | <= 2 beta.  a, b are (k, 3)."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
-    da = np.linalg.norm(a[:, None, :] - a[None, :, :], axis=2)
-    db = np.linalg.norm(b[:, None, :] - b[None, :, :], axis=2)
-    adj = np.abs(db - da) <= 2.0 * beta
+    adj = np.abs(_pair_norms(b) - _pair_norms(a)) <= 2.0 * beta
     np.fill_diagonal(adj, False)
     return adj
 

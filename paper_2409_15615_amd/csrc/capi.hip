@@ -48,6 +48,12 @@ KMG_EXPORT size_t kmg_workspace_bytes(int32_t op, int64_t n0, int64_t n1, const 
         case KMG_OP_NORMALS: return kmg::normals_ws(n0);
         case KMG_OP_FPFH: return kmg::fpfh_ws(n0, p ? p->n_bins : 11);
         case KMG_OP_MATCH: return kmg::match_ws(n0, n1, p ? 3 * p->n_bins : 33);
+        case KMG_OP_GRAPH:
+            if (n1 < 1 || n1 > KMG_MAX_KCORE_VERTICES) return 0;
+            return kmg::graph_ws(n0, static_cast<int32_t>(n1));
+        case KMG_OP_KCORE:
+            if (n0 > KMG_MAX_KCORE_VERTICES) return 0;
+            return kmg::kcore_ws(static_cast<int32_t>(n0));
         default: return 0;
     }
 }
@@ -151,3 +157,28 @@ KMG_EXPORT kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int6
 }
 
 }  // extern "C"
+
+KMG_EXPORT kmg_status kmg_corr_graph(const float* src_xyz, int64_t m_src, const float* tgt_xyz, int64_t m_tgt,
+                                     const int32_t* pairs, const float* d1, const float* d2, int64_t n_corr,
+                                     int32_t n_tau, double beta, int32_t* sel, int32_t* off, int32_t* adj,
+                                     int64_t adj_cap, int32_t* n_sel, int64_t* nnz, void* ws, size_t ws_bytes,
+                                     void* stream) {
+    if (!n_sel || !nnz || !off || !ws) return KMG_ERR_ARG;
+    if (n_corr < 0 || n_corr > INT32_MAX || m_src < 0 || m_tgt < 0 || adj_cap < 0) return KMG_ERR_ARG;
+    if (n_tau < 1 || n_tau > KMG_MAX_KCORE_VERTICES || !(beta > 0.0) || !isfinite(beta)) return KMG_ERR_ARG;
+    if (n_corr > 0 && (!src_xyz || !tgt_xyz || !pairs || !d1 || !d2 || !sel || m_src == 0 || m_tgt == 0))
+        return KMG_ERR_ARG;
+    if (adj_cap > 0 && !adj) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::graph_ws(n_corr, n_tau)) return KMG_ERR_WORKSPACE;
+    return kmg::corr_graph(src_xyz, m_src, tgt_xyz, m_tgt, pairs, d1, d2, n_corr, n_tau, beta, sel, off, adj,
+                           adj_cap, n_sel, nnz, ws, ws_bytes, as_stream(stream));
+}
+
+KMG_EXPORT kmg_status kmg_max_kcore(const int32_t* off, const int32_t* adj, int32_t n, int32_t* core,
+                                    int32_t* members, int32_t* n_members, int32_t* max_core, void* ws,
+                                    size_t ws_bytes, void* stream) {
+    if (!n_members || !max_core || !ws || n < 0 || n > KMG_MAX_KCORE_VERTICES) return KMG_ERR_ARG;
+    if (n > 0 && (!off || !core || !members)) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::kcore_ws(n)) return KMG_ERR_WORKSPACE;
+    return kmg::max_kcore(off, adj, n, core, members, n_members, max_core, ws, ws_bytes, as_stream(stream));
+}

@@ -295,6 +295,16 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim);
 kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                        const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s);
 
+// ---- graph.hip: ratio filter, Eq. (3) graph, max k-core ----------------------
+size_t graph_ws(int64_t n_corr, int32_t n_tau);
+size_t kcore_ws(int32_t n);
+kmg_status corr_graph(const float* src, int64_t src_stride, const float* tgt, int64_t tgt_stride,
+                      const int32_t* pairs, const float* d1, const float* d2, int64_t n_corr, int32_t n_tau,
+                      double beta, int32_t* sel, int32_t* off, int32_t* adj, int64_t adj_cap, int32_t* n_sel_host,
+                      int64_t* nnz_host, void* ws, size_t ws_bytes, hipStream_t s);
+kmg_status max_kcore(const int32_t* off, const int32_t* adj, int32_t n, int32_t* core, int32_t* members,
+                     int32_t* n_members_host, int32_t* max_core_host, void* ws, size_t ws_bytes, hipStream_t s);
+
 // ---- stages.hip: single-cloud entry points --------------------------------
 size_t voxelize_ws(int64_t n);
 kmg_status voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz, int64_t cap,

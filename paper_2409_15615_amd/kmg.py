@@ -25,7 +25,7 @@ KMG_ERR_RANGE = -4
 KMG_ERR_WORKSPACE = -5
 
 KMG_FP32, KMG_BF16, KMG_FP16 = 0, 1, 2
-OP_VOXELIZE, OP_NORMALS, OP_FPFH, OP_MATCH = 0, 1, 2, 3
+OP_VOXELIZE, OP_NORMALS, OP_FPFH, OP_MATCH, OP_GRAPH, OP_KCORE = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp32": KMG_FP32, "bf16": KMG_BF16, "fp16": KMG_FP16}
 
 
@@ -92,6 +92,12 @@ def load():
     lib.kmg_batch_run.restype = i32
     lib.kmg_register_batch.argtypes = [cp, op, i32, i64, i64, i32, vp, vp, sz, vp]
     lib.kmg_register_batch.restype = i32
+    i32p = C.POINTER(C.c_int32)
+    lib.kmg_corr_graph.argtypes = [vp, i64, vp, i64, vp, vp, vp, i64, i32, dbl, vp, vp, vp, i64, i32p, i64p, vp, sz,
+                                   vp]
+    lib.kmg_corr_graph.restype = i32
+    lib.kmg_max_kcore.argtypes = [vp, vp, i32, vp, vp, i32p, i32p, vp, sz, vp]
+    lib.kmg_max_kcore.restype = i32
     lib.kmg_timing_enable.argtypes = [i32]
     lib.kmg_timing_enable.restype = i32
     lib.kmg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
@@ -288,6 +294,64 @@ def match(desc_p, desc_q, rows_p=None, rows_q=None, prec="fp32", ws=None):
     _raise("kmg_match", st)
     k = npairs.value
     return MatchOut(pairs[:k], d1[:k], d2[:k], nfb.value)
+
+
+@dataclass
+class GraphOut:
+    sel: torch.Tensor   # (n,) int32: correspondence of each vertex
+    off: torch.Tensor   # (n + 1,) int32
+    adj: torch.Tensor   # (nnz,) int32, rows ascending
+
+
+def corr_graph(src_xyz, tgt_xyz, pairs, d1, d2, n_tau=3000, beta=0.45, ws=None):
+    """kmg_corr_graph: ratio filter to n_tau correspondences, Eq. (3) graph in CSR.
+    src_xyz/tgt_xyz: (3, m) float32 kept clouds; pairs (k, 2) int32; d1, d2 (k,) float32."""
+    lib = load()
+    _check_dev(src_xyz, torch.float32, "src_xyz")
+    _check_dev(tgt_xyz, torch.float32, "tgt_xyz")
+    pairs = pairs.contiguous()
+    k = int(pairs.shape[0])
+    dev = src_xyz.device
+    n_tau = int(n_tau)
+    sel = torch.empty(max(n_tau, 1), dtype=torch.int32, device=dev)
+    off = torch.empty(n_tau + 1, dtype=torch.int32, device=dev)
+    w = _ws(ws).get(int(lib.kmg_workspace_bytes(OP_GRAPH, k, n_tau, None)))
+    n_sel = C.c_int32(0)
+    nnz = C.c_int64(0)
+    cap = max(1, min(k, n_tau) * 64)
+    for _ in range(2):
+        adj = torch.empty(cap, dtype=torch.int32, device=dev)
+        st = lib.kmg_corr_graph(_ptr(src_xyz), src_xyz.shape[1], _ptr(tgt_xyz), tgt_xyz.shape[1], _ptr(pairs),
+                                _ptr(d1), _ptr(d2), k, n_tau, float(beta), _ptr(sel), _ptr(off), _ptr(adj), cap,
+                                C.byref(n_sel), C.byref(nnz), _ptr(w), w.numel(), _stream())
+        if st == KMG_ERR_CAPACITY and nnz.value > cap:
+            cap = int(nnz.value)
+            continue
+        _raise("kmg_corr_graph", st)
+        break
+    n = n_sel.value
+    return GraphOut(sel[:n], off[:n + 1], adj[:nnz.value])
+
+
+@dataclass
+class KcoreOut:
+    core: torch.Tensor     # (n,) int32 core numbers
+    members: torch.Tensor  # vertices of the maximum k-core, ascending
+    max_core: int
+
+
+def max_kcore(off, adj, n, ws=None):
+    """kmg_max_kcore on a CSR graph of n vertices (device int32 tensors)."""
+    lib = load()
+    dev = off.device
+    core = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    members = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    w = _ws(ws).get(int(lib.kmg_workspace_bytes(OP_KCORE, n, 0, None)))
+    nm = C.c_int32(0)
+    mx = C.c_int32(0)
+    _raise("kmg_max_kcore", lib.kmg_max_kcore(_ptr(off), _ptr(adj), int(n), _ptr(core), _ptr(members), C.byref(nm),
+                                              C.byref(mx), _ptr(w), w.numel(), _stream()))
+    return KcoreOut(core[:n], members[:nm.value], mx.value)
 
 
 def _match_ws_dim(np_, nq, dim):
