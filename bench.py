@@ -31,6 +31,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -296,6 +298,140 @@ def run_serve(args, lib, kmg, torch, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_c3(args, lib, kmg, torch, synth, dev):
+    """Matching of exactly 100,000 x 100,000 FPFH rows in three candidate precisions."""
+    t_gen = time.perf_counter()
+    d = synth.c3_pair(0)
+    t_gen = time.perf_counter() - t_gen
+    p = d["params"]
+    ws = kmg.Workspace(dev)
+    rows = []
+    for xyz, vp in ((d["src"], d["vp_src"]), (d["tgt"], d["vp_tgt"])):
+        prm = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, vp)
+        out = kmg.faster_pfh(torch.from_numpy(xyz).to(dev), prm, ws)
+        j = out.feats.j_idx.long()
+        if j.numel() < 100000:
+            raise RuntimeError(f"only {j.numel()} descriptor rows; need 100000")
+        pick = torch.from_numpy(np.sort(np.random.default_rng(2409).permutation(j.numel())[:100000])).to(dev)
+        rows.append(out.feats.fpfh[j[pick]].contiguous())
+    X, Y = rows
+    stats = {"max": [round(float(v), 2) for v in X.max(0).values.cpu()],
+             "mean": [round(float(v), 3) for v in X.mean(0).cpu()]}
+    sync = torch.cuda.synchronize
+    res = {}
+    ref = None
+    for prec in ("fp32", "fp16", "bf16"):
+        state = {}
+
+        def step():
+            state["m"] = kmg.match(X, Y, prec=prec, ws=ws)
+
+        step()
+        lib.kmg_timing_enable(1)
+        t, lat = timed(step, args.steps, sync)
+        names, ms, ln = read_stages(lib, args.steps)
+        lib.kmg_timing_enable(0)
+        m = state["m"]
+        if ref is None:
+            ref = m
+        same = (torch.equal(m.pairs, ref.pairs) and torch.equal(m.d1, ref.d1) and torch.equal(m.d2, ref.d2))
+        res[prec] = {"ms_per_match": round(1e3 * t / args.steps, 3),
+                     "stages_ms": {names[i]: round(ms[i] / args.steps, 4) for i in range(len(names))
+                                   if names[i].startswith("match")},
+                     "uncertified_queries": int(m.n_fallback), "correspondences": int(m.pairs.shape[0]),
+                     "identical_to_fp64_form": bool(same)}
+    flops = 2.0 * (2.0 * 1e5 * 1e5 * 33)
+    tk = res["fp32"]["stages_ms"]["match_topk"] * 1e-3
+    out = {
+        "metric": "descriptor matchings/s (100k x 100k mutual NN, exact)",
+        "value": round(1e3 / res["fp16"]["ms_per_match"], 3),
+        "unit": "matchings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": res["fp16"]["ms_per_match"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": "FPFH rows of two submaps, each four ray-cast scans 8 m apart (128 beams x 3,750 "
+                               "azimuths; voxel 0.15 m, r_normal 0.45 m, r_FPFH 0.75 m; 20% target outliers), "
+                               "exactly 100,000 J rows per side (seeded subset), "
+                               "mutual NN with FP16 / BF16 candidate tiles + FP64 certificate and re-run; value = "
+                               "FP16 form", "generation_s": round(t_gen, 1), "descriptor_stats": stats},
+        "precisions": res,
+        "roofline": {"kernel": "topk_tiles, FP64 form", "bound": "mfma", "achieved": round(flops / tk / 1e12, 3),
+                     "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(flops / tk / 1e12 / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_graph(args, lib, kmg, torch, synth, dev):
+    """kmg_corr_graph + kmg_max_kcore on the LiDAR pair's correspondences."""
+    d = synth.c1_pair(args.item)
+    p = d["params"]
+    ps = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_src"])
+    pt = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_tgt"])
+    ws = kmg.Workspace(dev)
+    a, b, mt = kmg.register_pair(torch.from_numpy(d["src"]).to(dev), torch.from_numpy(d["tgt"]).to(dev), ps, pt,
+                                 ws=ws)
+    beta = 1.5 * p.voxel
+    n_tau = 3000
+    sync = torch.cuda.synchronize
+    state = {}
+
+    def step():
+        g = kmg.corr_graph(a.xyz, b.xyz, mt.pairs, mt.d1, mt.d2, n_tau, beta, ws=ws)
+        state["g"] = g
+        state["k"] = kmg.max_kcore(g.off, g.adj, int(g.sel.numel()), ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    lib.kmg_timing_enable(1)
+    t, lat = timed(step, args.steps, sync)
+    lib.kmg_timing_enable(0)
+    g, kc = state["g"], state["k"]
+    n = int(g.sel.numel())
+    out = {
+        "metric": "correspondence graphs/s (ratio filter N_tau=3000 + Eq. 3 graph + max k-core)",
+        "value": round(args.steps / t, 3),
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "correspondences of the LiDAR-scale pair (voxel 0.3 m, beta = 1.5 v)",
+                   "correspondences": int(mt.pairs.shape[0]), "vertices": n, "edges": int(g.adj.numel()),
+                   "pair_tests": n * (n - 1), "max_core": kc.max_core, "core_members": int(kc.members.numel())},
+        "p50_ms": round(statistics.median(lat), 4),
+        "p99_ms": round(pct(lat, 0.99), 4),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import pose
+
+        pr = mt.pairs.cpu().numpy()
+        d1, d2 = mt.d1.cpu().numpy(), mt.d2.cpu().numpy()
+        sx, tx = a.xyz.cpu().numpy(), b.xyz.cpu().numpy()
+        tc = time.perf_counter()
+        sel = pose.ratio_filter(d1, d2, n_tau)
+        adj = pose.compat_graph(sx.T[pr[sel, 0]].astype(np.float64), tx.T[pr[sel, 1]].astype(np.float64), beta)
+        core = pose.core_numbers(adj)
+        tc = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": round(1.0 / tc, 4), "unit": "graphs/s", "cores": 1, "kind": "oracle",
+                               "sample": "one graph of the same correspondences: numpy ratio filter, dense Eq. (3) "
+                                         "test, bucket k-core; %.2f s" % tc}
+        out["oracle_equal"] = bool((g.sel.cpu().numpy() == sel).all() and int(adj.sum()) == int(g.adj.numel())
+                                   and (kc.core.cpu().numpy() == core).all())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,11 +440,13 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--item", type=int, default=0)
-    ap.add_argument("--workload", default="lidar", choices=["lidar", "batch64", "serve"],
+    ap.add_argument("--workload", default="lidar", choices=["lidar", "batch64", "serve", "graph", "c3"],
                     help="lidar: one 25k-point LiDAR pair per step (default); batch64: 64 uneven pairs "
                          "(kept sizes log-uniform in [2k, 60k], half indoor, half LiDAR) per step; serve: "
                          "Poisson request traces at 50, 200 and 800 pairs/s, served in continuous batches "
-                         "and one at a time")
+                         "and one at a time; graph: ratio filter + Eq. (3) graph + maximum k-core on the "
+                         "LiDAR pair's correspondences; c3: 100k x 100k FPFH rows of dense scans matched "
+                         "with FP64, FP16 and BF16 candidate tiles")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests per rate (after 200 warm-up)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the JSON line, run a streaming add over MIB MiB (read MIB, write MIB) three "
@@ -333,6 +471,12 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args, lib, kmg, torch, synth, dev)
+        return
+    if args.workload == "graph":
+        run_graph(args, lib, kmg, torch, synth, dev)
+        return
+    if args.workload == "c3":
+        run_c3(args, lib, kmg, torch, synth, dev)
         return
     d = synth.c1_pair(args.item)
     p = d["params"]

@@ -75,7 +75,7 @@ __global__ void build_sets(const CloudState* cs, int n_clouds, const float* fpfh
     s.rows = jlist + cs[c].j_off;
     s.n = &cs[c].j_cnt;
     s.row_base = cs[c].kept_off;
-    s.pad = 0;
+    s.flags = 0;
     sets[c] = s;
 }
 

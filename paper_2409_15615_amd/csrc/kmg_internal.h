@@ -71,8 +71,9 @@ struct MatchSet {
     const int32_t* rows;  // nullable
     const int32_t* n;     // device count
     int32_t row_base;     // subtracted from rows[i] in the output
-    int32_t pad;
+    int32_t flags;        // kSetRowsOnly: rows for the partner only, no queries
 };
+constexpr int32_t kSetRowsOnly = 1;
 
 // Per-set plan written by the device planner.
 struct SetPlan {
@@ -271,15 +272,42 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
                           hipStream_t s);
 
 // ---- match.hip ------------------------------------------------------------
+constexpr int kLpMaxDim = 64;  // descriptor length of the FP16 / BF16 tiles (two K = 32 steps)
+// Per pair of the reduced-precision form: the centre of both sets' rows and a
+// power-of-two scale (max |x - mu| * scale <= 2^14).
+struct PairLp {
+    double mu[kLpMaxDim];
+    double scale;
+    double inv_s2;
+    unsigned long long maxabs_bits;  // max |x - mu| over both sets (FP64 bits)
+};
+// Re-run of the queries the reduced-precision certificate left open: their
+// own sets (query rows listed through f_row) against the full partner sets
+// (rows only), through the FP64 form with its own status block and its own
+// workspace region (carved on the host when used).
+struct RerunWs {
+    DevStatus* st;
+    MatchSet* sets;      // 2 per main set
+    int32_t* f_slot;     // main query slot of each listed query
+    int32_t* f_row;      // its descriptor row
+    int32_t* f_count;    // listed queries per main set
+    int64_t* f_total;
+    char* region;        // nullptr when not carved
+    size_t region_bytes;
+};
 struct MatchWs {
     SetPlan* plan;
     double* pk;           // packed rows
     double* n2;           // exact squared norms per query slot
     double* part;         // per-segment top-4 lists of encoded scores
+    double* lp_nx;        // reduced-precision form: ||x - mu|| per query slot
+    PairLp* lp_pairs;     // reduced-precision form: per pair centre and scale
+    RerunWs rr;           // reduced-precision form: FP64 re-run of uncertified queries
     int32_t* nn;
     double* best;
     double* second;
-    int32_t* fb_list;
+    int32_t* fb_list;     // queries left to the exact scan, in slot order
+    int64_t* fb_total;
     int32_t* flag;
     int32_t* pos;
     int64_t* scan_tmp;
@@ -288,7 +316,7 @@ struct MatchWs {
     int64_t part_cap;     // partial entries
     int kp;
 };
-MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim);
+MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun = true);
 // Matches sets 2i and 2i+1 for every pair i (both directions, mutual check).
 // counts[i * counts_stride + 0] receives the number of correspondences of
 // pair i and [.. + 5] the number of exact re-scans of its queries.

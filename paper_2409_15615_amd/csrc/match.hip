@@ -113,8 +113,10 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     const int c = threadIdx.x;
     const bool live = c < n_sets;
     const int n = live ? *sets[c].n : 0;
+    const bool rows_only = live && (sets[c].flags & kSetRowsOnly);
     const int chunks = (n + kTileRows - 1) / kTileRows;
-    const int cblocks = (n + kColsPerBlock - 1) / kColsPerBlock;
+    const int cblocks = rows_only ? 0 : (n + kColsPerBlock - 1) / kColsPerBlock;
+    const int n_q = rows_only ? 0 : n;  // queries that need partial lists
     int64_t tq, tc, tb;
     const int64_t q_off = block_excl_scan64(n, smem, tq);
     const int64_t c_off = block_excl_scan64(chunks, smem, tc);
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     int segs = s_segs > deep ? s_segs : deep;
     segs = segs < pch ? segs : (pch > 0 ? pch : 1);
     int64_t tpart;
-    block_excl_scan64(live ? static_cast<int64_t>(n) * segs * kTopK : 0, smem, tpart);
+    block_excl_scan64(live ? static_cast<int64_t>(n_q) * segs * kTopK : 0, smem, tpart);
     if (tpart > part_cap) {
         // too many partial lists for the buffer: one common count, halved until they fit
         // (one segment per set always fits, the buffer holds kTopK entries per query)
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     const int tiles = (live && pn > 0) ? cblocks * segs : 0;
     int64_t tt;
     const int64_t t_off = block_excl_scan64(tiles, smem, tt);
-    const int64_t p_off = block_excl_scan64(live ? static_cast<int64_t>(n) * segs * kTopK : 0, smem, tpart);
+    const int64_t p_off = block_excl_scan64(live ? static_cast<int64_t>(n_q) * segs * kTopK : 0, smem, tpart);
     if (live) {
         SetPlan pl;
         pl.n = n;
@@ -182,6 +184,26 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
 
 // ------------------------------------------------------------- packing --
 
+// plan[c].max_norm_bits = max(.., v) (v >= 0): one atomic per wave when the
+// wave's live lanes share a set (the common case).
+__device__ __forceinline__ void wave_max_norm(SetPlan* plan, int c, double v) {
+    const uint64_t live = ballot(true);
+    const int c0 = __shfl(c, __ffsll(static_cast<unsigned long long>(live)) - 1, kWave);
+    const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(v));
+    if (ballot(c == c0) == live) {
+        unsigned long long mx = bits;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const unsigned long long o = __shfl_xor(mx, d, kWave);
+            const bool o_live = (live >> (lane_id() ^ d)) & 1ull;
+            if (o_live && o > mx) mx = o;
+        }
+        if (lane_id() == __ffsll(static_cast<unsigned long long>(live)) - 1) atomicMax(&plan[c].max_norm_bits, mx);
+    } else {
+        atomicMax(&plan[c].max_norm_bits, bits);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void row_norms(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
                                                     int dim, double* __restrict__ n2, const DevStatus* st) {
 #pragma clang fp contract(off)
@@ -196,22 +218,7 @@ __global__ __launch_bounds__(kBlock) void row_norms(const MatchSet* __restrict__
             acc = acc + v * v;
         }
         n2[t] = acc;
-        // one atomic per wave when the wave's rows share a set (the common case)
-        const uint64_t live = ballot(true);
-        const int c0 = __shfl(c, __ffsll(static_cast<unsigned long long>(live)) - 1, kWave);
-        const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(acc));
-        if (ballot(c == c0) == live) {
-            unsigned long long mx = bits;
-#pragma unroll
-            for (int d = kWave / 2; d > 0; d >>= 1) {
-                const unsigned long long o = __shfl_xor(mx, d, kWave);
-                const bool o_live = (live >> (lane_id() ^ d)) & 1ull;
-                if (o_live && o > mx) mx = o;
-            }
-            if (lane_id() == __ffsll(static_cast<unsigned long long>(live)) - 1) atomicMax(&plan[c].max_norm_bits, mx);
-        } else {
-            atomicMax(&plan[c].max_norm_bits, bits);
-        }
+        wave_max_norm(plan, c, acc);
     }
 }
 
@@ -482,12 +489,12 @@ constexpr int kQuad = 4;  // lanes per query in the re-scoring kernel
 
 // Four lanes per query slot: lane q merges the segment lists q, q + 4, ..,
 // the quad merges its lists, lane q re-scores candidate q exactly, and the
-// first lane certifies the result or queues the query for an exact scan.
+// first lane certifies the result or flags the query for an exact scan.
 __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
                                                   int dim, const double* __restrict__ part,
                                                   const double* __restrict__ n2, int32_t* __restrict__ nn,
                                                   double* __restrict__ best, double* __restrict__ second,
-                                                  int32_t* __restrict__ fb_list, DevStatus* st) {
+                                                  int32_t* __restrict__ failed, DevStatus* st) {
     const int64_t total = st->total_queries;
     const int q = lane_id() & (kQuad - 1);
     const int quad0 = lane_id() & ~(kQuad - 1);
@@ -495,6 +502,7 @@ __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ s
     for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
          slot += gs) {
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the quad
         const int p = c ^ 1;
         const SetPlan qc = plan[c];
         const int j = static_cast<int>(slot - qc.q_off);
@@ -504,6 +512,7 @@ __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ s
                 nn[slot] = -1;
                 best[slot] = INFINITY;
                 second[slot] = INFINITY;
+                failed[slot] = 0;
             }
             continue;
         }
@@ -564,10 +573,9 @@ __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ s
             best[slot] = b1;
             second[slot] = b2;
         } else {
-            const uint32_t at = atomicAdd(&st->n_fallback, 1u);
-            fb_list[at] = static_cast<int32_t>(slot);
             atomicAdd(&plan[c].n_fb, 1);
         }
+        failed[slot] = ok ? 0 : 1;
     }
 }
 
@@ -583,56 +591,144 @@ __device__ __forceinline__ void combine_best(double& b1, int& j1, double& b2, do
     b2 = nb2;
 }
 
-// One block per queued query: exact FP64 scan over all partner rows.
-__global__ __launch_bounds__(kBlock) void exact_scan(const MatchSet* __restrict__ sets,
-                                                     const SetPlan* __restrict__ plan, int n_sets, int dim,
-                                                     const int32_t* __restrict__ fb_list, const DevStatus* st,
-                                                     int32_t* __restrict__ nn, double* __restrict__ best,
-                                                     double* __restrict__ second) {
-    __shared__ double s_b1[kBlock / kWave], s_b2[kBlock / kWave];
-    __shared__ int s_j1[kBlock / kWave];
-    const int lane = lane_id();
+// The queries whose certificate failed, in slot order: fl[pos[slot]] = slot.
+__global__ __launch_bounds__(kBlock) void fb_gather(const int32_t* __restrict__ failed,
+                                                    const int32_t* __restrict__ pos, int32_t* __restrict__ fl,
+                                                    const DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs)
+        if (failed[slot]) fl[pos[slot]] = static_cast<int32_t>(slot);
+}
+
+constexpr int kXRows = 128;              // partner rows per LDS tile of the exact scan
+constexpr int kXStride = kLpMaxDim + 1;  // odd row stride in LDS (no bank conflicts)
+constexpr int kXSegMax = 32;             // row segments per group of the exact scan
+
+// Row segments of the exact scan: as many as the partial buffer holds for F
+// listed queries, at most kXSegMax.
+__device__ __forceinline__ int exact_segs(int64_t F, int64_t part_cap) {
+    const int64_t s = F > 0 ? part_cap / (3 * F) : 1;
+    return static_cast<int>(s < 1 ? 1 : (s > kXSegMax ? kXSegMax : s));
+}
+
+// Exact FP64 scans for the listed queries (fl, in slot order, *f_total of
+// them).  A work item is (group of 64 consecutive entries, row segment): lane
+// L of every wave holds entry L, the partner rows of the segment stream
+// through LDS one row per thread, and each wave scores every fourth row,
+// ascending, with the plain FP64 sum in dimension order.  The four waves
+// merge their (best, index, second) and write them as the segment's partial
+// result; a group that spans several sets visits their partners one after
+// another.
+__global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restrict__ sets,
+                                                        const SetPlan* __restrict__ plan, int n_sets, int dim,
+                                                        const int32_t* __restrict__ fl,
+                                                        const int64_t* __restrict__ f_total, int64_t part_cap,
+                                                        double* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ float s_x[kXRows * kXStride];
+    __shared__ float s_y[kWave * kXStride];
+    __shared__ double s_b1[kBlock], s_b2[kBlock];
+    __shared__ int s_j1[kBlock];
+    __shared__ int s_next;
+    constexpr int kWaves = kBlock / kWave;
+    const int L = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
-    const int nfb = static_cast<int>(st->n_fallback);
-    for (int w = blockIdx.x; w < nfb; w += gridDim.x) {
-        const int64_t slot = fb_list[w];
-        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
-        const int p = c ^ 1;
-        const int j = static_cast<int>(slot - plan[c].q_off);
-        const int np = plan[p].n;
-        const float* y = set_row(sets[c], j, dim);
+    const int64_t F = *f_total;
+    const int S = exact_segs(F, part_cap);
+    double* pb1 = part;
+    double* pb2 = part + F * S;
+    int32_t* pj1 = reinterpret_cast<int32_t*>(part + 2 * F * S);
+    const int64_t items = (F + kWave - 1) / kWave * S;
+    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t g = item / S;
+        const int sg = static_cast<int>(item % S);
+        const int64_t e = g * kWave + L;
+        const bool have = e < F;
+        const int64_t slot = have ? fl[e] : 0;
+        const int c_e = have ? find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); })
+                             : INT_MAX;
+        if (wv == 0 && have) {
+            const float* y = set_row(sets[c_e], static_cast<int>(slot - plan[c_e].q_off), dim);
+            for (int t = 0; t < dim; ++t) s_y[L * kXStride + t] = y[t];
+        }
+        int c_cur = find_set(n_sets, fl[g * kWave], [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
         double b1 = INFINITY, b2 = INFINITY;
-        int j1 = INT32_MAX;
-        for (int i = threadIdx.x; i < np; i += kBlock) {  // ascending per thread
-            const double d = exact_d2(set_row(sets[p], i, dim), y, dim);
-            if (d < b1) {
-                b2 = b1;
-                b1 = d;
-                j1 = i;
-            } else if (d < b2) {
-                b2 = d;
+        int j1 = INT_MAX;
+        while (true) {
+            const int p = c_cur ^ 1;
+            const int np = p < n_sets ? plan[p].n : 0;
+            const int len = (np + S - 1) / S;
+            const int r_begin = min(np, sg * len), r_end = min(np, r_begin + len);
+            for (int r0 = r_begin; r0 < r_end; r0 += kXRows) {
+                const int nr = min(kXRows, r_end - r0);
+                __syncthreads();
+                if (static_cast<int>(threadIdx.x) < nr) {
+                    const float* x = set_row(sets[p], r0 + static_cast<int>(threadIdx.x), dim);
+                    for (int t = 0; t < dim; ++t) s_x[threadIdx.x * kXStride + t] = x[t];
+                }
+                __syncthreads();
+                if (c_e == c_cur) {
+                    for (int r = wv; r < nr; r += kWaves) {
+                        double acc = 0.0;
+                        for (int t = 0; t < dim; ++t) {
+                            const double df = static_cast<double>(s_x[r * kXStride + t]) -
+                                              static_cast<double>(s_y[L * kXStride + t]);
+                            acc = acc + df * df;
+                        }
+                        if (acc < b1) {
+                            b2 = b1;
+                            b1 = acc;
+                            j1 = r0 + r;
+                        } else if (acc < b2) {
+                            b2 = acc;
+                        }
+                    }
+                }
             }
+            __syncthreads();
+            if (threadIdx.x == 0) s_next = INT_MAX;
+            __syncthreads();
+            if (c_e != INT_MAX && c_e > c_cur) atomicMin(&s_next, c_e);
+            __syncthreads();
+            const int nx = s_next;
+            if (nx == INT_MAX) break;
+            c_cur = nx;
         }
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-            const double ob1 = __shfl_xor(b1, d, kWave);
-            const double ob2 = __shfl_xor(b2, d, kWave);
-            const int oj1 = __shfl_xor(j1, d, kWave);
-            combine_best(b1, j1, b2, ob1, oj1, ob2);
-        }
-        if (lane == 0) {
-            s_b1[wv] = b1;
-            s_b2[wv] = b2;
-            s_j1[wv] = j1;
+        s_b1[threadIdx.x] = b1;
+        s_b2[threadIdx.x] = b2;
+        s_j1[threadIdx.x] = j1;
+        __syncthreads();
+        if (wv == 0 && have) {
+            for (int o = 1; o < kWaves; ++o)
+                combine_best(b1, j1, b2, s_b1[o * kWave + L], s_j1[o * kWave + L], s_b2[o * kWave + L]);
+            pb1[e * S + sg] = b1;
+            pb2[e * S + sg] = b2;
+            pj1[e * S + sg] = j1;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int o = 1; o < kBlock / kWave; ++o) combine_best(b1, j1, b2, s_b1[o], s_j1[o], s_b2[o]);
-            nn[slot] = (j1 == INT32_MAX) ? -1 : j1;
-            best[slot] = b1;
-            second[slot] = b2;
-        }
-        __syncthreads();
+    }
+}
+
+// Merges the segment partials of every listed query in segment order.
+__global__ __launch_bounds__(kBlock) void exact_merge(const int32_t* __restrict__ fl,
+                                                      const int64_t* __restrict__ f_total, int64_t part_cap,
+                                                      const double* __restrict__ part, int32_t* __restrict__ nn,
+                                                      double* __restrict__ best, double* __restrict__ second) {
+    const int64_t F = *f_total;
+    const int S = exact_segs(F, part_cap);
+    const double* pb1 = part;
+    const double* pb2 = part + F * S;
+    const int32_t* pj1 = reinterpret_cast<const int32_t*>(part + 2 * F * S);
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < F; e += gs) {
+        double b1 = pb1[e * S], b2 = pb2[e * S];
+        int j1 = pj1[e * S];
+        for (int sg = 1; sg < S; ++sg) combine_best(b1, j1, b2, pb1[e * S + sg], pj1[e * S + sg], pb2[e * S + sg]);
+        const int64_t slot = fl[e];
+        nn[slot] = (j1 == INT_MAX) ? -1 : j1;
+        best[slot] = b1;
+        second[slot] = b2;
     }
 }
 
@@ -691,9 +787,489 @@ __global__ void pair_counts(const SetPlan* __restrict__ plan, int n_sets, const 
     counts[static_cast<int64_t>(i) * stride + 5] = plan[2 * i].n_fb + plan[2 * i + 1].n_fb;
 }
 
+// ------------------------------------------------ reduced-precision tiles --
+//
+// FP16 / BF16 candidate generation.  Rows of each pair are centred on the
+// pair's mean mu (FP64) and scaled by a power of two s (max |x - mu| s <= 2^14),
+// and every centred, scaled value v is split into hi = T(v) and lo = T(v - hi).
+// 16x16x32 MFMA steps form hi.hi of each K half (accumulators h0, h1) and
+// hi.lo + lo.hi over both halves (accumulator c), FP32 accumulation; the
+// product lo.lo is dropped.  With x' = x - mu, y' = y - mu, D = ||x' - y'||^2 = T + ||y'||^2 where
+// T = ||x'||^2 - 2 x'.y', and the tile computes, in FP64,
+//   L = a_x - 2 (h0 + h1 + c) / s^2 - k_y nx,
+// with a_x = ||x'||^2 (1 - 2^-46) and nx = ||x'||: a lower bound of T when
+// k_y = 2 e ||y'|| + 2^-22 sqrt(dim) / s bounds the dot-product error per unit
+// of nx (e from the split and accumulation error analysis below).  Rows are
+// ranked by L, so a non-candidate row has T >= L_4 and
+// D >= L_4 + ||y'||^2 - 2^-22 sqrt(dim) ||y'|| / s (the per-query part of the
+// split floor term); the exact second distance below that certifies the
+// query, as in the FP64 form.
+//
+// Error per unit ||x'|| ||y'|| of the dot product (eps = 2^-11 for FP16 and
+// 2^-8 for BF16, each widened by 2^-12 for the rounding through FP32 on the
+// way): split 3 eps^2; h0, h1: at
+// most 33 FP32 roundings each of sums bounded by S = sum |v_x v_y| <=
+// ||v_x|| ||v_y||, counted twice for directed rounding; c: 129 roundings of a
+// sum bounded by 2 eps S.  FP16 subnormals add 2^-24 per element, the 2^-22 sqrt(dim) / s
+// terms above.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLpPieces = 2 * 2 * kWave;  // 16-byte pieces per chunk: K half x {hi, lo} x lane (4 KB)
+constexpr int kLpSample = 1024;           // rows averaged for a pair's centre
+
+template <class T>
+struct Lp;
+template <>
+struct Lp<_Float16> {
+    using vec = f16x8;
+    static constexpr double kEps = 0x1p-11 * (1.0 + 0x1p-12);  // rounding through FP32 adds 2^-24 relative
+    __device__ static f32x4 mfma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+    __device__ static _Float16 from(double v) { return static_cast<_Float16>(static_cast<float>(v)); }
+};
+template <>
+struct Lp<__bf16> {
+    using vec = bf16x8;
+    static constexpr double kEps = 0x1p-8 * (1.0 + 0x1p-12);
+    __device__ static f32x4 mfma(vec a, vec b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static __bf16 from(double v) { return static_cast<__bf16>(static_cast<float>(v)); }
+};
+
+template <class T>
+__host__ __device__ constexpr double lp_dot_err() {
+    return 3.0 * Lp<T>::kEps * Lp<T>::kEps + 2.0 * 33.0 * 0x1p-24 + 2.0 * 129.0 * 0x1p-24 * 2.0 * Lp<T>::kEps;
+}
+
+// One block per pair: mu = the mean (FP64, four fixed partial sums per
+// dimension) of up to kLpSample rows taken at even strides over both sets.
+// Any fixed mu is valid, since every bound is stated in ||x - mu||; a mean of
+// the bulk keeps those norms, and the errors, small.
+__global__ __launch_bounds__(kBlock) void lp_center(const MatchSet* __restrict__ sets, const SetPlan* __restrict__ plan,
+                                                    int n_sets, int dim, PairLp* __restrict__ pp) {
+    __shared__ double s_part[kBlock];
+    const int pair = blockIdx.x;
+    const int a = 2 * pair, b = 2 * pair + 1;
+    const int na = plan[a].n, nb = b < n_sets ? plan[b].n : 0;
+    const int64_t nt = static_cast<int64_t>(na) + nb;
+    const int ns = static_cast<int>(nt < kLpSample ? nt : kLpSample);
+    const int d = threadIdx.x % kLpMaxDim, g = threadIdx.x / kLpMaxDim;
+    constexpr int kGroups = kBlock / kLpMaxDim;
+    double sum = 0.0;
+    if (d < dim) {
+#pragma unroll 8
+        for (int k = g; k < ns; k += kGroups) {
+            const int r = static_cast<int>(static_cast<int64_t>(k) * nt / ns);
+            const float* x = r < na ? set_row(sets[a], r, dim) : set_row(sets[b], r - na, dim);
+            sum += static_cast<double>(x[d]);
+        }
+    }
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    if (g == 0) {
+        double t = 0.0;
+        for (int q = 0; q < kGroups; ++q) t += s_part[q * kLpMaxDim + d];
+        pp[pair].mu[d] = (d < dim && ns > 0) ? t / static_cast<double>(ns) : 0.0;
+    }
+    if (threadIdx.x == 0) pp[pair].maxabs_bits = 0ull;
+}
+
+// The scale of each pair from the largest |x - mu| (after lp_rows).
+__global__ void lp_scale(PairLp* __restrict__ pp, int n_pairs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    const double m = __longlong_as_double(static_cast<long long>(pp[i].maxabs_bits));
+    int e = 0;
+    if (m > 0.0) {
+        frexp(m, &e);  // m < 2^e: scale 2^(14 - e) keeps every |v| below 2^14
+        e = 14 - e;
+    }
+    e = e > 60 ? 60 : (e < -60 ? -60 : e);
+    pp[i].scale = ldexp(1.0, e);
+    pp[i].inv_s2 = ldexp(1.0, -2 * e);
+}
+
+// one atomic per wave for the common case of a wave within one pair
+__device__ __forceinline__ void wave_max_abs(PairLp* pp, int pair, double v) {
+    const uint64_t live = ballot(true);
+    const int p0 = __shfl(pair, __ffsll(static_cast<unsigned long long>(live)) - 1, kWave);
+    const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(v));
+    if (ballot(pair == p0) == live) {
+        unsigned long long mx = bits;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const unsigned long long o = __shfl_xor(mx, d, kWave);
+            const bool o_live = (live >> (lane_id() ^ d)) & 1ull;
+            if (o_live && o > mx) mx = o;
+        }
+        if (lane_id() == __ffsll(static_cast<unsigned long long>(live)) - 1) atomicMax(&pp[pair].maxabs_bits, mx);
+    } else {
+        atomicMax(&pp[pair].maxabs_bits, bits);
+    }
+}
+
+// Per query slot: a = ||x'||^2 (1 - 2^-46) and nx = ||x'|| (FP64); the largest
+// ||x'||^2 of each set goes to plan[c].max_norm_bits.
+__global__ __launch_bounds__(kBlock) void lp_rows(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
+                                                  int dim, PairLp* __restrict__ pp, double* __restrict__ lp_a,
+                                                  double* __restrict__ lp_nx, const DevStatus* st) {
+#pragma clang fp contract(off)
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total; t += gs) {
+        const int c = find_set(n_sets, t, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const float* x = set_row(sets[c], static_cast<int>(t - plan[c].q_off), dim);
+        const double* mu = pp[c >> 1].mu;
+        double acc = 0.0, mabs = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            const double v = static_cast<double>(x[k]) - mu[k];
+            acc = acc + v * v;
+            mabs = fmax(mabs, fabs(v));
+        }
+        lp_a[t] = acc - acc * 0x1p-46;
+        lp_nx[t] = sqrt(acc);
+        wave_max_norm(plan, c, acc);
+        wave_max_abs(pp, c >> 1, mabs);
+    }
+}
+
+// Thread per 16-byte piece: chunk g, K half s, part p (hi / lo), lane l holds
+// rows (or query columns) l % 16 of the chunk and k = 32 s + 8 (l / 16) + 0..7.
+template <class T>
+__global__ __launch_bounds__(kBlock) void lp_pack(const MatchSet* __restrict__ sets, const SetPlan* __restrict__ plan,
+                                                  int n_sets, int dim, const PairLp* __restrict__ pp,
+                                                  uint4* __restrict__ pk, const DevStatus* st) {
+    const int64_t total = st->total_chunks * kLpPieces;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total; t += gs) {
+        const int l = static_cast<int>(t % kWave);
+        const int part = static_cast<int>((t / kWave) % 2);
+        const int s = static_cast<int>((t / (2 * kWave)) % 2);
+        const int64_t g = t / kLpPieces;
+        const int c = find_set(n_sets, g, [&](int q) { return static_cast<int64_t>(plan[q].chunk_off); });
+        const int i = static_cast<int>(g - plan[c].chunk_off) * kTileRows + l % kTileRows;
+        const PairLp& P = pp[c >> 1];
+        typename Lp<T>::vec out;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 32 * s + 8 * (l / kTileRows) + e;
+            double v = 0.0;
+            if (i < plan[c].n && k < dim) v = (static_cast<double>(set_row(sets[c], i, dim)[k]) - P.mu[k]) * P.scale;
+            const T hi = Lp<T>::from(v);
+            out[e] = part == 0 ? hi : Lp<T>::from(v - static_cast<double>(hi));
+        }
+        pk[t] = __builtin_bit_cast(uint4, out);
+    }
+}
+
+__device__ __forceinline__ void absorb4(double* top, double w0, double w1, double w2, double w3) {
+    sort4(w0, w1, w2, w3);
+    merge4(top, w0, w1, w2, w3);
+}
+
+// One block of four waves, as the FP64 tile: 64 query columns per wave
+// against the partner's chunks [c_begin, c_end), chunks staged in LDS
+// (4 KB of packed halves + the 16 rows' a and nx).
+template <class T>
+__device__ __forceinline__ void tile_block_lp(const uint4* __restrict__ pk, const double* __restrict__ lp_a,
+                                              const double* __restrict__ lp_nx, int dim, const SetPlan& qc,
+                                              const SetPlan& pc, const PairLp& P, int col0, int c_begin, int c_end,
+                                              int seg, double* __restrict__ part, uint4* lds_pk, double* lds_rows) {
+    using V = typename Lp<T>::vec;
+    const int lane = lane_id();
+    const int g = lane >> 4;
+    const int l16 = lane & 15;
+    V bh[kTilesPerWave][2], bl[kTilesPerWave][2];
+    double ky[kTilesPerWave];
+    const double kdot = 2.0 * lp_dot_err<T>() + 0x1p-48;
+    const double kfloor = 0x1p-22 * sqrt(static_cast<double>(dim)) / P.scale;
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) {
+        const int chunk = min(col0 / kTileCols + t, qc.chunks - 1);
+        const uint4* src = pk + static_cast<int64_t>(qc.chunk_off + chunk) * kLpPieces;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            bh[t][s] = __builtin_bit_cast(V, src[(2 * s + 0) * kWave + lane]);
+            bl[t][s] = __builtin_bit_cast(V, src[(2 * s + 1) * kWave + lane]);
+        }
+        const int col = min(col0 + kTileCols * t + l16, qc.n - 1);
+        ky[t] = kdot * lp_nx[qc.q_off + col] + kfloor;
+    }
+    double top[kTilesPerWave][4];
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) top[t][0] = top[t][1] = top[t][2] = top[t][3] = INFINITY;
+    const unsigned keep = keep_mask(row_bits(pc.chunks));
+    const double m2is2 = -2.0 * P.inv_s2;
+    if (c_begin < c_end) {  // uniform over the block
+        const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint4*>(pk + static_cast<int64_t>(pc.chunk_off) * kLpPieces), 0,
+            static_cast<int>(min(static_cast<int64_t>(pc.chunks) * kLpPieces * 16, static_cast<int64_t>(INT32_MAX))),
+            static_cast<int>(kBufferWord3));
+        // stage: piece threadIdx.x of the chunk, and row value min(threadIdx.x, 31): a (0..15), nx (16..31)
+        const int rv = min(static_cast<int>(threadIdx.x), 31);
+        auto load = [&](int c, uint4& piece, double& rowv) {
+            piece = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rows, (c * kLpPieces + static_cast<int>(threadIdx.x)) * 16, 0, 0));
+            const int i = c * kTileRows + (rv & 15);
+            const int ic = min(i, pc.n - 1);
+            const double* rsrc = rv < 16 ? lp_a : lp_nx;  // one unpredicated load
+            const double v = rsrc[pc.q_off + ic];
+            rowv = i < pc.n ? v : (rv < 16 ? kPadScore : 0.0);
+        };
+        uint4 piece;
+        double rowv;
+        load(c_begin, piece, rowv);
+        lds_pk[threadIdx.x] = piece;
+        lds_rows[rv] = rowv;
+        __syncthreads();
+        for (int c = c_begin; c < c_end; ++c) {
+            const int buf = (c - c_begin) & 1;
+            const uint4* sp = lds_pk + buf * kLpPieces;
+            const double* sr = lds_rows + buf * 32;
+            const V ah0 = __builtin_bit_cast(V, sp[0 * kWave + lane]), al0 = __builtin_bit_cast(V, sp[1 * kWave + lane]);
+            const V ah1 = __builtin_bit_cast(V, sp[2 * kWave + lane]), al1 = __builtin_bit_cast(V, sp[3 * kWave + lane]);
+            double ar[4], nr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ar[r] = sr[4 * g + r];
+                nr[r] = sr[16 + 4 * g + r];
+            }
+            load(min(c + 1, c_end - 1), piece, rowv);
+            __builtin_amdgcn_sched_barrier(0);
+            // result register r of lane l holds tile row 4 (l / 16) + r, column l % 16
+            const unsigned row0 = static_cast<unsigned>(c * kTileRows + 4 * g);
+#pragma unroll
+            for (int t = 0; t < kTilesPerWave; ++t) {
+                const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                const f32x4 h0 = Lp<T>::mfma(ah0, bh[t][0], z);
+                const f32x4 h1 = Lp<T>::mfma(ah1, bh[t][1], z);
+                f32x4 x = Lp<T>::mfma(ah0, bl[t][0], z);
+                x = Lp<T>::mfma(al0, bh[t][0], x);
+                x = Lp<T>::mfma(ah1, bl[t][1], x);
+                x = Lp<T>::mfma(al1, bh[t][1], x);
+                double w[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double dot = (static_cast<double>(h0[r]) + static_cast<double>(h1[r])) + static_cast<double>(x[r]);
+                    const double lb = fma(-ky[t], nr[r], fma(dot, m2is2, ar[r]));
+                    w[r] = encode(lb, keep, row0 + r);
+                }
+                absorb4(top[t], w[0], w[1], w[2], w[3]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            lds_pk[(buf ^ 1) * kLpPieces + threadIdx.x] = piece;
+            lds_rows[(buf ^ 1) * 32 + rv] = rowv;
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) {
+        merge_lane(top[t], 16);
+        merge_lane(top[t], 32);
+        const int col = col0 + kTileCols * t + l16;
+        if (g == 0 && col < qc.n) {
+            double* dst = part + qc.part_off + (static_cast<int64_t>(seg) * qc.n + col) * kTopK;
+            dst[0] = top[t][0];
+            dst[1] = top[t][1];
+            dst[2] = top[t][2];
+            dst[3] = top[t][3];
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void topk_lp(
+    const SetPlan* __restrict__ plan, int n_sets, const uint4* __restrict__ pk, const double* __restrict__ lp_a,
+    const double* __restrict__ lp_nx, const PairLp* __restrict__ pp, int dim, double* __restrict__ part,
+    DevStatus* st) {
+    __shared__ uint4 lds_pk[2 * kLpPieces];
+    __shared__ double lds_rows[2 * 32];
+    __shared__ int s_tile;
+    const int wv = threadIdx.x / kWave;
+    const int total = st->err_capacity ? 0 : st->total_tiles;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= total) break;
+        const int c = find_set(n_sets, tile, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
+        const SetPlan qc = plan[c];
+        const SetPlan pc = plan[c ^ 1];
+        const int local = tile - qc.tile_off;
+        const int seg = local % qc.segs;
+        const int cblk = local / qc.segs;
+        const int cps = (pc.chunks + qc.segs - 1) / qc.segs;
+        const int c_begin = seg * cps;
+        const int c_end = min(c_begin + cps, pc.chunks);
+        const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
+        tile_block_lp<T>(pk, lp_a, lp_nx, dim, qc, pc, pp[c >> 1], col0, c_begin, c_end, seg, part, lds_pk,
+                         lds_rows);
+    }
+}
+
+// As rescore, with the lower-bound certificate of the reduced-precision tiles.
+__global__ __launch_bounds__(kBlock) void rescore_lp(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
+                                                     int dim, const double* __restrict__ part,
+                                                     const double* __restrict__ lp_nx,
+                                                     const PairLp* __restrict__ pp, int32_t* __restrict__ nn,
+                                                     double* __restrict__ best, double* __restrict__ second,
+                                                     int32_t* __restrict__ failed, DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int q = lane_id() & (kQuad - 1);
+    const int quad0 = lane_id() & ~(kQuad - 1);
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * (kBlock / kQuad);
+    for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
+         slot += gs) {
+        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const int p = c ^ 1;
+        const SetPlan qc = plan[c];
+        const int j = static_cast<int>(slot - qc.q_off);
+        const int np = p < n_sets ? plan[p].n : 0;
+        if (np == 0) {
+            if (q == 0) {
+                nn[slot] = -1;
+                best[slot] = INFINITY;
+                second[slot] = INFINITY;
+                failed[slot] = 0;
+            }
+            continue;
+        }
+        double top[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+        for (int sg = q; sg < qc.segs; sg += kQuad) {
+            const double* src = part + qc.part_off + (static_cast<int64_t>(sg) * qc.n + j) * kTopK;
+            merge4(top, src[0], src[1], src[2], src[3]);
+        }
+        merge_lane(top, 1);
+        merge_lane(top, 2);
+        const int bits = row_bits(plan[p].chunks);
+        const double mine = q == 0 ? top[0] : (q == 1 ? top[1] : (q == 2 ? top[2] : top[3]));
+        int row = -1;
+        if (mine < kNoScore) {
+            row = decode_row(mine, keep_mask(bits));
+            if (row >= np) row = -1;
+        }
+        const double d = row >= 0 ? exact_d2(set_row(sets[p], row, dim), set_row(sets[c], j, dim), dim) : INFINITY;
+        double dq[kQuad];
+        int rq[kQuad];
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            dq[k] = __shfl(d, quad0 + k, kWave);
+            rq[k] = __shfl(row, quad0 + k, kWave);
+        }
+        if (q != 0) continue;
+        double b1 = INFINITY, b2 = INFINITY;
+        int j1 = -1;
+        int ncand = 0;
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const int i = rq[k];
+            if (i < 0) continue;
+            ++ncand;
+            const double dk = dq[k];
+            if (dk < b1 || (dk == b1 && i < j1)) {
+                b2 = b1;
+                b1 = dk;
+                j1 = i;
+            } else if (dk < b2) {
+                b2 = dk;
+            }
+        }
+        bool ok;
+        if (ncand >= np) {
+            ok = true;
+        } else {
+            const double mx = __longlong_as_double(static_cast<long long>(plan[p].max_norm_bits));
+            const double ny = lp_nx[slot];
+            const double ny2 = ny * ny;
+            const double cz = 0x1p-22 * sqrt(static_cast<double>(dim)) * ny / pp[c >> 1].scale;
+            const double enc_err = ldexp(1.0, bits - 52) * (4.0 * mx + 4.0 * ny2 + 4.0);
+            const double slack = 0x1p-44 * (fabs(top[3]) + ny2 + b2 + 4.0 * mx) + 1e-300;
+            const double bound = top[3] + ny2 - cz - enc_err - slack;
+            ok = ncand == 4 && b2 < bound;
+        }
+        if (ok) {
+            nn[slot] = j1;
+            best[slot] = b1;
+            second[slot] = b2;
+        } else {
+            atomicAdd(&plan[c].n_fb, 1);
+        }
+        failed[slot] = ok ? 0 : 1;
+    }
+}
+
+// ---------------------------------------------------- FP64 re-run lists --
+
+// Lists the queries the reduced-precision certificate left open, in slot
+// order (so each set's entries are contiguous).
+__global__ __launch_bounds__(kBlock) void rerun_gather(const MatchSet* __restrict__ sets,
+                                                       const SetPlan* __restrict__ plan, int n_sets,
+                                                       const int32_t* __restrict__ failed,
+                                                       const int32_t* __restrict__ pos, int32_t* __restrict__ f_slot,
+                                                       int32_t* __restrict__ f_row, const DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+        if (!failed[slot]) continue;
+        const int c = find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
+        const int j = static_cast<int>(slot - plan[c].q_off);
+        const int f = pos[slot];
+        f_slot[f] = static_cast<int32_t>(slot);
+        f_row[f] = sets[c].rows ? sets[c].rows[j] : j;
+    }
+}
+
+// Set 2c of the re-run: the listed queries of main set c; set 2c + 1: the
+// full partner of c, rows only.
+__global__ void rerun_sets(const MatchSet* __restrict__ sets, const SetPlan* __restrict__ plan, int n_sets,
+                           const int32_t* __restrict__ pos, const int64_t* __restrict__ f_total, int64_t q_cap,
+                           const int32_t* __restrict__ f_row, int32_t* __restrict__ f_count,
+                           MatchSet* __restrict__ rr) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_sets) return;
+    auto start = [&](int k) -> int64_t {
+        return (k < n_sets && plan[k].q_off < q_cap) ? pos[plan[k].q_off] : *f_total;
+    };
+    const int64_t b = start(c), e = start(c + 1);
+    f_count[c] = static_cast<int32_t>(e - b);
+    MatchSet q = sets[c];
+    q.rows = f_row + b;
+    q.n = f_count + c;
+    q.flags = 0;
+    MatchSet r = sets[c ^ 1];
+    r.flags |= kSetRowsOnly;
+    rr[2 * c] = q;
+    rr[2 * c + 1] = r;
+}
+
+// Copies the re-run's answers to the main query slots.
+__global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restrict__ plan2, int n_sets2,
+                                                        const DevStatus* st2, const int32_t* __restrict__ nn2,
+                                                        const double* __restrict__ best2,
+                                                        const double* __restrict__ second2,
+                                                        const SetPlan* __restrict__ plan, const int32_t* __restrict__ pos,
+                                                        const int32_t* __restrict__ f_slot, int32_t* __restrict__ nn,
+                                                        double* __restrict__ best, double* __restrict__ second,
+                                                        DevStatus* st) {
+    const int64_t total = st2->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total; t += gs) {
+        const int c2 = find_set(n_sets2, t, [&](int q) { return static_cast<int64_t>(plan2[q].q_off); });
+        if (c2 & 1) continue;  // rows-only sets have no answers
+        const int i = static_cast<int>(t - plan2[c2].q_off);
+        const int64_t slot = f_slot[pos[plan[c2 >> 1].q_off] + i];
+        nn[slot] = nn2[t];
+        best[slot] = best2[t];
+        second[slot] = second2[t];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && st2->err_capacity) st->err_capacity = 1;
+}
+
 }  // namespace
 
-MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim) {
+MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     MatchWs w;
     w.kp = (dim + 1 <= 36) ? 36 : 68;  // 4 KS for the two kernel instantiations (dim <= 64)
     w.q_cap = std::max<int64_t>(q_cap, 1);
@@ -703,21 +1279,135 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim) {
     w.plan = c.take<SetPlan>(static_cast<size_t>(std::max(n_sets, 1)));
     w.pk = c.take<double>(static_cast<size_t>(w.chunk_cap) * w.kp * kTileRows);
     w.n2 = c.take<double>(static_cast<size_t>(w.q_cap));
+    w.lp_nx = c.take<double>(static_cast<size_t>(w.q_cap));
+    w.lp_pairs = c.take<PairLp>(static_cast<size_t>(n_sets / 2 + 1));
     w.part = c.take<double>(static_cast<size_t>(w.part_cap));
     w.nn = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.best = c.take<double>(static_cast<size_t>(w.q_cap));
     w.second = c.take<double>(static_cast<size_t>(w.q_cap));
     w.fb_list = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.fb_total = c.take<int64_t>(1);
     w.flag = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.pos = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.scan_tmp = c.take<int64_t>(scan_temp_elems(w.q_cap));
+    w.rr = RerunWs{};
+    if (rerun && 2 * n_sets <= kPlanThreads) {
+        w.rr.st = c.take<DevStatus>(1);
+        w.rr.sets = c.take<MatchSet>(static_cast<size_t>(2 * n_sets));
+        w.rr.f_slot = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+        w.rr.f_row = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+        w.rr.f_count = c.take<int32_t>(static_cast<size_t>(std::max(n_sets, 1)));
+        w.rr.f_total = c.take<int64_t>(1);
+        Carver probe(nullptr, 0);
+        carve_match(probe, 2 * n_sets, 2 * w.q_cap, dim, false);
+        w.rr.region_bytes = probe.off;
+        w.rr.region = c.take<char>(probe.off);
+    }
     return w;
 }
 
+kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
+                    hipStream_t s);
+kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
+kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
+                          hipStream_t s);
+
 kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                        const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s) {
-    (void)prec;
     if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
+    if (prec == KMG_FP16 || prec == KMG_BF16) {
+        KMG_TRY(match_lp(sets, n_sets, dim, prec, st, w, s));
+    } else {
+        KMG_TRY(match_fp64(sets, n_sets, dim, st, w, s));
+    }
+    {
+        StageScope sc(ST_MATCH_MUTUAL, s);
+        mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
+        KMG_TRY(launch_status());
+        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
+        emit_pairs<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best,
+                                                               w.second, outs, st);
+        KMG_TRY(launch_status());
+        pair_counts<<<grid_for(n_sets / 2, 64), 64, 0, s>>>(w.plan, n_sets, w.pos, st, counts, counts_stride);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
+// Candidates in FP16 / BF16 with FP32 accumulation (lower-bound ranking),
+// exact FP64 re-score and certificate; the queries left uncertified re-run
+// through the FP64 form against their full partner sets (or, when the batch
+// has too many sets for a second plan, are re-scanned exactly).
+kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
+                    hipStream_t s) {
+    if (dim > kLpMaxDim) return KMG_ERR_ARG;
+    uint4* pk = reinterpret_cast<uint4*>(w.pk);  // a chunk of halves (4 KB) fits a 36-deep FP64 chunk
+    const int n_pairs = n_sets / 2;
+    {
+        StageScope sc(ST_MATCH_PACK, s);
+        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st);
+        KMG_TRY(launch_status());
+        lp_center<<<n_pairs, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.lp_pairs);
+        KMG_TRY(launch_status());
+        lp_rows<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.lp_pairs, w.n2, w.lp_nx,
+                                                            st);
+        KMG_TRY(launch_status());
+        lp_scale<<<grid_for(n_pairs, 64), 64, 0, s>>>(w.lp_pairs, n_pairs);
+        KMG_TRY(launch_status());
+        if (prec == KMG_FP16) {
+            lp_pack<_Float16><<<grid_cap(w.chunk_cap * kLpPieces, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim,
+                                                                                        w.lp_pairs, pk, st);
+        } else {
+            lp_pack<__bf16><<<grid_cap(w.chunk_cap * kLpPieces, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim,
+                                                                                      w.lp_pairs, pk, st);
+        }
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_MATCH_TOPK, s);
+        if (prec == KMG_FP16) {
+            topk_lp<_Float16><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, pk, w.n2, w.lp_nx, w.lp_pairs, dim,
+                                                             w.part, st);
+        } else {
+            topk_lp<__bf16><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, n_sets, pk, w.n2, w.lp_nx, w.lp_pairs, dim,
+                                                           w.part, st);
+        }
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_MATCH_RESCORE, s);
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
+        rescore_lp<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.lp_nx,
+                                                                        w.lp_pairs, w.nn, w.best, w.second, w.flag,
+                                                                        st);
+        KMG_TRY(launch_status());
+        if (!w.rr.region) return exact_fallback(sets, n_sets, dim, st, w, s);
+        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s));
+        rerun_gather<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.rr.f_slot,
+                                                                 w.rr.f_row, st);
+        KMG_TRY(launch_status());
+        rerun_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets, w.plan, n_sets, w.pos, w.rr.f_total, w.q_cap,
+                                                       w.rr.f_row, w.rr.f_count, w.rr.sets);
+        KMG_TRY(launch_status());
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.rr.st), 0u, sizeof(DevStatus) / 4, s));
+    }
+    Carver c2(w.rr.region, w.rr.region_bytes);
+    const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
+    if (!c2.fits()) return KMG_ERR_WORKSPACE;
+    KMG_TRY(match_fp64(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
+    {
+        StageScope sc(ST_MATCH_RESCORE, s);
+        rerun_scatter<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best,
+                                                                   w2.second, w.plan, w.pos, w.rr.f_slot, w.nn,
+                                                                   w.best, w.second, st);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
+// Candidates on FP64 matrix cores, exact re-score and certificate, exact
+// scans for the rest.
+kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s) {
     const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     {
         StageScope sc(ST_MATCH_PACK, s);
@@ -742,25 +1432,27 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
     }
     {
         StageScope sc(ST_MATCH_RESCORE, s);
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
         rescore<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2, w.nn,
-                                                                    w.best, w.second, w.fb_list, st);
+                                                                    w.best, w.second, w.flag, st);
         KMG_TRY(launch_status());
-        exact_scan<<<grid_cap(w.q_cap, 1), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, st, w.nn, w.best,
-                                                          w.second);
-        KMG_TRY(launch_status());
-    }
-    {
-        StageScope sc(ST_MATCH_MUTUAL, s);
-        mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
-        KMG_TRY(launch_status());
-        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
-        emit_pairs<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best,
-                                                               w.second, outs, st);
-        KMG_TRY(launch_status());
-        pair_counts<<<grid_for(n_sets / 2, 64), 64, 0, s>>>(w.plan, n_sets, w.pos, st, counts, counts_stride);
-        KMG_TRY(launch_status());
+        KMG_TRY(exact_fallback(sets, n_sets, dim, st, w, s));
     }
     return KMG_OK;
+}
+
+// Exact scans of the queries flagged in w.flag, grouped in slot order.
+kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
+                          hipStream_t s) {
+    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.fb_total, w.scan_tmp, s));
+    fb_gather<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.flag, w.pos, w.fb_list, st);
+    KMG_TRY(launch_status());
+    exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total, w.part_cap,
+                                                   w.part);
+    KMG_TRY(launch_status());
+    exact_merge<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.fb_list, w.fb_total, w.part_cap, w.part, w.nn, w.best,
+                                                            w.second);
+    return launch_status();
 }
 
 // ---------------------------------------------------- single pair entry --
@@ -792,7 +1484,7 @@ kmg_status match(const float* dp, const int32_t* rp, int64_t np, const float* dq
     if (np == 0 || nq == 0) return KMG_OK;
     KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(st), 0u, sizeof(DevStatus) / 4, s));
     KMG_TRY(fill_u64(reinterpret_cast<uint64_t*>(counts), 0ull, 8, s));
-    MatchSet a{dp, rp, nullptr, 0, 0}, b{dq, rq, nullptr, 0, 0};
+    MatchSet a{dp, rp, nullptr, 0, 0}, b{dq, rq, nullptr, 0, 0};  // query sets, flags 0
     PairOutDev o{pairs, d1, d2, cap};
     write_pair_sets<<<1, 1, 0, s>>>(sets, cnt, a, b, static_cast<int32_t>(np), static_cast<int32_t>(nq), outs, o);
     KMG_TRY(launch_status());

@@ -28,4 +28,5 @@ from .scenes import (  # noqa: F401
     c4_trace,
     c4_pool,
     c4_requests,
+    c3_pair,
 )

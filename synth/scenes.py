@@ -471,3 +471,47 @@ def c4_requests(rate: float, n_requests: int = 2000, warmup: int = 200, config: 
         out.append(req)
     return out
 
+
+def c3_pair(item: int = 0, config: int = 3, n_beams: int = 128, n_az: int = 3750, n_poses: int = 4,
+            step: float = 8.0, outlier_frac: float = 0.20) -> dict:
+    """Submap pair for the large matching workload: each side accumulates
+    n_poses scans taken `step` metres apart along the heading of its first
+    pose, expressed in that pose's frame; the target's first pose is yawed
+    and moved 2-10 m from the source's, and 20% of its points are replaced by
+    uniform outliers.  Voxel 0.15 m, r_normal 0.45 m, r_FPFH 0.75 m."""
+    rng = rng_for(config, item)
+    height = 1.73
+    yaw = rng.uniform(0.0, 2 * math.pi)
+    dist = rng.uniform(2.0, 10.0)
+    ang = rng.uniform(0.0, 2 * math.pi)
+    s0 = np.array([0.0, 0.0, height])
+    s1 = np.array([dist * math.cos(ang), dist * math.sin(ang), height])
+    fwd0 = np.array([1.0, 0.0, 0.0])
+    fwd1 = np.array([math.cos(yaw), math.sin(yaw), 0.0])
+    track = [s0 + k * step * fwd0 for k in range(n_poses)] + [s1 + k * step * fwd1 for k in range(n_poses)]
+    boxes = _boxes(rng, 40, [p[:2] for p in track], height)
+
+    def submap(origin, heading_yaw, fwd):
+        cy, sy = math.cos(heading_yaw), math.sin(heading_yaw)
+        Rz = np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]])
+        parts = []
+        for k in range(n_poses):
+            o = origin + k * step * fwd
+            local = lidar_scan(rng, o, heading_yaw, boxes, n_beams, n_az)  # in the frame of pose k
+            world = local @ Rz.T + o
+            parts.append((world - origin) @ Rz)  # frame of the first pose
+        return np.concatenate(parts, axis=0)
+
+    src = submap(s0, 0.0, fwd0)
+    tgt = submap(s1, yaw, fwd1)
+    n = tgt.shape[0]
+    n_out = int(round(outlier_frac * n))
+    lo, hi = tgt.min(axis=0), tgt.max(axis=0)
+    sel = rng.choice(n, size=n_out, replace=False)
+    tgt[sel] = rng.uniform(lo, hi, (n_out, 3))
+    cy, sy = math.cos(yaw), math.sin(yaw)
+    Rz = np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]])
+    return dict(src=_soa(src), tgt=_soa(tgt), vp_src=np.zeros(3), vp_tgt=np.zeros(3), R=Rz.T,
+                t=Rz.T @ (s0 - s1), params=Params(voxel=0.15, r_normal=0.45, r_fpfh=0.75),
+                name=f"submap {n_poses}x({n_beams}x{n_az}) v=0.15")
+
