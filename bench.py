@@ -368,6 +368,57 @@ def run_c3(args, lib, kmg, torch, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_classic(args, lib, kmg, torch, synth, dev):
+    """Faster-PFH vs classical FPFH (Section III-C ablation) on the LiDAR pair, per-stage form."""
+    d = synth.c1_pair(args.item)
+    p = d["params"]
+    src = torch.from_numpy(d["src"]).to(dev)
+    tgt = torch.from_numpy(d["tgt"]).to(dev)
+    ws = kmg.Workspace(dev)
+    sync = torch.cuda.synchronize
+    res = {}
+    for name, mode in (("faster_pfh", kmg.MODE_FASTER_PFH), ("classic_fpfh", kmg.MODE_CLASSIC_FPFH)):
+        ps = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_src"], mode=mode)
+        pt = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_tgt"], mode=mode)
+        state = {}
+
+        def desc():
+            state["a"] = kmg.faster_pfh(src, ps, ws)
+            state["b"] = kmg.faster_pfh(tgt, pt, ws)
+
+        def whole():
+            state["r"] = kmg.register_pair(src, tgt, ps, pt, ws=ws)
+
+        for _ in range(args.warmup):
+            whole()
+        t_desc, lat_desc = timed(desc, args.steps, sync)
+        t_all, lat_all = timed(whole, args.steps, sync)
+        a, b, mt = state["r"]
+        res[name] = {"descriptor_ms_per_pair": round(1e3 * t_desc / args.steps, 4),
+                     "pairs_per_s": round(args.steps / t_all, 3),
+                     "descriptor_rows_J": [int(a.feats.j_idx.numel()), int(b.feats.j_idx.numel())],
+                     "correspondences": int(mt.pairs.shape[0])}
+    ratio = res["classic_fpfh"]["descriptor_ms_per_pair"] / res["faster_pfh"]["descriptor_ms_per_pair"]
+    out = {
+        "metric": "Faster-PFH speed-up over classical FPFH (descriptor stages, per-stage form)",
+        "value": round(ratio, 3),
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["faster_pfh"]["descriptor_ms_per_pair"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "LiDAR-scale pair (64 x 1,875 rays, voxel 0.3 m, r_normal 0.9 m, r_FPFH 1.5 m): "
+                               "voxelize + normals + SPFH/FPFH of both clouds with each descriptor pipeline"},
+        "modes": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_graph(args, lib, kmg, torch, synth, dev):
     """kmg_corr_graph + kmg_max_kcore on the LiDAR pair's correspondences."""
     d = synth.c1_pair(args.item)
@@ -440,13 +491,14 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--item", type=int, default=0)
-    ap.add_argument("--workload", default="lidar", choices=["lidar", "batch64", "serve", "graph", "c3"],
+    ap.add_argument("--workload", default="lidar", choices=["lidar", "batch64", "serve", "graph", "c3", "classic"],
                     help="lidar: one 25k-point LiDAR pair per step (default); batch64: 64 uneven pairs "
                          "(kept sizes log-uniform in [2k, 60k], half indoor, half LiDAR) per step; serve: "
                          "Poisson request traces at 50, 200 and 800 pairs/s, served in continuous batches "
                          "and one at a time; graph: ratio filter + Eq. (3) graph + maximum k-core on the "
                          "LiDAR pair's correspondences; c3: 100k x 100k FPFH rows of dense scans matched "
-                         "with FP64, FP16 and BF16 candidate tiles")
+                         "with FP64, FP16 and BF16 candidate tiles; classic: the LiDAR pair with classical FPFH "
+                         "(three searches, no filters) beside Faster-PFH, per-stage form")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests per rate (after 200 warm-up)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the JSON line, run a streaming add over MIB MiB (read MIB, write MIB) three "
@@ -477,6 +529,9 @@ def main():
         return
     if args.workload == "c3":
         run_c3(args, lib, kmg, torch, synth, dev)
+        return
+    if args.workload == "classic":
+        run_classic(args, lib, kmg, torch, synth, dev)
         return
     d = synth.c1_pair(args.item)
     p = d["params"]

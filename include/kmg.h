@@ -64,13 +64,31 @@ typedef struct {
     int32_t tau_num;
     int32_t n_bins;
     double viewpoint[3];
+    int32_t mode;      /* KMG_MODE_FASTER_PFH (default) or KMG_MODE_CLASSIC_FPFH */
+    int32_t reserved;  /* must be 0 */
 } kmg_params;
+
+/*
+ * Descriptor pipelines (kmg_params.mode).
+ *   KMG_MODE_FASTER_PFH: Faster-PFH (Section III-C, Algorithm 1): one radius
+ *     search at r_FPFH serves both the normals (its r_normal subset) and the
+ *     features; the tau_num and tau_lin filters decide B and J.
+ *   KMG_MODE_CLASSIC_FPFH: the FPFH of Rusu et al. as Section III-C describes
+ *     it (Fig. 3a): normals from their own radius search at r_normal (any
+ *     point with >= 3 neighbours there, q included, gets a normal; no
+ *     linearity filter), angular features and SPFH over a second search at
+ *     r_FPFH, and the FPFH sum over a third search at r_FPFH; every point with
+ *     a normal gets a descriptor.  tau_num and tau_lin are ignored.  The
+ *     per-stage entry points only; the batch form runs Faster-PFH.
+ */
+#define KMG_MODE_FASTER_PFH 0
+#define KMG_MODE_CLASSIC_FPFH 1
 
 /* Operation codes for kmg_workspace_bytes(). */
 enum {
     KMG_OP_VOXELIZE = 0, /* n0 = raw points */
-    KMG_OP_NORMALS = 1,  /* n0 = kept points m */
-    KMG_OP_FPFH = 2,     /* n0 = kept points m */
+    KMG_OP_NORMALS = 1,  /* n0 = kept points m; classic mode: n1 = neighbour capacity of the r_normal search */
+    KMG_OP_FPFH = 2,     /* n0 = kept points m; classic mode: n1 = neighbour entries of the r_FPFH lists */
     KMG_OP_MATCH = 3,    /* n0 = rows of P (np), n1 = rows of Q (nq) */
     KMG_OP_GRAPH = 4,    /* n0 = correspondences, n1 = N_tau */
     KMG_OP_KCORE = 5     /* n0 = graph vertices */

@@ -216,17 +216,25 @@ def mutual_match(X, Y):
                 best_xy=b_xy, second_xy=s_xy)
 
 
-def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True):
+def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True, classical: bool = False):
     """Algorithm 1 and Eq. A1-A5 on one voxelized cloud.
 
     With boundary_fp32 the chain rounds the normals to float32 before the
     histogram step, because the library's interface stores normals as a
-    float32 array between the two calls."""
+    float32 array between the two calls.
+
+    classical=True gives the FPFH that Section III-C contrasts with
+    Faster-PFH (Fig. 3a): normals from the r_normal neighbourhood of every
+    point with at least 3 points there, no linearity filter, SPFH and FPFH
+    for every point with a normal.  The r_normal neighbourhood is the strict
+    r_normal subset of the r_FPFH list, which is exactly what a separate
+    radius search at r_normal returns."""
     H = int(params.n_bins)
+    tau_normal, tau_lin, tau_j = (3, 1.0, 1) if classical else (params.tau_num, params.tau_lin, params.tau_num)
     off, idx = radius_search(xyz_kept, params.r_fpfh)
-    nr = normals(xyz_kept, off, idx, params.r_normal, params.tau_num, params.tau_lin, vp)
+    nr = normals(xyz_kept, off, idx, params.r_normal, tau_normal, tau_lin, vp)
     n64 = nr["normals"].astype(np.float32).astype(np.float64) if boundary_fp32 else nr["normals"]
-    sp = spfh(xyz_kept, n64, off, idx, nr["B"], params.tau_num, H)
+    sp = spfh(xyz_kept, n64, off, idx, nr["B"], tau_j, H)
     fp = fpfh(xyz_kept, off, idx, nr["B"], sp["J"], sp["spfh"], sp["Pq"], H)
     j_idx = np.nonzero(sp["J"])[0].astype(np.int32)
     return dict(off=off, idx=idx, normals=nr["normals"], normals_used=n64, plin=nr["plin"], gap=nr["gap"],
@@ -234,7 +242,7 @@ def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True):
                 edges=sp["edges"], fpfh=fp, j_idx=j_idx)
 
 
-def run_pair(src_raw, tgt_raw, params, vp_src, vp_tgt, match: bool = True):
+def run_pair(src_raw, tgt_raw, params, vp_src, vp_tgt, match: bool = True, classical: bool = False):
     """Whole hot path for one pair: voxelize both clouds, Faster-PFH on both, then
     mutual matching of the float32 descriptors of the J points.  Correspondences
     are returned as kept-cloud indices (i in the source, j in the target)."""
@@ -242,7 +250,7 @@ def run_pair(src_raw, tgt_raw, params, vp_src, vp_tgt, match: bool = True):
     for tag, raw, vp in (("src", src_raw, vp_src), ("tgt", tgt_raw, vp_tgt)):
         kept, keys = voxelize(raw, params.voxel)
         xyz = np.ascontiguousarray(_soa(raw)[:, kept])
-        fp = faster_pfh(xyz, params, vp)
+        fp = faster_pfh(xyz, params, vp, classical=classical)
         fp.update(kept=kept, keys=keys, xyz=xyz)
         out[tag] = fp
     if match:

@@ -16,6 +16,8 @@ bool params_ok(const kmg_params* p) {
     if (p->n_bins < 1 || p->n_bins > kmg::kMaxBins) return false;
     for (int c = 0; c < 3; ++c)
         if (!isfinite(p->viewpoint[c])) return false;
+    if (p->mode != KMG_MODE_FASTER_PFH && p->mode != KMG_MODE_CLASSIC_FPFH) return false;
+    if (p->reserved != 0) return false;
     return true;
 }
 
@@ -45,8 +47,8 @@ KMG_EXPORT size_t kmg_workspace_bytes(int32_t op, int64_t n0, int64_t n1, const 
     if (n0 < 0 || n1 < 0 || n0 > INT32_MAX || n1 > INT32_MAX) return 0;
     switch (op) {
         case KMG_OP_VOXELIZE: return kmg::voxelize_ws(n0);
-        case KMG_OP_NORMALS: return kmg::normals_ws(n0);
-        case KMG_OP_FPFH: return kmg::fpfh_ws(n0, p ? p->n_bins : 11);
+        case KMG_OP_NORMALS: return kmg::normals_ws(n0, p ? p->mode : 0, n1);
+        case KMG_OP_FPFH: return kmg::fpfh_ws(n0, p ? p->n_bins : 11, p ? p->mode : 0, n1);
         case KMG_OP_MATCH: return kmg::match_ws(n0, n1, p ? 3 * p->n_bins : 33);
         case KMG_OP_GRAPH:
             if (n1 < 1 || n1 > KMG_MAX_KCORE_VERTICES) return 0;
@@ -83,7 +85,8 @@ KMG_EXPORT kmg_status kmg_normals(const float* xyz, int64_t m, const kmg_params*
     if (!nbr_off || !ws) return KMG_ERR_ARG;
     if (m > 0 && (!xyz || !normals || !flags)) return KMG_ERR_ARG;
     if (nbr_cap > 0 && !nbr_idx) return KMG_ERR_ARG;
-    if (ws_bytes < kmg::normals_ws(m)) return KMG_ERR_WORKSPACE;
+    const int64_t nbr_n = p->mode == KMG_MODE_CLASSIC_FPFH ? nbr_cap : 0;
+    if (ws_bytes < kmg::normals_ws(m, p->mode, nbr_n)) return KMG_ERR_WORKSPACE;
     return kmg::normals(xyz, m, *p, normals, flags, nbr_off, nbr_idx, nbr_cap, nnz, n_normal, ws, ws_bytes,
                         as_stream(stream));
 }
@@ -93,7 +96,7 @@ KMG_EXPORT kmg_status kmg_fpfh(const float* xyz, const float* normals, uint8_t* 
                     int32_t* j_idx, int64_t* n_j, int64_t* stats, void* ws, size_t ws_bytes, void* stream) {
     if (!params_ok(p) || !n_j || m < 0 || m > INT32_MAX - 1 || !ws) return KMG_ERR_ARG;
     if (m > 0 && (!xyz || !normals || !flags || !nbr_off || !nbr_idx || !fpfh || !j_idx)) return KMG_ERR_ARG;
-    if (ws_bytes < kmg::fpfh_ws(m, p->n_bins)) return KMG_ERR_WORKSPACE;
+    if (ws_bytes < kmg::fpfh_ws(m, p->n_bins, p->mode, 0)) return KMG_ERR_WORKSPACE;
     return kmg::fpfh(xyz, normals, flags, nbr_off, nbr_idx, m, *p, spfh, fpfh, j_idx, n_j, stats, ws, ws_bytes,
                      as_stream(stream));
 }
@@ -113,6 +116,7 @@ KMG_EXPORT kmg_status kmg_batch_upload(const kmg_cloud* clouds, const kmg_match_
     int64_t total = 0;
     for (int k = 0; k < 2 * n_pairs; ++k) {
         if (!params_ok(&clouds[k].params) || clouds[k].params.n_bins != H) return KMG_ERR_ARG;
+        if (clouds[k].params.mode != KMG_MODE_FASTER_PFH) return KMG_ERR_ARG;  // the batch form is Faster-PFH
         if (clouds[k].n < 0 || (clouds[k].n > 0 && !clouds[k].xyz)) return KMG_ERR_ARG;
         total += clouds[k].n;
     }

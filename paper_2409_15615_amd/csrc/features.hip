@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
         }
         if (lane == 0) {
             Pq[q] = P;
-            jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_num) ? 1 : 0;
+            jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_j) ? 1 : 0;
             if (n64) atomicAdd(&st->feat_fp64, n64);
             if (nedge) atomicAdd(&st->feat_edge, nedge);
         }
@@ -354,20 +354,24 @@ FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
     return w;
 }
 
-kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
-                          const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
-                          const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
-                          uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s) {
+kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
+                      int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, const int32_t* nbr,
+                      const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s) {
     KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)), s));
     if (m_cap > 0) {
-        {
-            StageScope sc(ST_SPFH, s);
-            spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
-                                                                  nrm_stride, flags, off, nbr, H, w.spfh64,
-                                                                  spfh_out, w.Pq, w.jflag, st);
-            KMG_TRY(launch_status());
-        }
+        StageScope sc(ST_SPFH, s);
+        spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
+                                                              flags, off, nbr, H, w.spfh64, spfh_out, w.Pq, w.jflag,
+                                                              st);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
+kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
+                      const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
+                      int32_t* j_idx, CloudState* cs, hipStream_t s) {
+    if (m_cap > 0) {
         StageScope sc(ST_FPFH, s);
         fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, off, nbr, H,
                                                               w.spfh64, w.Pq, fpfh_out, st);
@@ -384,6 +388,15 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
         KMG_TRY(launch_status());
     }
     return KMG_OK;
+}
+
+kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
+                          const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
+                          const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                          uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
+                          hipStream_t s) {
+    KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm, nrm_stride, flags, spfh_out, s));
+    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nbr, flags, fpfh_out, j_idx, cs, s);
 }
 
 }  // namespace kmg

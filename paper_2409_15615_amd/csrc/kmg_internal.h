@@ -57,6 +57,8 @@ struct CloudDev {
     double tau_lin;
     double vp[3];
     RadiusTest rf, rn;
+    int32_t tau_j;     // |M[q]| needed for J (tau_num; 1 in the classic mode, where J = B)
+    int32_t mode;      // KMG_MODE_*
 };
 
 // Per-cloud values produced on the device.
@@ -245,14 +247,17 @@ SearchWs carve_search(Carver& c, int64_t m_cap);
 // Grid build and the count pass over the kept points (count st->m_kept <=
 // m_cap, SoA stride `stride`, cloud ids kept_cloud (nullable = cloud 0)).
 // off receives m_cap + 1 offsets; the total goes to st->nnz.
+// use_rn: search at r_normal instead of r_FPFH; build_grid false reuses the
+// cell grid of an earlier call on the same workspace.
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
-                              int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s);
+                              int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
+                              bool build_grid = true, int use_rn = 0);
 // Fill pass (lists ascending) and normals.  Writes nothing into nbr when
 // st->nnz > nbr_cap (device-side check; st->err_capacity is set).
 kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                              int64_t m_cap, int64_t nbr_cap, bool dense_pass, DevStatus* st, const SearchWs& w,
                              const int32_t* off, int32_t* nbr, float* nrm, int64_t nrm_stride, uint8_t* flags,
-                             int32_t* n_normal, hipStream_t s);
+                             int32_t* n_normal, hipStream_t s, int use_rn = 0, bool with_normals = true);
 
 // ---- features.hip ---------------------------------------------------------
 struct FeatWs {
@@ -270,6 +275,14 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
                           const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
                           hipStream_t s);
+// The two halves of features_batch: SPFH (and J) over (off, nbr); then the
+// FPFH sum over (off, nbr) and the J list.
+kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
+                      int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, const int32_t* nbr,
+                      const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s);
+kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
+                      const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
+                      int32_t* j_idx, CloudState* cs, hipStream_t s);
 
 // ---- match.hip ------------------------------------------------------------
 constexpr int kLpMaxDim = 64;  // descriptor length of the FP16 / BF16 tiles (two K = 32 steps)
@@ -337,11 +350,11 @@ kmg_status max_kcore(const int32_t* off, const int32_t* adj, int32_t n, int32_t*
 size_t voxelize_ws(int64_t n);
 kmg_status voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz, int64_t cap,
                     int64_t* n_kept_host, void* ws, size_t ws_bytes, hipStream_t s);
-size_t normals_ws(int64_t m);
+size_t normals_ws(int64_t m, int mode = 0, int64_t nbr_cap = 0);
 kmg_status normals(const float* xyz, int64_t m, const kmg_params& p, float* nrm, uint8_t* flags, int32_t* off,
                    int32_t* nbr, int64_t nbr_cap, int64_t* nnz_host, int32_t* n_normal, void* ws, size_t ws_bytes,
                    hipStream_t s);
-size_t fpfh_ws(int64_t m, int H);
+size_t fpfh_ws(int64_t m, int H, int mode = 0, int64_t nnz = 0);
 kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_t* off, const int32_t* nbr,
                 int64_t m, const kmg_params& p, float* spfh_out, float* fpfh_out, int32_t* j_idx, int64_t* n_j_host,
                 int64_t* stats_host, void* ws, size_t ws_bytes, hipStream_t s);

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
                                                                int64_t m_cap, int32_t* __restrict__ deg,
                                                                const int32_t* __restrict__ off,
                                                                int32_t* __restrict__ nbr, int64_t nbr_cap,
-                                                               int dense, DevStatus* st) {
+                                                               int dense, int use_rn, DevStatus* st) {
     __shared__ int32_t s_incl[kWaves][32];
     __shared__ int32_t s_start[kWaves][32];
     __shared__ int32_t s_list[kWaves][kFill ? kCap : 1];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
         }
         const int c = cloud_of(kept_cloud, q);
         const double inv_c = cl[c].inv_cell;
-        const RadiusTest rt = cl[c].rf;
+        const RadiusTest rt = use_rn ? cl[c].rn : cl[c].rf;
         // the 27 neighbour cells: lanes 0..26 look one up each
         int cc = 0, cs = 0;
         if (lane < 27) {
@@ -332,13 +332,13 @@ SearchWs carve_search(Carver& c, int64_t m_cap) {
 }
 
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
-                              int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s) {
-    {
+                              int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
+                              bool build_grid, int use_rn) {
+    if (build_grid) {
         StageScope sc(ST_GRID, s);
         KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
         KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ccount), 0u, w.cap_table, s));
         KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.cfill), 0u, w.cap_table, s));
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
         if (m_cap > 0) {
             cell_insert<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, w.keys,
                                                                   w.ccount, w.cap_table - 1, w.pslot, st);
@@ -353,9 +353,10 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
     }
     {
         StageScope sc(ST_SEARCH_COUNT, s);
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
         if (m_cap > 0) {
             radius_search<false, 1, kSearchWaves><<<grid_cap(m_cap, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
-                cl, grid_of(w), kept_cloud, m_cap, w.deg, nullptr, nullptr, 0, 0, st);
+                cl, grid_of(w), kept_cloud, m_cap, w.deg, nullptr, nullptr, 0, 0, use_rn, st);
             KMG_TRY(launch_status());
         }
         KMG_TRY(scan_exclusive(w.deg, off, m_cap + 1, &st->nnz, w.scan_tmp, s));
@@ -366,22 +367,22 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
 kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                              int64_t m_cap, int64_t nbr_cap, bool dense_pass, DevStatus* st, const SearchWs& w,
                              const int32_t* off, int32_t* nbr, float* nrm, int64_t nrm_stride, uint8_t* flags,
-                             int32_t* n_normal, hipStream_t s) {
+                             int32_t* n_normal, hipStream_t s, int use_rn, bool with_normals) {
     if (m_cap <= 0) return KMG_OK;
     {
         StageScope sc(ST_SEARCH_FILL, s);
         flag_capacity<<<1, 64, 0, s>>>(st, nbr_cap);
         KMG_TRY(launch_status());
         radius_search<true, kListSmall, kSearchWaves><<<grid_cap(m_cap, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
-            cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 0, st);
+            cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 0, use_rn, st);
         KMG_TRY(launch_status());
         if (dense_pass) {
             radius_search<true, kMaxDegree, 1><<<grid_cap(m_cap, 1), kWave, 0, s>>>(
-                cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 1, st);
+                cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 1, use_rn, st);
             KMG_TRY(launch_status());
         }
     }
-    {
+    if (with_normals) {
         StageScope sc(ST_NORMALS, s);
         normals_kernel<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, off, nbr,
                                                                  nbr_cap, nrm, nrm_stride, flags, n_normal, st);

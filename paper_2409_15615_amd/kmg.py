@@ -38,7 +38,12 @@ class KmgParams(C.Structure):
         ("tau_num", C.c_int32),
         ("n_bins", C.c_int32),
         ("viewpoint", C.c_double * 3),
+        ("mode", C.c_int32),
+        ("reserved", C.c_int32),
     ]
+
+
+MODE_FASTER_PFH, MODE_CLASSIC_FPFH = 0, 1
 
 
 class KmgCloud(C.Structure):
@@ -108,10 +113,12 @@ def load():
     return lib
 
 
-def make_params(voxel, r_normal, r_fpfh, tau_num=3, tau_lin=0.99, n_bins=11, viewpoint=(0.0, 0.0, 0.0)):
+def make_params(voxel, r_normal, r_fpfh, tau_num=3, tau_lin=0.99, n_bins=11, viewpoint=(0.0, 0.0, 0.0),
+                mode=MODE_FASTER_PFH):
     p = KmgParams()
     p.voxel, p.r_normal, p.r_fpfh, p.tau_lin = float(voxel), float(r_normal), float(r_fpfh), float(tau_lin)
     p.tau_num, p.n_bins = int(tau_num), int(n_bins)
+    p.mode, p.reserved = int(mode), 0
     for c in range(3):
         p.viewpoint[c] = float(viewpoint[c])
     return p
@@ -208,15 +215,16 @@ def normals(xyz, params, ws=None, want_n_normal=True):
     flags = torch.empty(max(m, 1), dtype=torch.uint8, device=dev)
     off = torch.empty(m + 1, dtype=torch.int32, device=dev)
     n_normal = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if want_n_normal else None
-    w = _ws(ws).get(workspace_bytes(OP_NORMALS, m, 0, params))
     cap = max(_nbr_cap_hint.get(dev.index, 0), 64 * m, 1)
-    for _ in range(2):
+    for _ in range(3):  # the classic mode may need a larger capacity for each of its two searches
+        # the classic mode keeps its r_normal lists in the workspace, sized like nbr_idx
+        w = _ws(ws).get(workspace_bytes(OP_NORMALS, m, cap if params.mode == MODE_CLASSIC_FPFH else 0, params))
         idx = torch.empty(cap, dtype=torch.int32, device=dev)
         nnz = C.c_int64(0)
         st = lib.kmg_normals(_ptr(xyz), m, C.byref(params), _ptr(nrm), _ptr(flags), _ptr(off), _ptr(idx), cap,
                              C.byref(nnz), _ptr(n_normal), _ptr(w), w.numel(), _stream())
         if st == KMG_ERR_CAPACITY:
-            cap = int(nnz.value)
+            cap = max(cap, int(nnz.value))
             _nbr_cap_hint[dev.index] = cap
             continue
         _raise("kmg_normals", st)
@@ -249,7 +257,8 @@ def fpfh(xyz, nrm, flags, off, idx, params, ws=None, want_spfh=False):
     sp = torch.empty((max(m, 1), D), dtype=torch.float32, device=dev) if want_spfh else None
     j_idx = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
     idx_arg = idx if idx.numel() else torch.empty(1, dtype=torch.int32, device=dev)
-    w = _ws(ws).get(workspace_bytes(OP_FPFH, m, 0, params))
+    # the classic mode runs a third search: its lists need as many entries as idx
+    w = _ws(ws).get(workspace_bytes(OP_FPFH, m, idx.numel() if params.mode == MODE_CLASSIC_FPFH else 0, params))
     nj = C.c_int64(0)
     stats = (C.c_int64 * 2)()
     st = lib.kmg_fpfh(_ptr(xyz), _ptr(nrm), _ptr(flags), _ptr(off), _ptr(idx_arg), m, C.byref(params), _ptr(sp),

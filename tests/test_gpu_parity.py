@@ -316,3 +316,38 @@ def test_determinism(K, orc):
         outs.append([host(x).copy() for x in (a.normals.normals, a.feats.fpfh, b.feats.fpfh, mt.pairs, mt.d1, mt.d2)])
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
+
+
+# ---------------------------------------------------------- classical FPFH --
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_classic_fpfh_mode(K, orc, name):
+    """Classical FPFH (three searches, no filters) against the oracle's
+    classical mode on the oracle's kept points."""
+    d, ref = oracle_pair(orc, name)
+    p = d["params"]
+    for tag in ("src", "tgt"):
+        xyz = ref[tag]["xyz"]
+        vp = d["vp_src" if tag == "src" else "vp_tgt"]
+        r = orc.faster_pfh(xyz, p, vp, classical=True)
+        prm = K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, vp,
+                            mode=K.MODE_CLASSIC_FPFH)
+        nr = K.normals(dev(xyz), prm)
+        np.testing.assert_array_equal(host(nr.off).astype(np.int64), r["off"])
+        np.testing.assert_array_equal(host(nr.idx), r["idx"])
+        np.testing.assert_array_equal(host(nr.flags) & 1, r["B"])
+        has = r["B"] == 1
+        ang = angle_between(host(nr.normals).astype(np.float64)[:, has], r["normals"][:, has])
+        well = r["gap"][has] >= 1e-6
+        assert np.all(ang[well] <= 1e-5)
+        # histogram step on the oracle's float32 normals (shared input, as in the Faster-PFH tests)
+        n32 = r["normals"].astype(np.float32)
+        out = K.fpfh(dev(xyz), dev(n32), dev(r["B"].astype(np.uint8)), dev(r["off"].astype(np.int32)),
+                     dev(r["idx"]), prm, want_spfh=True)
+        np.testing.assert_array_equal((host(out.flags) >> 1) & 1, r["J"])
+        np.testing.assert_array_equal(host(out.j_idx), r["j_idx"])
+        assert np.abs(host(out.spfh).astype(np.float64) - r["spfh"]).max() <= 1e-4
+        gf = host(out.fpfh).astype(np.float64)
+        S = np.maximum(r["fpfh"][:, :p.n_bins].sum(1, keepdims=True), 100.0)
+        assert (np.abs(gf - r["fpfh"]) / (S / 100.0)).max() <= 1e-4
+        print(f"{name}/{tag}: classical |J| = {out.j_idx.numel()} (Faster-PFH |J| = {len(ref[tag]['j_idx'])})")
