@@ -118,12 +118,19 @@ int32_t kmg_version(void);
  * its stream).  Not thread-safe: for single-threaded profiling runs.
  * kmg_timing_enable(0) stops timing.  Returns 0, or -1 if events could not
  * be created.  kmg_timing_read copies up to n stage totals (milliseconds and
- * number of bracketed launches; the match_topk stage is bracketed once per
- * direction, i.e. per kernel launch) and returns the number of stages;
- * kmg_stage_name(i) names stage i (static storage).
+ * number of bracketed launches; match_topk is the candidate tile launch of
+ * the first matching direction, match_image the whole matching back) and
+ * returns the number of stages; kmg_stage_name(i) names stage i (static
+ * storage).  kmg_timing_work copies up to n per-stage work counts of the
+ * stage's last timed launch (for match_topk and match_image with the norm
+ * bands: query-row distances the tiles evaluated; 0 where a stage counts
+ * none, -1 if the count could not be read) and returns the number of stages;
+ * it reads device memory of the last call's workspace, which must still be
+ * allocated.
  */
 int32_t kmg_timing_enable(int32_t on);
 int32_t kmg_timing_read(double* ms, int64_t* launches, int32_t n);
+int32_t kmg_timing_work(int64_t* work, int32_t n);
 const char* kmg_stage_name(int32_t stage);
 
 /*
@@ -241,7 +248,9 @@ kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, con
  * outs[i].cap is too small), 7 neighbour entries of the whole batch.
  *
  * Capacities: raw_cap >= total raw points of the batch; nnz_cap = neighbour
- * entries reserved for the batch; at most 511 pairs.
+ * entries reserved for the batch; at most 511 pairs.  The batch matches the
+ * descriptors, so 3 * n_bins <= 64 (n_bins <= 21; KMG_ERR_ARG beyond, and a
+ * zero workspace size).
  *
  * kmg_batch_upload copies the cloud and output tables into the workspace
  * (host call; returns after the copy).  kmg_batch_run enqueues the batch on

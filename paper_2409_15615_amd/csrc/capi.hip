@@ -66,6 +66,8 @@ KMG_EXPORT int32_t kmg_timing_read(double* ms, int64_t* launches, int32_t n) {
     return kmg::timer_read(ms, launches, n);
 }
 
+KMG_EXPORT int32_t kmg_timing_work(int64_t* work, int32_t n) { return kmg::timer_work(work, n); }
+
 KMG_EXPORT const char* kmg_stage_name(int32_t stage) { return kmg::stage_name(stage); }
 
 KMG_EXPORT kmg_status kmg_voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept_idx, float* kept_xyz,
@@ -103,7 +105,7 @@ KMG_EXPORT kmg_status kmg_fpfh(const float* xyz, const float* normals, uint8_t* 
 
 KMG_EXPORT size_t kmg_batch_workspace_bytes(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins) {
     if (n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds || raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 ||
-        nnz_cap > INT32_MAX || n_bins < 1 || n_bins > kmg::kMaxBins)
+        nnz_cap > INT32_MAX || n_bins < 1 || 3 * n_bins > kmg::kMaxMatchDim)
         return 0;
     return kmg::batch_ws(n_pairs, raw_cap, nnz_cap, n_bins);
 }
@@ -113,6 +115,7 @@ KMG_EXPORT kmg_status kmg_batch_upload(const kmg_cloud* clouds, const kmg_match_
     if (!clouds || !outs || !ws || n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds) return KMG_ERR_ARG;
     if (raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 || nnz_cap > INT32_MAX) return KMG_ERR_ARG;
     const int H = clouds[0].params.n_bins;
+    if (3 * H > kmg::kMaxMatchDim) return KMG_ERR_ARG;  // the batch form matches the descriptors
     int64_t total = 0;
     for (int k = 0; k < 2 * n_pairs; ++k) {
         if (!params_ok(&clouds[k].params) || clouds[k].params.n_bins != H) return KMG_ERR_ARG;
@@ -132,7 +135,7 @@ KMG_EXPORT kmg_status kmg_batch_run(int32_t n_pairs, int64_t raw_cap, int64_t nn
                                     int32_t prec, int64_t* counts, void* ws, size_t ws_bytes, void* stream) {
     if (!counts || !ws || n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds) return KMG_ERR_ARG;
     if (raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 || nnz_cap > INT32_MAX) return KMG_ERR_ARG;
-    if (n_bins < 1 || n_bins > kmg::kMaxBins) return KMG_ERR_ARG;
+    if (n_bins < 1 || 3 * n_bins > kmg::kMaxMatchDim) return KMG_ERR_ARG;
     if (prec != KMG_FP32 && prec != KMG_BF16 && prec != KMG_FP16) return KMG_ERR_ARG;
     if (ws_bytes < kmg::batch_ws(n_pairs, raw_cap, nnz_cap, n_bins)) return KMG_ERR_WORKSPACE;
     return kmg::batch_run(n_pairs, raw_cap, nnz_cap, n_bins, prec, counts, ws, ws_bytes, as_stream(stream));
@@ -151,7 +154,7 @@ KMG_EXPORT kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int6
                      float* d2, int64_t cap, int64_t* n_pairs, int64_t* n_fallback, void* ws, size_t ws_bytes,
                      void* stream) {
     if (!n_pairs || np < 0 || nq < 0 || np > INT32_MAX / 2 || nq > INT32_MAX / 2 || cap < 0) return KMG_ERR_ARG;
-    if (dim < 1 || dim > 64 || !ws) return KMG_ERR_ARG;
+    if (dim < 1 || dim > kmg::kMaxMatchDim || !ws) return KMG_ERR_ARG;
     if (prec != KMG_FP32 && prec != KMG_BF16 && prec != KMG_FP16) return KMG_ERR_ARG;
     if ((np > 0 && !desc_p) || (nq > 0 && !desc_q)) return KMG_ERR_ARG;
     if (cap > 0 && (!pairs || !d1 || !d2)) return KMG_ERR_ARG;

@@ -26,6 +26,7 @@ constexpr int kMaxClouds = 1022;                             // 10 bits of cloud
 constexpr int kListSmall = 1024;                             // LDS neighbour list of the common fill pass
 constexpr int kMaxDegree = 8192;                             // largest |N(q)| accepted
 constexpr int kMaxBins = 32;                                 // largest H (3H <= 96 descriptor values)
+constexpr int kMaxMatchDim = 64;                             // longest descriptor the matcher takes
 constexpr int kTopK = 4;                                     // candidates kept per query before re-scoring
 constexpr int kPersistBlocks = 2048;                         // grid of the grid-stride kernels
 
@@ -89,6 +90,8 @@ struct SetPlan {
     int32_t n_fb;       // queries of this set re-scanned exactly
     int64_t part_off;   // first partial entry
     unsigned long long max_norm_bits;  // max squared norm (FP64 bits, non-negative)
+    int32_t wave_off;   // norm-band matching: first query wave of the set
+    int32_t rank_off;   // norm-band matching: first rank work item of the set
 };
 
 // Matching output of one pair (device buffers).
@@ -120,7 +123,11 @@ struct DevStatus {
     int32_t total_queries;
     int64_t total_chunks;
     int64_t pairs_total;      // correspondences over the batch
-    int32_t pad1[6];
+    int32_t total_waves;      // norm-band matching: query waves
+    int32_t rank_items;       // norm-band matching: rank work items
+    int32_t band_step;        // norm-band matching: chunks per tile
+    int32_t pad1;
+    int64_t band_pairs;       // norm-band matching: query-row distances evaluated by the tiles
 };
 
 // Linear workspace allocator; with base == nullptr it only measures.
@@ -183,6 +190,7 @@ enum Stage {
     ST_MATCH_TOPK,
     ST_MATCH_RESCORE,
     ST_MATCH_MUTUAL,
+    ST_MATCH_IMAGE,
     kStageCount
 };
 void timer_begin(int stage, hipStream_t s);
@@ -190,6 +198,9 @@ void timer_end(int stage, hipStream_t s);
 void timer_collect();  // call after the stream has been synchronised
 int timer_enable(int on);
 int timer_read(double* ms, int64_t* launches, int n);
+// The open stage's work units live in *dev (a device counter read back by timer_work).
+void timer_note_work(const int64_t* dev);
+int timer_work(int64_t* work, int n);
 const char* stage_name(int stage);
 
 // Brackets the launches of one stage in the current scope.
@@ -315,7 +326,18 @@ struct MatchWs {
     double* part;         // per-segment top-4 lists of encoded scores
     double* lp_nx;        // reduced-precision form: ||x - mu|| per query slot
     PairLp* lp_pairs;     // reduced-precision form: per pair centre and scale
-    RerunWs rr;           // reduced-precision form: FP64 re-run of uncertified queries
+    RerunWs rr;           // FP64 re-runs: uncertified queries, the one-sided form's matching back
+    MatchSet* one_sided;  // the sets of the one-sided form's first direction (null: both in full)
+    int32_t* rank;        // norm-band matching: packed position of every slot in its set
+    int32_t* perm;        // norm-band matching: local row of every packed position
+    double* r2;           // norm-band matching: seed bound R^2 per query slot
+    uint32_t* skey;       // norm-band matching: sort key of every packed partner position
+    int32_t* wave_c0;     // norm-band matching: first partner chunk of every query wave's band
+    int32_t* wave_len;    // norm-band matching: chunks in the band
+    int32_t* wave_tile;   // norm-band matching: first tile of every wave (wave_cap + 1 entries)
+    int4* tinfo;          // norm-band matching: per tile {wave, set, first chunk, end chunk}
+    int64_t wave_cap;
+    int64_t tile_cap;
     int32_t* nn;
     double* best;
     double* second;

@@ -49,8 +49,9 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kColsPerBlock = kColsPerWave * kWavesPerBlock;
 constexpr int kBlock = 256;
 constexpr int kPlanThreads = 1024;
-constexpr int kTargetTiles = 4096;  // tiles wanted per launch (8 per persistent block)
-constexpr int kMaxSegs = 32;
+constexpr int kTargetTiles = 8192;  // tiles per launch the partial buffer is sized for
+constexpr int kMaxSegs = 128;
+constexpr double kTileOverhead = 2.0;  // fixed cost of a tile, in partner chunks
 constexpr int kSegChunks = 64;     // deepest tile (partner chunks) once a set needs more segments
 constexpr int kTopkBlocks = 512;    // persistent grid of the tile kernel (2 blocks per CU)
 constexpr double kPadScore = 0x1p1000;  // score of padding rows: finite, so it can carry an index
@@ -104,6 +105,29 @@ __device__ int64_t block_excl_scan64(int64_t v, int64_t* smem, int64_t& total) {
     return before + incl - v;
 }
 
+// Common segment count.  The persistent grid takes the tiles in rounds of
+// kTopkBlocks; a tile costs its sweep of partner chunks plus a fixed overhead
+// (query operands, list merges and stores) of about kTileOverhead chunks.  The
+// count with the least modelled time wins: enough tiles to keep every block
+// busy to the end, few enough that the overhead stays small.  From 8 on only
+// multiples of 8 are tried.
+__device__ int common_segs(int64_t col_blocks, int64_t chunk_work) {
+    if (col_blocks <= 0 || chunk_work <= 0) return 1;
+    int best = 1;
+    double best_t = INFINITY;
+    for (int S = 1; S <= kMaxSegs; S = S < 8 ? S + 1 : S + 8) {
+        const int64_t tiles = col_blocks * S;
+        const int64_t rounds = (tiles + kTopkBlocks - 1) / kTopkBlocks;
+        const double t = static_cast<double>(rounds) *
+                         (static_cast<double>(chunk_work) / static_cast<double>(tiles) + kTileOverhead);
+        if (t < best_t) {
+            best_t = t;
+            best = S;
+        }
+    }
+    return best;
+}
+
 __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __restrict__ sets, int n_sets, int kp,
                                                          int64_t part_cap, SetPlan* plan, DevStatus* st) {
     __shared__ int64_t smem[kPlanThreads / kWave];
@@ -112,8 +136,13 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     __shared__ int s_n[kPlanThreads];
     const int c = threadIdx.x;
     const bool live = c < n_sets;
-    const int n = live ? *sets[c].n : 0;
     const bool rows_only = live && (sets[c].flags & kSetRowsOnly);
+    int n = live ? *sets[c].n : 0;
+    if (rows_only && (c ^ 1) < n_sets) {
+        // rows that no query is matched against need neither slots nor packing
+        const MatchSet& o = sets[c ^ 1];
+        if ((o.flags & kSetRowsOnly) || *o.n == 0) n = 0;
+    }
     const int chunks = (n + kTileRows - 1) / kTileRows;
     const int cblocks = rows_only ? 0 : (n + kColsPerBlock - 1) / kColsPerBlock;
     const int n_q = rows_only ? 0 : n;  // queries that need partial lists
@@ -125,12 +154,6 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     s_n[c] = n;
     // one buffer descriptor spans a set's packed rows: keep them below 2 GiB
     if (static_cast<int64_t>(chunks) * kp * kTileRows * 8 > INT32_MAX) st->err_capacity = 1;
-    if (c == 0) {
-        int S = static_cast<int>(tb > 0 ? kTargetTiles / tb : 1);
-        S = S < 1 ? 1 : (S > kMaxSegs ? kMaxSegs : S);
-        if (S >= 8) S &= ~7;  // a multiple of 8: the tiles of a column block spread over the eight XCDs
-        s_segs = S;
-    }
     __syncthreads();
     // the partner's rows are split into segments (sets pair up as 2i, 2i + 1): at least the
     // common count, and enough that no tile sweeps more than kSegChunks chunks, so the tiles
@@ -138,6 +161,10 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
     const int p = c ^ 1;
     const int pch = (live && p < n_sets) ? s_chunks[p] : 0;
     const int pn = (live && p < n_sets) ? s_n[p] : 0;
+    int64_t tw;
+    block_excl_scan64((live && pn > 0) ? static_cast<int64_t>(cblocks) * pch : 0, smem, tw);
+    if (c == 0) s_segs = common_segs(tb, tw);
+    __syncthreads();
     const int deep = (pch + kSegChunks - 1) / kSegChunks;
     int segs = s_segs > deep ? s_segs : deep;
     segs = segs < pch ? segs : (pch > 0 ? pch : 1);
@@ -204,8 +231,10 @@ __device__ __forceinline__ void wave_max_norm(SetPlan* plan, int c, double v) {
     }
 }
 
+// Squared norms per slot (and rank[slot] = 0 when rank is given).
 __global__ __launch_bounds__(kBlock) void row_norms(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
-                                                    int dim, double* __restrict__ n2, const DevStatus* st) {
+                                                    int dim, double* __restrict__ n2, const DevStatus* st,
+                                                    int32_t* __restrict__ rank) {
 #pragma clang fp contract(off)
     const int64_t total = st->total_queries;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
@@ -213,11 +242,23 @@ __global__ __launch_bounds__(kBlock) void row_norms(const MatchSet* __restrict__
         const int c = find_set(n_sets, t, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
         const float* x = set_row(sets[c], static_cast<int>(t - plan[c].q_off), dim);
         double acc = 0.0;
-        for (int k = 0; k < dim; ++k) {
+        int k = 0;
+        for (; k + 8 <= dim; k += 8) {  // eight loads in flight, the sum in order
+            float xs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xs[u] = x[k + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double v = xs[u];
+                acc = acc + v * v;
+            }
+        }
+        for (; k < dim; ++k) {
             const double v = x[k];
             acc = acc + v * v;
         }
         n2[t] = acc;
+        if (rank) rank[t] = 0;
         wave_max_norm(plan, c, acc);
     }
 }
@@ -475,10 +516,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
 
 // ------------------------------------------------------ exact re-scoring --
 
+// The plain FP64 sum in dimension order; the loads of eight dimensions issue
+// together (the sum keeps its order).
 __device__ __forceinline__ double exact_d2(const float* __restrict__ x, const float* __restrict__ y, int dim) {
 #pragma clang fp contract(off)
     double acc = 0.0;
-    for (int t = 0; t < dim; ++t) {
+    int t = 0;
+    for (; t + 8 <= dim; t += 8) {
+        float xs[8], ys[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            xs[u] = x[t + u];
+            ys[u] = y[t + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double df = static_cast<double>(xs[u]) - static_cast<double>(ys[u]);
+            acc = acc + df * df;
+        }
+    }
+    for (; t < dim; ++t) {
         const double df = static_cast<double>(x[t]) - static_cast<double>(y[t]);
         acc = acc + df * df;
     }
@@ -1123,6 +1180,7 @@ __global__ __launch_bounds__(kBlock) void rescore_lp(const MatchSet* __restrict_
     for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
          slot += gs) {
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the quad: no queries, no partials
         const int p = c ^ 1;
         const SetPlan qc = plan[c];
         const int j = static_cast<int>(slot - qc.q_off);
@@ -1267,6 +1325,631 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
     if (blockIdx.x == 0 && threadIdx.x == 0 && st2->err_capacity) st->err_capacity = 1;
 }
 
+// ------------------------------------------------------ one-sided form --
+//
+// A row can only be in a mutual pair if it is the nearest neighbour of some
+// row of the other set.  So each pair is matched in one direction first, with
+// the smaller set as queries (the other set rows only), and then only the
+// image of that nearest-neighbour map is matched back.
+
+// Copy of the sets with the larger set of each pair (the second on a tie)
+// marked rows-only.
+__global__ void one_sided_sets(const MatchSet* __restrict__ sets, int n_sets, MatchSet* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_sets) return;
+    MatchSet m = sets[c];
+    if ((c ^ 1) < n_sets) {
+        const int mine = *m.n, other = *sets[c ^ 1].n;
+        const bool rows_only = (c & 1) ? mine >= other : mine > other;
+        if (rows_only) m.flags |= kSetRowsOnly;
+    }
+    out[c] = m;
+}
+
+// flag[slot] = 1 for every rows-only slot that some query has as its nearest
+// neighbour (flag cleared before); nn of the rows-only slots <- -1 until the
+// matching back fills the flagged ones.
+__global__ __launch_bounds__(kBlock) void image_flags(const MatchSet* __restrict__ sets,
+                                                      const SetPlan* __restrict__ plan, int n_sets,
+                                                      int32_t* __restrict__ nn, int32_t* __restrict__ flag,
+                                                      const DevStatus* st) {
+    const int64_t total = st->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+        const int c = find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
+        if (sets[c].flags & kSetRowsOnly) {
+            nn[slot] = -1;
+        } else {
+            const int j = nn[slot];
+            if (j >= 0 && (c ^ 1) < n_sets) flag[plan[c ^ 1].q_off + j] = 1;
+        }
+    }
+}
+
+// Exact re-scans of the matching back, counted with the queries they answer.
+__global__ void add_rescans(const SetPlan* __restrict__ plan2, int n_sets, SetPlan* __restrict__ plan) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n_sets) plan[c].n_fb += plan2[2 * c].n_fb;
+}
+
+// ------------------------------------------------------------ norm bands --
+//
+// Exact pruning of the FP64 form by the triangle inequality
+// ||x - y|| >= | ||x|| - ||y|| |.  For every query the exact distances to the
+// 64 partner rows nearest to it in norm give R^2 (the second smallest of
+// them): the true second nearest neighbour is no farther, so a partner row
+// whose norm differs from the query's by more than R (widened for rounding)
+// can be neither of the two nearest, ties included.  Partner rows are packed
+// in order of (squared norm, index), so the chunks' norm ranges ascend and a
+// band of norms is a contiguous chunk range; queries are packed in order of
+// (class of R, norm, index), so that the 64 queries of one wavefront need one
+// narrow band.  Each wave's band is cut into tiles of at most T chunks; the
+// tile lists are merged, re-scored and certified as in the full form (the rows
+// outside the band are farther than R, and two rows inside are within it).
+
+constexpr int kBandWave = kColsPerWave;  // queries per band wave (one wavefront)
+constexpr int kRankBlock = 256;          // keys per rank work item
+constexpr int kRankSpan = 1024;          // keys compared per rank work item
+constexpr int kBandTiles = 8192;         // band tiles the partial buffer holds beyond one per wave
+constexpr int kSeedRows = kWave;         // partner rows around the query's norm for R
+constexpr int kBandSlots = kTopkBlocks * kWavesPerBlock;  // wavefronts of the band tile kernel
+
+__global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
+                                                         SetPlan* plan, DevStatus* st) {
+    __shared__ int64_t smem[kPlanThreads / kWave];
+    const int c = threadIdx.x;
+    const bool live = c < n_sets;
+    const bool rows_only = live && (sets[c].flags & kSetRowsOnly);
+    int n = live ? *sets[c].n : 0;
+    if (rows_only) {
+        // rows that no query is matched against need neither slots nor packing
+        if ((c ^ 1) >= n_sets || (sets[c ^ 1].flags & kSetRowsOnly) || *sets[c ^ 1].n == 0) n = 0;
+    }
+    const int chunks = (n + kTileRows - 1) / kTileRows;
+    const int waves = (live && !rows_only) ? (n + kBandWave - 1) / kBandWave : 0;
+    const int64_t items = static_cast<int64_t>((n + kRankBlock - 1) / kRankBlock) * ((n + kRankSpan - 1) / kRankSpan);
+    int64_t tq, tc, tw, ti;
+    const int64_t q_off = block_excl_scan64(n, smem, tq);
+    const int64_t c_off = block_excl_scan64(chunks, smem, tc);
+    const int64_t w_off = block_excl_scan64(waves, smem, tw);
+    const int64_t i_off = block_excl_scan64(items, smem, ti);
+    // one buffer descriptor spans a set's packed rows: keep them below 2 GiB
+    if (static_cast<int64_t>(chunks) * kp * kTileRows * 8 > INT32_MAX) st->err_capacity = 1;
+    if (live) {
+        SetPlan pl;
+        pl.n = n;
+        pl.q_off = static_cast<int32_t>(q_off);
+        pl.chunk_off = static_cast<int32_t>(c_off);
+        pl.chunks = chunks;
+        pl.tile_off = 0;
+        pl.cblocks = waves;
+        pl.segs = 0;
+        pl.n_fb = 0;
+        pl.part_off = 0;
+        pl.max_norm_bits = 0ull;
+        pl.wave_off = static_cast<int32_t>(w_off);
+        pl.rank_off = static_cast<int32_t>(i_off);
+        plan[c] = pl;
+    }
+    if (c == 0) {
+        st->total_queries = static_cast<int32_t>(tq);
+        st->total_chunks = tc;
+        st->total_waves = static_cast<int32_t>(tw);
+        st->rank_items = static_cast<int32_t>(ti);
+        st->total_tiles = 0;
+        st->tile_next = 0;
+        st->n_fallback = 0;
+        st->band_step = 0;
+    }
+}
+
+// 32-bit sort key of a slot.  Partners: the top 32 bits of the squared norm's
+// FP64 pattern (an order-preserving truncation: a key k stands for squared
+// norms in [dec(k), dec(k + 1)), dec(k) = the double with bits k << 32).
+// Queries: (class of R^2, top 23 bits of the squared norm), the class being
+// the binary exponent of R^2 halved (R in octaves).
+__device__ __forceinline__ uint32_t norm_key(double n2) {
+    return static_cast<uint32_t>(static_cast<unsigned long long>(__double_as_longlong(n2)) >> 32);
+}
+
+__device__ __forceinline__ uint32_t band_key(bool partner, double n2, double r2) {
+    const unsigned long long nb = static_cast<unsigned long long>(__double_as_longlong(n2));
+    if (partner) return static_cast<uint32_t>(nb >> 32);
+    const int e = static_cast<int>((static_cast<unsigned long long>(__double_as_longlong(r2)) >> 52) & 0x7ffull);
+    const int cls = min(max(e - 1023 + 256, 0), 511) >> 1;
+    return (static_cast<uint32_t>(cls) << 24) | static_cast<uint32_t>(nb >> 40);
+}
+
+// Rank of every slot of the sets of one role (rows-only partners, or query
+// sets) within its set by (key, local index), a unique 64-bit value: a work
+// item counts, for kRankBlock values, the smaller ones among kRankSpan others
+// of the same set and adds the counts to rank[] (cleared by row_norms).
+__global__ __launch_bounds__(kRankBlock) void rank_slots(const MatchSet* __restrict__ sets,
+                                                         const SetPlan* __restrict__ plan, int n_sets, int partner,
+                                                         const double* __restrict__ n2,
+                                                         const double* __restrict__ r2, int32_t* __restrict__ rank,
+                                                         const DevStatus* st) {
+    __shared__ unsigned long long s_key[kRankSpan];
+    const bool pr = partner != 0;
+    const int64_t total = st->rank_items;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_set(n_sets, item, [&](int s) { return static_cast<int64_t>(plan[s].rank_off); });
+        if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;  // uniform over the block
+        const SetPlan pc = plan[c];
+        const int local = static_cast<int>(item - pc.rank_off);
+        const int kr = (pc.n + kRankSpan - 1) / kRankSpan;
+        const int i = (local / kr) * kRankBlock + static_cast<int>(threadIdx.x);
+        const int j0 = (local % kr) * kRankSpan;
+        const int nj = min(kRankSpan, pc.n - j0);
+        __syncthreads();  // the previous item's keys are read no more
+        for (int e = threadIdx.x; e < kRankSpan; e += kRankBlock) {
+            unsigned long long v = ~0ull;  // past the set: larger than every key
+            if (e < nj) {
+                const int64_t sl = pc.q_off + j0 + e;
+                v = (static_cast<unsigned long long>(band_key(pr, n2[sl], pr ? 0.0 : r2[sl])) << 32) |
+                    static_cast<uint32_t>(j0 + e);
+            }
+            s_key[e] = v;
+        }
+        __syncthreads();
+        if (i < pc.n) {
+            const int64_t sl = pc.q_off + i;
+            const unsigned long long ki =
+                (static_cast<unsigned long long>(band_key(pr, n2[sl], pr ? 0.0 : r2[sl])) << 32) | static_cast<uint32_t>(i);
+            int cnt = 0;
+#pragma unroll 16
+            for (int e = 0; e < kRankSpan; ++e) cnt += s_key[e] < ki ? 1 : 0;
+            if (cnt) atomicAdd(&rank[sl], cnt);
+        }
+    }
+}
+
+// Packs the rows of the sets of one role at their ranks (layout of pack_rows:
+// k-major chunks of 16 rows, the squared norm at k = dim, padding rows scored
+// kPadScore) and records perm[q_off + position] = local row (and, for
+// partners, the sort key of the position).
+__global__ __launch_bounds__(kBlock) void scatter_pack(const MatchSet* __restrict__ sets,
+                                                       const SetPlan* __restrict__ plan, int n_sets, int dim, int kp,
+                                                       int partner, const double* __restrict__ n2,
+                                                       const int32_t* __restrict__ rank, double* __restrict__ pk,
+                                                       int32_t* __restrict__ perm, uint32_t* __restrict__ skey,
+                                                       DevStatus* st) {
+    const bool pr = partner != 0;
+    const int64_t total = static_cast<int64_t>(st->total_queries) * kp;
+    const int64_t pads = static_cast<int64_t>(n_sets) * kTileRows * kp;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total + pads; t += gs) {
+        if (t < total) {
+            const int64_t slot = t / kp;
+            const int k = static_cast<int>(t % kp);
+            const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+            if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;
+            const SetPlan pc = plan[c];
+            const int j = static_cast<int>(slot - pc.q_off);
+            const int pos = rank[slot];
+            if (pos < 0 || pos >= pc.n) {  // ranks are a permutation of 0 .. n - 1
+                st->err_capacity = 1;
+                continue;
+            }
+            double v = 0.0;
+            if (k < dim) v = set_row(sets[c], j, dim)[k];
+            else if (k == dim) v = n2[slot];
+            pk[(static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp + k) * kTileRows + pos % kTileRows] = v;
+            if (k == 0) {
+                perm[pc.q_off + pos] = j;
+                if (pr) skey[pc.q_off + pos] = norm_key(n2[slot]);
+            }
+        } else {
+            const int64_t u = t - total;
+            const int c = static_cast<int>(u / (kTileRows * kp));
+            const int i = static_cast<int>((u / kp) % kTileRows);
+            const int k = static_cast<int>(u % kp);
+            if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;
+            const SetPlan pc = plan[c];
+            const int pos = pc.n + i;
+            if (pos >= pc.chunks * kTileRows) continue;
+            pk[(static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp + k) * kTileRows + pos % kTileRows] =
+                k == dim ? kPadScore : 0.0;
+        }
+    }
+}
+
+// First position in [0, n) at which below(position) is false, where below
+// holds on a prefix: a 64-way search by one wavefront (three rounds for 2^18).
+template <class F>
+__device__ __forceinline__ int wave_search(int n, F below) {
+    int lo = 0, hi = n;
+    while (lo < hi) {  // uniform over the wave
+        const int stride = (hi - lo + kWave - 1) / kWave;
+        const int probe = lo + (lane_id() + 1) * stride - 1;
+        const bool b = probe < hi && below(probe);
+        const int cnt = __popcll(ballot(b));
+        const int nlo = lo + cnt * stride;
+        hi = min(hi, lo + (cnt + 1) * stride - 1);
+        lo = nlo;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+// One wavefront per query slot: R^2 = the second smallest exact distance
+// (the plain FP64 sum in dimension order, as exact_d2) to the kSeedRows
+// partner rows around the query's norm key in the partner's packed order, read
+// from the packed chunks; infinite when the partner has fewer than two rows.
+__global__ __launch_bounds__(kBlock) void band_seeds(const MatchSet* __restrict__ sets,
+                                                     const SetPlan* __restrict__ plan, int n_sets, int dim, int kp,
+                                                     const double* __restrict__ pk, const double* __restrict__ n2,
+                                                     const uint32_t* __restrict__ skey, double* __restrict__ r2,
+                                                     const DevStatus* st) {
+#pragma clang fp contract(off)
+    const int lane = lane_id();
+    const int64_t total = st->total_queries;
+    const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; slot < total;
+         slot += gw) {
+        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the wave
+        const int p = c ^ 1;
+        const int np = p < n_sets ? plan[p].n : 0;
+        if (np < 2) {
+            if (lane == 0) r2[slot] = INFINITY;
+            continue;
+        }
+        const SetPlan pc = plan[p];
+        const uint32_t kq = norm_key(n2[slot]);
+        const uint32_t* pkey = skey + pc.q_off;
+        const int at = wave_search(np, [&](int pos) { return pkey[pos] < kq; });
+        const int nw = min(np, kSeedRows);
+        const int w0 = min(max(at - nw / 2, 0), np - nw);
+        // lane L < dim holds the query's value L
+        const float* y = set_row(sets[c], static_cast<int>(slot - plan[c].q_off), dim);
+        const float yv = lane < dim ? y[lane] : 0.0f;
+        const int pos = w0 + min(lane, nw - 1);
+        const double* xr = pk + (static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp) * kTileRows + pos % kTileRows;
+        double acc = 0.0;
+        int k = 0;
+        for (; k + 8 <= dim; k += 8) {
+            double xs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xs[u] = xr[(k + u) * kTileRows];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double df = xs[u] - static_cast<double>(__shfl(yv, k + u, kWave));
+                acc = acc + df * df;
+            }
+        }
+        for (; k < dim; ++k) {
+            const double df = xr[k * kTileRows] - static_cast<double>(__shfl(yv, k, kWave));
+            acc = acc + df * df;
+        }
+        const double d = lane < nw ? acc : INFINITY;
+        const double m1 = wave_min_d(d);
+        const int n_eq = __popcll(ballot(d == m1));
+        const double m2 = n_eq >= 2 ? m1 : wave_min_d(d == m1 ? INFINITY : d);
+        if (lane == 0) r2[slot] = m2;
+    }
+}
+
+// One wavefront per query wave: the band of norms its queries need,
+// [nu - R - m, nu + R + m] over the wave with m = 2^-38 (nu + R) for the
+// rounding of the norms and distances, and the partner chunks that can hold a
+// squared norm in [lo^2 (1 - 2^-50), hi^2 (1 + 2^-50)], found on the chunks'
+// first and last sort keys (a key k holds squared norms in [dec(k), dec(k + 1))).
+__global__ __launch_bounds__(kBlock) void band_waves(const MatchSet* __restrict__ sets,
+                                                     const SetPlan* __restrict__ plan, int n_sets,
+                                                     const double* __restrict__ n2, const double* __restrict__ r2,
+                                                     const int32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ skey,
+                                                     int32_t* __restrict__ wave_c0, int32_t* __restrict__ wave_len,
+                                                     const DevStatus* st) {
+    const int lane = lane_id();
+    const int64_t total = st->total_waves;
+    const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t w = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; w < total; w += gw) {
+        const int c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+        const SetPlan qc = plan[c];
+        const int p = c ^ 1;
+        const int np = p < n_sets ? plan[p].n : 0;
+        const int pos = static_cast<int>(w - qc.wave_off) * kBandWave + lane;
+        double lo = INFINITY, hi = -INFINITY;
+        const int jq = pos < qc.n ? perm[qc.q_off + pos] : -1;
+        if (jq >= 0 && jq < qc.n) {
+            const int64_t sl = qc.q_off + jq;
+            const double nu = sqrt(n2[sl]);
+            const double R = sqrt(r2[sl]);
+            const double m = 0x1p-38 * (nu + R);
+            lo = nu - R - m;
+            hi = nu + R + m;
+        }
+        lo = wave_min_d(lo);
+        hi = wave_max_d(hi);
+        int k0 = 0, k1 = 0;
+        if (np > 0 && lo <= hi) {
+            const SetPlan pc = plan[p];
+            const uint32_t* pkey = skey + pc.q_off;
+            const int pch = pc.chunks;
+            if (lo > 0.0) {
+                // chunks whose last key is below that of lo^2 hold only squared norms below it
+                const uint32_t klo = norm_key(lo * lo * (1.0 - 0x1p-50));
+                k0 = wave_search(pch, [&](int k) { return pkey[min(k * kTileRows + kTileRows - 1, np - 1)] < klo; });
+            }
+            if (hi == INFINITY) {
+                k1 = pch;
+            } else {
+                // chunks whose first key is above that of hi^2 hold only squared norms above it
+                const uint32_t khi = norm_key(hi * hi * (1.0 + 0x1p-50));
+                k1 = wave_search(pch, [&](int k) { return pkey[k * kTileRows] <= khi; });
+            }
+        }
+        if (lane == 0) {
+            wave_c0[w] = k0;
+            wave_len[w] = k1 > k0 ? k1 - k0 : 0;
+        }
+    }
+}
+
+// Cuts the bands into tiles of at most T chunks, T from the rounds model of
+// common_segs over the band kernel's wavefronts (tiles ~ total / T + waves / 2),
+// then each wave's first tile and every tile's {wave, set, first chunk, end}.
+__global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restrict__ plan, int n_sets,
+                                                          const int32_t* __restrict__ wave_c0,
+                                                          const int32_t* __restrict__ wave_len,
+                                                          int32_t* __restrict__ wave_tile, int4* __restrict__ tinfo,
+                                                          int64_t tile_cap, DevStatus* st) {
+    __shared__ int64_t smem[kPlanThreads / kWave];
+    const int W = st->total_waves;
+    int64_t len_sum = 0;
+    for (int w = threadIdx.x; w < W; w += kPlanThreads) len_sum += wave_len[w];
+    int64_t tot_len;
+    block_excl_scan64(len_sum, smem, tot_len);
+    int T = 1 << 30;  // one tile per wave always fits
+    double best_t = INFINITY;
+    for (int cand = 2; cand <= 4096; cand *= 2) {
+        for (int half = 0; half < 2; ++half) {
+            const int t_len = half ? cand + cand / 2 : cand;
+            const double tiles = static_cast<double>(tot_len) / t_len + 0.5 * W;
+            if (tiles + W > static_cast<double>(tile_cap)) continue;  // the bound total / T + W must fit
+            const double rounds = ceil(tiles / kBandSlots);
+            const double t = rounds * (static_cast<double>(tot_len) / fmax(tiles, 1.0) + kTileOverhead);
+            if (t < best_t) {
+                best_t = t;
+                T = t_len;
+            }
+        }
+    }
+    int64_t carry = 0;
+    int64_t pairs = 0;  // query-row distances of the tiles (real queries and rows)
+    for (int base = 0; base < W; base += kPlanThreads) {
+        const int w = base + static_cast<int>(threadIdx.x);
+        const int L = w < W ? wave_len[w] : 0;
+        const int nt = (L + T - 1) / T;
+        int64_t round_total;
+        const int64_t off = carry + block_excl_scan64(nt, smem, round_total);
+        if (w < W) {
+            wave_tile[w] = static_cast<int32_t>(off);
+            const int c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+            const int c0 = wave_c0[w];
+            if (L > 0) {
+                const int nq = min(kBandWave, plan[c].n - (w - plan[c].wave_off) * kBandWave);
+                const int np = plan[c ^ 1].n;
+                pairs += static_cast<int64_t>(nq) * (min((c0 + L) * kTileRows, np) - c0 * kTileRows);
+            }
+            if (off + nt <= tile_cap) {
+                for (int k = 0; k < nt; ++k)
+                    tinfo[off + k] = make_int4(w, c, c0 + k * T, min(c0 + (k + 1) * T, c0 + L));
+            }
+        }
+        carry += round_total;
+    }
+    int64_t pairs_total;
+    block_excl_scan64(pairs, smem, pairs_total);
+    if (threadIdx.x == 0) {
+        st->band_pairs = pairs_total;
+        wave_tile[W] = static_cast<int32_t>(carry);
+        st->total_tiles = static_cast<int32_t>(carry);
+        st->tile_next = 0;
+        st->band_step = T;
+        if (carry > tile_cap) st->err_capacity = 1;
+    }
+}
+
+// Band tiles: each wavefront pulls tiles (64 queries of one wave against a
+// range of partner chunks) from an atomic queue.  The partner chunk operands
+// come straight from memory with raw buffer loads, one chunk ahead of the
+// products; the waves share no data, so there is no barrier.
+template <int KS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 ? 2 : 1))) void band_tiles(
+    const SetPlan* __restrict__ plan, const double* __restrict__ pk, int dim, const int4* __restrict__ tinfo,
+    double* __restrict__ part, DevStatus* st) {
+    constexpr int kp = 4 * KS;
+    constexpr int kChunk = kp * kTileRows;
+    const int lane = lane_id();
+    const int g = lane >> 4;
+    const int l16 = lane & 15;
+    const int total = st->err_capacity ? 0 : st->total_tiles;
+    while (true) {
+        int tile = 0;
+        if (lane == 0) tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
+        tile = __shfl(tile, 0, kWave);
+        if (tile >= total) break;
+        const int4 ti = tinfo[tile];
+        const SetPlan qc = plan[ti.y];
+        const SetPlan pc = plan[ti.y ^ 1];
+        const int col0 = (ti.x - qc.wave_off) * kBandWave;
+        double bq[kTilesPerWave][KS];
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) {
+            const int chunk = min(col0 / kTileCols + t, qc.chunks - 1);
+            const double* src = pk + static_cast<int64_t>(qc.chunk_off + chunk) * kChunk;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int k = 4 * s + g;
+                const double scale = k < dim ? -2.0 : 0.0;
+                const double add = k == dim ? 1.0 : 0.0;
+                bq[t][s] = src[k * kTileRows + l16] * scale + add;
+            }
+        }
+        double top[kTilesPerWave][4];
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) top[t][0] = top[t][1] = top[t][2] = top[t][3] = INFINITY;
+        const unsigned keep = keep_mask(row_bits(pc.chunks));
+        const int c_begin = ti.z, c_end = ti.w;
+        if (c_begin < c_end) {  // uniform over the wave
+            const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<double*>(pk + static_cast<int64_t>(pc.chunk_off) * kChunk), 0,
+                static_cast<int>(min(static_cast<int64_t>(pc.chunks) * kChunk * 8, static_cast<int64_t>(INT32_MAX))),
+                static_cast<int>(kBufferWord3));
+            double a[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                a[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                       rows, ((c_begin * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
+            for (int c = c_begin; c < c_end; ++c) {
+                const int cn = min(c + 1, c_end - 1);
+                double an[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    an[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                            rows, ((cn * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
+                __builtin_amdgcn_sched_barrier(0);
+                doublex4 acc[kTilesPerWave];
+                chunk_mfma<KS>(acc, a, bq);
+                const unsigned row0 = static_cast<unsigned>(c * kTileRows + g);
+#pragma unroll
+                for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], acc[t], row0, keep);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < KS; ++s) a[s] = an[s];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) {
+            merge_lane(top[t], 16);
+            merge_lane(top[t], 32);
+            const int col = kTileCols * t + l16;
+            if (g == 0 && col0 + col < qc.n) {
+                double* dst = part + (static_cast<int64_t>(tile) * kBandWave + col) * kTopK;
+                dst[0] = top[t][0];
+                dst[1] = top[t][1];
+                dst[2] = top[t][2];
+                dst[3] = top[t][3];
+            }
+        }
+    }
+}
+
+// As rescore, for the band tiles: the query's lists are those of its wave's
+// tiles, and candidates are packed partner positions mapped back through perm.
+__global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
+                                                       int dim, const double* __restrict__ part,
+                                                       const double* __restrict__ n2, const int32_t* __restrict__ rank,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ wave_tile, int32_t* __restrict__ nn,
+                                                       double* __restrict__ best, double* __restrict__ second,
+                                                       int32_t* __restrict__ failed, DevStatus* st) {
+    const int64_t total = st->err_capacity ? 0 : st->total_queries;  // no tiles were computed
+    const int q = lane_id() & (kQuad - 1);
+    const int quad0 = lane_id() & ~(kQuad - 1);
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * (kBlock / kQuad);
+    for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
+         slot += gs) {
+        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the quad
+        const int p = c ^ 1;
+        const SetPlan qc = plan[c];
+        const int j = static_cast<int>(slot - qc.q_off);
+        const int np = p < n_sets ? plan[p].n : 0;
+        if (np == 0) {
+            if (q == 0) {
+                nn[slot] = -1;
+                best[slot] = INFINITY;
+                second[slot] = INFINITY;
+                failed[slot] = 0;
+            }
+            continue;
+        }
+        const int pos = min(max(rank[slot], 0), qc.n - 1);
+        const int w = qc.wave_off + pos / kBandWave;
+        const int col = pos % kBandWave;
+        const int t0 = wave_tile[w], t1 = wave_tile[w + 1];
+        double top[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+        for (int t = t0 + q; t < t1; t += kQuad) {
+            const double* src = part + (static_cast<int64_t>(t) * kBandWave + col) * kTopK;
+            merge4(top, src[0], src[1], src[2], src[3]);
+        }
+        merge_lane(top, 1);
+        merge_lane(top, 2);
+        const SetPlan pc = plan[p];
+        const int bits = row_bits(pc.chunks);
+        const double mine = q == 0 ? top[0] : (q == 1 ? top[1] : (q == 2 ? top[2] : top[3]));
+        int row = -1;
+        if (mine < kNoScore) {
+            const int at = decode_row(mine, keep_mask(bits));
+            if (at < np) row = perm[pc.q_off + at];  // only real rows are ever candidates
+            if (row >= np) row = -1;
+        }
+        const double d = row >= 0 ? exact_d2(set_row(sets[p], row, dim), set_row(sets[c], j, dim), dim) : INFINITY;
+        double dq[kQuad];
+        int rq[kQuad];
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            dq[k] = __shfl(d, quad0 + k, kWave);
+            rq[k] = __shfl(row, quad0 + k, kWave);
+        }
+        if (q != 0) continue;
+        double b1 = INFINITY, b2 = INFINITY;
+        int j1 = -1;
+        int ncand = 0;
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const int i = rq[k];
+            if (i < 0) continue;
+            ++ncand;
+            const double dk = dq[k];
+            if (dk < b1 || (dk == b1 && i < j1)) {
+                b2 = b1;
+                b1 = dk;
+                j1 = i;
+            } else if (dk < b2) {
+                b2 = dk;
+            }
+        }
+        bool ok;
+        if (ncand >= np) {
+            ok = true;  // every row was a candidate
+        } else {
+            // rows outside the band are farther than R >= the second distance; inside it,
+            // the bound of the full form: MFMA error 128 u (2 max ||x||^2 + 2 ||y||^2)
+            // plus the encoding error 2^(bits - 52) |t|
+            const double mx = __longlong_as_double(static_cast<long long>(pc.max_norm_bits));
+            const double rel = 0x1p-46 + ldexp(1.0, bits - 52);
+            const double E = rel * (2.0 * mx + 2.0 * n2[slot]) + 1e-300;
+            const double bound = top[3] + n2[slot] - E;
+            ok = ncand == 4 && b2 < bound;
+        }
+        if (ok) {
+            nn[slot] = j1;
+            best[slot] = b1;
+            second[slot] = b2;
+        } else {
+            atomicAdd(&plan[c].n_fb, 1);
+        }
+        failed[slot] = ok ? 0 : 1;
+    }
+}
+
+
 }  // namespace
 
 MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
@@ -1274,8 +1957,10 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     w.kp = (dim + 1 <= 36) ? 36 : 68;  // 4 KS for the two kernel instantiations (dim <= 64)
     w.q_cap = std::max<int64_t>(q_cap, 1);
     w.chunk_cap = q_cap / kTileRows + n_sets + 1;
-    // segments are chosen so that queries x segments stays near kTargetTiles x kColsPerBlock
-    w.part_cap = kTopK * (w.q_cap + 2 * static_cast<int64_t>(kTargetTiles) * kColsPerBlock);
+    // the modelled segment counts keep queries x segments within about kTargetTiles x kColsPerBlock
+    w.part_cap = kTopK * (w.q_cap + static_cast<int64_t>(kTargetTiles) * kColsPerBlock);
+    // the band tiles hold kBandWave lists each
+    w.part_cap = std::max<int64_t>(w.part_cap, kTopK * kBandWave * (kBandTiles + w.q_cap / kBandWave + n_sets + 1));
     w.plan = c.take<SetPlan>(static_cast<size_t>(std::max(n_sets, 1)));
     w.pk = c.take<double>(static_cast<size_t>(w.chunk_cap) * w.kp * kTileRows);
     w.n2 = c.take<double>(static_cast<size_t>(w.q_cap));
@@ -1290,8 +1975,20 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     w.flag = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.pos = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.scan_tmp = c.take<int64_t>(scan_temp_elems(w.q_cap));
+    w.wave_cap = w.q_cap / kBandWave + n_sets + 1;
+    w.tile_cap = kBandTiles + w.wave_cap;
+    w.rank = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.perm = c.take<int32_t>(static_cast<size_t>(w.q_cap));
+    w.r2 = c.take<double>(static_cast<size_t>(w.q_cap));
+    w.skey = c.take<uint32_t>(static_cast<size_t>(w.q_cap));
+    w.wave_c0 = c.take<int32_t>(static_cast<size_t>(w.wave_cap));
+    w.wave_len = c.take<int32_t>(static_cast<size_t>(w.wave_cap));
+    w.wave_tile = c.take<int32_t>(static_cast<size_t>(w.wave_cap + 1));
+    w.tinfo = c.take<int4>(static_cast<size_t>(w.tile_cap));
     w.rr = RerunWs{};
+    w.one_sided = nullptr;
     if (rerun && 2 * n_sets <= kPlanThreads) {
+        w.one_sided = c.take<MatchSet>(static_cast<size_t>(n_sets));
         w.rr.st = c.take<DevStatus>(1);
         w.rr.sets = c.take<MatchSet>(static_cast<size_t>(2 * n_sets));
         w.rr.f_slot = c.take<int32_t>(static_cast<size_t>(w.q_cap));
@@ -1309,17 +2006,30 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
 kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                     hipStream_t s);
 kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
+kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s);
+
+kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
 
 kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                        const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s) {
     if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
-    if (prec == KMG_FP16 || prec == KMG_BF16) {
-        KMG_TRY(match_lp(sets, n_sets, dim, prec, st, w, s));
-    } else {
-        KMG_TRY(match_fp64(sets, n_sets, dim, st, w, s));
+    // one-sided form when the workspace holds the second plan, else both directions in full
+    const MatchSet* first = sets;
+    if (w.one_sided) {
+        one_sided_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets, n_sets, w.one_sided);
+        KMG_TRY(launch_status());
+        first = w.one_sided;
     }
+    if (prec == KMG_FP16 || prec == KMG_BF16) {
+        KMG_TRY(match_lp(first, n_sets, dim, prec, st, w, s));
+    } else if (w.one_sided) {
+        KMG_TRY(match_band(first, n_sets, dim, st, w, s));
+    } else {
+        KMG_TRY(match_fp64(first, n_sets, dim, st, w, s));
+    }
+    if (w.one_sided) KMG_TRY(match_back(first, n_sets, dim, st, w, s));
     {
         StageScope sc(ST_MATCH_MUTUAL, s);
         mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
@@ -1394,7 +2104,7 @@ kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStat
     Carver c2(w.rr.region, w.rr.region_bytes);
     const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
     if (!c2.fits()) return KMG_ERR_WORKSPACE;
-    KMG_TRY(match_fp64(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
+    KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
     {
         StageScope sc(ST_MATCH_RESCORE, s);
         rerun_scatter<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best,
@@ -1413,7 +2123,7 @@ kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
         StageScope sc(ST_MATCH_PACK, s);
         plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st);
         KMG_TRY(launch_status());
-        row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st);
+        row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
         pack_rows<<<grid_cap(w.chunk_cap * w.kp * kTileRows, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim,
                                                                                      w.kp, w.n2, w.pk, st);
@@ -1435,6 +2145,90 @@ kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
         KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
         rescore<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2, w.nn,
                                                                     w.best, w.second, w.flag, st);
+        KMG_TRY(launch_status());
+        KMG_TRY(exact_fallback(sets, n_sets, dim, st, w, s));
+    }
+    return KMG_OK;
+}
+
+// The matching back of the one-sided form: the rows-only rows that are some
+// query's nearest neighbour are matched in FP64 against their full partner
+// sets (the re-run machinery with the image as its list), and the answers
+// land in their main slots.
+kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s) {
+    StageScope sc(ST_MATCH_IMAGE, s);
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
+    image_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.nn, w.flag, st);
+    KMG_TRY(launch_status());
+    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s));
+    rerun_gather<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.flag, w.pos, w.rr.f_slot,
+                                                             w.rr.f_row, st);
+    KMG_TRY(launch_status());
+    rerun_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets1, w.plan, n_sets, w.pos, w.rr.f_total, w.q_cap, w.rr.f_row,
+                                                   w.rr.f_count, w.rr.sets);
+    KMG_TRY(launch_status());
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.rr.st), 0u, sizeof(DevStatus) / 4, s));
+    Carver c2(w.rr.region, w.rr.region_bytes);
+    const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
+    if (!c2.fits()) return KMG_ERR_WORKSPACE;
+    KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
+    rerun_scatter<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best,
+                                                               w2.second, w.plan, w.pos, w.rr.f_slot, w.nn, w.best,
+                                                               w.second, st);
+    KMG_TRY(launch_status());
+    add_rescans<<<grid_for(n_sets, 64), 64, 0, s>>>(w2.plan, n_sets, w.plan);
+    return launch_status();
+}
+
+// The FP64 form with norm bands, for sets paired as (queries, rows-only
+// partner) in either order: partner rows ranked and packed by norm, seed
+// bounds, queries ranked by (class, norm) and packed, bands, band tiles, exact
+// re-score and certificate, exact scans for the rest.
+kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s) {
+    const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
+    if (ks != 9 && ks != 17) return KMG_ERR_ARG;
+    {
+        StageScope sc(ST_MATCH_PACK, s);
+        plan_band<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.plan, st);
+        KMG_TRY(launch_status());
+        row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, w.rank);
+        KMG_TRY(launch_status());
+        rank_slots<<<kPersistBlocks, kRankBlock, 0, s>>>(sets, w.plan, n_sets, 1, w.n2, w.r2, w.rank, st);
+        KMG_TRY(launch_status());
+        scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, 1, w.n2,
+                                                                         w.rank, w.pk, w.perm, w.skey, st);
+        KMG_TRY(launch_status());
+        band_seeds<<<grid_cap(w.q_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, w.pk, w.n2,
+                                                                        w.skey, w.r2, st);
+        KMG_TRY(launch_status());
+        rank_slots<<<kPersistBlocks, kRankBlock, 0, s>>>(sets, w.plan, n_sets, 0, w.n2, w.r2, w.rank, st);
+        KMG_TRY(launch_status());
+        scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, 0, w.n2,
+                                                                         w.rank, w.pk, w.perm, w.skey, st);
+        KMG_TRY(launch_status());
+        band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2, w.perm,
+                                                                           w.skey, w.wave_c0, w.wave_len, st);
+        KMG_TRY(launch_status());
+        band_plan<<<1, kPlanThreads, 0, s>>>(w.plan, n_sets, w.wave_c0, w.wave_len, w.wave_tile, w.tinfo, w.tile_cap,
+                                             st);
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_MATCH_TOPK, s);
+        if (ks == 9) {
+            band_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+        } else {
+            band_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+        }
+        KMG_TRY(launch_status());
+        timer_note_work(&st->band_pairs);
+    }
+    {
+        StageScope sc(ST_MATCH_RESCORE, s);
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
+        rescore_band<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2,
+                                                                          w.rank, w.perm, w.wave_tile, w.nn, w.best,
+                                                                          w.second, w.flag, st);
         KMG_TRY(launch_status());
         KMG_TRY(exact_fallback(sets, n_sets, dim, st, w, s));
     }

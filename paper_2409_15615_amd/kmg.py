@@ -107,6 +107,8 @@ def load():
     lib.kmg_timing_enable.restype = i32
     lib.kmg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
     lib.kmg_timing_read.restype = i32
+    lib.kmg_timing_work.argtypes = [C.POINTER(C.c_int64), i32]
+    lib.kmg_timing_work.restype = i32
     lib.kmg_stage_name.argtypes = [i32]
     lib.kmg_stage_name.restype = C.c_char_p
     _lib = lib
