@@ -84,14 +84,14 @@ struct SetPlan {
     int32_t q_off;      // first query slot in the flattened query space
     int32_t chunk_off;  // first packed 16-row chunk
     int32_t chunks;
-    int32_t tile_off;   // first tile of this set as the query side
+    int32_t tile_off;   // first tile of this set as the query side (norm bands: first sorted tile)
     int32_t cblocks;    // 256-query column blocks
     int32_t segs;       // segments of the partner's rows
     int32_t n_fb;       // queries of this set re-scanned exactly
     int64_t part_off;   // first partial entry
     unsigned long long max_norm_bits;  // max squared norm (FP64 bits, non-negative)
     int32_t wave_off;   // norm-band matching: first query wave of the set
-    int32_t rank_off;   // norm-band matching: first rank work item of the set
+    int32_t rank_off;   // norm-band matching: first tile pair of the set's cross ranking
 };
 
 // Matching output of one pair (device buffers).
@@ -124,9 +124,9 @@ struct DevStatus {
     int64_t total_chunks;
     int64_t pairs_total;      // correspondences over the batch
     int32_t total_waves;      // norm-band matching: query waves
-    int32_t rank_items;       // norm-band matching: rank work items
     int32_t band_step;        // norm-band matching: chunks per tile
-    int32_t pad1;
+    int32_t rank_items;       // norm-band matching: tile pairs of the cross ranking
+    int32_t sort_items;       // norm-band matching: sorted tiles
     int64_t band_pairs;       // norm-band matching: query-row distances evaluated by the tiles
 };
 
@@ -215,9 +215,12 @@ struct StageScope {
 constexpr int kScanTile = 2048;  // items per scan block (256 threads x 8)
 size_t scan_temp_elems(int64_t n);
 // Exclusive prefix sum of n int32 values; the int64 total goes to *total
-// (device).  `temp` holds scan_temp_elems(n) int64 values.
+// (device).  `temp` holds scan_temp_elems(n) int64 values.  With `live`
+// (device), values at positions >= *live count as 0 and are not read.  With
+// `list`, every position i with in[i] == 1 is also written to list[out[i]]
+// (a stream compaction of 0/1 flags, in position order).  Two launches.
 kmg_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
-                          hipStream_t s);
+                          hipStream_t s, const int32_t* live = nullptr, int32_t* list = nullptr);
 kmg_status fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
 kmg_status fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 kmg_status fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
@@ -328,7 +331,7 @@ struct MatchWs {
     PairLp* lp_pairs;     // reduced-precision form: per pair centre and scale
     RerunWs rr;           // FP64 re-runs: uncertified queries, the one-sided form's matching back
     MatchSet* one_sided;  // the sets of the one-sided form's first direction (null: both in full)
-    int32_t* rank;        // norm-band matching: packed position of every slot in its set
+    int32_t* rank;        // norm-band matching: packed position of every query slot in its set
     int32_t* perm;        // norm-band matching: local row of every packed position
     double* r2;           // norm-band matching: seed bound R^2 per query slot
     uint32_t* skey;       // norm-band matching: sort key of every packed partner position

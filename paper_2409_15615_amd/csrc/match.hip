@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
         pl.n_fb = 0;
         pl.part_off = p_off;
         pl.max_norm_bits = 0ull;
+        pl.wave_off = 0;
         plan[c] = pl;
     }
     if (c == 0) {
@@ -559,7 +560,10 @@ __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ s
     for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
          slot += gs) {
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
-        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the quad
+        if (sets[c].flags & kSetRowsOnly) {  // uniform over the quad: no queries
+            if (q == 0) failed[slot] = 0;
+            continue;
+        }
         const int p = c ^ 1;
         const SetPlan qc = plan[c];
         const int j = static_cast<int>(slot - qc.q_off);
@@ -646,16 +650,6 @@ __device__ __forceinline__ void combine_best(double& b1, int& j1, double& b2, do
         j1 = oj1;
     }
     b2 = nb2;
-}
-
-// The queries whose certificate failed, in slot order: fl[pos[slot]] = slot.
-__global__ __launch_bounds__(kBlock) void fb_gather(const int32_t* __restrict__ failed,
-                                                    const int32_t* __restrict__ pos, int32_t* __restrict__ fl,
-                                                    const DevStatus* st) {
-    const int64_t total = st->total_queries;
-    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs)
-        if (failed[slot]) fl[pos[slot]] = static_cast<int32_t>(slot);
 }
 
 constexpr int kXRows = 128;              // partner rows per LDS tile of the exact scan
@@ -812,10 +806,21 @@ __global__ __launch_bounds__(kBlock) void emit_pairs(const MatchSet* __restrict_
                                                      const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
                                                      const int32_t* __restrict__ nn, const double* __restrict__ best,
                                                      const double* __restrict__ second,
-                                                     const PairOutDev* __restrict__ outs, const DevStatus* st) {
+                                                     const PairOutDev* __restrict__ outs, const DevStatus* st,
+                                                     int64_t* counts, int stride) {
     const int64_t total = st->total_queries;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (2 * tid + 1 < n_sets) {
+        // per pair: correspondences (the pair's mutual flags counted by pos) and exact re-scans
+        const int i = static_cast<int>(tid);
+        const int64_t a = plan[2 * i].q_off, b = plan[2 * i + 1].q_off;
+        const int64_t pa = a < total ? pos[a] : st->pairs_total;
+        const int64_t pb = b < total ? pos[b] : st->pairs_total;
+        counts[static_cast<int64_t>(i) * stride + 0] = pb - pa;
+        counts[static_cast<int64_t>(i) * stride + 5] = plan[2 * i].n_fb + plan[2 * i + 1].n_fb;
+    }
+    for (int64_t slot = tid; slot < total; slot += gs) {
         if (!flag[slot]) continue;
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
         const PairOutDev o = outs[c >> 1];
@@ -830,18 +835,6 @@ __global__ __launch_bounds__(kBlock) void emit_pairs(const MatchSet* __restrict_
         o.d1[at] = static_cast<float>(sqrt(best[slot]));
         o.d2[at] = static_cast<float>(sqrt(second[slot]));
     }
-}
-
-__global__ void pair_counts(const SetPlan* __restrict__ plan, int n_sets, const int32_t* __restrict__ pos,
-                            const DevStatus* st, int64_t* counts, int stride) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (2 * i + 1 >= n_sets) return;
-    const int64_t total = st->total_queries;
-    const int64_t a = plan[2 * i].q_off, b = plan[2 * i + 1].q_off;
-    const int64_t pa = a < total ? pos[a] : st->pairs_total;
-    const int64_t pb = b < total ? pos[b] : st->pairs_total;
-    counts[static_cast<int64_t>(i) * stride + 0] = pb - pa;
-    counts[static_cast<int64_t>(i) * stride + 5] = plan[2 * i].n_fb + plan[2 * i + 1].n_fb;
 }
 
 // ------------------------------------------------ reduced-precision tiles --
@@ -1180,7 +1173,10 @@ __global__ __launch_bounds__(kBlock) void rescore_lp(const MatchSet* __restrict_
     for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
          slot += gs) {
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
-        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the quad: no queries, no partials
+        if (sets[c].flags & kSetRowsOnly) {  // uniform over the quad: no queries
+            if (q == 0) failed[slot] = 0;
+            continue;
+        }
         const int p = c ^ 1;
         const SetPlan qc = plan[c];
         const int j = static_cast<int>(slot - qc.q_off);
@@ -1260,16 +1256,23 @@ __global__ __launch_bounds__(kBlock) void rescore_lp(const MatchSet* __restrict_
 
 // ---------------------------------------------------- FP64 re-run lists --
 
-// Lists the queries the reduced-precision certificate left open, in slot
-// order (so each set's entries are contiguous).
-__global__ __launch_bounds__(kBlock) void rerun_gather(const MatchSet* __restrict__ sets,
-                                                       const SetPlan* __restrict__ plan, int n_sets,
-                                                       const int32_t* __restrict__ failed,
-                                                       const int32_t* __restrict__ pos, int32_t* __restrict__ f_slot,
-                                                       int32_t* __restrict__ f_row, const DevStatus* st) {
+// The lists of an FP64 re-run (the queries the reduced-precision
+// certificate left open, or the image rows of the one-sided form), flagged in
+// `failed` and counted by pos: f_slot[f] = main slot, f_row[f] = its row;
+// set 2c of the re-run holds the listed queries of main set c, set 2c + 1 the
+// full partner of c, rows only; the re-run's status is cleared.
+__global__ __launch_bounds__(kBlock) void rerun_lists(const MatchSet* __restrict__ sets,
+                                                      const SetPlan* __restrict__ plan, int n_sets,
+                                                      const int32_t* __restrict__ failed,
+                                                      const int32_t* __restrict__ pos,
+                                                      const int64_t* __restrict__ f_total, int64_t q_cap,
+                                                      int32_t* __restrict__ f_slot, int32_t* __restrict__ f_row,
+                                                      int32_t* __restrict__ f_count, MatchSet* __restrict__ rr,
+                                                      DevStatus* st2, const DevStatus* st) {
     const int64_t total = st->total_queries;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
+    for (int64_t slot = tid; slot < total; slot += gs) {
         if (!failed[slot]) continue;
         const int c = find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
         const int j = static_cast<int>(slot - plan[c].q_off);
@@ -1277,29 +1280,23 @@ __global__ __launch_bounds__(kBlock) void rerun_gather(const MatchSet* __restric
         f_slot[f] = static_cast<int32_t>(slot);
         f_row[f] = sets[c].rows ? sets[c].rows[j] : j;
     }
-}
-
-// Set 2c of the re-run: the listed queries of main set c; set 2c + 1: the
-// full partner of c, rows only.
-__global__ void rerun_sets(const MatchSet* __restrict__ sets, const SetPlan* __restrict__ plan, int n_sets,
-                           const int32_t* __restrict__ pos, const int64_t* __restrict__ f_total, int64_t q_cap,
-                           const int32_t* __restrict__ f_row, int32_t* __restrict__ f_count,
-                           MatchSet* __restrict__ rr) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_sets) return;
-    auto start = [&](int k) -> int64_t {
-        return (k < n_sets && plan[k].q_off < q_cap) ? pos[plan[k].q_off] : *f_total;
-    };
-    const int64_t b = start(c), e = start(c + 1);
-    f_count[c] = static_cast<int32_t>(e - b);
-    MatchSet q = sets[c];
-    q.rows = f_row + b;
-    q.n = f_count + c;
-    q.flags = 0;
-    MatchSet r = sets[c ^ 1];
-    r.flags |= kSetRowsOnly;
-    rr[2 * c] = q;
-    rr[2 * c + 1] = r;
+    if (tid < n_sets) {
+        const int c = static_cast<int>(tid);
+        auto start = [&](int k) -> int64_t {
+            return (k < n_sets && plan[k].q_off < q_cap) ? pos[plan[k].q_off] : *f_total;
+        };
+        const int64_t b = start(c), e = start(c + 1);
+        f_count[c] = static_cast<int32_t>(e - b);
+        MatchSet q = sets[c];
+        q.rows = f_row + b;
+        q.n = f_count + c;
+        q.flags = 0;
+        MatchSet r = sets[c ^ 1];
+        r.flags |= kSetRowsOnly;
+        rr[2 * c] = q;
+        rr[2 * c + 1] = r;
+    }
+    if (tid < static_cast<int64_t>(sizeof(DevStatus) / 4)) reinterpret_cast<uint32_t*>(st2)[tid] = 0u;
 }
 
 // Copies the re-run's answers to the main query slots.
@@ -1307,13 +1304,16 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
                                                         const DevStatus* st2, const int32_t* __restrict__ nn2,
                                                         const double* __restrict__ best2,
                                                         const double* __restrict__ second2,
-                                                        const SetPlan* __restrict__ plan, const int32_t* __restrict__ pos,
+                                                        SetPlan* __restrict__ plan, const int32_t* __restrict__ pos,
                                                         const int32_t* __restrict__ f_slot, int32_t* __restrict__ nn,
                                                         double* __restrict__ best, double* __restrict__ second,
-                                                        DevStatus* st) {
+                                                        DevStatus* st, int add_rescans) {
     const int64_t total = st2->total_queries;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total; t += gs) {
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    // with add_rescans: the re-run's exact re-scans are counted with the queries they answer
+    if (add_rescans && tid < n_sets2 / 2) plan[tid].n_fb += plan2[2 * tid].n_fb;
+    for (int64_t t = tid; t < total; t += gs) {
         const int c2 = find_set(n_sets2, t, [&](int q) { return static_cast<int64_t>(plan2[q].q_off); });
         if (c2 & 1) continue;  // rows-only sets have no answers
         const int i = static_cast<int>(t - plan2[c2].q_off);
@@ -1347,8 +1347,9 @@ __global__ void one_sided_sets(const MatchSet* __restrict__ sets, int n_sets, Ma
 }
 
 // flag[slot] = 1 for every rows-only slot that some query has as its nearest
-// neighbour (flag cleared before); nn of the rows-only slots <- -1 until the
-// matching back fills the flagged ones.
+// neighbour, 0 for the query slots; the rows-only slots come in cleared (the
+// re-score wrote 0 there).  nn of the rows-only slots <- -1 until the matching
+// back fills the flagged ones.
 __global__ __launch_bounds__(kBlock) void image_flags(const MatchSet* __restrict__ sets,
                                                       const SetPlan* __restrict__ plan, int n_sets,
                                                       int32_t* __restrict__ nn, int32_t* __restrict__ flag,
@@ -1360,16 +1361,11 @@ __global__ __launch_bounds__(kBlock) void image_flags(const MatchSet* __restrict
         if (sets[c].flags & kSetRowsOnly) {
             nn[slot] = -1;
         } else {
+            flag[slot] = 0;
             const int j = nn[slot];
             if (j >= 0 && (c ^ 1) < n_sets) flag[plan[c ^ 1].q_off + j] = 1;
         }
     }
-}
-
-// Exact re-scans of the matching back, counted with the queries they answer.
-__global__ void add_rescans(const SetPlan* __restrict__ plan2, int n_sets, SetPlan* __restrict__ plan) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n_sets) plan[c].n_fb += plan2[2 * c].n_fb;
 }
 
 // ------------------------------------------------------------ norm bands --
@@ -1388,31 +1384,76 @@ __global__ void add_rescans(const SetPlan* __restrict__ plan2, int n_sets, SetPl
 // outside the band are farther than R, and two rows inside are within it).
 
 constexpr int kBandWave = kColsPerWave;  // queries per band wave (one wavefront)
-constexpr int kRankBlock = 256;          // keys per rank work item
-constexpr int kRankSpan = 1024;          // keys compared per rank work item
+constexpr int kSortTile = 1024;          // elements per LDS-sorted tile of the ordering
+constexpr int kSortThreads = 256;
 constexpr int kBandTiles = 8192;         // band tiles the partial buffer holds beyond one per wave
 constexpr int kSeedRows = kWave;         // partner rows around the query's norm for R
 constexpr int kBandSlots = kTopkBlocks * kWavesPerBlock;  // wavefronts of the band tile kernel
 
+// Block-wide exclusive scan of K int32 values per thread in one pass (two
+// barriers): v[k] <- the sum over lower threads, tot[k] <- the block total.
+template <int K>
+__device__ __forceinline__ void block_scan_k(int* v, int* tot, int* smem /* K x waves */) {
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    constexpr int kWaves = kPlanThreads / kWave;
+    int incl[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) incl[k] = wave_incl_scan(v[k]);
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) smem[k * kWaves + wave] = incl[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int before = 0, total = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const int t = smem[k * kWaves + w];
+            before += w < wave ? t : 0;
+            total += t;
+        }
+        v[k] = before + incl[k] - v[k];
+        tot[k] = total;
+    }
+    __syncthreads();
+}
+
+// With `oside`, the sets are first made one-sided (the larger set of each
+// pair, the second on a tie, becomes rows-only) and written there; the
+// kernels after the planner then read oside.
 __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
-                                                         SetPlan* plan, DevStatus* st) {
-    __shared__ int64_t smem[kPlanThreads / kWave];
+                                                         SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside) {
+    __shared__ int s_scan[5 * (kPlanThreads / kWave)];
     const int c = threadIdx.x;
     const bool live = c < n_sets;
-    const bool rows_only = live && (sets[c].flags & kSetRowsOnly);
+    const bool paired = live && (c ^ 1) < n_sets;
     int n = live ? *sets[c].n : 0;
-    if (rows_only) {
-        // rows that no query is matched against need neither slots nor packing
-        if ((c ^ 1) >= n_sets || (sets[c ^ 1].flags & kSetRowsOnly) || *sets[c ^ 1].n == 0) n = 0;
+    const int n_other = paired ? *sets[c ^ 1].n : 0;
+    bool rows_only = live && (sets[c].flags & kSetRowsOnly);
+    bool other_rows = paired && (sets[c ^ 1].flags & kSetRowsOnly);
+    if (oside) {
+        if (paired) {
+            rows_only = (c & 1) ? n >= n_other : n > n_other;
+            other_rows = !rows_only;
+        }
+        if (live) {
+            MatchSet m = sets[c];
+            m.flags = rows_only ? (m.flags | kSetRowsOnly) : (m.flags & ~kSetRowsOnly);
+            oside[c] = m;
+        }
     }
+    // rows that no query is matched against need neither slots nor packing
+    if (rows_only && (!paired || other_rows || n_other == 0)) n = 0;
     const int chunks = (n + kTileRows - 1) / kTileRows;
     const int waves = (live && !rows_only) ? (n + kBandWave - 1) / kBandWave : 0;
-    const int64_t items = static_cast<int64_t>((n + kRankBlock - 1) / kRankBlock) * ((n + kRankSpan - 1) / kRankSpan);
-    int64_t tq, tc, tw, ti;
-    const int64_t q_off = block_excl_scan64(n, smem, tq);
-    const int64_t c_off = block_excl_scan64(chunks, smem, tc);
-    const int64_t w_off = block_excl_scan64(waves, smem, tw);
-    const int64_t i_off = block_excl_scan64(items, smem, ti);
+    const int sort_tiles = (n + kSortTile - 1) / kSortTile;
+    // the counts of a plan stay below 2^31 (slots are int32)
+    int v[5] = {n, chunks, waves, sort_tiles, sort_tiles * sort_tiles};
+    int tot[5];
+    block_scan_k<5>(v, tot, s_scan);
+    const int q_off = v[0], c_off = v[1], w_off = v[2], s_off = v[3], i_off = v[4];
+    const int tq = tot[0], tc = tot[1], tw = tot[2], ts = tot[3], ti = tot[4];
     // one buffer descriptor spans a set's packed rows: keep them below 2 GiB
     if (static_cast<int64_t>(chunks) * kp * kTileRows * 8 > INT32_MAX) st->err_capacity = 1;
     if (live) {
@@ -1421,7 +1462,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __rest
         pl.q_off = static_cast<int32_t>(q_off);
         pl.chunk_off = static_cast<int32_t>(c_off);
         pl.chunks = chunks;
-        pl.tile_off = 0;
+        pl.tile_off = static_cast<int32_t>(s_off);
         pl.cblocks = waves;
         pl.segs = 0;
         pl.n_fb = 0;
@@ -1436,6 +1477,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __rest
         st->total_chunks = tc;
         st->total_waves = static_cast<int32_t>(tw);
         st->rank_items = static_cast<int32_t>(ti);
+        st->sort_items = static_cast<int32_t>(ts);
         st->total_tiles = 0;
         st->tile_next = 0;
         st->n_fallback = 0;
@@ -1460,46 +1502,89 @@ __device__ __forceinline__ uint32_t band_key(bool partner, double n2, double r2)
     return (static_cast<uint32_t>(cls) << 24) | static_cast<uint32_t>(nb >> 40);
 }
 
-// Rank of every slot of the sets of one role (rows-only partners, or query
-// sets) within its set by (key, local index), a unique 64-bit value: a work
-// item counts, for kRankBlock values, the smaller ones among kRankSpan others
-// of the same set and adds the counts to rank[] (cleared by row_norms).
-__global__ __launch_bounds__(kRankBlock) void rank_slots(const MatchSet* __restrict__ sets,
-                                                         const SetPlan* __restrict__ plan, int n_sets, int partner,
-                                                         const double* __restrict__ n2,
-                                                         const double* __restrict__ r2, int32_t* __restrict__ rank,
-                                                         const DevStatus* st) {
-    __shared__ unsigned long long s_key[kRankSpan];
+// Ordering of the sets of one role (rows-only partners, or query sets) by
+// (key, local index), a unique 64-bit value: rank[slot] = the element's packed
+// position.  tile_sort sorts every tile of kSortTile consecutive elements of a
+// set (bitonic, one element per thread) and stores the tile's sorted values and each element's
+// place in its tile as its first rank term; cross_rank takes a pair of tiles
+// (A, B) of one set and adds to every element of A the count of B's values
+// below its own (a binary search in B's sorted values, staged in LDS).
+
+__device__ __forceinline__ unsigned long long rank_value(bool partner, double n2, double r2, int idx) {
+    return (static_cast<unsigned long long>(band_key(partner, n2, r2)) << 32) | static_cast<uint32_t>(idx);
+}
+
+// One element per thread: compare-exchange partners closer than a wavefront
+// trade through shuffles, farther ones through LDS (ten of the 55 stages).
+__global__ __launch_bounds__(kSortTile) void tile_sort(const MatchSet* __restrict__ sets,
+                                                       const SetPlan* __restrict__ plan, int n_sets, int partner,
+                                                       const double* __restrict__ n2, const double* __restrict__ r2,
+                                                       unsigned long long* __restrict__ sorted,
+                                                       int32_t* __restrict__ rank, const DevStatus* st) {
+    __shared__ unsigned long long s_v[kSortTile];
+    const bool pr = partner != 0;
+    const int r = threadIdx.x;
+    const int64_t total = st->sort_items;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_set(n_sets, item, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
+        if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;  // uniform over the block
+        const SetPlan pc = plan[c];
+        const int e0 = static_cast<int>(item - pc.tile_off) * kSortTile;
+        const int cnt = min(kSortTile, pc.n - e0);
+        const int64_t sl = pc.q_off + e0 + r;
+        unsigned long long v = r < cnt ? rank_value(pr, n2[sl], pr ? 0.0 : r2[sl], e0 + r) : ~0ull;  // ~0 sorts last
+        for (int k = 2; k <= kSortTile; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                unsigned long long o;
+                if (j >= kWave) {  // uniform over the block
+                    __syncthreads();  // the last exchange's values are read
+                    s_v[r] = v;
+                    __syncthreads();
+                    o = s_v[r ^ j];
+                } else {
+                    o = __shfl_xor(v, j, kWave);
+                }
+                const bool keep_min = ((r & j) == 0) == ((r & k) == 0);
+                v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+            }
+        }
+        if (r < cnt) {
+            sorted[pc.q_off + e0 + r] = v;
+            rank[pc.q_off + static_cast<int>(v & 0xffffffffull)] = r;
+        }
+        __syncthreads();  // s_v is free for the next item
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void cross_rank(const MatchSet* __restrict__ sets,
+                                                           const SetPlan* __restrict__ plan, int n_sets, int partner,
+                                                           const unsigned long long* __restrict__ sorted,
+                                                           int32_t* __restrict__ rank, const DevStatus* st) {
+    __shared__ unsigned long long s_b[kSortTile];
     const bool pr = partner != 0;
     const int64_t total = st->rank_items;
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
         const int c = find_set(n_sets, item, [&](int s) { return static_cast<int64_t>(plan[s].rank_off); });
         if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;  // uniform over the block
         const SetPlan pc = plan[c];
+        const int m = (pc.n + kSortTile - 1) / kSortTile;
         const int local = static_cast<int>(item - pc.rank_off);
-        const int kr = (pc.n + kRankSpan - 1) / kRankSpan;
-        const int i = (local / kr) * kRankBlock + static_cast<int>(threadIdx.x);
-        const int j0 = (local % kr) * kRankSpan;
-        const int nj = min(kRankSpan, pc.n - j0);
-        __syncthreads();  // the previous item's keys are read no more
-        for (int e = threadIdx.x; e < kRankSpan; e += kRankBlock) {
-            unsigned long long v = ~0ull;  // past the set: larger than every key
-            if (e < nj) {
-                const int64_t sl = pc.q_off + j0 + e;
-                v = (static_cast<unsigned long long>(band_key(pr, n2[sl], pr ? 0.0 : r2[sl])) << 32) |
-                    static_cast<uint32_t>(j0 + e);
-            }
-            s_key[e] = v;
-        }
+        const int ta = local / m, tb = local % m;
+        if (ta == tb) continue;  // the tile's own order is the first rank term
+        const int b0 = tb * kSortTile, nb = min(kSortTile, pc.n - b0);
+        const int a0 = ta * kSortTile, na = min(kSortTile, pc.n - a0);
         __syncthreads();
-        if (i < pc.n) {
-            const int64_t sl = pc.q_off + i;
-            const unsigned long long ki =
-                (static_cast<unsigned long long>(band_key(pr, n2[sl], pr ? 0.0 : r2[sl])) << 32) | static_cast<uint32_t>(i);
-            int cnt = 0;
-#pragma unroll 16
-            for (int e = 0; e < kRankSpan; ++e) cnt += s_key[e] < ki ? 1 : 0;
-            if (cnt) atomicAdd(&rank[sl], cnt);
+        for (int r = threadIdx.x; r < nb; r += kSortThreads) s_b[r] = sorted[pc.q_off + b0 + r];
+        __syncthreads();
+        for (int r = threadIdx.x; r < na; r += kSortThreads) {
+            const unsigned long long v = sorted[pc.q_off + a0 + r];
+            int lo = 0, hi = nb;  // first of B's values not below v
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_b[mid] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo) atomicAdd(&rank[pc.q_off + static_cast<int>(v & 0xffffffffull)], lo);
         }
     }
 }
@@ -1728,6 +1813,7 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
             }
         }
     }
+    __shared__ int s_off[kPlanThreads], s_c0[kPlanThreads], s_len[kPlanThreads], s_set[kPlanThreads];
     int64_t carry = 0;
     int64_t pairs = 0;  // query-row distances of the tiles (real queries and rows)
     for (int base = 0; base < W; base += kPlanThreads) {
@@ -1735,21 +1821,38 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
         const int L = w < W ? wave_len[w] : 0;
         const int nt = (L + T - 1) / T;
         int64_t round_total;
-        const int64_t off = carry + block_excl_scan64(nt, smem, round_total);
+        const int64_t rel = block_excl_scan64(nt, smem, round_total);
+        int c = 0, c0 = 0;
         if (w < W) {
-            wave_tile[w] = static_cast<int32_t>(off);
-            const int c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
-            const int c0 = wave_c0[w];
+            wave_tile[w] = static_cast<int32_t>(carry + rel);
+            c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+            c0 = wave_c0[w];
             if (L > 0) {
                 const int nq = min(kBandWave, plan[c].n - (w - plan[c].wave_off) * kBandWave);
                 const int np = plan[c ^ 1].n;
                 pairs += static_cast<int64_t>(nq) * (min((c0 + L) * kTileRows, np) - c0 * kTileRows);
             }
-            if (off + nt <= tile_cap) {
-                for (int k = 0; k < nt; ++k)
-                    tinfo[off + k] = make_int4(w, c, c0 + k * T, min(c0 + (k + 1) * T, c0 + L));
-            }
         }
+        s_off[threadIdx.x] = static_cast<int>(rel);
+        s_c0[threadIdx.x] = c0;
+        s_len[threadIdx.x] = L;
+        s_set[threadIdx.x] = c;
+        __syncthreads();
+        // the round's tiles, one per thread: the owning wave is the last whose first tile is <= t
+        const int in_round = min(kPlanThreads, W - base);
+        for (int64_t t = threadIdx.x; t < round_total; t += kPlanThreads) {
+            if (carry + t >= tile_cap) break;
+            int lo = 0, hi = in_round - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int k = static_cast<int>(t - s_off[lo]);
+            const int a = s_c0[lo] + k * T;
+            tinfo[carry + t] = make_int4(base + lo, s_set[lo], a, min(a + T, s_c0[lo] + s_len[lo]));
+        }
+        __syncthreads();
         carry += round_total;
     }
     int64_t pairs_total;
@@ -1858,14 +1961,18 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
                                                        const int32_t* __restrict__ wave_tile, int32_t* __restrict__ nn,
                                                        double* __restrict__ best, double* __restrict__ second,
                                                        int32_t* __restrict__ failed, DevStatus* st) {
-    const int64_t total = st->err_capacity ? 0 : st->total_queries;  // no tiles were computed
+    const int64_t total = st->total_queries;
+    const bool no_tiles = st->err_capacity != 0;  // the results are void; the flags stay well defined
     const int q = lane_id() & (kQuad - 1);
     const int quad0 = lane_id() & ~(kQuad - 1);
     const int64_t gs = static_cast<int64_t>(gridDim.x) * (kBlock / kQuad);
     for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
          slot += gs) {
         const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
-        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the quad
+        if (no_tiles || (sets[c].flags & kSetRowsOnly)) {  // uniform over the quad: no queries
+            if (q == 0) failed[slot] = 0;
+            continue;
+        }
         const int p = c ^ 1;
         const SetPlan qc = plan[c];
         const int j = static_cast<int>(slot - qc.q_off);
@@ -2006,7 +2113,9 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
 kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                     hipStream_t s);
 kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
-kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
+// With oside, the sets are made one-sided by the planner and written there.
+kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s,
+                      MatchSet* oside = nullptr);
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s);
 
@@ -2016,16 +2125,15 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
                        const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s) {
     if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
     // one-sided form when the workspace holds the second plan, else both directions in full
-    const MatchSet* first = sets;
-    if (w.one_sided) {
-        one_sided_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets, n_sets, w.one_sided);
-        KMG_TRY(launch_status());
-        first = w.one_sided;
-    }
+    const MatchSet* first = w.one_sided ? w.one_sided : sets;
     if (prec == KMG_FP16 || prec == KMG_BF16) {
+        if (w.one_sided) {
+            one_sided_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets, n_sets, w.one_sided);
+            KMG_TRY(launch_status());
+        }
         KMG_TRY(match_lp(first, n_sets, dim, prec, st, w, s));
     } else if (w.one_sided) {
-        KMG_TRY(match_band(first, n_sets, dim, st, w, s));
+        KMG_TRY(match_band(sets, n_sets, dim, st, w, s, w.one_sided));  // the planner writes the one-sided sets
     } else {
         KMG_TRY(match_fp64(first, n_sets, dim, st, w, s));
     }
@@ -2035,10 +2143,8 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
         mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
         KMG_TRY(launch_status());
         KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
-        emit_pairs<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best,
-                                                               w.second, outs, st);
-        KMG_TRY(launch_status());
-        pair_counts<<<grid_for(n_sets / 2, 64), 64, 0, s>>>(w.plan, n_sets, w.pos, st, counts, counts_stride);
+        emit_pairs<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
+            sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best, w.second, outs, st, counts, counts_stride);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
@@ -2086,20 +2192,16 @@ kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStat
     }
     {
         StageScope sc(ST_MATCH_RESCORE, s);
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
         rescore_lp<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.lp_nx,
                                                                         w.lp_pairs, w.nn, w.best, w.second, w.flag,
                                                                         st);
         KMG_TRY(launch_status());
         if (!w.rr.region) return exact_fallback(sets, n_sets, dim, st, w, s);
-        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s));
-        rerun_gather<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.rr.f_slot,
-                                                                 w.rr.f_row, st);
+        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s, &st->total_queries));
+        rerun_lists<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets + 64, kBlock)), kBlock, 0, s>>>(sets, w.plan, n_sets, w.flag, w.pos, w.rr.f_total,
+                                                                w.q_cap, w.rr.f_slot, w.rr.f_row, w.rr.f_count,
+                                                                w.rr.sets, w.rr.st, st);
         KMG_TRY(launch_status());
-        rerun_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets, w.plan, n_sets, w.pos, w.rr.f_total, w.q_cap,
-                                                       w.rr.f_row, w.rr.f_count, w.rr.sets);
-        KMG_TRY(launch_status());
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.rr.st), 0u, sizeof(DevStatus) / 4, s));
     }
     Carver c2(w.rr.region, w.rr.region_bytes);
     const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
@@ -2109,7 +2211,7 @@ kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStat
         StageScope sc(ST_MATCH_RESCORE, s);
         rerun_scatter<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best,
                                                                    w2.second, w.plan, w.pos, w.rr.f_slot, w.nn,
-                                                                   w.best, w.second, st);
+                                                                   w.best, w.second, st, 0);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
@@ -2142,7 +2244,6 @@ kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
     }
     {
         StageScope sc(ST_MATCH_RESCORE, s);
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
         rescore<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2, w.nn,
                                                                     w.best, w.second, w.flag, st);
         KMG_TRY(launch_status());
@@ -2157,26 +2258,20 @@ kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
 // land in their main slots.
 kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s) {
     StageScope sc(ST_MATCH_IMAGE, s);
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
     image_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.nn, w.flag, st);
     KMG_TRY(launch_status());
-    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s));
-    rerun_gather<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.flag, w.pos, w.rr.f_slot,
-                                                             w.rr.f_row, st);
+    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s, &st->total_queries));
+    rerun_lists<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets + 64, kBlock)), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.flag, w.pos, w.rr.f_total,
+                                                            w.q_cap, w.rr.f_slot, w.rr.f_row, w.rr.f_count, w.rr.sets,
+                                                            w.rr.st, st);
     KMG_TRY(launch_status());
-    rerun_sets<<<grid_for(n_sets, 64), 64, 0, s>>>(sets1, w.plan, n_sets, w.pos, w.rr.f_total, w.q_cap, w.rr.f_row,
-                                                   w.rr.f_count, w.rr.sets);
-    KMG_TRY(launch_status());
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.rr.st), 0u, sizeof(DevStatus) / 4, s));
     Carver c2(w.rr.region, w.rr.region_bytes);
     const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
     if (!c2.fits()) return KMG_ERR_WORKSPACE;
     KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
-    rerun_scatter<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best,
-                                                               w2.second, w.plan, w.pos, w.rr.f_slot, w.nn, w.best,
-                                                               w.second, st);
-    KMG_TRY(launch_status());
-    add_rescans<<<grid_for(n_sets, 64), 64, 0, s>>>(w2.plan, n_sets, w.plan);
+    rerun_scatter<<<std::max(grid_cap(w2.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
+        w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best, w2.second, w.plan, w.pos, w.rr.f_slot, w.nn, w.best, w.second,
+        st, 1);
     return launch_status();
 }
 
@@ -2184,28 +2279,34 @@ kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st,
 // partner) in either order: partner rows ranked and packed by norm, seed
 // bounds, queries ranked by (class, norm) and packed, bands, band tiles, exact
 // re-score and certificate, exact scans for the rest.
-kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s) {
+kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s,
+                      MatchSet* oside) {
     const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     if (ks != 9 && ks != 17) return KMG_ERR_ARG;
+    const MatchSet* sets = oside ? oside : sets_in;
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_band<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.plan, st);
+        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside);
         KMG_TRY(launch_status());
-        row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, w.rank);
+        row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
-        rank_slots<<<kPersistBlocks, kRankBlock, 0, s>>>(sets, w.plan, n_sets, 1, w.n2, w.r2, w.rank, st);
-        KMG_TRY(launch_status());
-        scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, 1, w.n2,
-                                                                         w.rank, w.pk, w.perm, w.skey, st);
-        KMG_TRY(launch_status());
-        band_seeds<<<grid_cap(w.q_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, w.pk, w.n2,
-                                                                        w.skey, w.r2, st);
-        KMG_TRY(launch_status());
-        rank_slots<<<kPersistBlocks, kRankBlock, 0, s>>>(sets, w.plan, n_sets, 0, w.n2, w.r2, w.rank, st);
-        KMG_TRY(launch_status());
-        scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, 0, w.n2,
-                                                                         w.rank, w.pk, w.perm, w.skey, st);
-        KMG_TRY(launch_status());
+        // the sorted tile values live in best, which the re-score writes only afterwards
+        unsigned long long* sorted = reinterpret_cast<unsigned long long*>(w.best);
+        for (int role = 1; role >= 0; --role) {  // partners first: the seeds need their order
+            if (role == 0) {
+                band_seeds<<<grid_cap(w.q_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, w.pk,
+                                                                                w.n2, w.skey, w.r2, st);
+                KMG_TRY(launch_status());
+            }
+            tile_sort<<<grid_cap((w.q_cap / kSortTile + n_sets + 1) * kBlock, kBlock), kSortTile, 0, s>>>(
+                sets, w.plan, n_sets, role, w.n2, w.r2, sorted, w.rank, st);
+            KMG_TRY(launch_status());
+            cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
+            KMG_TRY(launch_status());
+            scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
+                                                                             w.n2, w.rank, w.pk, w.perm, w.skey, st);
+            KMG_TRY(launch_status());
+        }
         band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2, w.perm,
                                                                            w.skey, w.wave_c0, w.wave_len, st);
         KMG_TRY(launch_status());
@@ -2225,7 +2326,6 @@ kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
     }
     {
         StageScope sc(ST_MATCH_RESCORE, s);
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.flag), 0u, static_cast<size_t>(w.q_cap), s));
         rescore_band<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2,
                                                                           w.rank, w.perm, w.wave_tile, w.nn, w.best,
                                                                           w.second, w.flag, st);
@@ -2238,9 +2338,7 @@ kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
 // Exact scans of the queries flagged in w.flag, grouped in slot order.
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s) {
-    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.fb_total, w.scan_tmp, s));
-    fb_gather<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.flag, w.pos, w.fb_list, st);
-    KMG_TRY(launch_status());
+    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.fb_total, w.scan_tmp, s, &st->total_queries, w.fb_list));
     exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total, w.part_cap,
                                                    w.part);
     KMG_TRY(launch_status());

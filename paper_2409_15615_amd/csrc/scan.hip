@@ -1,5 +1,5 @@
-// Device-wide exclusive prefix sum (three launches: tile sums, scan of the
-// tile sums, tile-local scans) and fill kernels.
+// Device-wide exclusive prefix sum (two launches: tile sums, then tile-local
+// scans whose blocks each add up the tile sums before them) and fill kernels.
 #include "kmg_device.h"
 
 namespace kmg {
@@ -28,56 +28,61 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t* smem /* >= 4 */, int64_t&
     return total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void tile_sums(const int32_t* in, int64_t n, int64_t* sums) {
+__device__ __forceinline__ int64_t live_count(int64_t n, const int32_t* live) {
+    if (!live) return n;
+    const int64_t l = *live;
+    return l < n ? (l < 0 ? 0 : l) : n;
+}
+
+__global__ __launch_bounds__(kScanThreads) void tile_sums(const int32_t* in, int64_t n, const int32_t* live,
+                                                          int64_t* sums) {
     __shared__ int64_t smem[kScanThreads / kWave];
+    const int64_t nl = live_count(n, live);
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
     int64_t acc = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k * kScanThreads + threadIdx.x;
-        if (i < n) acc += in[i];
+        if (i < nl) acc += in[i];
     }
     int64_t excl;
     int64_t total = block_excl_scan(acc, smem, excl);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// One block: exclusive scan of the tile sums in place; writes the grand total.
-__global__ __launch_bounds__(kScanThreads) void scan_sums(int64_t* sums, int64_t nt, int64_t* total) {
-    __shared__ int64_t smem[kScanThreads / kWave];
-    int64_t carry = 0;
-    for (int64_t base = 0; base < nt; base += kScanThreads) {
-        int64_t i = base + threadIdx.x;
-        int64_t v = (i < nt) ? sums[i] : 0;
-        int64_t excl;
-        int64_t t = block_excl_scan(v, smem, excl);
-        if (i < nt) sums[i] = carry + excl;
-        carry += t;
-    }
-    if (threadIdx.x == 0) *total = carry;
-}
-
+// Each block sums the tile sums before its own (at most a few thousand, read
+// once per block) for its prefix; the last block writes the grand total.
 __global__ __launch_bounds__(kScanThreads) void tile_scan(const int32_t* in, int32_t* out, int64_t n,
-                                                          const int64_t* sums) {
+                                                          const int32_t* live, const int64_t* sums, int64_t* total,
+                                                          int32_t* list) {
     __shared__ int64_t smem[kScanThreads / kWave];
+    const int64_t nl = live_count(n, live);
+    int64_t before = 0;
+    for (int64_t k = threadIdx.x; k < static_cast<int64_t>(blockIdx.x); k += kScanThreads) before += sums[k];
+    int64_t prefix, unused;
+    prefix = block_excl_scan(before, smem, unused);
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
     int32_t v[kScanItems];
     int64_t acc = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k;
-        v[k] = (i < n) ? in[i] : 0;
+        v[k] = (i < nl) ? in[i] : 0;
         acc += v[k];
     }
     int64_t excl;
-    block_excl_scan(acc, smem, excl);
-    int64_t run = sums[blockIdx.x] + excl;
+    const int64_t tile_total = block_excl_scan(acc, smem, excl);
+    int64_t run = prefix + excl;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k;
-        if (i < n) out[i] = static_cast<int32_t>(run);
+        if (i < n) {
+            out[i] = static_cast<int32_t>(run);
+            if (list && v[k] == 1) list[run] = static_cast<int32_t>(i);
+        }
         run += v[k];
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = prefix + tile_total;
 }
 
 template <class T>
@@ -100,19 +105,13 @@ kmg_status fill(T* p, T v, size_t n, hipStream_t s) {
 size_t scan_temp_elems(int64_t n) { return static_cast<size_t>((n + kScanTile - 1) / kScanTile) + 1; }
 
 kmg_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
-                          hipStream_t s) {
+                          hipStream_t s, const int32_t* live, int32_t* list) {
     const int64_t nt = (n + kScanTile - 1) / kScanTile;
-    if (nt > 0) {
-        tile_sums<<<static_cast<unsigned>(nt), kScanThreads, 0, s>>>(in, n, temp);
-        KMG_TRY(launch_status());
-    }
-    scan_sums<<<1, kScanThreads, 0, s>>>(temp, nt, total);
+    if (nt == 0) return fill_u64(reinterpret_cast<uint64_t*>(total), 0ull, 1, s);
+    tile_sums<<<static_cast<unsigned>(nt), kScanThreads, 0, s>>>(in, n, live, temp);
     KMG_TRY(launch_status());
-    if (nt > 0) {
-        tile_scan<<<static_cast<unsigned>(nt), kScanThreads, 0, s>>>(in, out, n, temp);
-        KMG_TRY(launch_status());
-    }
-    return KMG_OK;
+    tile_scan<<<static_cast<unsigned>(nt), kScanThreads, 0, s>>>(in, out, n, live, temp, total, list);
+    return launch_status();
 }
 
 kmg_status fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s) { return fill<uint8_t>(p, v, n, s); }
