@@ -27,7 +27,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kBatch = 8;  // SPFH rows loaded together in the FPFH sum
+constexpr int kBatch = 8;          // SPFH rows loaded together in the FPFH sum
+constexpr int kBatchNarrow = 16;   // the same for rows of at most 64 values
 
 struct V3f {
     float x, y, z;
@@ -105,7 +106,10 @@ __device__ __forceinline__ void crossd(const double a[3], const double b[3], dou
 // angle, d = (a_b - a_a) / ||.||, u = n_a, v = d x u normalised, w = u x v,
 // f = (atan2(w.n_b, u.n_b), v.n_b, u.d); f = (0, 0, u.d) when d x u = 0.
 // Bin h = floor(H (f - lo) / (hi - lo)) clamped to [0, H-1].
-__device__ void bins_f64(V3f pq32, V3f nq32, V3f pk32, V3f nk32, int H, int bins[3], bool& edge) {
+// Out of line: the FP64 recomputation is rare, and inlined it would hold the
+// registers of the whole SPFH loop.
+__device__ __attribute__((noinline)) void bins_f64(V3f pq32, V3f nq32, V3f pk32, V3f nk32, int H, int bins[3],
+                                                   bool& edge) {
 #pragma clang fp contract(off)
     const double pq[3] = {pq32.x, pq32.y, pq32.z}, nq[3] = {nq32.x, nq32.y, nq32.z};
     const double pk[3] = {pk32.x, pk32.y, pk32.z}, nk[3] = {nk32.x, nk32.y, nk32.z};
@@ -276,8 +280,19 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
             }
             __builtin_amdgcn_wave_barrier();
             const int nuse = __popcll(bm);
-            // eight SPFH rows in flight at a time, accumulated in ascending neighbour order
+            // SPFH rows in flight kBatchNarrow (rows of at most 64 values) or kBatch at a time,
+            // accumulated in ascending neighbour order
             int j = 0;
+            if (D <= kWave) {
+                for (; j + kBatchNarrow <= nuse; j += kBatchNarrow) {
+                    double v0[kBatchNarrow];
+#pragma unroll
+                    for (int u = 0; u < kBatchNarrow; ++u)
+                        v0[u] = spfh64[static_cast<int64_t>(s_k[wv][j + u]) * D + lb0];
+#pragma unroll
+                    for (int u = 0; u < kBatchNarrow; ++u) acc0 = acc0 + s_w[wv][j + u] * v0[u];
+                }
+            }
             for (; j + kBatch <= nuse; j += kBatch) {
                 double v0[kBatch], v1[kBatch];
 #pragma unroll

@@ -9,8 +9,8 @@
 // whose lanes walk the flattened candidate list of the 27 cells.  The search
 // runs twice: a count pass (|N(q)|), then, after a prefix sum has placed
 // every list, a fill pass that collects the accepted indices in LDS and
-// writes them in ascending order (rank sort).  Normals are then estimated one
-// thread per point from the stored list: FP64 moments of the r_normal subset,
+// writes them in ascending order (rank sort).  Normals are then estimated by
+// 16 lanes per point from the stored list: FP64 moments of the r_normal subset,
 // a cyclic Jacobi eigen-solver in FP64, the linearity test and viewpoint
 // orientation.
 #include <climits>
@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSearchWaves = 4;  // waves (queries) per block in the count and fill passes
+constexpr int kNormalLanes = 16; // lanes per point in the normal estimation
 
 struct Grid {
     const float4* pts;     // cell-sorted points; w = bit pattern of the kept index
@@ -80,6 +81,45 @@ __global__ __launch_bounds__(kBlock) void cell_scatter(const float* __restrict__
         const int pos = start[h] + atomicAdd(fill + h, 1);
         pts[pos] = make_float4(xyz[p], xyz[stride + p], xyz[2 * stride + p], __int_as_float(static_cast<int>(p)));
     }
+}
+
+// Ascending sort of n <= 64 E distinct indices held in LDS, written to out: a
+// bitonic network over 64 E values, value i = 64 u + lane in register u
+// (partners closer than a wavefront trade through shuffles).
+template <int E>
+__device__ __forceinline__ void wave_sort_write(const int32_t* list, int n, int32_t* out) {
+    const int lane = lane_id();
+    int v[E];
+#pragma unroll
+    for (int u = 0; u < E; ++u) v[u] = (u * kWave + lane < n) ? list[u * kWave + lane] : INT_MAX;
+#pragma unroll
+    for (int k = 2; k <= E * kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= kWave) {
+                const int ju = j / kWave;
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    if (u & ju) continue;
+                    const int i = u * kWave + lane;
+                    const int a = v[u], b = v[u | ju];
+                    const bool asc = (i & k) == 0;
+                    v[u] = asc ? min(a, b) : max(a, b);
+                    v[u | ju] = asc ? max(a, b) : min(a, b);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int i = u * kWave + lane;
+                    const int o = __shfl_xor(v[u], j, kWave);
+                    v[u] = (((i & j) == 0) == ((i & k) == 0)) ? min(v[u], o) : max(v[u], o);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        if (u * kWave + lane < n) out[u * kWave + lane] = v[u];
 }
 
 // One wavefront per query, queries visited in cell-sorted order (grid-stride).
@@ -169,14 +209,22 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
             continue;
         }
         __builtin_amdgcn_wave_barrier();
-        // ranks are unique (distinct indices): scatter each entry to its sorted slot
         int32_t* out = nbr + off[q];
         const int nf = found < kCap ? found : kCap;
-        for (int e = lane; e < nf; e += kWave) {
-            const int v = s_list[wv][e];
-            int r = 0;
-            for (int k = 0; k < nf; ++k) r += (s_list[wv][k] < v) ? 1 : 0;
-            out[r] = v;
+        if (nf <= kWave) {
+            wave_sort_write<1>(s_list[wv], nf, out);
+        } else if (nf <= 2 * kWave) {
+            wave_sort_write<2>(s_list[wv], nf, out);
+        } else if (nf <= 4 * kWave) {
+            wave_sort_write<4>(s_list[wv], nf, out);
+        } else {
+            // ranks are unique (distinct indices): scatter each entry to its sorted slot
+            for (int e = lane; e < nf; e += kWave) {
+                const int v = s_list[wv][e];
+                int r = 0;
+                for (int k = 0; k < nf; ++k) r += (s_list[wv][k] < v) ? 1 : 0;
+                out[r] = v;
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -220,8 +268,11 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
                                                          DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->nnz > nbr_cap) return;
-    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < m; q += gs) {
+    // kNormalLanes lanes per point: each sums every kNormalLanes-th list entry, then
+    // the group adds up its partial moments (every lane ends with the totals)
+    const int sub = lane_id() % kNormalLanes;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * (kBlock / kNormalLanes);
+    for (int64_t q = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kNormalLanes; q < m; q += gs) {
         const int c = cloud_of(kept_cloud, q);
         const RadiusTest rn = cl[c].rn;
         const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[2 * stride + q];
@@ -229,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
         int nn = 0;
         // moments of the r_normal subset, shifted to the query (FP64)
         double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
-        for (int k = b; k < e; ++k) {
+        for (int k = b + sub; k < e; k += kNormalLanes) {
             const int s = nbr[k];
             const float x = xyz[s], y = xyz[stride + s], z = xyz[2 * stride + s];
             if (!in_radius(rn, qx, qy, qz, x, y, z)) continue;
@@ -246,6 +297,20 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
             syz += dy * dz;
             szz += dz * dz;
         }
+#pragma unroll
+        for (int d = 1; d < kNormalLanes; d <<= 1) {
+            nn += __shfl_xor(nn, d, kNormalLanes);
+            sx += __shfl_xor(sx, d, kNormalLanes);
+            sy += __shfl_xor(sy, d, kNormalLanes);
+            sz += __shfl_xor(sz, d, kNormalLanes);
+            sxx += __shfl_xor(sxx, d, kNormalLanes);
+            sxy += __shfl_xor(sxy, d, kNormalLanes);
+            sxz += __shfl_xor(sxz, d, kNormalLanes);
+            syy += __shfl_xor(syy, d, kNormalLanes);
+            syz += __shfl_xor(syz, d, kNormalLanes);
+            szz += __shfl_xor(szz, d, kNormalLanes);
+        }
+        if (sub != 0) continue;  // the group's first lane finishes the point
         if (n_normal) n_normal[q] = nn;
         const int tau_num = cl[c].tau_num;
         if (e - b < tau_num || nn < tau_num) {
@@ -384,8 +449,8 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
     }
     if (with_normals) {
         StageScope sc(ST_NORMALS, s);
-        normals_kernel<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, off, nbr,
-                                                                 nbr_cap, nrm, nrm_stride, flags, n_normal, st);
+        normals_kernel<<<grid_cap(m_cap * kNormalLanes, kBlock), kBlock, 0, s>>>(
+            cl, xyz, stride, kept_cloud, m_cap, off, nbr, nbr_cap, nrm, nrm_stride, flags, n_normal, st);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
