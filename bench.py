@@ -39,18 +39,19 @@ sys.path.insert(0, ROOT)
 METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency vs plain"
 PEAK_FP64_MFMA_TFLOPS = 78.6
 
-# HBM bytes per launch of the distance-tile kernel, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 14 launches on this workload),
-# each scaled by what the same counter reads for a streaming add of 256 MiB in and
-# 256 MiB out (FETCH_SIZE 131085 KiB -> x2.0, WRITE_SIZE 262144 KiB -> x1.0).  The
-# figures hold for the matcher source with this SHA-256 only; after any change to it
-# the field is reported as null until the counters are taken again.
+# HBM bytes per launch of the first-direction band tile kernel, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 14 launches on
+# this workload), each scaled by what the same counter reads for a streaming add of
+# 256 MiB in and 256 MiB out (FETCH_SIZE 131084.4 KiB -> x2.0, WRITE_SIZE
+# 262144 KiB -> x1.0).  The figures hold for the matcher source with this SHA-256
+# only; after any change to it the field is reported as null until the counters
+# are taken again.
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
-    "sha256": "2fb470a224084a0695f57cd54d5b5a11f62d0573364e09b3a79cdb9091605f8e",
-    "fetch_kib": 91844.0,
-    "fetch_scale": 262144.0 / 131085.4,
-    "write_kib": 28549.6,
+    "sha256": "11120aa5e9bbf5623ebd4876b4bd8d566484a83662ae56c15d90b6153f7e13c0",
+    "fetch_kib": 27128.6,
+    "fetch_scale": 262144.0 / 131084.4,
+    "write_kib": 8027.9,
     "write_scale": 262144.0 / 262144.0,
 }
 

@@ -1871,7 +1871,9 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
 // range of partner chunks) from an atomic queue.  The partner chunk operands
 // come straight from memory with raw buffer loads, one chunk ahead of the
 // products; the waves share no data, so there is no barrier.
-template <int KS>
+// kBack only names the launch: 0 for the first direction, 1 for the matching
+// back and FP64 re-runs (so that profiles tell them apart).
+template <int KS, int kBack>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 ? 2 : 1))) void band_tiles(
     const SetPlan* __restrict__ plan, const double* __restrict__ pk, int dim, const int4* __restrict__ tinfo,
     double* __restrict__ part, DevStatus* st) {
@@ -2317,9 +2319,11 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     {
         StageScope sc(ST_MATCH_TOPK, s);
         if (ks == 9) {
-            band_tiles<9><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            if (oside) band_tiles<9, 0><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            else band_tiles<9, 1><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
         } else {
-            band_tiles<17><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            if (oside) band_tiles<17, 0><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            else band_tiles<17, 1><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
         }
         KMG_TRY(launch_status());
         timer_note_work(&st->band_pairs);
