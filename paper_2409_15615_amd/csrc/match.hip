@@ -663,8 +663,8 @@ __device__ __forceinline__ int exact_segs(int64_t F, int64_t part_cap) {
     return static_cast<int>(s < 1 ? 1 : (s > kXSegMax ? kXSegMax : s));
 }
 
-// Exact FP64 scans for the listed queries (fl, in slot order, *f_total of
-// them).  A work item is (group of 64 consecutive entries, row segment): lane
+// Exact FP64 scans for the listed queries (fl, *f_total of them, in any
+// order; slot order keeps a group within few sets).  A work item is (group of 64 consecutive entries, row segment): lane
 // L of every wave holds entry L, the partner rows of the segment stream
 // through LDS one row per thread, and each wave scores every fourth row,
 // ascending, with the plain FP64 sum in dimension order.  The four waves
@@ -703,7 +703,12 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
             const float* y = set_row(sets[c_e], static_cast<int>(slot - plan[c_e].q_off), dim);
             for (int t = 0; t < dim; ++t) s_y[L * kXStride + t] = y[t];
         }
-        int c_cur = find_set(n_sets, fl[g * kWave], [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
+        // the group's sets in increasing order, from the smallest (the list may come in any order)
+        if (threadIdx.x == 0) s_next = INT_MAX;
+        __syncthreads();
+        if (c_e != INT_MAX) atomicMin(&s_next, c_e);
+        __syncthreads();
+        int c_cur = s_next;
         double b1 = INFINITY, b2 = INFINITY;
         int j1 = INT_MAX;
         while (true) {
@@ -1423,7 +1428,8 @@ __device__ __forceinline__ void block_scan_k(int* v, int* tot, int* smem /* K x 
 // pair, the second on a tie, becomes rows-only) and written there; the
 // kernels after the planner then read oside.
 __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
-                                                         SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside) {
+                                                         SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside,
+                                                         int64_t* __restrict__ fb_total) {
     __shared__ int s_scan[5 * (kPlanThreads / kWave)];
     const int c = threadIdx.x;
     const bool live = c < n_sets;
@@ -1482,6 +1488,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __rest
         st->tile_next = 0;
         st->n_fallback = 0;
         st->band_step = 0;
+        *fb_total = 0;  // the re-score lists the uncertified queries from zero
     }
 }
 
@@ -1962,7 +1969,8 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ wave_tile, int32_t* __restrict__ nn,
                                                        double* __restrict__ best, double* __restrict__ second,
-                                                       int32_t* __restrict__ failed, DevStatus* st) {
+                                                       int32_t* __restrict__ failed, int32_t* __restrict__ fb_list,
+                                                       int64_t* __restrict__ fb_total, DevStatus* st) {
     const int64_t total = st->total_queries;
     const bool no_tiles = st->err_capacity != 0;  // the results are void; the flags stay well defined
     const int q = lane_id() & (kQuad - 1);
@@ -2052,7 +2060,9 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
             best[slot] = b1;
             second[slot] = b2;
         } else {
+            // listed for the exact scan (in any order: each query's scan stands alone)
             atomicAdd(&plan[c].n_fb, 1);
+            fb_list[atomicAdd(reinterpret_cast<unsigned long long*>(fb_total), 1ull)] = static_cast<int32_t>(slot);
         }
         failed[slot] = ok ? 0 : 1;
     }
@@ -2120,6 +2130,7 @@ kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
                       MatchSet* oside = nullptr);
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s);
+kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s);
 
 kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
 
@@ -2288,7 +2299,7 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     const MatchSet* sets = oside ? oside : sets_in;
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside);
+        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, w.fb_total);
         KMG_TRY(launch_status());
         row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
@@ -2332,9 +2343,10 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
         StageScope sc(ST_MATCH_RESCORE, s);
         rescore_band<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2,
                                                                           w.rank, w.perm, w.wave_tile, w.nn, w.best,
-                                                                          w.second, w.flag, st);
+                                                                          w.second, w.flag, w.fb_list, w.fb_total,
+                                                                          st);
         KMG_TRY(launch_status());
-        KMG_TRY(exact_fallback(sets, n_sets, dim, st, w, s));
+        KMG_TRY(exact_listed(sets, n_sets, dim, w, s));
     }
     return KMG_OK;
 }
@@ -2343,6 +2355,11 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s) {
     KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.fb_total, w.scan_tmp, s, &st->total_queries, w.fb_list));
+    return exact_listed(sets, n_sets, dim, w, s);
+}
+
+// Exact scans of the queries already listed in w.fb_list (*w.fb_total of them).
+kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s) {
     exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total, w.part_cap,
                                                    w.part);
     KMG_TRY(launch_status());

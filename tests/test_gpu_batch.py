@@ -150,3 +150,18 @@ def test_graph_capture_replays(K):
     got = [as_host(r) for r in b.results()]
     for i, gi in enumerate(got):
         np.testing.assert_array_equal(gi[0], expect[len(pairs) - 1 - i][0])
+
+
+def test_exact_fallbacks_from_several_pairs(K, orc):
+    # lattice planes give many equal descriptors, so the certificate fails for
+    # many queries of several pairs at once and one list of exact scans mixes
+    # their query sets (in whatever order the re-score appends them)
+    pairs = [synth.lattice_pair(0), synth.c0_pair(0), synth.lattice_pair(1, spacing=0.06), synth.c0_pair(1)]
+    res, _ = K.register_batch([c for d in pairs for c in clouds_of(K, d)])
+    for d, r in zip(pairs, res):
+        assert r.status == 0
+        ref = orc.run_pair(d["src"], d["tgt"], d["params"], d["vp_src"], d["vp_tgt"])
+        np.testing.assert_array_equal(r.pairs.cpu().numpy(), ref["pairs"])
+        np.testing.assert_array_equal(r.d1.cpu().numpy(), ref["d1"].astype(np.float32))
+        np.testing.assert_array_equal(r.d2.cpu().numpy(), ref["d2"].astype(np.float32))
+        print(f"{d['name']}: {len(ref['pairs'])} correspondences, {int(r.n_fallback)} exact scans")
