@@ -92,6 +92,7 @@ struct SetPlan {
     unsigned long long max_norm_bits;  // max squared norm (FP64 bits, non-negative)
     int32_t wave_off;   // norm-band matching: first query wave of the set
     int32_t rank_off;   // norm-band matching: first tile pair of the set's cross ranking
+    int32_t n_img;      // one-sided form: rows of this set listed for the matching back
 };
 
 // Matching output of one pair (device buffers).

@@ -198,6 +198,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __rest
         pl.part_off = p_off;
         pl.max_norm_bits = 0ull;
         pl.wave_off = 0;
+        pl.n_img = 0;
         plan[c] = pl;
     }
     if (c == 0) {
@@ -1304,7 +1305,8 @@ __global__ __launch_bounds__(kBlock) void rerun_lists(const MatchSet* __restrict
     if (tid < static_cast<int64_t>(sizeof(DevStatus) / 4)) reinterpret_cast<uint32_t*>(st2)[tid] = 0u;
 }
 
-// Copies the re-run's answers to the main query slots.
+// Copies the re-run's answers to the main query slots (set c's list starts at
+// pos[its first slot], or, without pos, at its first slot: the image lists).
 __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restrict__ plan2, int n_sets2,
                                                         const DevStatus* st2, const int32_t* __restrict__ nn2,
                                                         const double* __restrict__ best2,
@@ -1322,7 +1324,7 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
         const int c2 = find_set(n_sets2, t, [&](int q) { return static_cast<int64_t>(plan2[q].q_off); });
         if (c2 & 1) continue;  // rows-only sets have no answers
         const int i = static_cast<int>(t - plan2[c2].q_off);
-        const int64_t slot = f_slot[pos[plan[c2 >> 1].q_off] + i];
+        const int64_t slot = f_slot[(pos ? pos[plan[c2 >> 1].q_off] : plan[c2 >> 1].q_off) + i];
         nn[slot] = nn2[t];
         best[slot] = best2[t];
         second[slot] = second2[t];
@@ -1351,26 +1353,71 @@ __global__ void one_sided_sets(const MatchSet* __restrict__ sets, int n_sets, Ma
     out[c] = m;
 }
 
-// flag[slot] = 1 for every rows-only slot that some query has as its nearest
-// neighbour, 0 for the query slots; the rows-only slots come in cleared (the
-// re-score wrote 0 there).  nn of the rows-only slots <- -1 until the matching
-// back fills the flagged ones.
-__global__ __launch_bounds__(kBlock) void image_flags(const MatchSet* __restrict__ sets,
-                                                      const SetPlan* __restrict__ plan, int n_sets,
+// The image of the first direction, listed for the matching back in one pass:
+// every rows-only row that some query has as its nearest neighbour is claimed
+// once (its flag goes 0 -> 1; the re-score left the rows-only flags at 0) and
+// appended, in no particular order, to its set's own range of the re-run lists
+// (f_slot, f_row from the set's first slot on, counted in plan[c].n_img, which
+// the planner zeroed).  nn of the rows-only slots <- -1 until the matching back
+// fills the listed ones.  Also writes the re-run sets (set c's listed rows as
+// queries against its partner's rows) and clears the re-run status.
+__global__ __launch_bounds__(kBlock) void image_lists(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
                                                       int32_t* __restrict__ nn, int32_t* __restrict__ flag,
+                                                      int32_t* __restrict__ f_slot, int32_t* __restrict__ f_row,
+                                                      MatchSet* __restrict__ rr, DevStatus* st2,
                                                       const DevStatus* st) {
     const int64_t total = st->total_queries;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < total; slot += gs) {
-        const int c = find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
-        if (sets[c].flags & kSetRowsOnly) {
-            nn[slot] = -1;
-        } else {
-            flag[slot] = 0;
-            const int j = nn[slot];
-            if (j >= 0 && (c ^ 1) < n_sets) flag[plan[c ^ 1].q_off + j] = 1;
+    const int lane = lane_id();
+    // wave-uniform trip count: the appends are counted once per wave and set
+    for (int64_t w0 = tid - lane; w0 < total; w0 += gs) {
+        const int64_t slot = w0 + lane;
+        bool claim = false;
+        int p = 0, j = 0;
+        int32_t base = 0;
+        if (slot < total) {
+            const int c = find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); });
+            if (sets[c].flags & kSetRowsOnly) {
+                nn[slot] = -1;
+            } else {
+                j = nn[slot];
+                p = c ^ 1;
+                if (j >= 0 && p < n_sets) {
+                    base = plan[p].q_off;
+                    claim = atomicExch(&flag[base + j], 1) == 0;  // else another query has the row
+                }
+            }
+        }
+        uint64_t pending = ballot(claim);
+        int k = 0;
+        while (pending) {
+            const int lead = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+            const int pl = __shfl(p, lead, kWave);
+            const uint64_t same = ballot(claim && p == pl);
+            int at = 0;
+            if (lane == lead) at = atomicAdd(&plan[pl].n_img, __popcll(same));
+            at = __shfl(at, lead, kWave);
+            if (claim && p == pl) k = at + lanes_below(same);
+            pending &= ~same;
+        }
+        if (claim) {
+            f_slot[base + k] = base + j;
+            f_row[base + k] = sets[p].rows ? sets[p].rows[j] : j;
         }
     }
+    if (tid < n_sets) {
+        const int c = static_cast<int>(tid);
+        MatchSet q = sets[c];
+        q.rows = f_row + plan[c].q_off;
+        q.n = &plan[c].n_img;
+        q.flags = 0;
+        MatchSet r = sets[c ^ 1];
+        r.flags |= kSetRowsOnly;
+        rr[2 * c] = q;
+        rr[2 * c + 1] = r;
+    }
+    if (tid < static_cast<int64_t>(sizeof(DevStatus) / 4)) reinterpret_cast<uint32_t*>(st2)[tid] = 0u;
 }
 
 // ------------------------------------------------------------ norm bands --
@@ -1476,6 +1523,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __rest
         pl.max_norm_bits = 0ull;
         pl.wave_off = static_cast<int32_t>(w_off);
         pl.rank_off = static_cast<int32_t>(i_off);
+        pl.n_img = 0;
         plan[c] = pl;
     }
     if (c == 0) {
@@ -2271,20 +2319,16 @@ kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
 // land in their main slots.
 kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s) {
     StageScope sc(ST_MATCH_IMAGE, s);
-    image_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.nn, w.flag, st);
-    KMG_TRY(launch_status());
-    KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, w.rr.f_total, w.scan_tmp, s, &st->total_queries));
-    rerun_lists<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets + 64, kBlock)), kBlock, 0, s>>>(sets1, w.plan, n_sets, w.flag, w.pos, w.rr.f_total,
-                                                            w.q_cap, w.rr.f_slot, w.rr.f_row, w.rr.f_count, w.rr.sets,
-                                                            w.rr.st, st);
+    image_lists<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets + 64, kBlock)), kBlock, 0, s>>>(
+        sets1, w.plan, n_sets, w.nn, w.flag, w.rr.f_slot, w.rr.f_row, w.rr.sets, w.rr.st, st);
     KMG_TRY(launch_status());
     Carver c2(w.rr.region, w.rr.region_bytes);
     const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
     if (!c2.fits()) return KMG_ERR_WORKSPACE;
     KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
     rerun_scatter<<<std::max(grid_cap(w2.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
-        w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best, w2.second, w.plan, w.pos, w.rr.f_slot, w.nn, w.best, w.second,
-        st, 1);
+        w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best, w2.second, w.plan, nullptr, w.rr.f_slot, w.nn, w.best,
+        w.second, st, 1);
     return launch_status();
 }
 

@@ -122,6 +122,9 @@ __device__ __forceinline__ void wave_sort_write(const int32_t* list, int n, int3
         if (u * kWave + lane < n) out[u * kWave + lane] = v[u];
 }
 
+constexpr int kCandRounds = 4;  // candidate loads in flight per lane (list fill)
+constexpr int kNbrRounds = 4;   // neighbour-list entries in flight per lane (normals)
+
 // One wavefront per query, queries visited in cell-sorted order (grid-stride).
 // kFill = false: writes |N(q)| to deg[q].
 // kFill = true : writes N(q) ascending at nbr[off[q]..]; lists longer than
@@ -176,29 +179,38 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
             s_start[wv][lane] = cs;
         }
         __builtin_amdgcn_wave_barrier();
+        // candidates in rounds of kRounds x 64: the round's loads are all in
+        // flight before the first test, and the tests keep candidate order
+        constexpr int kRounds = kFill ? kCandRounds : 1;
         int found = 0;
-        for (int base = 0; base < total; base += kWave) {
-            const int t = base + lane;
-            bool in = false;
-            int sidx = 0;
-            if (t < total) {
-                int lo = 0, hi = 26;  // first cell whose inclusive prefix exceeds t
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_incl[wv][mid] > t) hi = mid;
-                    else lo = mid + 1;
+        for (int base = 0; base < total; base += kRounds * kWave) {
+            float4 sp[kRounds];
+#pragma unroll
+            for (int u = 0; u < kRounds; ++u) {
+                const int t = base + u * kWave + lane;
+                sp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < total) {
+                    int lo = 0, hi = 26;  // first cell whose inclusive prefix exceeds t
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_incl[wv][mid] > t) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const int before = lo ? s_incl[wv][lo - 1] : 0;
+                    sp[u] = g.pts[s_start[wv][lo] + (t - before)];
                 }
-                const int before = lo ? s_incl[wv][lo - 1] : 0;
-                const float4 sp = g.pts[s_start[wv][lo] + (t - before)];
-                in = in_radius(rt, qp.x, qp.y, qp.z, sp.x, sp.y, sp.z);
-                sidx = __float_as_int(sp.w);
             }
-            const uint64_t b = ballot(in);
-            if (kFill && in) {
-                const int at = found + lanes_below(b);
-                if (at < kCap) s_list[wv][at] = sidx;
+#pragma unroll
+            for (int u = 0; u < kRounds; ++u) {
+                const bool in = base + u * kWave + lane < total &&
+                                in_radius(rt, qp.x, qp.y, qp.z, sp[u].x, sp[u].y, sp[u].z);
+                const uint64_t b = ballot(in);
+                if (kFill && in) {
+                    const int at = found + lanes_below(b);
+                    if (at < kCap) s_list[wv][at] = __float_as_int(sp[u].w);
+                }
+                found += __popcll(b);
             }
-            found += __popcll(b);
         }
         if (!kFill) {
             if (lane == 0) {
@@ -280,22 +292,38 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
         int nn = 0;
         // moments of the r_normal subset, shifted to the query (FP64)
         double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
-        for (int k = b + sub; k < e; k += kNormalLanes) {
-            const int s = nbr[k];
-            const float x = xyz[s], y = xyz[stride + s], z = xyz[2 * stride + s];
-            if (!in_radius(rn, qx, qy, qz, x, y, z)) continue;
-            ++nn;
-            const double dx = static_cast<double>(x) - qx, dy = static_cast<double>(y) - qy,
-                         dz = static_cast<double>(z) - qz;
-            sx += dx;
-            sy += dy;
-            sz += dz;
-            sxx += dx * dx;
-            sxy += dx * dy;
-            sxz += dx * dz;
-            syy += dy * dy;
-            syz += dy * dz;
-            szz += dz * dz;
+        // kNbrRounds list entries per lane and round: their loads are in flight together
+        for (int k0 = b + sub; k0 < e; k0 += kNormalLanes * kNbrRounds) {
+            int id[kNbrRounds];
+#pragma unroll
+            for (int u = 0; u < kNbrRounds; ++u) {
+                const int k = k0 + u * kNormalLanes;
+                id[u] = k < e ? nbr[k] : -1;
+            }
+            float px[kNbrRounds], py[kNbrRounds], pz[kNbrRounds];
+#pragma unroll
+            for (int u = 0; u < kNbrRounds; ++u) {
+                const int s = id[u] < 0 ? 0 : id[u];
+                px[u] = xyz[s];
+                py[u] = xyz[stride + s];
+                pz[u] = xyz[2 * stride + s];
+            }
+#pragma unroll
+            for (int u = 0; u < kNbrRounds; ++u) {
+                if (id[u] < 0 || !in_radius(rn, qx, qy, qz, px[u], py[u], pz[u])) continue;
+                ++nn;
+                const double dx = static_cast<double>(px[u]) - qx, dy = static_cast<double>(py[u]) - qy,
+                             dz = static_cast<double>(pz[u]) - qz;
+                sx += dx;
+                sy += dy;
+                sz += dz;
+                sxx += dx * dx;
+                sxy += dx * dy;
+                sxz += dx * dz;
+                syy += dy * dy;
+                syz += dy * dz;
+                szz += dz * dz;
+            }
         }
 #pragma unroll
         for (int d = 1; d < kNormalLanes; d <<= 1) {
