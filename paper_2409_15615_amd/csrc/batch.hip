@@ -57,19 +57,33 @@ BatchWs carve_batch(Carver& c, int n_pairs, int64_t raw_cap, int64_t nnz_cap, in
     return w;
 }
 
-__global__ void batch_init(DevStatus* st, const CloudDev* cl, int n_clouds) {
-    uint32_t* w = reinterpret_cast<uint32_t*>(st);
-    for (int k = threadIdx.x; k < static_cast<int>(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
-    __syncthreads();
-    if (threadIdx.x == 0) st->n_raw = static_cast<int64_t>(cl[n_clouds - 1].raw_off) + cl[n_clouds - 1].n_raw;
+// Clears the status (block 0) and does every fill the step needs before its
+// first stage: the count table, the voxel and cell tables, the degrees and the
+// J flags (the stages are told that they come in cleared).
+__global__ __launch_bounds__(256) void batch_init(DevStatus* st, const CloudDev* cl, int n_clouds, FillJobs fills) {
+    if (blockIdx.x == 0) {
+        uint32_t* w = reinterpret_cast<uint32_t*>(st);
+        for (int k = threadIdx.x; k < static_cast<int>(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
+        __syncthreads();
+        if (threadIdx.x == 0) st->n_raw = static_cast<int64_t>(cl[n_clouds - 1].raw_off) + cl[n_clouds - 1].n_raw;
+    }
+    run_fill_jobs(fills);
 }
 
 // Set c: the J rows of cloud c (global kept indices into the FPFH array),
-// written back as cloud-local kept indices.
-__global__ void build_sets(const CloudState* cs, int n_clouds, const float* fpfh, const int32_t* jlist,
-                           MatchSet* sets) {
+// written back as cloud-local kept indices.  Its J range comes from the J
+// scan (pos) at the cloud's first and one-past-last kept point.
+__global__ void build_sets(CloudState* cs, int n_clouds, int64_t m_cap, const int32_t* __restrict__ pos,
+                           const DevStatus* st, const float* fpfh, const int32_t* jlist, MatchSet* sets) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_clouds) return;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    const int64_t nj = st->n_j;
+    const int64_t a = cs[c].kept_off, b = a + cs[c].kept_cnt;
+    const int64_t ja = a < m ? pos[a] : nj;
+    const int64_t jb = b < m ? pos[b] : nj;
+    cs[c].j_off = static_cast<int32_t>(ja);
+    cs[c].j_cnt = static_cast<int32_t>(jb - ja);
     MatchSet s;
     s.desc = fpfh;
     s.rows = jlist + cs[c].j_off;
@@ -137,17 +151,31 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
     if (!c.fits()) return KMG_ERR_WORKSPACE;
     const int C = 2 * n_pairs;
     const int D = 3 * H;
-    batch_init<<<1, 64, 0, s>>>(w.st, w.cl, C);
+    const int64_t rc = std::max<int64_t>(raw_cap, 1);
+    FillJobs fills{};
+    fills.job[0] = FillJob{counts, 0ull, static_cast<int64_t>(n_pairs) * kCountsStride, 8};
+    fills.job[1] = FillJob{w.vox.keys, kEmptyKey, w.vox.cap_table, 8};
+    fills.job[2] = FillJob{w.vox.mins, 0x7fffffffull, w.vox.cap_table, 4};
+    fills.job[3] = FillJob{w.srch.keys, kEmptyKey, w.srch.cap_table, 8};
+    fills.job[4] = FillJob{w.srch.ccount, 0ull, w.srch.cap_table, 4};
+    fills.job[5] = FillJob{w.srch.cfill, 0ull, w.srch.cap_table, 4};
+    fills.job[6] = FillJob{w.srch.deg, 0ull, raw_cap + 1, 4};
+    fills.job[7] = FillJob{w.feat.jflag, 0ull, rc, 4};
+    fills.n_jobs = 8;
+    const int64_t most = std::max<int64_t>({static_cast<int64_t>(w.vox.cap_table), w.srch.cap_table, rc + 1});
+    batch_init<<<static_cast<unsigned>(std::min<int64_t>((most + 255) / 256, 4096)), 256, 0, s>>>(w.st, w.cl, C,
+                                                                                                  fills);
     KMG_TRY(launch_status());
-    KMG_TRY(fill_u64(reinterpret_cast<uint64_t*>(counts), 0ull, static_cast<size_t>(n_pairs) * kCountsStride, s));
     KMG_TRY(voxelize_batch(w.cl, C, raw_cap, w.st, w.vox, raw_cap, raw_cap, w.kept_idx, w.kept_xyz, w.kept_cloud,
-                           w.cs, s));
-    KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s));
+                           w.cs, s, true));
+    KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s, true, 0,
+                               true));
     KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch, w.off,
                               w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
+    // the J ranges of the clouds come with the sets
     KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, w.nbr,
-                           w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, w.cs, s));
-    build_sets<<<grid_for(C, 64), 64, 0, s>>>(w.cs, C, w.fpfh, w.jlist, w.sets);
+                           w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, nullptr, s, true));
+    build_sets<<<grid_for(C, 64), 64, 0, s>>>(w.cs, C, raw_cap, w.feat.pos, w.st, w.fpfh, w.jlist, w.sets);
     KMG_TRY(launch_status());
     KMG_TRY(match_batch(w.sets, C, D, prec, w.st, w.match, w.outs, counts, kCountsStride, s));
     batch_counts<<<grid_for(n_pairs, 64), 64, 0, s>>>(w.cs, n_pairs, w.outs, w.st, nnz_cap, counts);

@@ -328,8 +328,8 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
     }
 }
 
-// flags |= J << 1; j_idx[jpos[q]] = q minus its cloud's kept offset (when cs is
-// given the J list is left in the global kept space for the matching stage).
+// flags |= J << 1; j_idx[jpos[q]] = q, the kept index in the batch's global
+// kept space (for one cloud, its own kept index).
 __global__ __launch_bounds__(kBlock) void j_emit(const int32_t* __restrict__ jflag, const int32_t* __restrict__ pos,
                                                  int64_t m_cap, uint8_t* __restrict__ flags,
                                                  int32_t* __restrict__ j_idx, const DevStatus* st) {
@@ -371,8 +371,10 @@ FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
 
 kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                       int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, const int32_t* nbr,
-                      const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s) {
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)), s));
+                      const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s,
+                      bool cleared) {
+    if (!cleared)
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)), s));
     if (m_cap > 0) {
         StageScope sc(ST_SPFH, s);
         spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
@@ -409,8 +411,9 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s) {
-    KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm, nrm_stride, flags, spfh_out, s));
+                          hipStream_t s, bool cleared) {
+    KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm, nrm_stride, flags, spfh_out, s,
+                       cleared));
     return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nbr, flags, fpfh_out, j_idx, cs, s);
 }
 

@@ -223,6 +223,28 @@ size_t scan_temp_elems(int64_t n);
 kmg_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
                           hipStream_t s, const int32_t* live = nullptr, int32_t* list = nullptr);
 kmg_status fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
+// Up to kMaxFillJobs fills (4- or 8-byte elements) done by one grid-stride pass.
+struct FillJob {
+    void* p;
+    uint64_t v;
+    int64_t n;
+    int32_t bytes;
+};
+constexpr int kMaxFillJobs = 8;
+struct FillJobs {
+    FillJob job[kMaxFillJobs];
+    int32_t n_jobs;
+};
+__device__ __forceinline__ void run_fill_jobs(const FillJobs& f) {
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int k = 0; k < f.n_jobs; ++k) {
+        const FillJob j = f.job[k];
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < j.n; i += gs) {
+            if (j.bytes == 8) static_cast<uint64_t*>(j.p)[i] = j.v;
+            else static_cast<uint32_t*>(j.p)[i] = static_cast<uint32_t>(j.v);
+        }
+    }
+}
 kmg_status fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 kmg_status fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 
@@ -242,9 +264,10 @@ VoxelWs carve_voxel(Carver& c, int64_t n_cap);
 // or the kept count when out_stride == 0), their cloud-local raw index to
 // kept_idx and their cloud to kept_cloud (nullable); per-cloud ranges to cs
 // (nullable).  Nothing is written when the kept count exceeds out_cap.
+// cleared: the caller has already emptied the voxel table (keys, mins).
 kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
                           int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
-                          int32_t* kept_cloud, CloudState* cs, hipStream_t s);
+                          int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared = false);
 
 // ---- search.hip -----------------------------------------------------------
 struct SearchWs {
@@ -263,10 +286,11 @@ SearchWs carve_search(Carver& c, int64_t m_cap);
 // m_cap, SoA stride `stride`, cloud ids kept_cloud (nullable = cloud 0)).
 // off receives m_cap + 1 offsets; the total goes to st->nnz.
 // use_rn: search at r_normal instead of r_FPFH; build_grid false reuses the
-// cell grid of an earlier call on the same workspace.
+// cell grid of an earlier call on the same workspace.  cleared: the caller
+// has already emptied the cell table (keys, ccount, cfill) and zeroed deg.
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
-                              bool build_grid = true, int use_rn = 0);
+                              bool build_grid = true, int use_rn = 0, bool cleared = false);
 // Fill pass (lists ascending) and normals.  Writes nothing into nbr when
 // st->nnz > nbr_cap (device-side check; st->err_capacity is set).
 kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
@@ -284,17 +308,20 @@ struct FeatWs {
 };
 FeatWs carve_feat(Carver& c, int64_t m_cap, int H);
 // Step 2, SPFH, FPFH and the J list over the kept points (count st->m_kept).
-// j_idx receives kept indices minus the cloud's kept offset when cs is given.
+// j_idx receives the kept indices of the J points (in the batch's global kept
+// space); cs, when given, receives the per-cloud J ranges.  cleared: jflag is
+// zero already.
 kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s);
+                          hipStream_t s, bool cleared = false);
 // The two halves of features_batch: SPFH (and J) over (off, nbr); then the
 // FPFH sum over (off, nbr) and the J list.
 kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                       int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, const int32_t* nbr,
-                      const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s);
+                      const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s,
+                      bool cleared = false);
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
                       const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
                       int32_t* j_idx, CloudState* cs, hipStream_t s);

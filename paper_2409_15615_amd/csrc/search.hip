@@ -143,6 +143,8 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     const int64_t m = clamp_count(st->m_kept, m_cap);
+    // lists that would overrun the caller's capacity are reported once (by the main fill pass)
+    if (kFill && !dense && blockIdx.x == 0 && threadIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
     // no search over a partial grid; no fill beyond the caller's list capacity
     if (st->err_range) return;
     if (kFill && st->nnz > nbr_cap) return;
@@ -394,10 +396,6 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
     }
 }
 
-__global__ void flag_capacity(DevStatus* st, int64_t nbr_cap) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
-}
-
 Grid grid_of(const SearchWs& w) {
     Grid g;
     g.pts = w.pts;
@@ -426,12 +424,14 @@ SearchWs carve_search(Carver& c, int64_t m_cap) {
 
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
-                              bool build_grid, int use_rn) {
+                              bool build_grid, int use_rn, bool cleared) {
     if (build_grid) {
         StageScope sc(ST_GRID, s);
-        KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ccount), 0u, w.cap_table, s));
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.cfill), 0u, w.cap_table, s));
+        if (!cleared) {
+            KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
+            KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ccount), 0u, w.cap_table, s));
+            KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.cfill), 0u, w.cap_table, s));
+        }
         if (m_cap > 0) {
             cell_insert<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, w.keys,
                                                                   w.ccount, w.cap_table - 1, w.pslot, st);
@@ -446,7 +446,7 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
     }
     {
         StageScope sc(ST_SEARCH_COUNT, s);
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
+        if (!cleared) KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
         if (m_cap > 0) {
             radius_search<false, 1, kSearchWaves><<<grid_cap(m_cap, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
                 cl, grid_of(w), kept_cloud, m_cap, w.deg, nullptr, nullptr, 0, 0, use_rn, st);
@@ -464,8 +464,6 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
     if (m_cap <= 0) return KMG_OK;
     {
         StageScope sc(ST_SEARCH_FILL, s);
-        flag_capacity<<<1, 64, 0, s>>>(st, nbr_cap);
-        KMG_TRY(launch_status());
         radius_search<true, kListSmall, kSearchWaves><<<grid_cap(m_cap, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
             cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 0, use_rn, st);
         KMG_TRY(launch_status());

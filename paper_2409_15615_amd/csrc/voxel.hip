@@ -117,10 +117,12 @@ VoxelWs carve_voxel(Carver& c, int64_t n_cap) {
 
 kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
                           int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
-                          int32_t* kept_cloud, CloudState* cs, hipStream_t s) {
+                          int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared) {
     StageScope sc(ST_VOXELIZE, s);
-    KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
-    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.mins), 0x7fffffffu, w.cap_table, s));
+    if (!cleared) {
+        KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.mins), 0x7fffffffu, w.cap_table, s));
+    }
     if (n_cap > 0) {
         voxel_insert<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.keys, w.mins,
                                                                w.cap_table - 1, w.slot, st);
