@@ -372,8 +372,10 @@ struct MatchWs {
     int32_t* nn;
     double* best;
     double* second;
-    int32_t* fb_list;     // queries left to the exact scan, in slot order
+    int32_t* fb_list;     // queries left to the exact scan (slot order, or any order from the band re-score)
     int64_t* fb_total;
+    int32_t* grp_done;    // exact scan: finished segments per 64-entry group (the planners zero them)
+    int64_t n_grp;
     int32_t* flag;
     int32_t* pos;
     int64_t* scan_tmp;

@@ -129,11 +129,13 @@ __device__ int common_segs(int64_t col_blocks, int64_t chunk_work) {
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_sets(const MatchSet* __restrict__ sets, int n_sets, int kp,
-                                                         int64_t part_cap, SetPlan* plan, DevStatus* st) {
+                                                         int64_t part_cap, SetPlan* plan, DevStatus* st,
+                                                         int32_t* __restrict__ grp_done, int64_t n_grp) {
     __shared__ int64_t smem[kPlanThreads / kWave];
     __shared__ int s_segs;
     __shared__ int s_chunks[kPlanThreads];
     __shared__ int s_n[kPlanThreads];
+    for (int64_t g = threadIdx.x; g < n_grp; g += kPlanThreads) grp_done[g] = 0;  // for the exact scans
     const int c = threadIdx.x;
     const bool live = c < n_sets;
     const bool rows_only = live && (sets[c].flags & kSetRowsOnly);
@@ -665,18 +667,22 @@ __device__ __forceinline__ int exact_segs(int64_t F, int64_t part_cap) {
 }
 
 // Exact FP64 scans for the listed queries (fl, *f_total of them, in any
-// order; slot order keeps a group within few sets).  A work item is (group of 64 consecutive entries, row segment): lane
-// L of every wave holds entry L, the partner rows of the segment stream
-// through LDS one row per thread, and each wave scores every fourth row,
-// ascending, with the plain FP64 sum in dimension order.  The four waves
-// merge their (best, index, second) and write them as the segment's partial
-// result; a group that spans several sets visits their partners one after
-// another.
+// order; slot order keeps a group within few sets).  A work item is (group of
+// 64 consecutive entries, row segment): lane L of every wave holds entry L,
+// the partner rows of the segment stream through LDS one row per thread, and
+// each wave scores every fourth row, ascending, with the plain FP64 sum in
+// dimension order.  The four waves merge their (best, index, second) and write
+// them as the segment's partial result; a group that spans several sets visits
+// their partners one after another.  The block that finishes a group's last
+// segment (counted in grp_done, which the planner zeroed) merges the group's
+// partials in segment order into nn, best and second, and resets the count.
 __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restrict__ sets,
                                                         const SetPlan* __restrict__ plan, int n_sets, int dim,
                                                         const int32_t* __restrict__ fl,
                                                         const int64_t* __restrict__ f_total, int64_t part_cap,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, int32_t* __restrict__ grp_done,
+                                                        int32_t* __restrict__ nn, double* __restrict__ best,
+                                                        double* __restrict__ second) {
 #pragma clang fp contract(off)
     __shared__ float s_x[kXRows * kXStride];
     __shared__ float s_y[kWave * kXStride];
@@ -763,29 +769,26 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
             pb2[e * S + sg] = b2;
             pj1[e * S + sg] = j1;
         }
+        // wave 0 wrote the partials: it publishes them and counts the segment
+        if (wv == 0) {
+            __threadfence();
+            int last = 0;
+            if (L == 0) last = atomicAdd(&grp_done[g], 1) == S - 1;
+            last = __shfl(last, 0, kWave);
+            if (last) {
+                __threadfence();  // the other segments' partials are visible from here on
+                if (have) {
+                    double m1 = pb1[e * S], m2 = pb2[e * S];
+                    int mj = pj1[e * S];
+                    for (int k = 1; k < S; ++k) combine_best(m1, mj, m2, pb1[e * S + k], pj1[e * S + k], pb2[e * S + k]);
+                    nn[slot] = (mj == INT_MAX) ? -1 : mj;
+                    best[slot] = m1;
+                    second[slot] = m2;
+                }
+                if (L == 0) grp_done[g] = 0;  // ready for a later scan on this workspace
+            }
+        }
         __syncthreads();
-    }
-}
-
-// Merges the segment partials of every listed query in segment order.
-__global__ __launch_bounds__(kBlock) void exact_merge(const int32_t* __restrict__ fl,
-                                                      const int64_t* __restrict__ f_total, int64_t part_cap,
-                                                      const double* __restrict__ part, int32_t* __restrict__ nn,
-                                                      double* __restrict__ best, double* __restrict__ second) {
-    const int64_t F = *f_total;
-    const int S = exact_segs(F, part_cap);
-    const double* pb1 = part;
-    const double* pb2 = part + F * S;
-    const int32_t* pj1 = reinterpret_cast<const int32_t*>(part + 2 * F * S);
-    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < F; e += gs) {
-        double b1 = pb1[e * S], b2 = pb2[e * S];
-        int j1 = pj1[e * S];
-        for (int sg = 1; sg < S; ++sg) combine_best(b1, j1, b2, pb1[e * S + sg], pj1[e * S + sg], pb2[e * S + sg]);
-        const int64_t slot = fl[e];
-        nn[slot] = (j1 == INT_MAX) ? -1 : j1;
-        best[slot] = b1;
-        second[slot] = b2;
     }
 }
 
@@ -1476,8 +1479,10 @@ __device__ __forceinline__ void block_scan_k(int* v, int* tot, int* smem /* K x 
 // kernels after the planner then read oside.
 __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
                                                          SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside,
-                                                         int64_t* __restrict__ fb_total) {
+                                                         int64_t* __restrict__ fb_total, int32_t* __restrict__ grp_done,
+                                                         int64_t n_grp) {
     __shared__ int s_scan[5 * (kPlanThreads / kWave)];
+    for (int64_t g = threadIdx.x; g < n_grp; g += kPlanThreads) grp_done[g] = 0;  // for the exact scans
     const int c = threadIdx.x;
     const bool live = c < n_sets;
     const bool paired = live && (c ^ 1) < n_sets;
@@ -2139,6 +2144,8 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     w.second = c.take<double>(static_cast<size_t>(w.q_cap));
     w.fb_list = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.fb_total = c.take<int64_t>(1);
+    w.n_grp = w.q_cap / kWave + 1;
+    w.grp_done = c.take<int32_t>(static_cast<size_t>(w.n_grp));
     w.flag = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.pos = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.scan_tmp = c.take<int64_t>(scan_temp_elems(w.q_cap));
@@ -2222,7 +2229,7 @@ kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStat
     const int n_pairs = n_sets / 2;
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st);
+        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st, w.grp_done, w.n_grp);
         KMG_TRY(launch_status());
         lp_center<<<n_pairs, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.lp_pairs);
         KMG_TRY(launch_status());
@@ -2284,7 +2291,7 @@ kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
     const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st);
+        plan_sets<<<1, kPlanThreads, 0, s>>>(sets, n_sets, w.kp, w.part_cap, w.plan, st, w.grp_done, w.n_grp);
         KMG_TRY(launch_status());
         row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
@@ -2343,7 +2350,8 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     const MatchSet* sets = oside ? oside : sets_in;
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, w.fb_total);
+        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, w.fb_total, w.grp_done,
+                                             w.n_grp);
         KMG_TRY(launch_status());
         row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
@@ -2405,10 +2413,7 @@ kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* 
 // Exact scans of the queries already listed in w.fb_list (*w.fb_total of them).
 kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s) {
     exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total, w.part_cap,
-                                                   w.part);
-    KMG_TRY(launch_status());
-    exact_merge<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.fb_list, w.fb_total, w.part_cap, w.part, w.nn, w.best,
-                                                            w.second);
+                                                   w.part, w.grp_done, w.nn, w.best, w.second);
     return launch_status();
 }
 
