@@ -666,9 +666,11 @@ __device__ __forceinline__ int exact_segs(int64_t F, int64_t part_cap) {
     return static_cast<int>(s < 1 ? 1 : (s > kXSegMax ? kXSegMax : s));
 }
 
-// Exact FP64 scans for the listed queries (fl, *f_total of them, in any
-// order; slot order keeps a group within few sets).  A work item is (group of
-// 64 consecutive entries, row segment): lane L of every wave holds entry L,
+// Exact FP64 scans for the listed queries, *f_total of them: fl[0 .. F) in
+// any order (slot order keeps a group within few sets), or (per_set) the
+// lists of the sets, plan[c].n_fb entries from fl[plan[c].q_off] on, in
+// groups that never span two sets.  A work item is (group of up to 64 entries, row
+// segment): lane L of every wave holds entry L,
 // the partner rows of the segment stream through LDS one row per thread, and
 // each wave scores every fourth row, ascending, with the plain FP64 sum in
 // dimension order.  The four waves merge their (best, index, second) and write
@@ -679,8 +681,9 @@ __device__ __forceinline__ int exact_segs(int64_t F, int64_t part_cap) {
 __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restrict__ sets,
                                                         const SetPlan* __restrict__ plan, int n_sets, int dim,
                                                         const int32_t* __restrict__ fl,
-                                                        const int64_t* __restrict__ f_total, int64_t part_cap,
-                                                        double* __restrict__ part, int32_t* __restrict__ grp_done,
+                                                        const int64_t* __restrict__ f_total, int per_set,
+                                                        int64_t part_cap, double* __restrict__ part,
+                                                        int32_t* __restrict__ grp_done,
                                                         int32_t* __restrict__ nn, double* __restrict__ best,
                                                         double* __restrict__ second) {
 #pragma clang fp contract(off)
@@ -689,21 +692,67 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
     __shared__ double s_b1[kBlock], s_b2[kBlock];
     __shared__ int s_j1[kBlock];
     __shared__ int s_next;
+    __shared__ int s_pre[kPlanThreads + 1];   // per-set lists: the sets' first entries
+    __shared__ int s_gpre[kPlanThreads + 1];  // and first groups
     constexpr int kWaves = kBlock / kWave;
     const int L = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
     const int64_t F = *f_total;
+    if (F == 0) return;  // uniform: nothing listed
+    if (per_set) {
+        if (wv == 0) {  // lane L sums sets [kPer L, kPer (L + 1)), then the wave scans the sums
+            constexpr int kPer = (kPlanThreads + kWave) / kWave;
+            int v[kPer];
+            int sum = 0, gsum = 0;
+            for (int k = 0; k < kPer; ++k) {
+                const int c = L * kPer + k;
+                v[k] = c < n_sets ? plan[c].n_fb : 0;
+                sum += v[k];
+                gsum += (v[k] + kWave - 1) / kWave;
+            }
+            int run = wave_incl_scan(sum) - sum;
+            int grun = wave_incl_scan(gsum) - gsum;
+            for (int k = 0; k < kPer; ++k) {
+                const int c = L * kPer + k;
+                if (c <= n_sets) {
+                    s_pre[c] = run;
+                    s_gpre[c] = grun;
+                }
+                run += v[k];
+                grun += (v[k] + kWave - 1) / kWave;
+            }
+        }
+        __syncthreads();
+    }
     const int S = exact_segs(F, part_cap);
     double* pb1 = part;
     double* pb2 = part + F * S;
     int32_t* pj1 = reinterpret_cast<int32_t*>(part + 2 * F * S);
-    const int64_t items = (F + kWave - 1) / kWave * S;
+    const int64_t groups = per_set ? s_gpre[n_sets] : (F + kWave - 1) / kWave;
+    const int64_t items = groups * S;
     for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
         const int64_t g = item / S;
         const int sg = static_cast<int>(item % S);
-        const int64_t e = g * kWave + L;
-        const bool have = e < F;
-        const int64_t slot = have ? fl[e] : 0;
+        // lane L: the group's entry L (dense index e into the partials) and its slot
+        int64_t e;
+        bool have;
+        int64_t slot = 0;
+        if (!per_set) {
+            e = g * kWave + L;
+            have = e < F;
+            if (have) slot = fl[e];
+        } else {
+            int lo = 0, hi = n_sets - 1;  // the group's set: the last whose first group is <= g
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_gpre[mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            const int local = static_cast<int>(g - s_gpre[lo]) * kWave + L;
+            have = local < s_pre[lo + 1] - s_pre[lo];
+            e = s_pre[lo] + local;
+            if (have) slot = fl[plan[lo].q_off + local];
+        }
         const int c_e = have ? find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); })
                              : INT_MAX;
         if (wv == 0 && have) {
@@ -1541,7 +1590,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __rest
         st->tile_next = 0;
         st->n_fallback = 0;
         st->band_step = 0;
-        *fb_total = 0;  // the re-score lists the uncertified queries from zero
+        *fb_total = 0;  // the re-score counts the uncertified queries from zero
     }
 }
 
@@ -2113,9 +2162,9 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
             best[slot] = b1;
             second[slot] = b2;
         } else {
-            // listed for the exact scan (in any order: each query's scan stands alone)
-            atomicAdd(&plan[c].n_fb, 1);
-            fb_list[atomicAdd(reinterpret_cast<unsigned long long*>(fb_total), 1ull)] = static_cast<int32_t>(slot);
+            // listed for the exact scan in the set's own range (in any order: each query's scan stands alone)
+            fb_list[qc.q_off + atomicAdd(&plan[c].n_fb, 1)] = static_cast<int32_t>(slot);
+            atomicAdd(reinterpret_cast<unsigned long long*>(fb_total), 1ull);
         }
         failed[slot] = ok ? 0 : 1;
     }
@@ -2144,7 +2193,7 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     w.second = c.take<double>(static_cast<size_t>(w.q_cap));
     w.fb_list = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.fb_total = c.take<int64_t>(1);
-    w.n_grp = w.q_cap / kWave + 1;
+    w.n_grp = w.q_cap / kWave + n_sets + 1;  // per-set groups: at most one partial group per set
     w.grp_done = c.take<int32_t>(static_cast<size_t>(w.n_grp));
     w.flag = c.take<int32_t>(static_cast<size_t>(w.q_cap));
     w.pos = c.take<int32_t>(static_cast<size_t>(w.q_cap));
@@ -2185,7 +2234,8 @@ kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
                       MatchSet* oside = nullptr);
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s);
-kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s);
+kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s,
+                        bool per_set = false);
 
 kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
 
@@ -2398,7 +2448,7 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
                                                                           w.second, w.flag, w.fb_list, w.fb_total,
                                                                           st);
         KMG_TRY(launch_status());
-        KMG_TRY(exact_listed(sets, n_sets, dim, w, s));
+        KMG_TRY(exact_listed(sets, n_sets, dim, w, s, true));
     }
     return KMG_OK;
 }
@@ -2410,10 +2460,12 @@ kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* 
     return exact_listed(sets, n_sets, dim, w, s);
 }
 
-// Exact scans of the queries already listed in w.fb_list (*w.fb_total of them).
-kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s) {
-    exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total, w.part_cap,
-                                                   w.part, w.grp_done, w.nn, w.best, w.second);
+// Exact scans of the queries already listed in w.fb_list: *w.fb_total of them,
+// in slot order, or (per_set) plan[c].n_fb of set c from slot plan[c].q_off on.
+kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s, bool per_set) {
+    exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total,
+                                                   per_set ? 1 : 0, w.part_cap, w.part, w.grp_done, w.nn, w.best,
+                                                   w.second);
     return launch_status();
 }
 
