@@ -1893,35 +1893,110 @@ __global__ __launch_bounds__(kBlock) void band_waves(const MatchSet* __restrict_
     }
 }
 
-// Cuts the bands into tiles of at most T chunks, T from the rounds model of
-// common_segs over the band kernel's wavefronts (tiles ~ total / T + waves / 2),
-// then each wave's first tile and every tile's {wave, set, first chunk, end}.
+// Candidate tile lengths of the band plan: every length 1 .. 64, then four per
+// octave (80, 96, 112, 128, 160, ...) up to 4096.  The plan takes the one with
+// the least modelled time: with at most one tile per wavefront slot the
+// longest tile, min(T, longest band) plus the fixed cost; with more, the mean
+// load per slot (chunks plus the fixed cost of every tile) plus half a tile
+// for the tail.
+constexpr int kTileCands = 88;
+__host__ __device__ constexpr int tile_len_cand(int i) {
+    return i < 64 ? i + 1 : (64 << ((i - 64) / 4)) + (16 << ((i - 64) / 4)) * ((i - 64) % 4 + 1);
+}
+static_assert(tile_len_cand(kTileCands - 1) == 4096, "candidate lengths end at 4096");
+
+// Threads per candidate length when the plan counts tiles: 88 x 11 threads,
+// thread (i, k) sums ceil(L_w / T_i) over the waves w = k mod 11.  Beyond
+// kExactTileWaves waves (many rounds of tiles, where the count matters less
+// than its cost) the count is estimated as total / T + waves / 2 and bounded by
+// total / T + waves.
+constexpr int kCandThreads = 11;
+constexpr int kExactTileWaves = 4096;
+static_assert(kTileCands * kCandThreads <= kPlanThreads, "one thread per (candidate, stripe)");
+
+// Cuts the bands into tiles of at most T chunks (T the candidate length with
+// the least modelled time over the band kernel's wavefront slots), then writes
+// each wave's first tile and every tile's {wave, set, first chunk, end}.
 __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restrict__ plan, int n_sets,
                                                           const int32_t* __restrict__ wave_c0,
                                                           const int32_t* __restrict__ wave_len,
                                                           int32_t* __restrict__ wave_tile, int4* __restrict__ tinfo,
                                                           int64_t tile_cap, DevStatus* st) {
     __shared__ int64_t smem[kPlanThreads / kWave];
+    __shared__ int s_cnt[kTileCands][kCandThreads];  // tiles of each candidate length, per stripe of waves
+    __shared__ int s_lmax[kPlanThreads / kWave];
+    __shared__ int s_T;
     const int W = st->total_waves;
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
     int64_t len_sum = 0;
-    for (int w = threadIdx.x; w < W; w += kPlanThreads) len_sum += wave_len[w];
+    int lmax = 0;
+    for (int w = threadIdx.x; w < W; w += kPlanThreads) {
+        len_sum += wave_len[w];
+        lmax = max(lmax, wave_len[w]);
+    }
     int64_t tot_len;
     block_excl_scan64(len_sum, smem, tot_len);
-    int T = 1 << 30;  // one tile per wave always fits
-    double best_t = INFINITY;
-    for (int cand = 2; cand <= 4096; cand *= 2) {
-        for (int half = 0; half < 2; ++half) {
-            const int t_len = half ? cand + cand / 2 : cand;
-            const double tiles = static_cast<double>(tot_len) / t_len + 0.5 * W;
-            if (tiles + W > static_cast<double>(tile_cap)) continue;  // the bound total / T + W must fit
-            const double rounds = ceil(tiles / kBandSlots);
-            const double t = rounds * (static_cast<double>(tot_len) / fmax(tiles, 1.0) + kTileOverhead);
-            if (t < best_t) {
-                best_t = t;
-                T = t_len;
+    // exact tile counts sum_w ceil(L_w / T) of every candidate length; the quotient
+    // from a float reciprocal, corrected to the exact one (L + T - 1 < 2^24)
+    const bool exact = W <= kExactTileWaves;
+    if (exact && threadIdx.x < kTileCands * kCandThreads) {
+        const int i = threadIdx.x / kCandThreads, k = threadIdx.x % kCandThreads;
+        const int T = tile_len_cand(i);
+        const float inv = 1.0f / static_cast<float>(T);
+        int cnt = 0;
+        for (int w = k; w < W; w += kCandThreads) {
+            const int x = wave_len[w] + T - 1;
+            int q = static_cast<int>(static_cast<float>(x) * inv);
+            if ((q + 1) * T <= x) ++q;
+            if (q * T > x) --q;
+            cnt += q;
+        }
+        s_cnt[i][k] = cnt;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) lmax = max(lmax, __shfl_xor(lmax, d, kWave));
+    if (lane == 0) s_lmax[wv] = lmax;
+    __syncthreads();
+    // wave 0: the modelled time of each candidate (lanes L and L + 64), the least wins,
+    // the shorter length on a tie
+    if (wv == 0) {
+        int lm = 0;
+        for (int k = 0; k < kPlanThreads / kWave; ++k) lm = max(lm, s_lmax[k]);
+        double t_best = INFINITY;
+        int i_best = kTileCands;
+        for (int i = lane; i < kTileCands; i += kWave) {
+            const int Ti = tile_len_cand(i);
+            int64_t tiles = 0, bound;
+            if (exact) {
+                for (int k = 0; k < kCandThreads; ++k) tiles += s_cnt[i][k];
+                bound = tiles;
+            } else {
+                tiles = (tot_len + Ti - 1) / Ti + W / 2;
+                bound = (tot_len + Ti - 1) / Ti + W;
+            }
+            const double len = static_cast<double>(min(Ti, max(lm, 1)));
+            double t = INFINITY;
+            if (bound <= tile_cap) {
+                t = tiles <= kBandSlots
+                        ? len + kTileOverhead
+                        : (static_cast<double>(tot_len) + static_cast<double>(tiles) * kTileOverhead) / kBandSlots +
+                              0.5 * (len + kTileOverhead);
+            }
+            if (t < t_best) {
+                t_best = t;
+                i_best = i;
             }
         }
+        const double m = wave_min_d(t_best);
+        const int cand = t_best == m ? i_best : kTileCands;
+        int first = cand;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) first = min(first, __shfl_xor(first, d, kWave));
+        if (lane == 0) s_T = (m < INFINITY) ? tile_len_cand(first) : (1 << 30);  // one tile per wave always fits
     }
+    __syncthreads();
+    const int T = s_T;
     __shared__ int s_off[kPlanThreads], s_c0[kPlanThreads], s_len[kPlanThreads], s_set[kPlanThreads];
     int64_t carry = 0;
     int64_t pairs = 0;  // query-row distances of the tiles (real queries and rows)
