@@ -1359,6 +1359,11 @@ __global__ __launch_bounds__(kBlock) void rerun_lists(const MatchSet* __restrict
 
 // Copies the re-run's answers to the main query slots (set c's list starts at
 // pos[its first slot], or, without pos, at its first slot: the image lists).
+// With flag (the matching back of the one-sided form): also the mutual flags.
+// Image row j of set c whose nearest neighbour back is row i of the query set
+// c ^ 1 forms a mutual pair iff the query's nearest neighbour is j; the flag
+// sits on the slot of the pair's even set (the query slots come in cleared,
+// the image rows' claims are overwritten).
 __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restrict__ plan2, int n_sets2,
                                                         const DevStatus* st2, const int32_t* __restrict__ nn2,
                                                         const double* __restrict__ best2,
@@ -1366,7 +1371,8 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
                                                         SetPlan* __restrict__ plan, const int32_t* __restrict__ pos,
                                                         const int32_t* __restrict__ f_slot, int32_t* __restrict__ nn,
                                                         double* __restrict__ best, double* __restrict__ second,
-                                                        DevStatus* st, int add_rescans) {
+                                                        DevStatus* st, int add_rescans,
+                                                        int32_t* __restrict__ flag) {
     const int64_t total = st2->total_queries;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
     const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -1376,10 +1382,23 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
         const int c2 = find_set(n_sets2, t, [&](int q) { return static_cast<int64_t>(plan2[q].q_off); });
         if (c2 & 1) continue;  // rows-only sets have no answers
         const int i = static_cast<int>(t - plan2[c2].q_off);
-        const int64_t slot = f_slot[(pos ? pos[plan[c2 >> 1].q_off] : plan[c2 >> 1].q_off) + i];
-        nn[slot] = nn2[t];
+        const int c = c2 >> 1;
+        const int64_t slot = f_slot[(pos ? pos[plan[c].q_off] : plan[c].q_off) + i];
+        const int back = nn2[t];
+        nn[slot] = back;
         best[slot] = best2[t];
         second[slot] = second2[t];
+        if (flag) {
+            const int qs = c ^ 1;  // the query set (the image rows are in set c)
+            const int64_t qslot = back >= 0 ? plan[qs].q_off + back : -1;
+            const bool mutual = back >= 0 && nn[qslot] == static_cast<int>(slot - plan[c].q_off);
+            if (!(c & 1)) {
+                flag[slot] = mutual ? 1 : 0;
+            } else {
+                flag[slot] = 0;
+                if (mutual) flag[qslot] = 1;
+            }
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && st2->err_capacity) st->err_capacity = 1;
 }
@@ -1433,6 +1452,7 @@ __global__ __launch_bounds__(kBlock) void image_lists(const MatchSet* __restrict
             if (sets[c].flags & kSetRowsOnly) {
                 nn[slot] = -1;
             } else {
+                flag[slot] = 0;  // the mutual flags of the matching back start cleared
                 j = nn[slot];
                 p = c ^ 1;
                 if (j >= 0 && p < n_sets) {
@@ -2333,9 +2353,14 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
     if (w.one_sided) KMG_TRY(match_back(first, n_sets, dim, st, w, s));
     {
         StageScope sc(ST_MATCH_MUTUAL, s);
-        mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
-        KMG_TRY(launch_status());
-        KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
+        if (w.one_sided) {
+            // the matching back wrote the flags of the live slots
+            KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s, &st->total_queries));
+        } else {
+            mutual_flags<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(w.plan, n_sets, w.nn, w.q_cap, w.flag, st);
+            KMG_TRY(launch_status());
+            KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
+        }
         emit_pairs<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
             sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best, w.second, outs, st, counts, counts_stride);
         KMG_TRY(launch_status());
@@ -2404,7 +2429,7 @@ kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStat
         StageScope sc(ST_MATCH_RESCORE, s);
         rerun_scatter<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best,
                                                                    w2.second, w.plan, w.pos, w.rr.f_slot, w.nn,
-                                                                   w.best, w.second, st, 0);
+                                                                   w.best, w.second, st, 0, nullptr);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
@@ -2460,7 +2485,7 @@ kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st,
     KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
     rerun_scatter<<<std::max(grid_cap(w2.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
         w2.plan, 2 * n_sets, w.rr.st, w2.nn, w2.best, w2.second, w.plan, nullptr, w.rr.f_slot, w.nn, w.best,
-        w.second, st, 1);
+        w.second, st, 1, w.flag);
     return launch_status();
 }
 
