@@ -9,6 +9,8 @@ namespace kmg {
 
 namespace {
 
+// counts[i * 8 + k]: 0 correspondences, 1-2 kept points, 3-4 |J|, 5 exact
+// re-scans, 6 status, 7 neighbour entries of the batch.
 constexpr int kCountsStride = 8;
 
 struct BatchWs {
@@ -68,48 +70,6 @@ __global__ __launch_bounds__(256) void batch_init(DevStatus* st, const CloudDev*
         if (threadIdx.x == 0) st->n_raw = static_cast<int64_t>(cl[n_clouds - 1].raw_off) + cl[n_clouds - 1].n_raw;
     }
     run_fill_jobs(fills);
-}
-
-// Set c: the J rows of cloud c (global kept indices into the FPFH array),
-// written back as cloud-local kept indices.  Its J range comes from the J
-// scan (pos) at the cloud's first and one-past-last kept point.
-__global__ void build_sets(CloudState* cs, int n_clouds, int64_t m_cap, const int32_t* __restrict__ pos,
-                           const DevStatus* st, const float* fpfh, const int32_t* jlist, MatchSet* sets) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_clouds) return;
-    const int64_t m = clamp_count(st->m_kept, m_cap);
-    const int64_t nj = st->n_j;
-    const int64_t a = cs[c].kept_off, b = a + cs[c].kept_cnt;
-    const int64_t ja = a < m ? pos[a] : nj;
-    const int64_t jb = b < m ? pos[b] : nj;
-    cs[c].j_off = static_cast<int32_t>(ja);
-    cs[c].j_cnt = static_cast<int32_t>(jb - ja);
-    MatchSet s;
-    s.desc = fpfh;
-    s.rows = jlist + cs[c].j_off;
-    s.n = &cs[c].j_cnt;
-    s.row_base = cs[c].kept_off;
-    s.flags = 0;
-    sets[c] = s;
-}
-
-// counts[i * 8 + k]: 0 correspondences, 1-2 kept points, 3-4 |J|, 5 exact
-// re-scans, 6 status, 7 neighbour entries of the batch.
-__global__ void batch_counts(const CloudState* cs, int n_pairs, const PairOutDev* outs, const DevStatus* st,
-                             int64_t nnz_cap, int64_t* counts) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs) return;
-    int64_t* o = counts + static_cast<int64_t>(i) * kCountsStride;
-    o[1] = cs[2 * i].kept_cnt;
-    o[2] = cs[2 * i + 1].kept_cnt;
-    o[3] = cs[2 * i].j_cnt;
-    o[4] = cs[2 * i + 1].j_cnt;
-    o[7] = st->nnz;
-    int64_t status = KMG_OK;
-    if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
-    else if (st->err_capacity || st->nnz > nnz_cap) status = KMG_ERR_WORKSPACE;
-    else if (o[0] > outs[i].cap) status = KMG_ERR_CAPACITY;
-    o[6] = status;
 }
 
 }  // namespace
@@ -172,14 +132,11 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
                                true));
     KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch, w.off,
                               w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
-    // the J ranges of the clouds come with the sets
+    // the J list emission also writes the clouds' J ranges and matching sets
     KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, w.nbr,
-                           w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, nullptr, s, true));
-    build_sets<<<grid_for(C, 64), 64, 0, s>>>(w.cs, C, raw_cap, w.feat.pos, w.st, w.fpfh, w.jlist, w.sets);
-    KMG_TRY(launch_status());
-    KMG_TRY(match_batch(w.sets, C, D, prec, w.st, w.match, w.outs, counts, kCountsStride, s));
-    batch_counts<<<grid_for(n_pairs, 64), 64, 0, s>>>(w.cs, n_pairs, w.outs, w.st, nnz_cap, counts);
-    KMG_TRY(launch_status());
+                           w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, w.cs, s, true, w.sets));
+    // the pair counts and statuses come with the correspondences
+    KMG_TRY(match_batch(w.sets, C, D, prec, w.st, w.match, w.outs, counts, kCountsStride, s, w.cs, nnz_cap));
     timer_collect();  // waits for the stream only while timing is enabled
     return KMG_OK;
 }

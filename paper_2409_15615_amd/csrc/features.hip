@@ -330,15 +330,37 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
 
 // flags |= J << 1; j_idx[jpos[q]] = q, the kept index in the batch's global
 // kept space (for one cloud, its own kept index).
+// With sets (the batch form): block 0 also writes each cloud's J range (from
+// the scan at its first and one-past-last kept point) and its matching set:
+// the J rows of the cloud (global kept indices into fpfh), reported back as
+// cloud-local kept indices.
 __global__ __launch_bounds__(kBlock) void j_emit(const int32_t* __restrict__ jflag, const int32_t* __restrict__ pos,
                                                  int64_t m_cap, uint8_t* __restrict__ flags,
-                                                 int32_t* __restrict__ j_idx, const DevStatus* st) {
+                                                 int32_t* __restrict__ j_idx, const DevStatus* st, CloudState* cs,
+                                                 int n_clouds, const float* fpfh, MatchSet* sets) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < m; q += gs) {
         const int j = jflag[q];
         flags[q] = static_cast<uint8_t>((flags[q] & 1) | (j << 1));
         if (j) j_idx[pos[q]] = static_cast<int32_t>(q);
+    }
+    if (sets && blockIdx.x == 0) {
+        const int64_t nj = st->n_j;
+        for (int c = threadIdx.x; c < n_clouds; c += kBlock) {
+            const int64_t a = cs[c].kept_off, b = a + cs[c].kept_cnt;
+            const int64_t ja = a < m ? pos[a] : nj;
+            const int64_t jb = b < m ? pos[b] : nj;
+            cs[c].j_off = static_cast<int32_t>(ja);
+            cs[c].j_cnt = static_cast<int32_t>(jb - ja);
+            MatchSet ms;
+            ms.desc = fpfh;
+            ms.rows = j_idx + ja;
+            ms.n = &cs[c].j_cnt;
+            ms.row_base = cs[c].kept_off;
+            ms.flags = 0;
+            sets[c] = ms;
+        }
     }
 }
 
@@ -387,7 +409,7 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
 
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
                       const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
-                      int32_t* j_idx, CloudState* cs, hipStream_t s) {
+                      int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets) {
     if (m_cap > 0) {
         StageScope sc(ST_FPFH, s);
         fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, off, nbr, H,
@@ -396,11 +418,13 @@ kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_
     }
     StageScope sc(ST_J_COMPACT, s);
     KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
-    if (m_cap > 0) {
-        j_emit<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st);
+    if (sets && !cs) return KMG_ERR_ARG;
+    if (m_cap > 0 || sets) {
+        j_emit<<<std::max(grid_cap(m_cap, kBlock), 1u), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st, cs,
+                                                                      n_clouds, fpfh_out, sets);
         KMG_TRY(launch_status());
     }
-    if (cs) {
+    if (cs && !sets) {
         cloud_j_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(n_clouds, m_cap, w.pos, st, cs);
         KMG_TRY(launch_status());
     }
@@ -411,10 +435,10 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s, bool cleared) {
+                          hipStream_t s, bool cleared, MatchSet* sets) {
     KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm, nrm_stride, flags, spfh_out, s,
                        cleared));
-    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nbr, flags, fpfh_out, j_idx, cs, s);
+    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nbr, flags, fpfh_out, j_idx, cs, s, sets);
 }
 
 }  // namespace kmg

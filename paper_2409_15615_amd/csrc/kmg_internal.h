@@ -222,6 +222,10 @@ size_t scan_temp_elems(int64_t n);
 // (a stream compaction of 0/1 flags, in position order).  Two launches.
 kmg_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
                           hipStream_t s, const int32_t* live = nullptr, int32_t* list = nullptr);
+// The second launch alone, for producers that wrote the tile sums themselves:
+// temp[b] = the sum of in[b kScanTile .. (b + 1) kScanTile) for every tile b.
+kmg_status scan_exclusive_summed(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
+                                 hipStream_t s);
 kmg_status fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
 // Up to kMaxFillJobs fills (4- or 8-byte elements) done by one grid-stride pass.
 struct FillJob {
@@ -309,13 +313,13 @@ struct FeatWs {
 FeatWs carve_feat(Carver& c, int64_t m_cap, int H);
 // Step 2, SPFH, FPFH and the J list over the kept points (count st->m_kept).
 // j_idx receives the kept indices of the J points (in the batch's global kept
-// space); cs, when given, receives the per-cloud J ranges.  cleared: jflag is
-// zero already.
+// space); cs, when given, receives the per-cloud J ranges, and sets (with cs)
+// each cloud's matching set.  cleared: jflag is zero already.
 kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s, bool cleared = false);
+                          hipStream_t s, bool cleared = false, MatchSet* sets = nullptr);
 // The two halves of features_batch: SPFH (and J) over (off, nbr); then the
 // FPFH sum over (off, nbr) and the J list.
 kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
@@ -324,7 +328,7 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
                       bool cleared = false);
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
                       const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
-                      int32_t* j_idx, CloudState* cs, hipStream_t s);
+                      int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets = nullptr);
 
 // ---- match.hip ------------------------------------------------------------
 constexpr int kLpMaxDim = 64;  // descriptor length of the FP16 / BF16 tiles (two K = 32 steps)
@@ -388,8 +392,12 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun = 
 // Matches sets 2i and 2i+1 for every pair i (both directions, mutual check).
 // counts[i * counts_stride + 0] receives the number of correspondences of
 // pair i and [.. + 5] the number of exact re-scans of its queries.
+// With cs (the batch form), counts also receive per pair the kept points and
+// |J| of both clouds (from cs), the neighbour entries and the pair's status
+// (nnz_cap: the neighbour-list capacity the status is judged against).
 kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
-                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s);
+                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s,
+                       const CloudState* cs = nullptr, int64_t nnz_cap = 0);
 
 // ---- graph.hip: ratio filter, Eq. (3) graph, max k-core ----------------------
 size_t graph_ws(int64_t n_corr, int32_t n_tau);

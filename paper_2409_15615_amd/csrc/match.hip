@@ -865,7 +865,8 @@ __global__ __launch_bounds__(kBlock) void emit_pairs(const MatchSet* __restrict_
                                                      const int32_t* __restrict__ nn, const double* __restrict__ best,
                                                      const double* __restrict__ second,
                                                      const PairOutDev* __restrict__ outs, const DevStatus* st,
-                                                     int64_t* counts, int stride) {
+                                                     int64_t* counts, int stride, const CloudState* cs,
+                                                     int64_t nnz_cap) {
     const int64_t total = st->total_queries;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
     const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -875,8 +876,21 @@ __global__ __launch_bounds__(kBlock) void emit_pairs(const MatchSet* __restrict_
         const int64_t a = plan[2 * i].q_off, b = plan[2 * i + 1].q_off;
         const int64_t pa = a < total ? pos[a] : st->pairs_total;
         const int64_t pb = b < total ? pos[b] : st->pairs_total;
-        counts[static_cast<int64_t>(i) * stride + 0] = pb - pa;
-        counts[static_cast<int64_t>(i) * stride + 5] = plan[2 * i].n_fb + plan[2 * i + 1].n_fb;
+        int64_t* o = counts + static_cast<int64_t>(i) * stride;
+        o[0] = pb - pa;
+        o[5] = plan[2 * i].n_fb + plan[2 * i + 1].n_fb;
+        if (cs) {  // the batch form: sizes of the pair and its status
+            o[1] = cs[2 * i].kept_cnt;
+            o[2] = cs[2 * i + 1].kept_cnt;
+            o[3] = cs[2 * i].j_cnt;
+            o[4] = cs[2 * i + 1].j_cnt;
+            o[7] = st->nnz;
+            int64_t status = KMG_OK;
+            if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
+            else if (st->err_capacity || st->nnz > nnz_cap) status = KMG_ERR_WORKSPACE;
+            else if (o[0] > outs[i].cap) status = KMG_ERR_CAPACITY;
+            o[6] = status;
+        }
     }
     for (int64_t slot = tid; slot < total; slot += gs) {
         if (!flag[slot]) continue;
@@ -2335,7 +2349,8 @@ kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs
 kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
 
 kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
-                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s) {
+                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s,
+                       const CloudState* cs, int64_t nnz_cap) {
     if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
     // one-sided form when the workspace holds the second plan, else both directions in full
     const MatchSet* first = w.one_sided ? w.one_sided : sets;
@@ -2362,7 +2377,8 @@ kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevS
             KMG_TRY(scan_exclusive(w.flag, w.pos, w.q_cap, &st->pairs_total, w.scan_tmp, s));
         }
         emit_pairs<<<std::max(grid_cap(w.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
-            sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best, w.second, outs, st, counts, counts_stride);
+            sets, w.plan, n_sets, w.flag, w.pos, w.nn, w.best, w.second, outs, st, counts, counts_stride, cs,
+            nnz_cap);
         KMG_TRY(launch_status());
     }
     return KMG_OK;

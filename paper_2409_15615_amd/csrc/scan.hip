@@ -114,6 +114,14 @@ kmg_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int64_t* t
     return launch_status();
 }
 
+kmg_status scan_exclusive_summed(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
+                                 hipStream_t s) {
+    const int64_t nt = (n + kScanTile - 1) / kScanTile;
+    if (nt == 0) return fill_u64(reinterpret_cast<uint64_t*>(total), 0ull, 1, s);
+    tile_scan<<<static_cast<unsigned>(nt), kScanThreads, 0, s>>>(in, out, n, nullptr, temp, total, nullptr);
+    return launch_status();
+}
+
 kmg_status fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s) { return fill<uint8_t>(p, v, n, s); }
 kmg_status fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) { return fill<uint32_t>(p, v, n, s); }
 kmg_status fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) { return fill<uint64_t>(p, v, n, s); }

@@ -50,12 +50,32 @@ __global__ __launch_bounds__(kBlock) void voxel_insert(const CloudDev* __restric
     }
 }
 
+// One block per scan tile (kScanTile points, eight per thread): the flags and
+// the tile's sum for the scan that numbers the kept points.
 __global__ __launch_bounds__(kBlock) void voxel_mark(const int32_t* __restrict__ slot, const int32_t* mins,
-                                                     int64_t n_cap, int32_t* __restrict__ flag) {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < n_cap; t += stride) {
-        const int h = slot[t];
-        flag[t] = (h >= 0 && mins[h] == t) ? 1 : 0;
+                                                     int64_t n_cap, int32_t* __restrict__ flag,
+                                                     int64_t* __restrict__ tile_sum) {
+    static_assert(kScanTile % kBlock == 0, "whole tiles per block");
+    __shared__ int s_part[kBlock / kWave];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    int acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTile / kBlock; ++k) {
+        const int64_t t = base + k * kBlock + threadIdx.x;
+        if (t < n_cap) {
+            const int h = slot[t];
+            const int f = (h >= 0 && mins[h] == t) ? 1 : 0;
+            flag[t] = f;
+            acc += f;
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) tot += s_part[w];
+        tile_sum[blockIdx.x] = tot;
     }
 }
 
@@ -127,10 +147,11 @@ kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevSt
         voxel_insert<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.keys, w.mins,
                                                                w.cap_table - 1, w.slot, st);
         KMG_TRY(launch_status());
-        voxel_mark<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(w.slot, w.mins, n_cap, w.flag);
+        voxel_mark<<<static_cast<unsigned>((n_cap + kScanTile - 1) / kScanTile), kBlock, 0, s>>>(
+            w.slot, w.mins, n_cap, w.flag, w.scan_tmp);
         KMG_TRY(launch_status());
     }
-    KMG_TRY(scan_exclusive(w.flag, w.pos, n_cap, &st->m_kept, w.scan_tmp, s));
+    KMG_TRY(scan_exclusive_summed(w.flag, w.pos, n_cap, &st->m_kept, w.scan_tmp, s));
     if (n_cap > 0) {
         voxel_emit<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.flag, w.pos, st, out_cap,
                                                              out_stride, kept_idx, kept_xyz, kept_cloud);
