@@ -107,18 +107,25 @@ __device__ __forceinline__ void crossd(const double a[3], const double b[3], dou
 // f = (atan2(w.n_b, u.n_b), v.n_b, u.d); f = (0, 0, u.d) when d x u = 0.
 // Bin h = floor(H (f - lo) / (hi - lo)) clamped to [0, H-1].
 // Out of line: the FP64 recomputation is rare, and inlined it would hold the
-// registers of the whole SPFH loop.
-__device__ __attribute__((noinline)) void bins_f64(V3f pq32, V3f nq32, V3f pk32, V3f nk32, int H, int bins[3],
-                                                   bool& edge) {
+// registers of the whole SPFH loop.  The bins come back by value (in
+// registers), so the caller's bins never live in scratch memory.
+struct BinsF64 {
+    int b[3];
+    int edge;  // some feature within 1e-9 bins of a bin edge
+};
+__device__ __attribute__((noinline)) BinsF64 bins_f64(V3f pq32, V3f nq32, V3f pk32, V3f nk32, int H) {
 #pragma clang fp contract(off)
-    const double pq[3] = {pq32.x, pq32.y, pq32.z}, nq[3] = {nq32.x, nq32.y, nq32.z};
-    const double pk[3] = {pk32.x, pk32.y, pk32.z}, nk[3] = {nk32.x, nk32.y, nk32.z};
-    const double d0[3] = {pk[0] - pq[0], pk[1] - pq[1], pk[2] - pq[2]};
+    BinsF64 r;
+    r.edge = 0;
+    const double nq[3] = {nq32.x, nq32.y, nq32.z}, nk[3] = {nk32.x, nk32.y, nk32.z};
+    const double d0[3] = {static_cast<double>(pk32.x) - pq32.x, static_cast<double>(pk32.y) - pq32.y,
+                          static_cast<double>(pk32.z) - pq32.z};
     const bool qa = fabs(dotd(nq, d0)) >= fabs(dotd(nk, d0));
-    const double* pa = qa ? pq : pk;
-    const double* pb = qa ? pk : pq;
-    const double* u = qa ? nq : nk;
-    const double* nb = qa ? nk : nq;
+    // a, b and their normals by value selects (no pointers to local arrays)
+    const double pa[3] = {qa ? pq32.x : pk32.x, qa ? pq32.y : pk32.y, qa ? pq32.z : pk32.z};
+    const double pb[3] = {qa ? pk32.x : pq32.x, qa ? pk32.y : pq32.y, qa ? pk32.z : pq32.z};
+    const double u[3] = {qa ? nq[0] : nk[0], qa ? nq[1] : nk[1], qa ? nq[2] : nk[2]};
+    const double nb[3] = {qa ? nk[0] : nq[0], qa ? nk[1] : nq[1], qa ? nk[2] : nq[2]};
     double d[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
     const double dl = sqrt(dotd(d, d));
     for (int c = 0; c < 3; ++c) d[c] = d[c] / dl;
@@ -143,9 +150,10 @@ __device__ __attribute__((noinline)) void bins_f64(V3f pq32, V3f nq32, V3f pk32,
     for (int l = 0; l < 3; ++l) {
         const double s = (static_cast<double>(H) * (f[l] - lo[l])) / (hi[l] - lo[l]);
         const double fl = floor(s);
-        if (fabs(s - fl) < 1e-9 || fabs(s - (fl + 1.0)) < 1e-9) edge = true;
-        bins[l] = min(max(static_cast<int>(fl), 0), H - 1);
+        if (fabs(s - fl) < 1e-9 || fabs(s - (fl + 1.0)) < 1e-9) r.edge = 1;
+        r.b[l] = min(max(static_cast<int>(fl), 0), H - 1);
     }
+    return r;
 }
 
 __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
@@ -197,10 +205,12 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                     const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
                     const V3f nk = {nrm[k], nrm[nrm_stride + k], nrm[n2 + k]};
                     if (!bins_f32(pq, nq, pk, nk, H, bn)) {
-                        bool edge = false;
-                        bins_f64(pq, nq, pk, nk, H, bn, edge);
+                        const BinsF64 r = bins_f64(pq, nq, pk, nk, H);
+                        bn[0] = r.b[0];
+                        bn[1] = r.b[1];
+                        bn[2] = r.b[2];
                         ++n64;
-                        nedge += edge ? 1u : 0u;
+                        nedge += r.edge ? 1u : 0u;
                     }
                 }
             }
