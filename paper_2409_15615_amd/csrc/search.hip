@@ -83,25 +83,25 @@ __global__ __launch_bounds__(kBlock) void cell_scatter(const float* __restrict__
     }
 }
 
-// Ascending sort of n <= 64 E distinct indices held in LDS, written to out: a
-// bitonic network over 64 E values, value i = 64 u + lane in register u
-// (partners closer than a wavefront trade through shuffles).
-template <int E>
-__device__ __forceinline__ void wave_sort_write(const int32_t* list, int n, int32_t* out) {
-    const int lane = lane_id();
+// Ascending sort of n <= W E distinct indices held in LDS, written to out, by
+// a group of W lanes (a wavefront or half of one; gl = lane in the group): a
+// bitonic network over W E values, value i = W u + gl in register u (partners
+// closer than the group trade through shuffles within the group).
+template <int E, int W>
+__device__ __forceinline__ void group_sort_write(const int32_t* list, int n, int32_t* out, int gl) {
     int v[E];
 #pragma unroll
-    for (int u = 0; u < E; ++u) v[u] = (u * kWave + lane < n) ? list[u * kWave + lane] : INT_MAX;
+    for (int u = 0; u < E; ++u) v[u] = (u * W + gl < n) ? list[u * W + gl] : INT_MAX;
 #pragma unroll
-    for (int k = 2; k <= E * kWave; k <<= 1) {
+    for (int k = 2; k <= E * W; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= kWave) {
-                const int ju = j / kWave;
+            if (j >= W) {
+                const int ju = j / W;
 #pragma unroll
                 for (int u = 0; u < E; ++u) {
                     if (u & ju) continue;
-                    const int i = u * kWave + lane;
+                    const int i = u * W + gl;
                     const int a = v[u], b = v[u | ju];
                     const bool asc = (i & k) == 0;
                     v[u] = asc ? min(a, b) : max(a, b);
@@ -110,8 +110,8 @@ __device__ __forceinline__ void wave_sort_write(const int32_t* list, int n, int3
             } else {
 #pragma unroll
                 for (int u = 0; u < E; ++u) {
-                    const int i = u * kWave + lane;
-                    const int o = __shfl_xor(v[u], j, kWave);
+                    const int i = u * W + gl;
+                    const int o = __shfl_xor(v[u], j, W);
                     v[u] = (((i & j) == 0) == ((i & k) == 0)) ? min(v[u], o) : max(v[u], o);
                 }
             }
@@ -119,7 +119,12 @@ __device__ __forceinline__ void wave_sort_write(const int32_t* list, int n, int3
     }
 #pragma unroll
     for (int u = 0; u < E; ++u)
-        if (u * kWave + lane < n) out[u * kWave + lane] = v[u];
+        if (u * W + gl < n) out[u * W + gl] = v[u];
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort_write(const int32_t* list, int n, int32_t* out) {
+    group_sort_write<E, kWave>(list, n, out, lane_id());
 }
 
 constexpr int kCandRounds = 4;  // candidate loads in flight per lane (list fill)
@@ -316,6 +321,120 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_count2(const CloudDev* _
             deg[q] = found;
             // rare events only: no contended atomic per query
             if (found > kListSmall) atomicOr(&st->dense, found > kMaxDegree ? 3 : 1);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The common fill pass (lists of at most kListSmall entries) with two queries
+// per wavefront, one per half of 32 lanes: lookups and candidate tests as the
+// count pass, the found indices gathered in candidate order in the half's LDS
+// list, then sorted by the half and written ascending at nbr[off[q]..].
+template <int kWaves>
+__global__ __launch_bounds__(kWaves* kWave) void radius_fill2(const CloudDev* __restrict__ cl, Grid g,
+                                                              const int32_t* __restrict__ kept_cloud, int64_t m_cap,
+                                                              const int32_t* __restrict__ off,
+                                                              int32_t* __restrict__ nbr, int64_t nbr_cap,
+                                                              int use_rn, DevStatus* st) {
+    constexpr int kHalf = kWave / 2;
+    __shared__ int32_t s_incl[kWaves][2][kHalf];
+    __shared__ int32_t s_start[kWaves][2][kHalf];
+    __shared__ int32_t s_list[kWaves][2][kListSmall];
+    const int wv = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int hf = lane / kHalf, hl = lane % kHalf;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    // lists that would overrun the caller's capacity are reported once
+    if (blockIdx.x == 0 && threadIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
+    // no search over a partial grid; no fill beyond the caller's list capacity
+    if (st->err_range || st->nnz > nbr_cap) return;
+    for (int64_t pw = static_cast<int64_t>(blockIdx.x) * kWaves + wv; 2 * pw < m;
+         pw += static_cast<int64_t>(gridDim.x) * kWaves) {
+        const int64_t w = 2 * pw + hf;
+        const float4 qp = w < m ? g.pts[w] : make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+        const int q = __float_as_int(qp.w);
+        // longer lists are the dense pass's
+        const bool act = q >= 0 && q < m && off[q + 1] - off[q] <= kListSmall;
+        const int c = act ? cloud_of(kept_cloud, q) : 0;
+        const double inv_c = cl[c].inv_cell;
+        const RadiusTest rt = use_rn ? cl[c].rn : cl[c].rf;
+        int cc = 0, cs = 0;
+        if (act && hl < 27) {
+            const int64_t cx = cell_coord(qp.x, inv_c) + (hl % 3) - 1;
+            const int64_t cy = cell_coord(qp.y, inv_c) + (hl / 3) % 3 - 1;
+            const int64_t cz = cell_coord(qp.z, inv_c) + hl / 9 - 1;
+            const int h = hash_find(g.keys, g.mask, pack_key(c, cx, cy, cz));
+            if (h >= 0) {
+                cs = g.start[h];
+                cc = g.count[h];
+            }
+        }
+        int incl = cc;  // inclusive scan within the half
+#pragma unroll
+        for (int d = 1; d < kHalf; d <<= 1) {
+            const int t = __shfl_up(incl, d, kHalf);
+            if (hl >= d) incl += t;
+        }
+        const int total = __shfl(incl, hf * kHalf + 26, kWave);
+        const int tmax = max(total, __shfl_xor(total, kHalf, kWave));
+        __builtin_amdgcn_wave_barrier();
+        s_incl[wv][hf][hl] = (hl < 27) ? incl : INT_MAX;
+        s_start[wv][hf][hl] = cs;
+        __builtin_amdgcn_wave_barrier();
+        // candidates in rounds of kCandRounds x 32: the round's loads are all in
+        // flight before the first test, and the tests keep candidate order
+        int found = 0;
+        const uint32_t below = (1u << hl) - 1u;
+        for (int base = 0; base < tmax; base += kCandRounds * kHalf) {
+            float4 sp[kCandRounds];
+#pragma unroll
+            for (int u = 0; u < kCandRounds; ++u) {
+                const int t = base + u * kHalf + hl;
+                sp[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < total) {
+                    int lo = 0, hi = 26;  // first cell whose inclusive prefix exceeds t
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_incl[wv][hf][mid] > t) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const int before = lo ? s_incl[wv][hf][lo - 1] : 0;
+                    sp[u] = g.pts[s_start[wv][hf][lo] + (t - before)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kCandRounds; ++u) {
+                const bool in = base + u * kHalf + hl < total &&
+                                in_radius(rt, qp.x, qp.y, qp.z, sp[u].x, sp[u].y, sp[u].z);
+                const uint32_t b = static_cast<uint32_t>(ballot(in) >> (kHalf * hf));
+                if (in) {
+                    const int at = found + __popc(b & below);
+                    if (at < kListSmall) s_list[wv][hf][at] = __float_as_int(sp[u].w);
+                }
+                found += __popc(b);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int nf = act ? min(found, kListSmall) : 0;
+        const int nmax = max(nf, __shfl_xor(nf, kHalf, kWave));
+        int32_t* out = nbr + (act ? off[q] : 0);
+        const int32_t* lst = s_list[wv][hf];
+        if (nmax <= kHalf) {
+            group_sort_write<1, kHalf>(lst, nf, out, hl);
+        } else if (nmax <= 2 * kHalf) {
+            group_sort_write<2, kHalf>(lst, nf, out, hl);
+        } else if (nmax <= 4 * kHalf) {
+            group_sort_write<4, kHalf>(lst, nf, out, hl);
+        } else if (nmax <= 8 * kHalf) {
+            group_sort_write<8, kHalf>(lst, nf, out, hl);
+        } else {
+            // ranks are unique (distinct indices): scatter each entry to its sorted slot
+            for (int e = hl; e < nf; e += kHalf) {
+                const int v = lst[e];
+                int r = 0;
+                for (int k = 0; k < nf; ++k) r += (lst[k] < v) ? 1 : 0;
+                out[r] = v;
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -541,8 +660,8 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
     if (m_cap <= 0) return KMG_OK;
     {
         StageScope sc(ST_SEARCH_FILL, s);
-        radius_search<true, kListSmall, kSearchWaves><<<grid_cap(m_cap, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
-            cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 0, use_rn, st);
+        radius_fill2<kSearchWaves><<<grid_cap((m_cap + 1) / 2, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
+            cl, grid_of(w), kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st);
         KMG_TRY(launch_status());
         if (dense_pass) {
             radius_search<true, kMaxDegree, 1><<<grid_cap(m_cap, 1), kWave, 0, s>>>(
