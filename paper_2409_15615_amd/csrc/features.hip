@@ -160,6 +160,117 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
     return kept_cloud ? kept_cloud[q] : 0;
 }
 
+// Lists of a mean of at most kHalfListMean entries per point: two points per
+// wavefront, one per half of 32 lanes (each lane one neighbour of its half's
+// point per round, bin counts from ballots split by half, lane h of a half
+// holding bin h).  Longer lists: spfh_kernel, one point per wavefront.  Each
+// kernel checks the mean and returns at once when the other one serves it.
+// The threshold is measured: the 64-pair batch (mean 22.5) runs 1.5x faster
+// in pairs, the LiDAR pair (mean 29, but a long tail of structure points next
+// to scattered outliers with a few neighbours) 8% slower.
+constexpr int kHalfListMean = 24;
+
+__global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
+                                                     int64_t stride, const int32_t* __restrict__ kept_cloud,
+                                                     int64_t m_cap, const float* __restrict__ nrm,
+                                                     int64_t nrm_stride, const uint8_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ off,
+                                                     const int32_t* __restrict__ nbr, int H,
+                                                     double* __restrict__ spfh64, float* __restrict__ spfh_out,
+                                                     int32_t* __restrict__ Pq, int32_t* __restrict__ jflag,
+                                                     DevStatus* st) {
+    constexpr int kHalf = kWave / 2;
+    const int lane = lane_id();
+    const int hf = lane / kHalf, hl = lane % kHalf, sh = kHalf * hf;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
+    if (st->nnz > kHalfListMean * m) return;        // long lists: spfh_kernel
+    const int D = 3 * H;
+    const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
+    uint32_t n64 = 0, nedge = 0;
+    for (int64_t pw = global_wave(); 2 * pw < m; pw += wave_count()) {
+        const int64_t q = 2 * pw + hf;
+        const bool live = q < m;
+        const bool has_b = live && (flags[q] & 1);
+        V3f pq = {0.f, 0.f, 0.f}, nq = {0.f, 0.f, 0.f};
+        int b = 0, e = 0;
+        if (has_b) {
+            pq = {xyz[q], xyz[stride + q], xyz[s2 + q]};
+            nq = {nrm[q], nrm[nrm_stride + q], nrm[n2 + q]};
+            b = off[q];
+            e = off[q + 1];
+        }
+        const int len = e - b;
+        const int lmax = max(len, __shfl_xor(len, kHalf, kWave));
+        int n_valid = 0;
+        int c0 = 0, c1 = 0, c2 = 0;
+        for (int base = 0; base < lmax; base += kHalf) {
+            bool valid = false;
+            int bn[3] = {-1, -1, -1};
+            if (base + hl < len) {
+                const int k = nbr[b + base + hl];
+                valid = (flags[k] & 1) != 0;
+                if (valid && k != q) {
+                    const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
+                    const V3f nk = {nrm[k], nrm[nrm_stride + k], nrm[n2 + k]};
+                    if (!bins_f32(pq, nq, pk, nk, H, bn)) {
+                        const BinsF64 r = bins_f64(pq, nq, pk, nk, H);
+                        bn[0] = r.b[0];
+                        bn[1] = r.b[1];
+                        bn[2] = r.b[2];
+                        ++n64;
+                        nedge += r.edge ? 1u : 0u;
+                    }
+                }
+            }
+            n_valid += __popc(static_cast<uint32_t>(ballot(valid) >> sh));
+            for (int h = 0; h < H; ++h) {
+                const int a0 = __popc(static_cast<uint32_t>(ballot(bn[0] == h) >> sh));
+                const int a1 = __popc(static_cast<uint32_t>(ballot(bn[1] == h) >> sh));
+                const int a2 = __popc(static_cast<uint32_t>(ballot(bn[2] == h) >> sh));
+                if (hl == h) {
+                    c0 += a0;
+                    c1 += a1;
+                    c2 += a2;
+                }
+            }
+        }
+        if (!live) continue;
+        double* row = spfh64 + q * D;
+        if (!has_b) {
+            for (int t = hl; t < D; t += kHalf) {
+                row[t] = 0.0;
+                if (spfh_out) spfh_out[q * D + t] = 0.0f;
+            }
+            if (hl == 0) {
+                Pq[q] = 0;
+                jflag[q] = 0;
+            }
+            continue;
+        }
+        const int P = n_valid - 1;
+        if (hl < H) {
+            const int cs[3] = {c0, c1, c2};
+            for (int l = 0; l < 3; ++l) {
+                const double val = (P > 0) ? (100.0 * static_cast<double>(cs[l])) / static_cast<double>(P) : 0.0;
+                row[l * H + hl] = val;
+                if (spfh_out) spfh_out[q * D + l * H + hl] = static_cast<float>(val);
+            }
+        }
+        if (hl == 0) {
+            Pq[q] = P;
+            jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_j) ? 1 : 0;
+        }
+    }
+    // the FP64 recomputation counts, once per wave
+    n64 = wave_sum(n64);
+    nedge = wave_sum(nedge);
+    if (lane == 0) {
+        if (n64) atomicAdd(&st->feat_fp64, n64);
+        if (nedge) atomicAdd(&st->feat_edge, nedge);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
                                                       int64_t stride, const int32_t* __restrict__ kept_cloud,
                                                       int64_t m_cap, const float* __restrict__ nrm,
@@ -172,6 +283,7 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
     const int lane = lane_id();
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
+    if (st->nnz <= kHalfListMean * m) return;       // short lists: spfh_pairs
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
     for (int64_t q = global_wave(); q < m; q += wave_count()) {
@@ -412,6 +524,10 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
         spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
                                                               flags, off, nbr, H, w.spfh64, spfh_out, w.Pq, w.jflag,
                                                               st);
+        KMG_TRY(launch_status());
+        spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
+                                                                       nrm_stride, flags, off, nbr, H, w.spfh64,
+                                                                       spfh_out, w.Pq, w.jflag, st);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
