@@ -2104,7 +2104,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
     while (true) {
         int tile = 0;
         if (lane == 0) tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
-        tile = __shfl(tile, 0, kWave);
+        // uniform from here on: the tile's descriptor, plans and buffer resources live in
+        // scalar registers (a per-lane value would wrap every buffer load in a waterfall loop)
+        tile = __builtin_amdgcn_readfirstlane(tile);
         if (tile >= total) break;
         const int4 ti = tinfo[tile];
         const SetPlan qc = plan[ti.y];
