@@ -2214,9 +2214,19 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
         const int col = pos % kBandWave;
         const int t0 = wave_tile[w], t1 = wave_tile[w + 1];
         double top[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-        for (int t = t0 + q; t < t1; t += kQuad) {
-            const double* src = part + (static_cast<int64_t>(t) * kBandWave + col) * kTopK;
-            merge4(top, src[0], src[1], src[2], src[3]);
+        // the lane's lists four at a time: their loads in flight together
+        for (int t = t0 + q; t < t1; t += 4 * kQuad) {
+            double v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int tu = t + u * kQuad;
+                const double* src = part + (static_cast<int64_t>(tu < t1 ? tu : t) * kBandWave + col) * kTopK;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[u][r] = src[r];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (t + u * kQuad < t1) merge4(top, v[u][0], v[u][1], v[u][2], v[u][3]);
         }
         merge_lane(top, 1);
         merge_lane(top, 2);
