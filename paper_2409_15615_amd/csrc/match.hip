@@ -1741,7 +1741,7 @@ __global__ __launch_bounds__(kBlock) void scatter_pack(const MatchSet* __restric
                                                        int partner, const double* __restrict__ n2,
                                                        const int32_t* __restrict__ rank, double* __restrict__ pk,
                                                        int32_t* __restrict__ perm, uint32_t* __restrict__ skey,
-                                                       DevStatus* st) {
+                                                       int32_t* __restrict__ flag, DevStatus* st) {
     const bool pr = partner != 0;
     const int64_t total = static_cast<int64_t>(st->total_queries) * kp;
     const int64_t pads = static_cast<int64_t>(n_sets) * kTileRows * kp;
@@ -1765,7 +1765,10 @@ __global__ __launch_bounds__(kBlock) void scatter_pack(const MatchSet* __restric
             pk[(static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp + k) * kTileRows + pos % kTileRows] = v;
             if (k == 0) {
                 perm[pc.q_off + pos] = j;
-                if (pr) skey[pc.q_off + pos] = norm_key(n2[slot]);
+                if (pr) {
+                    skey[pc.q_off + pos] = norm_key(n2[slot]);
+                    flag[slot] = 0;  // rows-only slots: never uncertified (the matching back claims them)
+                }
             }
         } else {
             const int64_t u = t - total;
@@ -1822,12 +1825,15 @@ __global__ __launch_bounds__(kBlock) void band_seeds(const MatchSet* __restrict_
                                                      const DevStatus* st) {
 #pragma clang fp contract(off)
     const int lane = lane_id();
-    const int64_t total = st->total_queries;
+    // the queries only: index g = 64 (query wave) + position, rows-only sets have no waves
+    const int64_t total = static_cast<int64_t>(st->total_waves) * kBandWave;
     const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-    for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; slot < total;
-         slot += gw) {
-        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
-        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the wave
+    for (int64_t g = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; g < total; g += gw) {
+        const int64_t wq = g / kBandWave;
+        const int c = find_set(n_sets, wq, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+        const int jq = static_cast<int>(wq - plan[c].wave_off) * kBandWave + static_cast<int>(g % kBandWave);
+        if (jq >= plan[c].n) continue;  // uniform over the wave: the last wave's padding
+        const int64_t slot = plan[c].q_off + jq;
         const int p = c ^ 1;
         const int np = p < n_sets ? plan[p].n : 0;
         if (np < 2) {
@@ -2184,21 +2190,25 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
                                                        double* __restrict__ best, double* __restrict__ second,
                                                        int32_t* __restrict__ failed, int32_t* __restrict__ fb_list,
                                                        int64_t* __restrict__ fb_total, DevStatus* st) {
-    const int64_t total = st->total_queries;
+    // the queries only: index g = 64 (query wave) + position (scatter_pack clears the
+    // flags of the rows-only slots)
+    const int64_t total = static_cast<int64_t>(st->total_waves) * kBandWave;
     const bool no_tiles = st->err_capacity != 0;  // the results are void; the flags stay well defined
     const int q = lane_id() & (kQuad - 1);
     const int quad0 = lane_id() & ~(kQuad - 1);
     const int64_t gs = static_cast<int64_t>(gridDim.x) * (kBlock / kQuad);
-    for (int64_t slot = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; slot < total;
-         slot += gs) {
-        const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
-        if (no_tiles || (sets[c].flags & kSetRowsOnly)) {  // uniform over the quad: no queries
+    for (int64_t g = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kQuad; g < total; g += gs) {
+        const int64_t wq = g / kBandWave;
+        const int c = find_set(n_sets, wq, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+        const SetPlan qc = plan[c];
+        const int j = static_cast<int>(wq - qc.wave_off) * kBandWave + static_cast<int>(g % kBandWave);
+        if (j >= qc.n) continue;  // the last wave's padding (uniform over the quad)
+        const int64_t slot = qc.q_off + j;
+        if (no_tiles) {
             if (q == 0) failed[slot] = 0;
             continue;
         }
         const int p = c ^ 1;
-        const SetPlan qc = plan[c];
-        const int j = static_cast<int>(slot - qc.q_off);
         const int np = p < n_sets ? plan[p].n : 0;
         if (np == 0) {
             if (q == 0) {
@@ -2547,7 +2557,8 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
             cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
             KMG_TRY(launch_status());
             scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
-                                                                             w.n2, w.rank, w.pk, w.perm, w.skey, st);
+                                                                             w.n2, w.rank, w.pk, w.perm, w.skey, w.flag,
+                                                                             st);
             KMG_TRY(launch_status());
         }
         band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2, w.perm,
