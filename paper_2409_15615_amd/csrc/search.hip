@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kSearchWaves = 4;  // waves (queries) per block in the count and fill passes
-constexpr int kNormalLanes = 16; // lanes per point in the normal estimation
+constexpr int kNormalLanes = 4;  // lanes per point in the normal estimation
 
 struct Grid {
     const float4* pts;     // cell-sorted points; w = bit pattern of the kept index
