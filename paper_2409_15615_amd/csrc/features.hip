@@ -358,9 +358,12 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
     }
 }
 
+// One wavefront per point of the J list (j_list[0 .. n_j), from the J scan);
+// the rows of the other kept points are zeroed by a grid-stride pass first.
 __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ xyz, int64_t stride, int64_t m_cap,
                                                       const uint8_t* __restrict__ flags,
                                                       const int32_t* __restrict__ jflag,
+                                                      const int32_t* __restrict__ j_list,
                                                       const int32_t* __restrict__ off,
                                                       const int32_t* __restrict__ nbr, int H,
                                                       const double* __restrict__ spfh64,
@@ -375,12 +378,13 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     const int D = 3 * H;
     const int64_t s2 = 2 * stride;
-    for (int64_t q = global_wave(); q < m; q += wave_count()) {
+    const int64_t gt = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
+        if (!jflag[t / D]) fpfh[t] = 0.0f;
+    const int64_t n_j = clamp_count(st->n_j, m);
+    for (int64_t g = global_wave(); g < n_j; g += wave_count()) {
+        const int64_t q = j_list[g];
         float* out = fpfh + q * D;
-        if (!jflag[q]) {
-            for (int t = lane; t < D; t += kWave) out[t] = 0.0f;
-            continue;
-        }
         const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
         const int b = off[q], e = off[q + 1];
         // lanes own bins lane and lane + 64; lanes past D read bin D - 1 and are never stored
@@ -536,22 +540,25 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
                       const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
                       int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets) {
+    if (sets && !cs) return KMG_ERR_ARG;
+    {
+        // the J list first: the FPFH sums run over it
+        StageScope sc(ST_J_COMPACT, s);
+        KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
+        if (m_cap > 0 || sets) {
+            j_emit<<<std::max(grid_cap(m_cap, kBlock), 1u), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st,
+                                                                          cs, n_clouds, fpfh_out, sets);
+            KMG_TRY(launch_status());
+        }
+        if (cs && !sets) {
+            cloud_j_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(n_clouds, m_cap, w.pos, st, cs);
+            KMG_TRY(launch_status());
+        }
+    }
     if (m_cap > 0) {
         StageScope sc(ST_FPFH, s);
-        fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, off, nbr, H,
-                                                              w.spfh64, w.Pq, fpfh_out, st);
-        KMG_TRY(launch_status());
-    }
-    StageScope sc(ST_J_COMPACT, s);
-    KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
-    if (sets && !cs) return KMG_ERR_ARG;
-    if (m_cap > 0 || sets) {
-        j_emit<<<std::max(grid_cap(m_cap, kBlock), 1u), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st, cs,
-                                                                      n_clouds, fpfh_out, sets);
-        KMG_TRY(launch_status());
-    }
-    if (cs && !sets) {
-        cloud_j_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(n_clouds, m_cap, w.pos, st, cs);
+        fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, j_idx, off, nbr,
+                                                              H, w.spfh64, w.Pq, fpfh_out, st);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
