@@ -358,6 +358,108 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
     }
 }
 
+// FPFH of rows of at most 64 values over the J list, two points per
+// wavefront: a half of 32 lanes per point, lane l of the half summing bins l
+// and l + 32.  The neighbours of a round of 32 are compacted in order into
+// the half's LDS list and their SPFH rows summed in that order, term by term
+// the sum fpfh_kernel forms.  The rows of the other kept points are zeroed.
+__global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ xyz, int64_t stride, int64_t m_cap,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ jflag,
+                                                     const int32_t* __restrict__ j_list,
+                                                     const int32_t* __restrict__ off,
+                                                     const int32_t* __restrict__ nbr, int H,
+                                                     const double* __restrict__ spfh64,
+                                                     const int32_t* __restrict__ Pq, float* __restrict__ fpfh,
+                                                     const DevStatus* st) {
+#pragma clang fp contract(off)
+    constexpr int kHalf = kWave / 2;
+    __shared__ int32_t s_k[kWaves][2][kHalf];
+    __shared__ double s_w[kWaves][2][kHalf];
+    const int wv = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int hf = lane / kHalf, hl = lane % kHalf, sh = kHalf * hf;
+    const uint32_t below = (1u << hl) - 1u;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
+    const int D = 3 * H;
+    const int64_t s2 = 2 * stride;
+    const int64_t gt = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
+        if (!jflag[t / D]) fpfh[t] = 0.0f;
+    const int64_t n_j = clamp_count(st->n_j, m);
+    for (int64_t pw = global_wave(); 2 * pw < n_j; pw += wave_count()) {
+        const bool live = 2 * pw + hf < n_j;
+        const int64_t q = live ? j_list[2 * pw + hf] : 0;
+        float qx = 0.f, qy = 0.f, qz = 0.f;
+        int b = 0, e = 0;
+        if (live) {
+            qx = xyz[q];
+            qy = xyz[stride + q];
+            qz = xyz[s2 + q];
+            b = off[q];
+            e = off[q + 1];
+        }
+        const int len = e - b;
+        const int lmax = max(len, __shfl_xor(len, kHalf, kWave));
+        // lanes own bins hl and hl + 32; lanes past D read bin D - 1 and are never stored
+        const int lb0 = min(hl, D - 1), lb1 = min(hl + kHalf, D - 1);
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int base = 0; base < lmax; base += kHalf) {
+            bool use = false;
+            double w = 0.0;
+            int k = 0;
+            if (base + hl < len) {
+                k = nbr[b + base + hl];
+                const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
+                use = (k != q) && (flags[k] & 1);
+                w = 1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz));
+            }
+            const uint32_t bm = static_cast<uint32_t>(ballot(use) >> sh);
+            __builtin_amdgcn_wave_barrier();
+            if (use) {
+                const int at = __popc(bm & below);
+                s_k[wv][hf][at] = k;
+                s_w[wv][hf][at] = w;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int nuse = __popc(bm);
+            const int numax = max(nuse, __shfl_xor(nuse, kHalf, kWave));
+            for (int j = 0; j < numax; j += kBatchNarrow) {
+                double v0[kBatchNarrow], v1[kBatchNarrow];
+#pragma unroll
+                for (int u = 0; u < kBatchNarrow; ++u) {
+                    const int64_t r = j + u < nuse ? s_k[wv][hf][j + u] : q;
+                    const double* sk = spfh64 + r * D;
+                    v0[u] = sk[lb0];
+                    v1[u] = D > kHalf ? sk[lb1] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatchNarrow; ++u) {
+                    if (j + u < nuse) {
+                        const double wj = s_w[wv][hf][j + u];
+                        acc0 = acc0 + wj * v0[u];
+                        acc1 = acc1 + wj * v1[u];
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (!live) continue;
+        float* out = fpfh + q * D;
+        const int P = Pq[q];
+        const double* sq = spfh64 + q * D;
+        if (P == 0) {
+            if (hl < D) out[hl] = static_cast<float>(sq[hl]);
+            if (hl + kHalf < D) out[hl + kHalf] = static_cast<float>(sq[hl + kHalf]);
+            continue;
+        }
+        const double inv = 1.0 / static_cast<double>(P);
+        if (hl < D) out[hl] = static_cast<float>(sq[hl] + inv * acc0);
+        if (hl + kHalf < D) out[hl + kHalf] = static_cast<float>(sq[hl + kHalf] + inv * acc1);
+    }
+}
+
 // One wavefront per point of the J list (j_list[0 .. n_j), from the J scan);
 // the rows of the other kept points are zeroed by a grid-stride pass first.
 __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ xyz, int64_t stride, int64_t m_cap,
@@ -557,8 +659,13 @@ kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_
     }
     if (m_cap > 0) {
         StageScope sc(ST_FPFH, s);
-        fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, j_idx, off, nbr,
-                                                              H, w.spfh64, w.Pq, fpfh_out, st);
+        if (3 * H <= kWave) {
+            fpfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, j_idx,
+                                                                           off, nbr, H, w.spfh64, w.Pq, fpfh_out, st);
+        } else {
+            fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, j_idx, off,
+                                                                  nbr, H, w.spfh64, w.Pq, fpfh_out, st);
+        }
         KMG_TRY(launch_status());
     }
     return KMG_OK;
