@@ -48,10 +48,10 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 # are taken again.
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
-    "sha256": "a4a3f5efc4f9f30f35a9483a668b771cb46a5fb7128333ad97b7bded68baf918",
-    "fetch_kib": 27011.0,
-    "fetch_scale": 262144.0 / 131084.5,
-    "write_kib": 8027.9,
+    "sha256": "355f703bdda68b475bbcd6d826fd118c77248c146074b9630645ba741c4d1275",
+    "fetch_kib": 22515.5,
+    "fetch_scale": 262144.0 / 131084.4,
+    "write_kib": 4135.3,
     "write_scale": 262144.0 / 262144.0,
 }
 
