@@ -28,7 +28,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kBatch = 8;          // SPFH rows loaded together in the FPFH sum
-constexpr int kBatchNarrow = 16;   // the same for rows of at most 64 values
+constexpr int kBatchNarrow = 8;    // the same for rows of at most 64 values
 
 struct V3f {
     float x, y, z;
