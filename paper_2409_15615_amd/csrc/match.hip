@@ -1743,13 +1743,17 @@ __global__ __launch_bounds__(kBlock) void scatter_pack(const MatchSet* __restric
                                                        int32_t* __restrict__ perm, uint32_t* __restrict__ skey,
                                                        int32_t* __restrict__ flag, DevStatus* st) {
     const bool pr = partner != 0;
-    const int64_t total = static_cast<int64_t>(st->total_queries) * kp;
-    const int64_t pads = static_cast<int64_t>(n_sets) * kTileRows * kp;
+    // four threads per slot (each finds the slot's set, row and position, then
+    // writes a quarter of its kp = 4 KS values with all of their loads in flight);
+    // padding rows after them, one thread per (set, padding row)
+    const int ks = kp / 4;
+    const int64_t total = static_cast<int64_t>(st->total_queries) * 4;
+    const int64_t pads = static_cast<int64_t>(n_sets) * kTileRows;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total + pads; t += gs) {
         if (t < total) {
-            const int64_t slot = t / kp;
-            const int k = static_cast<int>(t % kp);
+            const int64_t slot = t / 4;
+            const int k0 = static_cast<int>(t % 4) * ks;
             const int c = find_set(n_sets, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
             if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;
             const SetPlan pc = plan[c];
@@ -1759,11 +1763,20 @@ __global__ __launch_bounds__(kBlock) void scatter_pack(const MatchSet* __restric
                 st->err_capacity = 1;
                 continue;
             }
-            double v = 0.0;
-            if (k < dim) v = set_row(sets[c], j, dim)[k];
-            else if (k == dim) v = n2[slot];
-            pk[(static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp + k) * kTileRows + pos % kTileRows] = v;
-            if (k == 0) {
+            const float* x = set_row(sets[c], j, dim);
+            double* dst = pk + static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp * kTileRows + pos % kTileRows;
+            double v[17];
+#pragma unroll
+            for (int u = 0; u < 17; ++u) {
+                const int k = k0 + u;
+                v[u] = (u < ks && k < dim) ? static_cast<double>(x[k]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 17; ++u) {
+                const int k = k0 + u;
+                if (u < ks) dst[k * kTileRows] = k == dim ? n2[slot] : v[u];
+            }
+            if (k0 == 0) {
                 perm[pc.q_off + pos] = j;
                 if (pr) {
                     skey[pc.q_off + pos] = norm_key(n2[slot]);
@@ -1772,15 +1785,14 @@ __global__ __launch_bounds__(kBlock) void scatter_pack(const MatchSet* __restric
             }
         } else {
             const int64_t u = t - total;
-            const int c = static_cast<int>(u / (kTileRows * kp));
-            const int i = static_cast<int>((u / kp) % kTileRows);
-            const int k = static_cast<int>(u % kp);
+            const int c = static_cast<int>(u / kTileRows);
+            const int i = static_cast<int>(u % kTileRows);
             if (((sets[c].flags & kSetRowsOnly) != 0) != pr) continue;
             const SetPlan pc = plan[c];
             const int pos = pc.n + i;
             if (pos >= pc.chunks * kTileRows) continue;
-            pk[(static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp + k) * kTileRows + pos % kTileRows] =
-                k == dim ? kPadScore : 0.0;
+            double* dst = pk + static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp * kTileRows + pos % kTileRows;
+            for (int k = 0; k < kp; ++k) dst[k * kTileRows] = k == dim ? kPadScore : 0.0;
         }
     }
 }
@@ -2556,7 +2568,7 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
             KMG_TRY(launch_status());
             cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
             KMG_TRY(launch_status());
-            scatter_pack<<<grid_cap(w.q_cap * w.kp, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
+            scatter_pack<<<grid_cap(w.q_cap * 4, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
                                                                              w.n2, w.rank, w.pk, w.perm, w.skey, w.flag,
                                                                              st);
             KMG_TRY(launch_status());
