@@ -249,75 +249,99 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
     }
 }
 
-// The count pass with two queries per wavefront, one per half of 32 lanes
-// (the 27 cells fit a half): the memory round trips of two queries overlap.
-// Queries 2 pw and 2 pw + 1 of the cell-sorted order go to wave pw; writes
-// |N(q)| to deg[q].
+// The count pass with kCountGroups queries per wavefront, one per group of
+// G = 64 / kCountGroups lanes: lane l of a group looks up cells l, l + G, ...
+// of the 27, the group scans the cell counts, and the group's lanes test its
+// query's candidates G at a time; the memory round trips of the wavefront's
+// queries overlap.  Queries kCountGroups pw .. of the cell-sorted order go to
+// wave pw; writes |N(q)| to deg[q].
+constexpr int kCountGroups = 2;
+
 template <int kWaves>
 __global__ __launch_bounds__(kWaves* kWave) void radius_count2(const CloudDev* __restrict__ cl, Grid g,
                                                                const int32_t* __restrict__ kept_cloud,
                                                                int64_t m_cap, int32_t* __restrict__ deg, int use_rn,
                                                                DevStatus* st) {
-    constexpr int kHalf = kWave / 2;
-    __shared__ int32_t s_incl[kWaves][2][kHalf];
-    __shared__ int32_t s_start[kWaves][2][kHalf];
+    constexpr int G = kWave / kCountGroups;
+    constexpr int kPer = (27 + G - 1) / G;  // cells per lane
+    __shared__ int32_t s_incl[kWaves][kCountGroups][32];
+    __shared__ int32_t s_start[kWaves][kCountGroups][32];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int hf = lane / kHalf, hl = lane % kHalf;
+    const int gi = lane / G, gl = lane % G, sh = G * gi;
+    const uint64_t gmask = (G == kWave) ? ~0ull : (((1ull << G) - 1ull) << sh);
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range) return;  // no search over a partial grid
-    for (int64_t pw = static_cast<int64_t>(blockIdx.x) * kWaves + wv; 2 * pw < m;
+    for (int64_t pw = static_cast<int64_t>(blockIdx.x) * kWaves + wv; kCountGroups * pw < m;
          pw += static_cast<int64_t>(gridDim.x) * kWaves) {
-        const int64_t w = 2 * pw + hf;
+        const int64_t w = kCountGroups * pw + gi;
         const float4 qp = w < m ? g.pts[w] : make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
         const int q = __float_as_int(qp.w);
         const bool act = q >= 0 && q < m;
         const int c = act ? cloud_of(kept_cloud, q) : 0;
         const double inv_c = cl[c].inv_cell;
         const RadiusTest rt = use_rn ? cl[c].rn : cl[c].rf;
-        // the 27 neighbour cells: lanes 0..26 of each half look one up each
-        int cc = 0, cs = 0;
-        if (act && hl < 27) {
-            const int64_t cx = cell_coord(qp.x, inv_c) + (hl % 3) - 1;
-            const int64_t cy = cell_coord(qp.y, inv_c) + (hl / 3) % 3 - 1;
-            const int64_t cz = cell_coord(qp.z, inv_c) + hl / 9 - 1;
-            const int h = hash_find(g.keys, g.mask, pack_key(c, cx, cy, cz));
-            if (h >= 0) {
-                cs = g.start[h];
-                cc = g.count[h];
-            }
-        }
-        int incl = cc;  // inclusive scan within the half
+        // cells gl, gl + G, ... : their counts and starts
+        int cc[kPer], cs[kPer];
+        int mine = 0;
 #pragma unroll
-        for (int d = 1; d < kHalf; d <<= 1) {
-            const int t = __shfl_up(incl, d, kHalf);
-            if (hl >= d) incl += t;
+        for (int u = 0; u < kPer; ++u) {
+            const int cell = gl + u * G;
+            cc[u] = 0;
+            cs[u] = 0;
+            if (act && cell < 27) {
+                const int64_t cx = cell_coord(qp.x, inv_c) + (cell % 3) - 1;
+                const int64_t cy = cell_coord(qp.y, inv_c) + (cell / 3) % 3 - 1;
+                const int64_t cz = cell_coord(qp.z, inv_c) + cell / 9 - 1;
+                const int h = hash_find(g.keys, g.mask, pack_key(c, cx, cy, cz));
+                if (h >= 0) {
+                    cs[u] = g.start[h];
+                    cc[u] = g.count[h];
+                }
+            }
+            mine += cc[u];
         }
-        const int total = __shfl(incl, hf * kHalf + 26, kWave);
-        const int tmax = max(total, __shfl_xor(total, kHalf, kWave));
-        __builtin_amdgcn_wave_barrier();
-        s_incl[wv][hf][hl] = (hl < 27) ? incl : INT_MAX;
-        s_start[wv][hf][hl] = cs;
+        // the group's inclusive scan of cells in order gl, gl + G, ... is taken per round u
+        int base_u = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            int incl = cc[u];
+#pragma unroll
+            for (int d = 1; d < G; d <<= 1) {
+                const int t = __shfl_up(incl, d, G);
+                if (gl >= d) incl += t;
+            }
+            const int cell = gl + u * G;
+            if (cell < 32) {
+                s_incl[wv][gi][cell] = (cell < 27) ? base_u + incl : INT_MAX;
+                s_start[wv][gi][cell] = cs[u];
+            }
+            base_u += __shfl(incl, sh + G - 1, kWave);
+        }
+        (void)mine;
+        const int total = base_u;
+        int tmax = total;
+#pragma unroll
+        for (int d = G; d < kWave; d <<= 1) tmax = max(tmax, __shfl_xor(tmax, d, kWave));
         __builtin_amdgcn_wave_barrier();
         int found = 0;
-        for (int base = 0; base < tmax; base += kHalf) {
-            const int t = base + hl;
+        for (int b0 = 0; b0 < tmax; b0 += G) {
+            const int t = b0 + gl;
             bool in = false;
             if (t < total) {
                 int lo = 0, hi = 26;  // first cell whose inclusive prefix exceeds t
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (s_incl[wv][hf][mid] > t) hi = mid;
+                    if (s_incl[wv][gi][mid] > t) hi = mid;
                     else lo = mid + 1;
                 }
-                const int before = lo ? s_incl[wv][hf][lo - 1] : 0;
-                const float4 sp = g.pts[s_start[wv][hf][lo] + (t - before)];
+                const int before = lo ? s_incl[wv][gi][lo - 1] : 0;
+                const float4 sp = g.pts[s_start[wv][gi][lo] + (t - before)];
                 in = in_radius(rt, qp.x, qp.y, qp.z, sp.x, sp.y, sp.z);
             }
-            const uint64_t b = ballot(in);
-            found += __popc(static_cast<uint32_t>(b >> (kHalf * hf)));
+            found += __popcll(ballot(in) & gmask);
         }
-        if (act && hl == 0) {
+        if (act && gl == 0) {
             deg[q] = found;
             // rare events only: no contended atomic per query
             if (found > kListSmall) atomicOr(&st->dense, found > kMaxDegree ? 3 : 1);
@@ -644,7 +668,8 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
         StageScope sc(ST_SEARCH_COUNT, s);
         if (!cleared) KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
         if (m_cap > 0) {
-            radius_count2<kSearchWaves><<<grid_cap((m_cap + 1) / 2, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
+            radius_count2<kSearchWaves><<<grid_cap((m_cap + kCountGroups - 1) / kCountGroups, kSearchWaves),
+                                         kSearchWaves * kWave, 0, s>>>(
                 cl, grid_of(w), kept_cloud, m_cap, w.deg, use_rn, st);
             KMG_TRY(launch_status());
         }
