@@ -688,6 +688,7 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
                                                         double* __restrict__ second) {
 #pragma clang fp contract(off)
     __shared__ float s_x[kXRows * kXStride];
+    __shared__ const float* s_row[kXRows];
     __shared__ float s_y[kWave * kXStride];
     __shared__ double s_b1[kBlock], s_b2[kBlock];
     __shared__ int s_j1[kBlock];
@@ -775,9 +776,24 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
             for (int r0 = r_begin; r0 < r_end; r0 += kXRows) {
                 const int nr = min(kXRows, r_end - r0);
                 __syncthreads();
-                if (static_cast<int>(threadIdx.x) < nr) {
-                    const float* x = set_row(sets[p], r0 + static_cast<int>(threadIdx.x), dim);
-                    for (int t = 0; t < dim; ++t) s_x[threadIdx.x * kXStride + t] = x[t];
+                // the tile's rows: their addresses first, then all values by all threads,
+                // eight loads in flight per thread
+                if (static_cast<int>(threadIdx.x) < nr)
+                    s_row[threadIdx.x] = set_row(sets[p], r0 + static_cast<int>(threadIdx.x), dim);
+                __syncthreads();
+                const int n_el = nr * dim;
+                for (int e0 = static_cast<int>(threadIdx.x); e0 < n_el; e0 += 8 * kBlock) {
+                    float v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * kBlock;
+                        v[u] = e < n_el ? s_row[e / dim][e % dim] : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * kBlock;
+                        if (e < n_el) s_x[(e / dim) * kXStride + e % dim] = v[u];
+                    }
                 }
                 __syncthreads();
                 if (c_e == c_cur) {
