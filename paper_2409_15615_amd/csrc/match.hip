@@ -655,9 +655,7 @@ __device__ __forceinline__ void combine_best(double& b1, int& j1, double& b2, do
     b2 = nb2;
 }
 
-constexpr int kXRows = 128;              // partner rows per LDS tile of the exact scan
-constexpr int kXStride = kLpMaxDim + 1;  // odd row stride in LDS (no bank conflicts)
-constexpr int kXSegMax = 32;             // row segments per group of the exact scan
+constexpr int kXSegMax = 32;  // row segments per group of the exact scan
 
 // Row segments of the exact scan: as many as the partial buffer holds for F
 // listed queries, at most kXSegMax.
@@ -670,14 +668,16 @@ __device__ __forceinline__ int exact_segs(int64_t F, int64_t part_cap) {
 // any order (slot order keeps a group within few sets), or (per_set) the
 // lists of the sets, plan[c].n_fb entries from fl[plan[c].q_off] on, in
 // groups that never span two sets.  A work item is (group of up to 64 entries, row
-// segment): lane L of every wave holds entry L,
-// the partner rows of the segment stream through LDS one row per thread, and
-// each wave scores every fourth row, ascending, with the plain FP64 sum in
-// dimension order.  The four waves merge their (best, index, second) and write
+// segment): lane L of every wave holds entry L in registers as FP64, padded with
+// zeros to 4 KS values, the partner rows of the segment stream through LDS as
+// FP64 with the same zero padding (a padded term adds an exact zero), and each
+// wave scores every fourth row, ascending, two rows at a time, with the plain
+// FP64 sum in dimension order.  The four waves merge their (best, index, second) and write
 // them as the segment's partial result; a group that spans several sets visits
 // their partners one after another.  The block that finishes a group's last
 // segment (counted in grp_done, which the planner zeroed) merges the group's
 // partials in segment order into nn, best and second, and resets the count.
+template <int KS>
 __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restrict__ sets,
                                                         const SetPlan* __restrict__ plan, int n_sets, int dim,
                                                         const int32_t* __restrict__ fl,
@@ -687,9 +687,10 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
                                                         int32_t* __restrict__ nn, double* __restrict__ best,
                                                         double* __restrict__ second) {
 #pragma clang fp contract(off)
-    __shared__ float s_x[kXRows * kXStride];
+    constexpr int kD = 4 * KS;                   // padded row length
+    constexpr int kXRows = KS <= 9 ? 128 : 64;   // partner rows per LDS tile
+    __shared__ __attribute__((aligned(16))) double s_x[kXRows * kD];
     __shared__ const float* s_row[kXRows];
-    __shared__ float s_y[kWave * kXStride];
     __shared__ double s_b1[kBlock], s_b2[kBlock];
     __shared__ int s_j1[kBlock];
     __shared__ int s_next;
@@ -700,6 +701,8 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
     const int wv = threadIdx.x / kWave;
     const int64_t F = *f_total;
     if (F == 0) return;  // uniform: nothing listed
+    for (int i = threadIdx.x; i < kXRows * (kD - dim); i += kBlock)  // the padding, zero for good
+        s_x[(i / (kD - dim)) * kD + dim + i % (kD - dim)] = 0.0;
     if (per_set) {
         if (wv == 0) {  // lane L sums sets [kPer L, kPer (L + 1)), then the wave scans the sums
             constexpr int kPer = (kPlanThreads + kWave) / kWave;
@@ -756,9 +759,11 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
         }
         const int c_e = have ? find_set(n_sets, slot, [&](int q) { return static_cast<int64_t>(plan[q].q_off); })
                              : INT_MAX;
-        if (wv == 0 && have) {
-            const float* y = set_row(sets[c_e], static_cast<int>(slot - plan[c_e].q_off), dim);
-            for (int t = 0; t < dim; ++t) s_y[L * kXStride + t] = y[t];
+        double y[kD];
+        {
+            const float* yr = have ? set_row(sets[c_e], static_cast<int>(slot - plan[c_e].q_off), dim) : nullptr;
+#pragma unroll
+            for (int t = 0; t < kD; ++t) y[t] = (have && t < dim) ? static_cast<double>(yr[t]) : 0.0;
         }
         // the group's sets in increasing order, from the smallest (the list may come in any order)
         if (threadIdx.x == 0) s_next = INT_MAX;
@@ -792,25 +797,37 @@ __global__ __launch_bounds__(kBlock) void exact_grouped(const MatchSet* __restri
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const int e = e0 + u * kBlock;
-                        if (e < n_el) s_x[(e / dim) * kXStride + e % dim] = v[u];
+                        if (e < n_el) s_x[(e / dim) * kD + e % dim] = static_cast<double>(v[u]);
                     }
                 }
                 __syncthreads();
                 if (c_e == c_cur) {
-                    for (int r = wv; r < nr; r += kWaves) {
-                        double acc = 0.0;
-                        for (int t = 0; t < dim; ++t) {
-                            const double df = static_cast<double>(s_x[r * kXStride + t]) -
-                                              static_cast<double>(s_y[L * kXStride + t]);
-                            acc = acc + df * df;
-                        }
+                    auto take = [&](double acc, int j) {
                         if (acc < b1) {
                             b2 = b1;
                             b1 = acc;
-                            j1 = r0 + r;
+                            j1 = j;
                         } else if (acc < b2) {
                             b2 = acc;
                         }
+                    };
+                    for (int r = wv; r < nr; r += 2 * kWaves) {
+                        const bool two = r + kWaves < nr;  // wave-uniform
+                        const double2* xa = reinterpret_cast<const double2*>(s_x + r * kD);
+                        const double2* xb = reinterpret_cast<const double2*>(s_x + (two ? r + kWaves : r) * kD);
+                        double a = 0.0, b = 0.0;
+#pragma unroll
+                        for (int t = 0; t < kD / 2; ++t) {
+                            const double2 va = xa[t], vb = xb[t];
+                            const double da0 = va.x - y[2 * t], db0 = vb.x - y[2 * t];
+                            a = a + da0 * da0;
+                            b = b + db0 * db0;
+                            const double da1 = va.y - y[2 * t + 1], db1 = vb.y - y[2 * t + 1];
+                            a = a + da1 * da1;
+                            b = b + db1 * db1;
+                        }
+                        take(a, r0 + r);
+                        if (two) take(b, r0 + r + kWaves);
                     }
                 }
             }
@@ -2630,9 +2647,15 @@ kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* 
 // Exact scans of the queries already listed in w.fb_list: *w.fb_total of them,
 // in slot order, or (per_set) plan[c].n_fb of set c from slot plan[c].q_off on.
 kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s, bool per_set) {
-    exact_grouped<<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total,
-                                                   per_set ? 1 : 0, w.part_cap, w.part, w.grp_done, w.nn, w.best,
-                                                   w.second);
+    if (dim < 1 || dim > 4 * 17) return KMG_ERR_ARG;
+    if (dim <= 4 * 9)
+        exact_grouped<9><<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total,
+                                                          per_set ? 1 : 0, w.part_cap, w.part, w.grp_done, w.nn,
+                                                          w.best, w.second);
+    else
+        exact_grouped<17><<<kPersistBlocks, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.fb_list, w.fb_total,
+                                                           per_set ? 1 : 0, w.part_cap, w.part, w.grp_done, w.nn,
+                                                           w.best, w.second);
     return launch_status();
 }
 
