@@ -1210,7 +1210,10 @@ __device__ __forceinline__ void tile_block_lp(const uint4* __restrict__ pk, cons
                     const double lb = fma(-ky[t], nr[r], fma(dot, m2is2, ar[r]));
                     w[r] = encode(lb, keep, row0 + r);
                 }
-                absorb4(top[t], w[0], w[1], w[2], w[3]);
+                // the wave skips the merge when no lane's four bounds undercut its fourth best
+                // (the scores are unique, so such a merge leaves top as it is)
+                const double wmin = fmin(fmin(w[0], w[1]), fmin(w[2], w[3]));
+                if (ballot(wmin < top[t][3])) absorb4(top[t], w[0], w[1], w[2], w[3]);
             }
             __builtin_amdgcn_sched_barrier(0);
             lds_pk[(buf ^ 1) * kLpPieces + threadIdx.x] = piece;
