@@ -2206,7 +2206,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
                 chunk_mfma<KS>(acc, a, bq);
                 const unsigned row0 = static_cast<unsigned>(c * kTileRows + g);
 #pragma unroll
-                for (int t = 0; t < kTilesPerWave; ++t) absorb(top[t], acc[t], row0, keep);
+                for (int t = 0; t < kTilesPerWave; ++t) {
+                    // the merge is skipped when no lane's four scores undercut its fourth best
+                    // (the encoded scores are unique, so such a merge leaves top as it is)
+                    double w0 = encode(acc[t][0], keep, row0), w1 = encode(acc[t][1], keep, row0 + 4u);
+                    double w2 = encode(acc[t][2], keep, row0 + 8u), w3 = encode(acc[t][3], keep, row0 + 12u);
+                    if (ballot(fmin(fmin(w0, w1), fmin(w2, w3)) < top[t][3])) {
+                        sort4(w0, w1, w2, w3);
+                        merge4(top[t], w0, w1, w2, w3);
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int s = 0; s < KS; ++s) a[s] = an[s];
