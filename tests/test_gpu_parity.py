@@ -258,6 +258,19 @@ def test_match_other_lengths(K, orc, dim):
     check_match(K, orc, X, Y)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("dim", [40, 64])
+def test_match_ties_long_rows(K, orc, dim, prec):
+    # 0/1 rows: distances are small integers, so best and second best tie for
+    # many queries and their certificates fail; those go to the exact scan of
+    # rows longer than 36 values (and a padded length above the row's)
+    rng = np.random.default_rng(100 + dim)
+    X = rng.integers(0, 2, (700, dim)).astype(np.float32)
+    Y = rng.integers(0, 2, (650, dim)).astype(np.float32)
+    out, _ = check_match(K, orc, X, Y, prec)
+    assert int(out.n_fallback) > 0
+
+
 def test_match_rows_and_capacity(K, orc):
     X, Y, _ = synth.synthetic_descriptors(900, 800, item=5)
     rows_p = np.arange(0, 900, 2, dtype=np.int32)
