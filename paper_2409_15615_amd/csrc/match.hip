@@ -522,6 +522,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
 
 // The plain FP64 sum in dimension order; the loads of eight dimensions issue
 // together (the sum keeps its order).
+// Adds one to plan[c].n_fb for every active lane (c its set), with one atomic
+// per distinct set among them: tens of thousands of open queries of one set
+// would otherwise queue on a single address.
+__device__ __forceinline__ void count_open(SetPlan* plan, int c) {
+    uint64_t pending = ballot(true);
+    while (pending) {  // uniform over the active lanes
+        const int lead = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+        const int cl = __shfl(c, lead, kWave);
+        const uint64_t same = ballot(c == cl);
+        if (lane_id() == lead) atomicAdd(&plan[cl].n_fb, static_cast<int32_t>(__popcll(same)));
+        pending &= ~same;
+    }
+}
+
 __device__ __forceinline__ double exact_d2(const float* __restrict__ x, const float* __restrict__ y, int dim) {
 #pragma clang fp contract(off)
     double acc = 0.0;
@@ -637,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void rescore(const MatchSet* __restrict__ s
             best[slot] = b1;
             second[slot] = b2;
         } else {
-            atomicAdd(&plan[c].n_fb, 1);
+            count_open(plan, c);
         }
         failed[slot] = ok ? 0 : 1;
     }
@@ -1356,7 +1370,7 @@ __global__ __launch_bounds__(kBlock) void rescore_lp(const MatchSet* __restrict_
             best[slot] = b1;
             second[slot] = b2;
         } else {
-            atomicAdd(&plan[c].n_fb, 1);
+            count_open(plan, c);
         }
         failed[slot] = ok ? 0 : 1;
     }
