@@ -536,6 +536,28 @@ __device__ __forceinline__ void count_open(SetPlan* plan, int c) {
     }
 }
 
+// As count_open, and each active lane's slot lands at fl[q_off + its place]
+// in its set's range; the list total grows by the number of active lanes.
+__device__ __forceinline__ void append_open(SetPlan* plan, int c, int64_t q_off, int32_t slot, int32_t* fl,
+                                            int64_t* f_total) {
+    const uint64_t act = ballot(true);
+    uint64_t pending = act;
+    int k = 0;
+    while (pending) {  // uniform over the active lanes
+        const int lead = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+        const int cl = __shfl(c, lead, kWave);
+        const uint64_t same = ballot(c == cl);
+        int at = 0;
+        if (lane_id() == lead) at = atomicAdd(&plan[cl].n_fb, static_cast<int32_t>(__popcll(same)));
+        at = __shfl(at, lead, kWave);
+        if (c == cl) k = at + lanes_below(same);
+        pending &= ~same;
+    }
+    fl[q_off + k] = slot;
+    if (lane_id() == __ffsll(static_cast<unsigned long long>(act)) - 1)
+        atomicAdd(reinterpret_cast<unsigned long long*>(f_total), static_cast<unsigned long long>(__popcll(act)));
+}
+
 __device__ __forceinline__ double exact_d2(const float* __restrict__ x, const float* __restrict__ y, int dim) {
 #pragma clang fp contract(off)
     double acc = 0.0;
@@ -2365,8 +2387,7 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
             second[slot] = b2;
         } else {
             // listed for the exact scan in the set's own range (in any order: each query's scan stands alone)
-            fb_list[qc.q_off + atomicAdd(&plan[c].n_fb, 1)] = static_cast<int32_t>(slot);
-            atomicAdd(reinterpret_cast<unsigned long long*>(fb_total), 1ull);
+            append_open(plan, c, qc.q_off, static_cast<int32_t>(slot), fb_list, fb_total);
         }
         failed[slot] = ok ? 0 : 1;
     }
