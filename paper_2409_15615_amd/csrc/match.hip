@@ -1596,6 +1596,7 @@ __global__ __launch_bounds__(kBlock) void image_lists(const MatchSet* __restrict
 constexpr int kBandWave = kColsPerWave;  // queries per band wave (one wavefront)
 constexpr int kSortTile = 1024;          // elements per LDS-sorted tile of the ordering
 constexpr int kSortThreads = 256;
+constexpr int kRankGroupDiv = 16;      // a set of m tiles ranks against max(1, m / 16) B tiles per item
 constexpr int kBandTiles = 8192;         // band tiles the partial buffer holds beyond one per wave
 constexpr int kSeedRows = kWave;         // partner rows around the query's norm for R
 constexpr int kBandSlots = kTopkBlocks * kWavesPerBlock;  // wavefronts of the band tile kernel
@@ -1721,9 +1722,10 @@ __device__ __forceinline__ uint32_t band_key(bool partner, double n2, double r2)
 // (key, local index), a unique 64-bit value: rank[slot] = the element's packed
 // position.  tile_sort sorts every tile of kSortTile consecutive elements of a
 // set (bitonic, one element per thread) and stores the tile's sorted values and each element's
-// place in its tile as its first rank term; cross_rank takes a pair of tiles
-// (A, B) of one set and adds to every element of A the count of B's values
-// below its own (a binary search in B's sorted values, staged in LDS).
+// place in its tile as its first rank term; cross_rank takes a tile A of one
+// set and a group of its other tiles B and adds to every element of A the
+// count of B's values below its own (binary searches in each B's sorted
+// values, staged in LDS).
 
 __device__ __forceinline__ unsigned long long rank_value(bool partner, double n2, double r2, int idx) {
     return (static_cast<unsigned long long>(band_key(partner, n2, r2)) << 32) | static_cast<uint32_t>(idx);
@@ -1785,21 +1787,41 @@ __global__ __launch_bounds__(kSortThreads) void cross_rank(const MatchSet* __res
         const int m = (pc.n + kSortTile - 1) / kSortTile;
         const int local = static_cast<int>(item - pc.rank_off);
         const int ta = local / m, tb = local % m;
-        if (ta == tb) continue;  // the tile's own order is the first rank term
-        const int b0 = tb * kSortTile, nb = min(kSortTile, pc.n - b0);
+        // a set of many tiles takes G of them as B per item, one atomic per element and item
+        // (the items of the other B tiles of the group return at once)
+        const int G = max(1, m / kRankGroupDiv);
+        if (tb % G != 0) continue;  // uniform over the block
         const int a0 = ta * kSortTile, na = min(kSortTile, pc.n - a0);
-        __syncthreads();
-        for (int r = threadIdx.x; r < nb; r += kSortThreads) s_b[r] = sorted[pc.q_off + b0 + r];
-        __syncthreads();
-        for (int r = threadIdx.x; r < na; r += kSortThreads) {
-            const unsigned long long v = sorted[pc.q_off + a0 + r];
-            int lo = 0, hi = nb;  // first of B's values not below v
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_b[mid] < v) lo = mid + 1;
-                else hi = mid;
+        constexpr int kPer = kSortTile / kSortThreads;
+        unsigned long long v[kPer];
+        int cnt[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int r = static_cast<int>(threadIdx.x) + kSortThreads * i;
+            v[i] = r < na ? sorted[pc.q_off + a0 + r] : 0ull;
+            cnt[i] = 0;
+        }
+        for (int b = tb; b < min(tb + G, m); ++b) {
+            if (b == ta) continue;  // the tile's own order is the first rank term
+            const int b0 = b * kSortTile, nb = min(kSortTile, pc.n - b0);
+            __syncthreads();
+            for (int r = threadIdx.x; r < nb; r += kSortThreads) s_b[r] = sorted[pc.q_off + b0 + r];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                int lo = 0, hi = nb;  // first of B's values not below v
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_b[mid] < v[i]) lo = mid + 1;
+                    else hi = mid;
+                }
+                cnt[i] += lo;
             }
-            if (lo) atomicAdd(&rank[pc.q_off + static_cast<int>(v & 0xffffffffull)], lo);
+        }
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int r = static_cast<int>(threadIdx.x) + kSortThreads * i;
+            if (r < na && cnt[i]) atomicAdd(&rank[pc.q_off + static_cast<int>(v[i] & 0xffffffffull)], cnt[i]);
         }
     }
 }
