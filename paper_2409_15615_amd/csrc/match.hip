@@ -1596,7 +1596,7 @@ __global__ __launch_bounds__(kBlock) void image_lists(const MatchSet* __restrict
 constexpr int kBandWave = kColsPerWave;  // queries per band wave (one wavefront)
 constexpr int kSortTile = 1024;          // elements per LDS-sorted tile of the ordering
 constexpr int kSortThreads = 256;
-constexpr int kRankGroupDiv = 16;      // a set of m tiles ranks against max(1, m / 16) B tiles per item
+constexpr int kRankGroupDiv = 8;       // a set of m tiles ranks against max(1, m / 8) B tiles per item
 constexpr int kBandTiles = 8192;         // band tiles the partial buffer holds beyond one per wave
 constexpr int kSeedRows = kWave;         // partner rows around the query's norm for R
 constexpr int kBandSlots = kTopkBlocks * kWavesPerBlock;  // wavefronts of the band tile kernel
