@@ -48,8 +48,8 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 # are taken again.
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
-    "sha256": "f1d4375ea068455568028b71325001ac08da039479c22d0a1571f16f8ae26009",
-    "fetch_kib": 22414.8,
+    "sha256": "cee1b72206d9334c26db174f7bd98cdc69427a0143092d6011cb7ed1c7b28ae5",
+    "fetch_kib": 22526.4,
     "fetch_scale": 262144.0 / 131084.4,
     "write_kib": 4135.2,
     "write_scale": 262144.0 / 262144.0,
