@@ -8,7 +8,9 @@
  * shares no code, header, table or constant with the GPU path.
  *
  * Every step follows the paper's definitions written out directly, in FP64,
- * with no blocking or reordering: brute-force O(m^2) radius search, a cyclic
+ * with no blocking or reordering: brute-force O(m^2) radius search (and, for
+ * clouds too large for it, the same test over the candidates of a uniform
+ * grid, checked against the brute force by the tests), a cyclic
  * Jacobi eigen-solver, direct evaluation of the angular features, histogram
  * bins, SPFH and FPFH, and brute-force O(|P||Q|) descriptor distances.
  * Build with -O2 -ffp-contract=off (no FMA contraction, no fast-math).
@@ -153,6 +155,96 @@ void orc_radius_fill(const float* xyz, int64_t m, double r, const int64_t* off, 
         for (int64_t s = 0; s < m; ++s)
             if (orc_d2(xyz, m, q, s) < r2) idx[w++] = (int32_t)s;
     }
+}
+
+/* The same two passes over candidates taken from a uniform grid of cell size
+ * c = r (1 + 1e-7): a point within r of q lies in one of the 27 cells around
+ * q's cell (|dx| < r < c, so floor(x_s / c) and floor(x_q / c) differ by at
+ * most 1 even after the rounding of the divisions), and every candidate is
+ * decided by the same strict FP64 test as the brute force.  For clouds whose
+ * O(m^2) brute force is too slow; tests check it against the brute force. */
+typedef struct {
+    int64_t key[3];
+    int32_t idx;
+} orc_cell;
+
+static int orc_cell_cmp(const void* a, const void* b) {
+    const orc_cell* x = (const orc_cell*)a;
+    const orc_cell* y = (const orc_cell*)b;
+    for (int c = 0; c < 3; ++c) {
+        if (x->key[c] < y->key[c]) return -1;
+        if (x->key[c] > y->key[c]) return 1;
+    }
+    return (x->idx < y->idx) ? -1 : (x->idx > y->idx);
+}
+
+/* First entry of cells[0..n) whose key is >= k (lexicographic). */
+static int64_t orc_cell_lower(const orc_cell* cells, int64_t n, const int64_t k[3]) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        int less = 0;
+        for (int c = 0; c < 3; ++c) {
+            if (cells[mid].key[c] < k[c]) { less = 1; break; }
+            if (cells[mid].key[c] > k[c]) break;
+        }
+        if (less) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+static orc_cell* orc_grid_build(const float* xyz, int64_t m, double c) {
+    orc_cell* cells = (orc_cell*)malloc(sizeof(orc_cell) * (size_t)(m > 0 ? m : 1));
+    for (int64_t i = 0; i < m; ++i) {
+        for (int a = 0; a < 3; ++a) cells[i].key[a] = (int64_t)floor((double)xyz[a * m + i] / c);
+        cells[i].idx = (int32_t)i;
+    }
+    qsort(cells, (size_t)m, sizeof(orc_cell), orc_cell_cmp);
+    return cells;
+}
+
+/* Visits the candidates of q (the 27 cells around its cell) and keeps those with
+ * d2 < r^2: counts them, or, when out != NULL, writes them and sorts them. */
+static int32_t orc_grid_query(const float* xyz, int64_t m, const orc_cell* cells, double c, double r2, int64_t q,
+                              int32_t* out) {
+    int64_t kq[3];
+    for (int a = 0; a < 3; ++a) kq[a] = (int64_t)floor((double)xyz[a * m + q] / c);
+    int32_t cnt = 0;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                int64_t k[3] = {kq[0] + dx, kq[1] + dy, kq[2] + dz};
+                for (int64_t e = orc_cell_lower(cells, m, k); e < m; ++e) {
+                    if (cells[e].key[0] != k[0] || cells[e].key[1] != k[1] || cells[e].key[2] != k[2]) break;
+                    if (orc_d2(xyz, m, q, cells[e].idx) < r2) {
+                        if (out) out[cnt] = cells[e].idx;
+                        ++cnt;
+                    }
+                }
+            }
+    if (out) qsort(out, (size_t)cnt, sizeof(int32_t), orc_i32_cmp);
+    return cnt;
+}
+
+int64_t orc_radius_count_grid(const float* xyz, int64_t m, double r, int32_t* cnt) {
+    const double c = r * (1.0 + 1e-7);
+    orc_cell* cells = orc_grid_build(xyz, m, c);
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : total)
+    for (int64_t q = 0; q < m; ++q) {
+        cnt[q] = orc_grid_query(xyz, m, cells, c, r * r, q, NULL);
+        total += cnt[q];
+    }
+    free(cells);
+    return total;
+}
+
+void orc_radius_fill_grid(const float* xyz, int64_t m, double r, const int64_t* off, int32_t* idx) {
+    const double c = r * (1.0 + 1e-7);
+    orc_cell* cells = orc_grid_build(xyz, m, c);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t q = 0; q < m; ++q) orc_grid_query(xyz, m, cells, c, r * r, q, idx + off[q]);
+    free(cells);
 }
 
 /* ------------------------------------------------------------------------ */

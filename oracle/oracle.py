@@ -58,6 +58,10 @@ def load():
     lib.orc_radius_count.restype = C.c_int64
     lib.orc_radius_fill.argtypes = [_f32p, C.c_int64, C.c_double, _i64p, _i32p]
     lib.orc_radius_fill.restype = None
+    lib.orc_radius_count_grid.argtypes = [_f32p, C.c_int64, C.c_double, _i32p]
+    lib.orc_radius_count_grid.restype = C.c_int64
+    lib.orc_radius_fill_grid.argtypes = [_f32p, C.c_int64, C.c_double, _i64p, _i32p]
+    lib.orc_radius_fill_grid.restype = None
     lib.orc_normals.argtypes = [_f32p, C.c_int64, _i64p, _i32p, C.c_double, C.c_int32, C.c_double, _f64p,
                                 _f64p, _f64p, _f64p, _i32p, _u8p]
     lib.orc_normals.restype = None
@@ -102,17 +106,21 @@ def voxelize(xyz, v: float):
     return kept[:m].copy(), flat
 
 
-def radius_search(xyz, r: float):
-    """Eq. A1 for every point: CSR (off int64[m+1], idx int32[nnz]), lists ascending."""
+def radius_search(xyz, r: float, grid: bool = False):
+    """Eq. A1 for every point: CSR (off int64[m+1], idx int32[nnz]), lists ascending.
+    grid=True takes the candidates from a uniform grid of cell size r instead of
+    all points (same sets; for clouds too large for the O(m^2) brute force)."""
     xyz = _soa(xyz)
     m = xyz.shape[1]
     lib = load()
+    count, fill = (lib.orc_radius_count_grid, lib.orc_radius_fill_grid) if grid else \
+        (lib.orc_radius_count, lib.orc_radius_fill)
     cnt = np.empty(max(m, 1), np.int32)
-    total = lib.orc_radius_count(xyz, m, float(r), cnt)
+    total = count(xyz, m, float(r), cnt)
     off = np.zeros(m + 1, np.int64)
     off[1:] = np.cumsum(cnt[:m])
     idx = np.empty(max(int(total), 1), np.int32)
-    lib.orc_radius_fill(xyz, m, float(r), off, idx)
+    fill(xyz, m, float(r), off, idx)
     return off, idx[: int(total)].copy()
 
 
@@ -216,7 +224,7 @@ def mutual_match(X, Y):
                 best_xy=b_xy, second_xy=s_xy)
 
 
-def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True, classical: bool = False):
+def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True, classical: bool = False, grid: bool = False):
     """Algorithm 1 and Eq. A1-A5 on one voxelized cloud.
 
     With boundary_fp32 the chain rounds the normals to float32 before the
@@ -231,7 +239,7 @@ def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True, classical: bool
     radius search at r_normal returns."""
     H = int(params.n_bins)
     tau_normal, tau_lin, tau_j = (3, 1.0, 1) if classical else (params.tau_num, params.tau_lin, params.tau_num)
-    off, idx = radius_search(xyz_kept, params.r_fpfh)
+    off, idx = radius_search(xyz_kept, params.r_fpfh, grid=grid)
     nr = normals(xyz_kept, off, idx, params.r_normal, tau_normal, tau_lin, vp)
     n64 = nr["normals"].astype(np.float32).astype(np.float64) if boundary_fp32 else nr["normals"]
     sp = spfh(xyz_kept, n64, off, idx, nr["B"], tau_j, H)
@@ -242,7 +250,8 @@ def faster_pfh(xyz_kept, params, vp, boundary_fp32: bool = True, classical: bool
                 edges=sp["edges"], fpfh=fp, j_idx=j_idx)
 
 
-def run_pair(src_raw, tgt_raw, params, vp_src, vp_tgt, match: bool = True, classical: bool = False):
+def run_pair(src_raw, tgt_raw, params, vp_src, vp_tgt, match: bool = True, classical: bool = False,
+             grid: bool = False):
     """Whole hot path for one pair: voxelize both clouds, Faster-PFH on both, then
     mutual matching of the float32 descriptors of the J points.  Correspondences
     are returned as kept-cloud indices (i in the source, j in the target)."""
@@ -250,7 +259,7 @@ def run_pair(src_raw, tgt_raw, params, vp_src, vp_tgt, match: bool = True, class
     for tag, raw, vp in (("src", src_raw, vp_src), ("tgt", tgt_raw, vp_tgt)):
         kept, keys = voxelize(raw, params.voxel)
         xyz = np.ascontiguousarray(_soa(raw)[:, kept])
-        fp = faster_pfh(xyz, params, vp, classical=classical)
+        fp = faster_pfh(xyz, params, vp, classical=classical, grid=grid)
         fp.update(kept=kept, keys=keys, xyz=xyz)
         out[tag] = fp
     if match:

@@ -23,6 +23,7 @@ from .scenes import (  # noqa: F401
     indoor_pair,
     lidar_pair,
     c2_batch,
+    c2_sizes,
     lattice_pair,
     synthetic_descriptors,
     c4_trace,

@@ -327,13 +327,20 @@ def indoor_pair(config: int, item: int, m_target: int, v: float = 0.025, n_raw: 
     )
 
 
-def c2_batch(n_pairs: int = 64, config: int = 2) -> list:
-    """Uneven batch: kept sizes log-uniform in [2k, 60k]; first half indoor, second half LiDAR-like."""
+def c2_sizes(n_pairs: int = 64, config: int = 2) -> np.ndarray:
+    """Kept-size targets of the uneven batch, log-uniform in [2k, 60k]."""
     rng = rng_for(config, 0)
-    sizes = np.round(np.exp(rng.uniform(math.log(2000), math.log(60000), n_pairs))).astype(int)
+    return np.round(np.exp(rng.uniform(math.log(2000), math.log(60000), n_pairs))).astype(int)
+
+
+def c2_batch(n_pairs: int = 64, config: int = 2, items=None) -> list:
+    """Uneven batch: kept sizes log-uniform in [2k, 60k]; first half indoor, second half LiDAR-like.
+    items: the pair indices to generate (default all); each pair has its own seed, so a
+    selection gives the same pairs as the whole batch."""
+    sizes = c2_sizes(n_pairs, config)
     pairs = []
     half = n_pairs // 2
-    for i in range(n_pairs):
+    for i in (range(n_pairs) if items is None else items):
         m = int(sizes[i])
         if i < half:
             pairs.append(indoor_pair(config, 1 + i, m))

@@ -165,3 +165,108 @@ def test_exact_fallbacks_from_several_pairs(K, orc):
         np.testing.assert_array_equal(r.d1.cpu().numpy(), ref["d1"].astype(np.float32))
         np.testing.assert_array_equal(r.d2.cpu().numpy(), ref["d2"].astype(np.float32))
         print(f"{d['name']}: {len(ref['pairs'])} correspondences, {int(r.n_fallback)} exact scans")
+
+
+# ----------------------------------------------------- kmg_register_batch --
+
+def register_batch_direct(K, clouds, prec, nnz_per_point=64):
+    """kmg_register_batch itself (upload + run in one call) through the C ABI; a batch
+    whose neighbour lists overflow the reserve (status KMG_ERR_WORKSPACE, with the
+    needed count in the counts table) is run once more with that reserve."""
+    import ctypes as C
+
+    lib = K.load()
+    n_pairs = len(clouds) // 2
+    raw = sum(int(x.shape[1]) for x, _ in clouds)
+    nnz_cap = max(1024, nnz_per_point * raw)
+    out_cap = max(1, raw // 2)
+    pairs = torch.empty((n_pairs, out_cap, 2), dtype=torch.int32, device="cuda")
+    d1 = torch.empty((n_pairs, out_cap), dtype=torch.float32, device="cuda")
+    d2 = torch.empty((n_pairs, out_cap), dtype=torch.float32, device="cuda")
+    counts = torch.zeros((n_pairs, K.COUNTS_STRIDE), dtype=torch.int64, device="cuda")
+    ct = (K.KmgCloud * len(clouds))()
+    for k, (xyz, prm) in enumerate(clouds):
+        ct[k].xyz, ct[k].n, ct[k].params = xyz.data_ptr(), xyz.shape[1], prm
+    ot = (K.KmgMatchOut * n_pairs)()
+    for i in range(n_pairs):
+        ot[i].pairs, ot[i].d1, ot[i].d2, ot[i].cap = pairs[i].data_ptr(), d1[i].data_ptr(), d2[i].data_ptr(), out_cap
+    for attempt in range(2):
+        ws = torch.empty(int(lib.kmg_batch_workspace_bytes(n_pairs, raw, nnz_cap, 11)), dtype=torch.uint8,
+                         device="cuda")
+        st = lib.kmg_register_batch(ct, ot, n_pairs, raw, nnz_cap, K.PRECISIONS[prec],
+                                    C.c_void_p(counts.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                    C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == K.KMG_OK, st
+        cnt = counts.cpu().numpy()
+        if attempt == 0 and np.any(cnt[:, 6] == K.KMG_ERR_WORKSPACE):
+            nnz_cap = int(cnt[0, 7]) + 1024
+            continue
+        break
+    out = []
+    for i in range(n_pairs):
+        assert cnt[i, 6] == K.KMG_OK, (i, cnt[i])
+        k = int(cnt[i, 0])
+        out.append((pairs[i, :k].cpu().numpy(), d1[i, :k].cpu().numpy(), d2[i, :k].cpu().numpy(),
+                    (int(cnt[i, 1]), int(cnt[i, 2])), (int(cnt[i, 3]), int(cnt[i, 4]))))
+    return out
+
+
+def subset_pairs(n_pairs, seed=5):
+    """Seeded random subsets (500-2,000 raw points per cloud) of the planes+spheres pair."""
+    d = synth.c0_pair(0)
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_pairs):
+        e = dict(d)
+        for key in ("src", "tgt"):
+            n = int(rng.integers(500, 2001))
+            e[key] = np.ascontiguousarray(d[key][:, np.sort(rng.choice(d[key].shape[1], n, replace=False))])
+        out.append(e)
+    return out
+
+
+def check_against_oracle(orc, pairs, got, grid=False):
+    for i, (d, g) in enumerate(zip(pairs, got)):
+        ref = orc.run_pair(d["src"], d["tgt"], d["params"], d["vp_src"], d["vp_tgt"], grid=grid)
+        assert g[3] == (len(ref["src"]["kept"]), len(ref["tgt"]["kept"])), i
+        assert g[4] == (len(ref["src"]["j_idx"]), len(ref["tgt"]["j_idx"])), i
+        np.testing.assert_array_equal(g[0], ref["pairs"], err_msg=f"pair {i}")
+        np.testing.assert_array_equal(g[1], ref["d1"].astype(np.float32), err_msg=f"pair {i}")
+        np.testing.assert_array_equal(g[2], ref["d2"].astype(np.float32), err_msg=f"pair {i}")
+
+
+def test_register_batch_entry_point(K, orc):
+    """kmg_register_batch (one call) gives the upload + run results and the oracle's."""
+    pairs = small_pairs()[:3]
+    clouds = [c for d in pairs for c in clouds_of(K, d)]
+    got = register_batch_direct(K, clouds, "fp32")
+    res, _ = K.register_batch(clouds)
+    for g, r in zip(got, res):
+        np.testing.assert_array_equal(g[0], r.pairs.cpu().numpy())
+        np.testing.assert_array_equal(g[1], r.d1.cpu().numpy())
+    check_against_oracle(orc, pairs, got)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_more_than_256_pairs(K, orc, prec):
+    """257 pairs: above the 256 pairs whose matching is planned one-sided, both
+    directions are matched in full; every pair must still equal the oracle."""
+    pairs = subset_pairs(257)
+    clouds = [c for d in pairs for c in clouds_of(K, d)]
+    got = register_batch_direct(K, clouds, prec)
+    check_against_oracle(orc, pairs, got)
+    print(f"{prec}: 257 pairs, {sum(len(g[0]) for g in got)} correspondences, oracle-equal")
+
+
+def test_uneven_batch_sizes_against_oracle(K, orc):
+    """Eight pairs of the 64-pair uneven batch recipe in one launch, the largest (~57k
+    kept-size target) included, each equal to the oracle (pairs, d1, d2, kept and |J|)."""
+    sizes = synth.c2_sizes()
+    indoor = [int(i) for i in np.argsort(sizes[:32])]
+    lidar = [32 + int(i) for i in np.argsort(sizes[32:])]
+    items = sorted({indoor[0], indoor[15], indoor[-1], lidar[0], lidar[10], lidar[20], lidar[-2], lidar[-1]})
+    assert int(np.argmax(sizes)) in items and len(items) == 8
+    pairs = synth.c2_batch(items=items)
+    got = register_batch_direct(K, [c for d in pairs for c in clouds_of(K, d)], "fp32")
+    check_against_oracle(orc, pairs, got, grid=True)
+    print("uneven batch items", items, "kept", [g[3] for g in got], "correspondences", [len(g[0]) for g in got])

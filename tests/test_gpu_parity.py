@@ -5,9 +5,10 @@ Bars (from the method's discrete/continuous outputs):
     J lists and correspondence sets: bit-exact;
   - normals: angle to the oracle normal <= 1e-5 rad wherever the relative
     eigen-gap (l2 - l3) / l1 is >= 1e-6 (ill-conditioned points are counted);
-  - SPFH: |delta| <= 1e-4 per bin; FPFH: |delta| <= 1e-4 * S_q / 100 per bin,
-    S_q being the sub-histogram sum (FPFH rows are rescaled sums of SPFH rows
-    weighted by 1 / distance, so the bar is stated per unit of S_q / 100);
+  - SPFH and FPFH: |delta| <= 1e-4 per bin, absolute; where float32 itself
+    cannot hold a value to 1e-4 (values of 2048 and more, whose half ulp
+    exceeds 1e-4: FPFH bins grow with 1 / distance of close neighbours) the
+    bar is the float32 rounding of the FP64 value, half an ulp;
   - d1, d2: the FP32 rounding of the oracle's FP64 values.
 The histogram step is compared on shared inputs: both sides take the oracle's
 CSR, B flags and the oracle's normals rounded to float32.
@@ -176,12 +177,20 @@ def check_features(K, orc, xyz, p, vp, csr=None):
     gs = host(out.spfh).astype(np.float64)
     assert np.abs(gs - sp["spfh"]).max() <= 1e-4
     gf = host(out.fpfh).astype(np.float64)
-    H = p.n_bins
-    S = np.maximum(fp[:, :H].sum(1, keepdims=True), 100.0)
-    rel = np.abs(gf - fp) / (S / 100.0)
-    assert rel.max() <= 1e-4, rel.max()
+    assert_hist_close(gf, fp)
     exact = np.mean(gf.astype(np.float32) == fp.astype(np.float32))
     return out, sp, fp, exact
+
+
+def hist_bar(ref):
+    """Per-bin bar: 1e-4 absolute, or half a float32 ulp of the value where that is larger."""
+    return np.maximum(1e-4, 0.5 * np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64))
+
+
+def assert_hist_close(got, ref):
+    err = np.abs(got - ref)
+    bar = hist_bar(ref)
+    assert np.all(err <= bar), (err.max(), float(ref[np.unravel_index(np.argmax(err - bar), err.shape)]))
 
 
 @pytest.mark.parametrize("name", ["c0", "c1"])
@@ -208,6 +217,95 @@ def test_features_closed_forms(K, orc):
     for q in range(4):
         np.testing.assert_allclose(f[q, g["spfh_support"]], g["fpfh_support_value"][q], rtol=1e-6)
         assert np.count_nonzero(f[q]) == 3
+
+
+def test_features_collinear_golden(K):
+    """Hand-derived SPFH / FPFH of four collinear points with given normals whose SPFH
+    rows all differ (tests/golden/collinear_fpfh.json; Eq. A2-A5), through kmg_fpfh."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "collinear_fpfh.json")))
+    n = len(g["x"])
+    pts = np.zeros((3, n), np.float32)
+    pts[0] = g["x"]
+    t = np.radians(g["normal_angle_deg"])
+    nrm = np.stack([np.sin(t), np.zeros(n), np.cos(t)]).astype(np.float32)
+    off = np.arange(0, n * n + 1, n, dtype=np.int32)
+    idx = np.tile(np.arange(n, dtype=np.int32), n)
+    p = synth.Params(voxel=1.0, r_normal=g["r"], r_fpfh=g["r"], tau_num=g["tau_num"])
+    out = K.fpfh(dev(pts), dev(nrm), dev(np.ones(n, np.uint8)), dev(off), dev(idx), kparams(K, p, np.zeros(3)),
+                 want_spfh=True)
+    assert host(out.j_idx).tolist() == list(range(n))
+    c = 100.0 / (n - 1)
+    H = g["H"]
+    for q in range(n):
+        sp = np.zeros(3 * H)
+        for b, v in g["spfh_counts"][q].items():
+            sp[int(b)] = c * v
+        fp = np.zeros(3 * H)
+        for b, (num, den) in g["fpfh_over_c"][q].items():
+            fp[int(b)] = c * num / den
+        assert np.abs(host(out.spfh)[q] - sp).max() <= 1e-4
+        assert np.abs(host(out.fpfh)[q] - fp).max() <= 1e-4
+
+
+def test_features_selection_tie_and_degenerate_frame(K):
+    """Eq. A2 at an exact tie of the two angles (the query is a: each point histograms
+    its own role assignment) and with normals along the connecting line (f = (0, 0, u.d),
+    f3 = +1 clamped into the last bin)."""
+    # tie: q = 0 with n = (0.6, 0, 0.8), k = (1, 0, 0) with n = (0.6, 0.8, 0); tests/golden/pair_features.json
+    pts = np.array([[0.0, 1.0], [0.0, 0.0], [0.0, 0.0]], np.float32)
+    nrm = np.array([[0.6, 0.6], [0.0, 0.8], [0.8, 0.0]], np.float32)
+    off = np.array([0, 2, 4], np.int32)
+    idx = np.array([0, 1, 0, 1], np.int32)
+    p = synth.Params(voxel=1.0, r_normal=5.0, r_fpfh=5.0, tau_num=2)
+    out = K.fpfh(dev(pts), dev(nrm), dev(np.ones(2, np.uint8)), dev(off), dev(idx), kparams(K, p, np.zeros(3)),
+                 want_spfh=True)
+    sp = host(out.spfh)
+    # query 0 (a = 0): f = (atan(4/3), -0.8, 0.6) -> bins 7, 1, 8; query 1 (a = 1): f = (-atan(4/3), -0.8, -0.6)
+    # -> bins 3, 1, 2
+    for q, bins in ((0, (7, 12, 30)), (1, (3, 12, 24))):
+        expect = np.zeros(33)
+        expect[list(bins)] = 100.0
+        np.testing.assert_allclose(sp[q], expect, atol=1e-4)
+    # degenerate frame: three points on the x axis, normals +e_x
+    pts = np.zeros((3, 3), np.float32)
+    pts[0] = [0.0, 1.0, 2.0]
+    nrm = np.zeros((3, 3), np.float32)
+    nrm[0] = 1.0
+    off = np.array([0, 3, 6, 9], np.int32)
+    idx = np.tile(np.arange(3, dtype=np.int32), 3)
+    p = synth.Params(voxel=1.0, r_normal=5.0, r_fpfh=5.0, tau_num=3)
+    out = K.fpfh(dev(pts), dev(nrm), dev(np.ones(3, np.uint8)), dev(off), dev(idx), kparams(K, p, np.zeros(3)),
+                 want_spfh=True)
+    sp = host(out.spfh)
+    for q, (behind, ahead) in enumerate([(0, 2), (1, 1), (2, 0)]):
+        expect = np.zeros(33)
+        expect[5] = expect[16] = 100.0
+        expect[22] += 50.0 * behind
+        expect[32] += 50.0 * ahead
+        np.testing.assert_allclose(sp[q], expect, atol=1e-4)
+
+
+def test_normals_orientation_exact_zero(K, orc):
+    """Axis planes through the viewpoint: the normal is exactly +-e and n . (vp - a_q) is
+    exactly 0 on both sides, so the first-nonzero-positive rule decides: n = +e.  (On
+    tilted planes through the viewpoint the zero is exact only in exact arithmetic; there
+    each side's rounding decides the sign, and the GPU counts such points as ambiguous.)"""
+    rng = np.random.default_rng(3)
+    n = 300
+    for axis in range(3):
+        xyz = np.ascontiguousarray(rng.uniform(-1, 1, (3, n)).astype(np.float32))
+        xyz[axis] = 0.0
+        vp = np.array([0.4, -0.9, 0.6])
+        vp[axis] = 0.0
+        out, nr, _ = check_normals(K, xyz, synth.Params(voxel=0.05, r_normal=0.3, r_fpfh=0.3), vp)
+        ok = host(out.flags) & 1 == 1
+        assert ok.sum() > 0.9 * n
+        expect = np.zeros(3, np.float32)
+        expect[axis] = 1.0
+        np.testing.assert_array_equal(host(out.normals)[:, ok].T, np.tile(expect, (int(ok.sum()), 1)))
 
 
 # ---------------------------------------------------------------- matching --
@@ -360,7 +458,5 @@ def test_classic_fpfh_mode(K, orc, name):
         np.testing.assert_array_equal((host(out.flags) >> 1) & 1, r["J"])
         np.testing.assert_array_equal(host(out.j_idx), r["j_idx"])
         assert np.abs(host(out.spfh).astype(np.float64) - r["spfh"]).max() <= 1e-4
-        gf = host(out.fpfh).astype(np.float64)
-        S = np.maximum(r["fpfh"][:, :p.n_bins].sum(1, keepdims=True), 100.0)
-        assert (np.abs(gf - r["fpfh"]) / (S / 100.0)).max() <= 1e-4
+        assert_hist_close(host(out.fpfh).astype(np.float64), r["fpfh"])
         print(f"{name}/{tag}: classical |J| = {out.j_idx.numel()} (Faster-PFH |J| = {len(ref[tag]['j_idx'])})")

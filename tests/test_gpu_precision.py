@@ -146,3 +146,55 @@ def test_full_size_sampled(K, orc, prec):
             assert host(b.d1)[k] == np.float32(np.sqrt(bst)) and host(b.d2)[k] == np.float32(np.sqrt(sec))
     print(f"{prec}: {len(pairs)} pairs; exact re-scans fp32 {a.n_fallback}, {prec} {b.n_fallback} "
           f"({100.0 * b.n_fallback / 2e5:.2f}% of queries); {int(mutual.sum())} of 300 sampled rows mutual")
+
+
+@pytest.fixture(scope="module")
+def c3_rows(orc):
+    """Exactly 100,000 J rows per side of the 100k x 100k matching workload (two submaps of
+    four ray-cast scans at voxel 0.15 m), computed by the oracle (grid radius search), then
+    a seeded subset as the benchmark takes it."""
+    d = synth.c3_pair(0)
+    p = d["params"]
+    rows = []
+    for key, vp in (("src", d["vp_src"]), ("tgt", d["vp_tgt"])):
+        kept, _ = orc.voxelize(d[key], p.voxel)
+        xyz = np.ascontiguousarray(d[key][:, kept])
+        fp = orc.faster_pfh(xyz, p, vp, grid=True)
+        j = fp["j_idx"]
+        assert j.size >= 100000
+        pick = np.sort(np.random.default_rng(2409).permutation(j.size)[:100000])
+        rows.append(np.ascontiguousarray(fp["fpfh"][j[pick]].astype(np.float32)))
+    return rows
+
+
+_c3_fp32 = {}
+
+
+@pytest.mark.parametrize("prec", ["fp32"] + PRECS)
+def test_c3_rows_sampled(K, orc, c3_rows, prec):
+    """The real FPFH rows of the 100k x 100k workload (tightly clustered, unlike the
+    synthetic rows): every precision gives the FP32 form's correspondences, d1 and d2,
+    and 300 sampled rows agree with the oracle's one-by-one NN and mutual test."""
+    X, Y = c3_rows
+    b = K.match(dev(X), dev(Y), prec=prec)
+    got = (host(b.pairs), host(b.d1), host(b.d2))
+    if prec == "fp32":
+        _c3_fp32["ref"] = got
+    elif "ref" in _c3_fp32:
+        for u, v in zip(got, _c3_fp32["ref"]):
+            np.testing.assert_array_equal(u, v)
+    pairs = got[0]
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(X.shape[0], 300, replace=False))
+    nn, best, second = orc.nn_rows(X, Y, rows)
+    back, _, _ = orc.nn_rows(Y, X, nn)
+    mutual = back == rows
+    index = {int(i): k for k, i in enumerate(pairs[:, 0])}
+    for r, n, bst, sec, mu in zip(rows, nn, best, second, mutual):
+        assert (int(r) in index) == bool(mu), r
+        if mu:
+            k = index[int(r)]
+            assert pairs[k, 1] == n
+            assert got[1][k] == np.float32(np.sqrt(bst)) and got[2][k] == np.float32(np.sqrt(sec))
+    print(f"c3 rows {prec}: {len(pairs)} pairs; exact re-scans {b.n_fallback} "
+          f"({100.0 * b.n_fallback / 2e5:.2f}% of queries); {int(mutual.sum())} of 300 sampled rows mutual")

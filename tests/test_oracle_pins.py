@@ -216,9 +216,32 @@ def test_pair_feature_golden(orc):
         np.testing.assert_allclose(f, c["f"], atol=1e-15)
         bins = [int(min(10, max(0, math.floor(11 * (f[l] - lo[l]) / (2 * -lo[l]))))) for l in range(3)]
         assert bins == c["bins"]
-        # the features do not depend on which point is the query
         f2 = orc.pair_features(c["pk"], c["nk"], c["pq"], c["nq"])
-        np.testing.assert_allclose(f2, f, atol=1e-15)
+        if c.get("query_dependent"):
+            # an exact tie of the two angles makes the query the point a
+            np.testing.assert_allclose(f2, c["f_swapped"], atol=1e-15)
+        else:
+            # otherwise the features do not depend on which point is the query
+            np.testing.assert_allclose(f2, f, atol=1e-15)
+
+
+def test_degenerate_frame_spfh(orc):
+    """Normals along the connecting line (Eq. A2 with d x u = 0): f = (0, 0, u.d) with
+    u.d = +1 toward a neighbour ahead of q along its normal and -1 behind it.  f3 = 1 is
+    the top of the range, whose scaled value H (f - lo) / (hi - lo) is exactly H: it lands
+    in the last bin (Eq. A3, clamped)."""
+    pts = np.zeros((3, 3), np.float32)
+    pts[0] = [0.0, 1.0, 2.0]
+    nrm = np.zeros((3, 3))
+    nrm[0] = 1.0
+    off, idx = orc.radius_search(pts, 5.0)
+    sp = orc.spfh(pts, nrm, off, idx, np.ones(3, np.uint8), 3, 11)
+    for q, (behind, ahead) in enumerate([(0, 2), (1, 1), (2, 0)]):
+        cnt = np.zeros(33, np.int32)
+        cnt[5] = cnt[16] = 2
+        cnt[22] += behind
+        cnt[32] += ahead
+        np.testing.assert_array_equal(sp["counts"][q], cnt)
 
 
 @pytest.mark.parametrize("inward", [True, False])
@@ -240,6 +263,105 @@ def test_sphere_closed_form(orc, inward):
         f = orc.pair_features(pq, nq, pk, nk)
         expect = (-phi, 0.0, c / (2 * R)) if inward else (phi, 0.0, -c / (2 * R))
         np.testing.assert_allclose(f, expect, atol=1e-12)
+
+
+def test_collinear_closed_form(orc):
+    """Points on a line e with unit normals n = sin(t) e + cos(t) m (m a unit vector normal
+    to e): n . d0 = +-sin(t), so a is the point of larger |sin t|, and Eq. A2 reduces to
+    f = (s (t_b - t_a), 0, s sin t_a) with s the sign of the step from a to b along e."""
+    rng = np.random.default_rng(17)
+    for _ in range(400):
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        m = np.cross(e, rng.standard_normal(3))
+        m /= np.linalg.norm(m)
+        o = rng.uniform(-2, 2, 3)
+        xq, xk = rng.uniform(-1, 1, 2)
+        tq, tk = rng.uniform(-1.5, 1.5, 2)
+        pq, pk = o + xq * e, o + xk * e
+        nq = math.sin(tq) * e + math.cos(tq) * m
+        nk = math.sin(tk) * e + math.cos(tk) * m
+        if abs(math.sin(tq)) >= abs(math.sin(tk)):
+            (xa, ta), (xb, tb) = (xq, tq), (xk, tk)
+        else:
+            (xa, ta), (xb, tb) = (xk, tk), (xq, tq)
+        s = 1.0 if xb > xa else -1.0
+        f = orc.pair_features(pq, nq, pk, nk)
+        np.testing.assert_allclose(f, (s * (tb - ta), 0.0, s * math.sin(ta)), atol=1e-12)
+
+
+def test_collinear_fpfh_golden(orc):
+    """Four collinear points with given normals whose SPFH rows all differ: the hand-derived
+    SPFH counts (Eq. A2-A4) and FPFH rows (Eq. A5) of tests/golden/collinear_fpfh.json.
+    Every neighbour contributes its own SPFH row, weighted by 1 / distance."""
+    g = _gold("collinear_fpfh.json")
+    n = len(g["x"])
+    pts = np.zeros((3, n), np.float32)
+    pts[0] = g["x"]
+    t = np.radians(g["normal_angle_deg"])
+    nrm = np.stack([np.sin(t), np.zeros(n), np.cos(t)])
+    off, idx = orc.radius_search(pts, g["r"])
+    assert np.array_equal(np.diff(off), [n] * n)
+    B = np.ones(n, np.uint8)
+    H = g["H"]
+    sp = orc.spfh(pts, nrm, off, idx, B, g["tau_num"], H)
+    assert sp["J"].tolist() == [1] * n and sp["Pq"].tolist() == [n - 1] * n
+    c = 100.0 / (n - 1)
+    for q in range(n):
+        cnt = np.zeros(3 * H, np.int32)
+        for b, v in g["spfh_counts"][q].items():
+            cnt[int(b)] = v
+        np.testing.assert_array_equal(sp["counts"][q], cnt)
+        np.testing.assert_allclose(sp["spfh"][q], c * cnt, rtol=1e-15, atol=0)
+    fp = orc.fpfh(pts, off, idx, B, sp["J"], sp["spfh"], sp["Pq"], H)
+    for q in range(n):
+        expect = np.zeros(3 * H)
+        for b, (num, den) in g["fpfh_over_c"][q].items():
+            expect[int(b)] = c * num / den
+        np.testing.assert_allclose(fp[q], expect, rtol=1e-13, atol=1e-12)
+
+
+def test_orientation_exact_zero(orc):
+    """Normal sign (viewpoint rule with the exact-zero convention): on planes through the
+    viewpoint n . (vp - a_q) is often exactly 0; there the first nonzero component of n is
+    positive, elsewhere n . (vp - a_q) > 0.  Axis planes give n = +e exactly."""
+    rng = np.random.default_rng(3)
+    n = 300
+    ties = 0
+    for (i, j), s in [((0, 1), 1), ((0, 1), -1), ((0, 2), 1), ((0, 2), -1), ((1, 2), 1), ((1, 2), -1)]:
+        k = 3 - i - j
+        t = rng.uniform(-1, 1, n).astype(np.float32)
+        f = rng.uniform(-1, 1, n).astype(np.float32)
+        xyz = np.zeros((3, n), np.float32)
+        xyz[i], xyz[j], xyz[k] = t, s * t, f
+        vp = np.zeros(3)
+        vp[i], vp[j], vp[k] = 0.7, s * 0.7, 3.0
+        off, idx = orc.radius_search(xyz, 0.3)
+        nr = orc.normals(xyz, off, idx, 0.3, 3, 0.99, vp)
+        ok = nr["B"] == 1
+        assert ok.sum() == n
+        nn = nr["normals"]
+        to_vp = vp[:, None] - xyz.astype(np.float64)
+        dot = (nn[0] * to_vp[0] + nn[1] * to_vp[1]) + nn[2] * to_vp[2]
+        assert np.all(dot >= 0.0)
+        zero = dot == 0.0
+        ties += int(zero.sum())
+        for q in np.nonzero(zero)[0]:
+            first = nn[np.nonzero(nn[:, q])[0][0], q]
+            assert first > 0.0, ((i, j, s), q, nn[:, q])
+    assert ties >= 700
+    for axis in range(3):
+        xyz = np.ascontiguousarray(rng.uniform(-1, 1, (3, n)).astype(np.float32))
+        xyz[axis] = 0.0
+        vp = np.array([0.4, -0.9, 0.6])
+        vp[axis] = 0.0
+        off, idx = orc.radius_search(xyz, 0.3)
+        nr = orc.normals(xyz, off, idx, 0.3, 3, 0.99, vp)
+        ok = nr["B"] == 1
+        assert ok.sum() > 0.9 * n
+        expect = np.zeros(3)
+        expect[axis] = 1.0
+        np.testing.assert_array_equal(nr["normals"][:, ok].T, np.tile(expect, (int(ok.sum()), 1)))
 
 
 def test_bin_map(orc):
@@ -407,3 +529,23 @@ def test_unrelated_pair_has_few_inliers(orc):
         return
     _, _, n_inl = pose.register(d0["src"], junk, pairs, mm["d1"], mm["d2"], p.voxel)
     assert n_inl < 30
+
+
+def test_grid_radius_search_equals_brute_force(orc):
+    """The grid form of the radius search (cell size r) returns exactly the brute-force
+    sets of Eq. A1, including points at exactly r, on cell faces and far from the origin."""
+    rng = np.random.default_rng(23)
+    r = 0.25
+    clouds = [rng.uniform(0, 2, (3, 3000)).astype(np.float32),
+              (rng.uniform(-1, 1, (3, 2000)) + 400.0).astype(np.float32),
+              (np.round(rng.uniform(-1, 1, (3, 2500)) * 8) / 8).astype(np.float32)]  # lattice at r / 2
+    axis = np.zeros((3, 9), np.float32)
+    axis[0] = np.arange(9) * 0.25  # neighbours at exactly r: excluded (strict)
+    clouds.append(axis)
+    for xyz in clouds:
+        xyz = np.ascontiguousarray(xyz)
+        ob, ib = orc.radius_search(xyz, r)
+        og, ig = orc.radius_search(xyz, r, grid=True)
+        np.testing.assert_array_equal(og, ob)
+        np.testing.assert_array_equal(ig, ib)
+    assert np.array_equal(np.diff(og), [1] * 9)
