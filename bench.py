@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency vs plain"
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the first-direction band tile kernel, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 14 launches on
@@ -114,6 +115,87 @@ PFH_STAGES = ("voxelize", "grid", "search_count", "search_fill", "normals", "spf
 
 def pfh_bytes(raw_points, kept_points, nnz):
     return 12.0 * raw_points + 482.0 * kept_points + 12.0 * nnz
+
+
+def pfh_roofline(stages, raw_points, kept_points, nnz):
+    """HBM roofline of the Faster-PFH stages together: algorithmic bytes over the summed
+    stage times (HIP events on the library stream)."""
+    ms = sum(stages[n] for n in PFH_STAGES)
+    b = pfh_bytes(raw_points, kept_points, nnz)
+    gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"stages": list(PFH_STAGES), "ms": round(ms, 5), "algorithmic_bytes": b, "bound": "hbm",
+            "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 5)}
+
+
+def p6_report(kmg, torch, d, ref, dev):
+    """End-to-end error of the GPU path against the pure oracle (the same raw
+    clouds through both): kept sets, neighbour lists, B / J flags, normal angles,
+    SPFH bin flips, the largest per-bin FPFH error and the correspondence sets."""
+    p = d["params"]
+    rep = {}
+    for tag, vp in (("src", d["vp_src"]), ("tgt", d["vp_tgt"])):
+        prm = kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, vp)
+        kept, xyz = kmg.voxelize(torch.from_numpy(d[tag]).to(dev), p.voxel)
+        xyz = xyz.contiguous()
+        nr = kmg.normals(xyz, prm)
+        ft = kmg.fpfh(xyz, nr.normals, nr.flags, nr.off, nr.idx, prm, want_spfh=True)
+        r = ref[tag]
+        kept = kept.cpu().numpy()
+        same_kept = np.array_equal(kept, r["kept"])
+        same_csr = same_kept and np.array_equal(nr.off.cpu().numpy().astype(np.int64), r["off"]) and \
+            np.array_equal(nr.idx.cpu().numpy(), r["idx"])
+        flags = ft.flags.cpu().numpy()
+        e = {"kept_equal": bool(same_kept), "csr_equal": bool(same_csr)}
+        if same_kept:
+            B, J = flags & 1, (flags >> 1) & 1
+            e["B_mismatch"] = int((B != r["B"]).sum())
+            e["J_mismatch"] = int((J != r["J"]).sum())
+            both = (B == 1) & (r["B"] == 1)
+            g = nr.normals.cpu().numpy().astype(np.float64)[:, both]
+            o = r["normals"][:, both]
+            g = g / np.linalg.norm(g, axis=0, keepdims=True)
+            ang = np.arctan2(np.linalg.norm(np.cross(g.T, o.T), axis=1), np.sum(g * o, axis=0))
+            well = r["gap"][both] >= 1e-6
+            e["normal_angle_rad"] = {"max": float(ang[well].max()) if well.any() else 0.0,
+                                     "p50": float(np.percentile(ang[well], 50)) if well.any() else 0.0,
+                                     "p99": float(np.percentile(ang[well], 99)) if well.any() else 0.0,
+                                     "ill_conditioned_excluded": int((~well).sum())}
+            sp_g = ft.spfh.cpu().numpy().astype(np.float64)
+            jb = (J == 1) & (r["J"] == 1)
+            Pq = r["Pq"].astype(np.float64)[:, None]
+            cnt_g = np.rint(sp_g * np.maximum(Pq, 1.0) / 100.0)
+            bb = both & (r["Pq"] > 0)
+            # pair features whose bin differs from the oracle's (each moves one count out and one in)
+            e["spfh_bin_flips"] = int(np.abs(cnt_g[bb] - r["counts"][bb]).sum() // 2)
+            e["spfh_pair_features"] = int(3 * r["Pq"][bb].sum())
+            fg = ft.fpfh.cpu().numpy().astype(np.float64)
+            e["fpfh_max_abs_err"] = float(np.abs(fg[jb] - r["fpfh"][jb]).max()) if jb.any() else 0.0
+            e["fpfh_max_abs_err_rows_without_flips"] = float(
+                np.abs(fg[jb] - r["fpfh"][jb]).max(axis=1)[np.all(cnt_g[jb] == r["counts"][jb], axis=1)].max()) \
+                if jb.any() else 0.0
+        rep[tag] = e
+    return rep
+
+
+def cpu_baseline(oracle, d, repeats_all, repeats_one):
+    """The FP64 oracle on one full pair: median of `repeats_all` runs at all host
+    threads, and `repeats_one` runs on one thread."""
+    p = d["params"]
+
+    def once():
+        t0 = time.perf_counter()
+        ref = oracle.run_pair(d["src"], d["tgt"], p, d["vp_src"], d["vp_tgt"])
+        return time.perf_counter() - t0, ref
+
+    threads = oracle.set_threads(os.cpu_count() or 1)
+    runs = [once() for _ in range(repeats_all)]
+    t_all = statistics.median(t for t, _ in runs)
+    one = []
+    if repeats_one > 0:
+        oracle.set_threads(1)
+        one = [once()[0] for _ in range(repeats_one)]
+        oracle.set_threads(threads)
+    return runs[-1][1], t_all, threads, one
 
 
 def run_batch64(args, lib, kmg, torch, synth, dev):
@@ -508,6 +590,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-repeats", type=int, default=3, help="oracle runs at all host threads (median)")
+    ap.add_argument("--cpu-repeats-one-thread", type=int, default=1, help="oracle runs on one thread")
     ap.add_argument("--item", type=int, default=0)
     ap.add_argument("--workload", default="lidar", choices=["lidar", "batch64", "serve", "graph", "c3", "classic"],
                     help="lidar: one 25k-point LiDAR pair per step (default); batch64: 64 uneven pairs "
@@ -672,15 +756,14 @@ def main():
             "flops_per_launch": flops_per_launch,
             "band_fraction": round(flops_per_launch / dense, 4),
         },
+        "roofline_faster_pfh": pfh_roofline(stages, int(src.shape[1]) + int(tgt.shape[1]), sum(res.kept),
+                                            batch.nnz()),
     }
 
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = oracle.set_threads(0)
-        tc0 = time.perf_counter()
-        ref = oracle.run_pair(d["src"], d["tgt"], p, d["vp_src"], d["vp_tgt"])
-        tc = time.perf_counter() - tc0
+        ref, tc, threads, one = cpu_baseline(oracle, d, args.cpu_repeats, args.cpu_repeats_one_thread)
         gp = {tuple(x) for x in res_g.pairs.cpu().numpy().tolist()}
         rp = {tuple(x) for x in ref["pairs"].tolist()}
         out["cpu_baseline"] = {
@@ -689,9 +772,14 @@ def main():
             "cores": threads,
             "kind": "oracle",
             "sample": "one full pair of the same workload (item %d): FP64 voxelize, brute-force radius search, "
-                      "Jacobi normals, SPFH/FPFH, brute-force FP64 mutual matching; %.2f s wall" % (args.item, tc),
+                      "Jacobi normals, SPFH/FPFH, brute-force FP64 mutual matching; median of %d runs on %d "
+                      "threads: %.2f s wall" % (args.item, args.cpu_repeats, threads, tc),
+            "one_thread": {"value": round(1.0 / statistics.median(one), 5), "unit": "pairs/s", "cores": 1,
+                           "runs_s": [round(t, 2) for t in one]} if one else None,
         }
         out["oracle_equal_correspondences"] = gp == rp
+        out["correspondence_jaccard"] = round(len(gp & rp) / max(1, len(gp | rp)), 6)
+        out["error_vs_oracle"] = p6_report(kmg, torch, d, ref, dev)
     print(json.dumps(out), flush=True)
 
     if args.copy_probe > 0:
