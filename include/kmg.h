@@ -14,7 +14,8 @@
  *    parameter is documented as a host pointer.  The library never allocates
  *    device memory: scratch space comes from the caller's workspace `ws` of
  *    `ws_bytes` bytes, sized by kmg_workspace_bytes().  `ws` must be
- *    256-byte aligned.
+ *    256-byte aligned.  (kmg_normals_static takes no workspace: its scratch
+ *    is a fixed array inside the library.)
  *  - Point clouds are float32 structure-of-arrays: x[0..n), y[0..n),
  *    z[0..n) stored back to back (3*n floats, row stride n).
  *  - Descriptors are row-major float32, 3*H values per point (H = n_bins).
@@ -178,6 +179,24 @@ kmg_status kmg_voxelize(const float* xyz, int64_t n, double voxel, int32_t* kept
 kmg_status kmg_normals(const float* xyz, int64_t m, const kmg_params* p, float* normals, uint8_t* flags,
                        int32_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nnz, int32_t* n_normal,
                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kmg_normals_static -- kmg_normals for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid it).  The same computation, arguments and errors as
+ * kmg_normals, without the workspace: the scratch is one array of 20 MiB per
+ * GPU inside the library, held until the process ends.
+ *   m          at most KMG_STATIC_MAX_POINTS (KMG_ERR_RANGE beyond).
+ *   p->mode    KMG_MODE_FASTER_PFH only (KMG_ERR_ARG otherwise).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * device (two streams, two threads) race and must be serialised by the
+ * caller.  The call itself allocates nothing; like kmg_normals it
+ * synchronises `stream` to return *nnz.
+ */
+#define KMG_STATIC_MAX_POINTS 262144
+kmg_status kmg_normals_static(const float* xyz, int64_t m, const kmg_params* p, float* normals, uint8_t* flags,
+                              int32_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nnz, int32_t* n_normal,
+                              void* stream);
 
 /*
  * kmg_fpfh -- Algorithm 1, Step 2 and Eq. A2-A5.

@@ -84,6 +84,8 @@ def load():
     lib.kmg_voxelize.restype = i32
     lib.kmg_normals.argtypes = [vp, i64, pp, vp, vp, vp, vp, i64, i64p, vp, vp, sz, vp]
     lib.kmg_normals.restype = i32
+    lib.kmg_normals_static.argtypes = [vp, i64, pp, vp, vp, vp, vp, i64, i64p, vp, vp]
+    lib.kmg_normals_static.restype = i32
     lib.kmg_fpfh.argtypes = [vp, vp, vp, vp, vp, i64, pp, vp, vp, vp, i64p, i64p, vp, sz, vp]
     lib.kmg_fpfh.restype = i32
     lib.kmg_match.argtypes = [vp, vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, i64, i64p, i64p, vp, sz, vp]
@@ -230,6 +232,37 @@ def normals(xyz, params, ws=None, want_n_normal=True):
             _nbr_cap_hint[dev.index] = cap
             continue
         _raise("kmg_normals", st)
+        break
+    nnz = nnz.value
+    return NormalsOut(nrm[: 3 * m].view(3, m), flags[:m], off, idx[:nnz],
+                      n_normal[:m] if n_normal is not None else None)
+
+
+STATIC_MAX_POINTS = 262144
+
+
+def normals_static(xyz, params, want_n_normal=True):
+    """kmg_normals_static: kmg_normals with the library's static scratch (no
+    workspace; m <= STATIC_MAX_POINTS, Faster-PFH mode).  The outputs are still
+    allocated here, by torch."""
+    lib = load()
+    _check_dev(xyz, torch.float32, "xyz")
+    m = xyz.shape[1]
+    dev = xyz.device
+    nrm = torch.empty(3 * max(m, 1), dtype=torch.float32, device=dev)
+    flags = torch.empty(max(m, 1), dtype=torch.uint8, device=dev)
+    off = torch.empty(m + 1, dtype=torch.int32, device=dev)
+    n_normal = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if want_n_normal else None
+    cap = max(_nbr_cap_hint.get(dev.index, 0), 64 * m, 1)
+    for _ in range(2):
+        idx = torch.empty(cap, dtype=torch.int32, device=dev)
+        nnz = C.c_int64(0)
+        st = lib.kmg_normals_static(_ptr(xyz), m, C.byref(params), _ptr(nrm), _ptr(flags), _ptr(off), _ptr(idx), cap,
+                                    C.byref(nnz), _ptr(n_normal), _stream())
+        if st == KMG_ERR_CAPACITY:
+            cap = max(cap, int(nnz.value))
+            continue
+        _raise("kmg_normals_static", st)
         break
     nnz = nnz.value
     return NormalsOut(nrm[: 3 * m].view(3, m), flags[:m], off, idx[:nnz],
