@@ -18,7 +18,8 @@ library records on its stream during the batched form's timed steps; the
 roofline entry reports the matching distance-tile kernel (the dominant one)
 from the same events.  The CPU baseline is the FP64 oracle on one full pair.
 
-Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 5] [--workload lidar|batch64]
+Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 5] [--workload lidar|batch64|...]
+       python bench.py --pmc-summary DIR...   (per-kernel means of rocprofv3 counter CSVs)
 """
 
 from __future__ import annotations
@@ -583,7 +584,44 @@ def run_graph(args, lib, kmg, torch, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def pmc_summary(paths, min_dispatches=1):
+    """Markdown table of rocprofv3 counter CSVs (--pmc ... --output-format csv): per
+    kernel, the dispatch count and the mean value per dispatch of every counter."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    files = []
+    for p in paths:
+        files += sorted(glob.glob(os.path.join(p, "**", "*counter_collection.csv"), recursive=True)) \
+            if os.path.isdir(p) else [p]
+    acc = defaultdict(lambda: defaultdict(list))
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                name = row["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+                name = name.replace("void ", "").replace("kmg::", "")
+                acc[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    counters = sorted({c for k in acc.values() for c in k})
+    lines = ["| kernel | dispatches | " + " | ".join(f"{c} (mean)" for c in counters) + " |",
+             "|---|---:|" + "---:|" * len(counters)]
+    rows = []
+    for name, cs in acc.items():
+        n = max(len(v) for v in cs.values())
+        if n < min_dispatches:
+            continue
+        vals = [statistics.fmean(cs[c]) if cs.get(c) else float("nan") for c in counters]
+        rows.append((name, n, vals))
+    rows.sort(key=lambda r: r[0])
+    for name, n, vals in rows:
+        lines.append(f"| `{name}` | {n} | " + " | ".join(f"{v:.4g}" for v in vals) + " |")
+    return "\n".join(lines)
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--pmc-summary":
+        print(pmc_summary(sys.argv[2:]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)

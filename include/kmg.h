@@ -95,8 +95,9 @@ enum {
     KMG_OP_KCORE = 5     /* n0 = graph vertices */
 };
 
-/* Largest graph kmg_max_kcore accepts (its state lives in on-chip memory). */
-#define KMG_MAX_KCORE_VERTICES 8192
+/* Largest graph kmg_max_kcore accepts (its state lives in on-chip memory,
+ * 8 bytes per vertex: 128 KiB of the CU's 160 KiB LDS at the limit). */
+#define KMG_MAX_KCORE_VERTICES 16384
 
 /* Workspace size in bytes needed by `op` for the given sizes (a host call;
  * touches no device).  For KMG_OP_MATCH the descriptor length is
@@ -328,7 +329,9 @@ kmg_status kmg_register_batch(const kmg_cloud* clouds, const kmg_match_out* outs
  * sorted): core (device int32[n]); members (device int32[n]) receives the
  * vertices of the maximum k-core, ascending, *n_members (host) their count and
  * *max_core (host) the largest core number (-1 for n = 0).  An adj entry
- * outside [0, n) gives KMG_ERR_RANGE.  Synchronises the stream.
+ * outside [0, n) gives KMG_ERR_RANGE, and so does a graph above 8,192
+ * vertices on a device that cannot give one workgroup more than 64 KiB of
+ * LDS.  Synchronises the stream.
  */
 kmg_status kmg_corr_graph(const float* src_xyz, int64_t m_src, const float* tgt_xyz, int64_t m_tgt,
                           const int32_t* pairs, const float* d1, const float* d2, int64_t n_corr, int32_t n_tau,

@@ -17,9 +17,10 @@
 // k-core.  Core numbers by level-synchronous peeling in one block: at level
 // k, every vertex whose remaining degree is <= k is removed (core number k)
 // and its alive neighbours lose one degree, round after round until none is
-// left at that level.  Core numbers are unique, so the parallel order of
+// left at that level; then the level jumps to the smallest remaining degree.  Core numbers are unique, so the parallel order of
 // removals cannot change them.  The maximum k-core is the set of vertices
 // whose core number is the largest.
+#include <climits>
 #include <math.h>
 
 #include "kmg_device.h"
@@ -30,7 +31,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kPeelThreads = 1024;
-constexpr int kMaxKcore = KMG_MAX_KCORE_VERTICES;  // LDS: 4 + 2 + 1 bytes per vertex
+constexpr int kMaxKcore = KMG_MAX_KCORE_VERTICES;  // LDS: 4 + 2 + 2 bytes per vertex
 
 __global__ __launch_bounds__(kBlock) void ratio_keys(const float* __restrict__ d1, const float* __restrict__ d2,
                                                      int64_t k, uint64_t* __restrict__ keys) {
@@ -42,29 +43,38 @@ __global__ __launch_bounds__(kBlock) void ratio_keys(const float* __restrict__ d
     }
 }
 
-// Block-stride over e; the block's threads walk the keys together through an
-// LDS tile, so every key is read once per block.
-__global__ __launch_bounds__(kBlock) void rank_select(const uint64_t* __restrict__ keys, int64_t k, int32_t n_tau,
-                                                      int32_t* __restrict__ sel) {
+// rank[e] = number of correspondences f ordered before e by (key, position).
+// Block (x, y) counts, for the keys of tile x, the keys of tiles y, y + gy, ...
+// (staged in LDS) that come first, and adds its counts with one atomic per key;
+// rank_emit then writes sel[rank] = e for the first n_tau ranks.
+constexpr int kRankTiles = 64;  // y tiles of the counting grid
+
+__global__ __launch_bounds__(kBlock) void rank_count(const uint64_t* __restrict__ keys, int64_t k,
+                                                     int32_t* __restrict__ rank) {
     __shared__ uint64_t s_key[kBlock];
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * kBlock; e0 < k; e0 += stride) {
-        const int64_t e = e0 + threadIdx.x;
-        const bool live = e < k;
-        const uint64_t me = live ? keys[e] : 0ull;
-        int64_t rank = 0;
-        for (int64_t f0 = 0; f0 < k; f0 += kBlock) {
-            __syncthreads();
-            if (f0 + threadIdx.x < k) s_key[threadIdx.x] = keys[f0 + threadIdx.x];
-            __syncthreads();
-            const int nf = static_cast<int>(min<int64_t>(kBlock, k - f0));
-            for (int t = 0; t < nf; ++t) {
-                const uint64_t o = s_key[t];
-                rank += (o < me || (o == me && f0 + t < e)) ? 1 : 0;
-            }
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const bool live = e < k;
+    const uint64_t me = live ? keys[e] : 0ull;
+    int cnt = 0;
+    for (int64_t f0 = static_cast<int64_t>(blockIdx.y) * kBlock; f0 < k;
+         f0 += static_cast<int64_t>(gridDim.y) * kBlock) {
+        __syncthreads();
+        if (f0 + threadIdx.x < k) s_key[threadIdx.x] = keys[f0 + threadIdx.x];
+        __syncthreads();
+        const int nf = static_cast<int>(min<int64_t>(kBlock, k - f0));
+        for (int t = 0; t < nf; ++t) {
+            const uint64_t o = s_key[t];
+            cnt += (o < me || (o == me && f0 + t < e)) ? 1 : 0;
         }
-        if (live && rank < n_tau) sel[rank] = static_cast<int32_t>(e);
     }
+    if (live && cnt) atomicAdd(rank + e, cnt);
+}
+
+__global__ __launch_bounds__(kBlock) void rank_emit(const int32_t* __restrict__ rank, int64_t k, int32_t n_tau,
+                                                    int32_t* __restrict__ sel) {
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < k;
+         e += static_cast<int64_t>(gridDim.x) * kBlock)
+        if (rank[e] < n_tau) sel[rank[e]] = static_cast<int32_t>(e);
 }
 
 // Correspondence indices outside the clouds set err and read point 0 instead.
@@ -125,21 +135,128 @@ __global__ __launch_bounds__(kBlock) void graph_rows(const float4* __restrict__ 
     }
 }
 
+// Core numbers as the fixed point of the h-index operator: start from h = degree
+// and replace h[v] by the largest x <= h[v] such that at least x neighbours u
+// have h[u] >= x.  Values only decrease and never fall below the core numbers;
+// a sweep that changes nothing proves a fixed point, and a fixed point reached
+// from above is the core numbers (if h[v] >= x, v has x neighbours with h >= x,
+// so {h >= x} lies in the x-core).  Updates are in place (a neighbour's newer,
+// smaller value only speeds convergence).  Sweep k runs only if sweep k - 1
+// changed something (flag[k] set); one wavefront per vertex.
+constexpr int kHSweeps = 48;  // sweeps launched; the block peel finishes graphs that need more
+constexpr int kHRegs = 8;     // neighbour values held in registers per lane (deg <= 512)
+
+__global__ __launch_bounds__(kBlock) void kcore_hinit(const int32_t* __restrict__ off, int32_t n,
+                                                      int32_t* __restrict__ h, int32_t* __restrict__ flag) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) h[v] = off[v + 1] - off[v];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i <= kHSweeps; i += gridDim.x * kBlock) flag[i] = i == 0;
+}
+
+__global__ __launch_bounds__(kBlock) void kcore_hsweep(const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ adj, int32_t n, int32_t* h,
+                                                       int32_t* flag, int sweep, int32_t* __restrict__ info) {
+    if (flag[sweep] == 0) return;  // converged
+    const int lane = lane_id();
+    bool changed = false;
+    for (int64_t vw = global_wave(); vw < n; vw += wave_count()) {
+        const int v = static_cast<int>(vw);
+        const int cap = h[v];
+        if (cap == 0) continue;
+        const int b = off[v], deg = off[v + 1] - b;
+        int hi = min(cap, deg);
+        int lo = 0;
+        int val[kHRegs];
+        const bool in_regs = deg <= kHRegs * kWave;
+#pragma unroll
+        for (int r = 0; r < kHRegs; ++r) {
+            const int t = r * kWave + lane;
+            val[r] = -1;
+            if (in_regs && t < deg) {
+                const int u = adj[b + t];
+                if (u < 0 || u >= n) info[2] = 1;  // not a vertex: reported, never followed
+                else val[r] = h[u];
+            }
+        }
+        // count of neighbour values >= x (from registers, or re-read for long rows)
+        auto count_ge = [&](int x) {
+            int c = 0;
+            if (in_regs) {
+#pragma unroll
+                for (int r = 0; r < kHRegs; ++r) c += __popcll(ballot(val[r] >= x));
+            } else {
+                for (int t0 = 0; t0 < deg; t0 += kWave) {
+                    const int t = t0 + lane;
+                    int w = -1;
+                    if (t < deg) {
+                        const int u = adj[b + t];
+                        if (u < 0 || u >= n) info[2] = 1;
+                        else w = h[u];
+                    }
+                    c += __popcll(ballot(w >= x));
+                }
+            }
+            return c;
+        };
+        if (count_ge(hi) >= hi) {
+            lo = hi;
+        } else {
+            --hi;  // invariant: count_ge(lo) >= lo, count_ge(hi + 1) < hi + 1
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (count_ge(mid) >= mid) lo = mid;
+                else hi = mid - 1;
+            }
+        }
+        if (lo < cap) {
+            if (lane == 0) h[v] = lo;
+            changed = true;
+        }
+    }
+    if (changed && lane == 0) flag[sweep + 1] = 1;
+}
+
+// After the sweeps: if they converged, the core numbers are h (and their maximum
+// goes to info[0]); otherwise the block peel has written both.
+__global__ __launch_bounds__(kBlock) void kcore_hfinish(const int32_t* __restrict__ h, int32_t n,
+                                                        const int32_t* __restrict__ flag, int32_t* __restrict__ core,
+                                                        int32_t* __restrict__ info) {
+    if (flag[kHSweeps] != 0) return;
+    int mx = -1;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        core[v] = h[v];
+        mx = max(mx, h[v]);
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) mx = max(mx, __shfl_xor(mx, d, kWave));
+    if (lane_id() == 0 && mx >= 0) atomicMax(info, mx);
+}
+
 // One block: core numbers of the graph (off, adj) on n <= kMaxKcore vertices.
-// Degrees, core numbers and the removal flags live in LDS, so the block's
-// atomics and plain reads see one coherent copy.
+// Remaining degrees, core numbers and the list of the round's removals live in
+// LDS (dynamic, 8 bytes per vertex), so the block's atomics and plain reads see
+// one coherent copy.  A round removes every alive vertex whose remaining
+// degree is <= the level (core number = level) and lists it; the block's
+// wavefronts then take the listed vertices and their lanes walk each one's
+// adjacency, decrementing alive neighbours.  A round that removes nothing
+// raises the level to the smallest remaining degree (no round is spent on
+// an empty level).
 __global__ __launch_bounds__(kPeelThreads) void kcore_peel(const int32_t* __restrict__ off,
                                                            const int32_t* __restrict__ adj, int32_t n,
                                                            int32_t* __restrict__ core_out,
-                                                           int32_t* __restrict__ info) {
-    __shared__ int32_t s_deg[kMaxKcore];
-    __shared__ int16_t s_core[kMaxKcore];
-    __shared__ uint8_t s_fresh[kMaxKcore];
-    __shared__ int s_changed, s_left, s_max;
+                                                           int32_t* __restrict__ info,
+                                                           const int32_t* __restrict__ skip) {
+    if (skip && *skip == 0) return;  // the h-index sweeps converged
+    extern __shared__ int32_t s_mem[];
+    int32_t* s_deg = s_mem;
+    int16_t* s_core = reinterpret_cast<int16_t*>(s_deg + n);
+    int16_t* s_list = s_core + n;
+    __shared__ int s_cnt, s_left, s_min, s_max;
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    constexpr int kWaves = kPeelThreads / kWave;
     for (int v = threadIdx.x; v < n; v += kPeelThreads) {
         s_deg[v] = off[v + 1] - off[v];
         s_core[v] = -1;
-        s_fresh[v] = 0;
     }
     if (threadIdx.x == 0) {
         s_left = n;
@@ -149,30 +266,44 @@ __global__ __launch_bounds__(kPeelThreads) void kcore_peel(const int32_t* __rest
     while (true) {
         __syncthreads();
         if (s_left == 0) break;
-        if (threadIdx.x == 0) s_changed = 0;
+        if (threadIdx.x == 0) {
+            s_cnt = 0;
+            s_min = INT_MAX;
+        }
         __syncthreads();
-        // removals of this round: alive vertices whose remaining degree is <= level
-        int removed = 0;
-        for (int v = threadIdx.x; v < n; v += kPeelThreads) {
-            if (s_core[v] < 0 && s_deg[v] <= level) {
-                s_core[v] = static_cast<int16_t>(level);
-                s_fresh[v] = 1;
-                ++removed;
+        int low = INT_MAX;
+        for (int v0 = 0; v0 < n; v0 += kPeelThreads) {
+            const int v = v0 + threadIdx.x;
+            bool rm = false;
+            if (v < n && s_core[v] < 0) {
+                const int d = s_deg[v];
+                if (d <= level) {
+                    s_core[v] = static_cast<int16_t>(level);
+                    rm = true;
+                } else {
+                    low = min(low, d);
+                }
             }
+            const uint64_t b = ballot(rm);
+            int base = 0;
+            if (lane == 0 && b) base = atomicAdd(&s_cnt, __popcll(b));
+            base = __shfl(base, 0, kWave);
+            if (rm) s_list[base + lanes_below(b)] = static_cast<int16_t>(v);
         }
-        if (removed) {
-            atomicAdd(&s_changed, 1);
-            atomicSub(&s_left, removed);
-        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) low = min(low, __shfl_xor(low, d, kWave));
+        if (lane == 0 && low != INT_MAX) atomicMin(&s_min, low);
         __syncthreads();
-        if (!s_changed) {
-            ++level;  // nothing left at this level
+        const int nrem = s_cnt;
+        if (nrem == 0) {
+            level = max(level + 1, s_min);  // every alive vertex has a larger degree
             continue;
         }
-        for (int v = threadIdx.x; v < n; v += kPeelThreads) {
-            if (!s_fresh[v]) continue;
-            s_fresh[v] = 0;
-            for (int t = off[v]; t < off[v + 1]; ++t) {
+        if (threadIdx.x == 0) s_left -= nrem;
+        for (int i = wv; i < nrem; i += kWaves) {
+            const int f = s_list[i];
+            const int e = off[f + 1];
+            for (int t = off[f] + lane; t < e; t += kWave) {
                 const int u = adj[t];
                 if (u < 0 || u >= n) {  // not a vertex: reported, never followed
                     info[2] = 1;
@@ -191,6 +322,8 @@ __global__ __launch_bounds__(kPeelThreads) void kcore_peel(const int32_t* __rest
     __syncthreads();
     if (threadIdx.x == 0) info[0] = s_max;
 }
+
+size_t kcore_lds_bytes(int32_t n) { return static_cast<size_t>(n) * 8 + 16; }
 
 // members: vertices with the largest core number, ascending (one block).
 __global__ __launch_bounds__(kPeelThreads) void kcore_members(const int32_t* __restrict__ core, int32_t n,
@@ -225,6 +358,7 @@ __global__ __launch_bounds__(kPeelThreads) void kcore_members(const int32_t* __r
 
 struct GraphWs {
     uint64_t* keys;
+    int32_t* rank;
     float4* va;
     float4* vb;
     int32_t* deg;
@@ -236,6 +370,7 @@ struct GraphWs {
 GraphWs carve_graph(Carver& c, int64_t n_corr, int32_t n_tau) {
     GraphWs w;
     w.keys = c.take<uint64_t>(static_cast<size_t>(std::max<int64_t>(n_corr, 1)));
+    w.rank = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(n_corr, 1)));
     w.va = c.take<float4>(static_cast<size_t>(std::max(n_tau, 1)));
     w.vb = c.take<float4>(static_cast<size_t>(std::max(n_tau, 1)));
     w.deg = c.take<int32_t>(static_cast<size_t>(n_tau) + 1);
@@ -247,11 +382,15 @@ GraphWs carve_graph(Carver& c, int64_t n_corr, int32_t n_tau) {
 
 struct KcoreWs {
     int32_t* info;
+    int32_t* h;
+    int32_t* flag;
 };
 
-KcoreWs carve_kcore(Carver& c, int32_t) {
+KcoreWs carve_kcore(Carver& c, int32_t n) {
     KcoreWs w;
     w.info = c.take<int32_t>(3);  // max core, members, bad index flag
+    w.h = c.take<int32_t>(static_cast<size_t>(std::max(n, 1)));
+    w.flag = c.take<int32_t>(kHSweeps + 1);
     return w;
 }
 
@@ -285,7 +424,14 @@ kmg_status corr_graph(const float* src, int64_t src_stride, const float* tgt, in
     }
     ratio_keys<<<grid_cap(n_corr, kBlock), kBlock, 0, s>>>(d1, d2, n_corr, w.keys);
     KMG_TRY(launch_status());
-    rank_select<<<grid_cap(n_corr, kBlock), kBlock, 0, s>>>(w.keys, n_corr, n_tau, sel);
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.rank), 0u, static_cast<size_t>(n_corr), s));
+    {
+        const int64_t tiles = (n_corr + kBlock - 1) / kBlock;
+        const dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(std::min<int64_t>(tiles, kRankTiles)));
+        rank_count<<<grid, kBlock, 0, s>>>(w.keys, n_corr, w.rank);
+        KMG_TRY(launch_status());
+    }
+    rank_emit<<<grid_cap(n_corr, kBlock), kBlock, 0, s>>>(w.rank, n_corr, n_tau, sel);
     KMG_TRY(launch_status());
     KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.err), 0u, 1, s));
     gather_vertices<<<grid_cap(n, kBlock), kBlock, 0, s>>>(src, src_stride, tgt, tgt_stride, pairs, sel, n, w.va,
@@ -317,7 +463,26 @@ kmg_status max_kcore(const int32_t* off, const int32_t* adj, int32_t n, int32_t*
     *max_core_host = -1;
     if (n == 0) return KMG_OK;
     KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.info), 0u, 3, s));
-    kcore_peel<<<1, kPeelThreads, 0, s>>>(off, adj, n, core, w.info);
+    const size_t lds = kcore_lds_bytes(n);
+    if (lds > 65536) {
+        static const hipError_t raised = hipFuncSetAttribute(reinterpret_cast<const void*>(&kcore_peel),
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                             static_cast<int>(kcore_lds_bytes(kMaxKcore)));
+        if (raised != hipSuccess) return KMG_ERR_RANGE;  // this device cannot hold the graph's state on chip
+    }
+    {
+        const unsigned g = grid_cap(std::max<int64_t>(n, kHSweeps + 1), kBlock);
+        kcore_hinit<<<g, kBlock, 0, s>>>(off, n, w.h, w.flag);
+        KMG_TRY(launch_status());
+        const unsigned gw = grid_cap(n, kBlock / kWave);
+        for (int k = 0; k < kHSweeps; ++k) {
+            kcore_hsweep<<<gw, kBlock, 0, s>>>(off, adj, n, w.h, w.flag, k, w.info);
+            KMG_TRY(launch_status());
+        }
+    }
+    kcore_peel<<<1, kPeelThreads, lds, s>>>(off, adj, n, core, w.info, w.flag + kHSweeps);
+    KMG_TRY(launch_status());
+    kcore_hfinish<<<grid_cap(n, kBlock), kBlock, 0, s>>>(w.h, n, w.flag, core, w.info);
     KMG_TRY(launch_status());
     kcore_members<<<1, kPeelThreads, 0, s>>>(core, n, members, w.info);
     KMG_TRY(launch_status());

@@ -136,13 +136,32 @@ def test_kcore_closed_cases(K, name, n, edges):
     np.testing.assert_array_equal(kc.members.cpu().numpy(), pose.max_kcore(adj))
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(6))
 def test_kcore_random_graphs(K, seed):
     rng = np.random.default_rng(20 + seed)
-    n = [300, 1000, 3000, 8192][seed]
-    p = [0.3, 0.05, 0.01, 0.002][seed]
+    n = [300, 1000, 3000, 8192, 12000, 16384][seed]
+    p = [0.3, 0.05, 0.01, 0.002, 0.004, 0.001][seed]
     upper = np.triu(rng.random((n, n)) < p, 1)
     adj = upper | upper.T
     off, idx = csr_of(adj)
     kc = K.max_kcore(dev(off), dev(idx), n)
     np.testing.assert_array_equal(kc.core.cpu().numpy(), pose.core_numbers(adj))
+
+
+def test_kcore_slow_convergence_falls_back_to_peel(K):
+    """A long path with shuffled labels: the h-index sweeps lower one step of the path per
+    sweep, so they do not converge within their budget and the block peel decides."""
+    rng = np.random.default_rng(31)
+    n = 4000
+    order = rng.permutation(n)
+    path, clique = order[:-20], order[-20:]
+    adj = np.zeros((n, n), bool)
+    adj[path[:-1], path[1:]] = True
+    # a clique apart from the path, so that the maximum core is not the path
+    adj[np.ix_(clique, clique)] = True
+    adj[clique, clique] = False
+    adj |= adj.T
+    off, idx = csr_of(adj)
+    kc = K.max_kcore(dev(off), dev(idx), n)
+    np.testing.assert_array_equal(kc.core.cpu().numpy(), pose.core_numbers(adj))
+    np.testing.assert_array_equal(kc.members.cpu().numpy(), pose.max_kcore(adj))
