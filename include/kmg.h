@@ -294,6 +294,23 @@ typedef struct {
 } kmg_match_out;
 
 size_t kmg_batch_workspace_bytes(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins);
+
+/*
+ * kmg_batch_descriptors -- after a kmg_batch_run (on `stream`, in stream
+ * order), copies cloud `cloud`'s Faster-PFH descriptors (Eq. A5) out of the
+ * batch workspace, so that a caller may keep them resident and match them
+ * again (kmg_match with rows = j_idx gives the batch's correspondences):
+ *   fpfh   [out] float32[cap_rows * 3 * n_bins]: the cloud's kept-point rows
+ *                (row i = kept point i of that cloud; zero outside J).
+ *   j_idx  [out] int32[cap_j]: the cloud's J points as its own kept indices,
+ *                ascending.
+ * The counts table of the run gives the sizes (kept points, |J|); at most
+ * cap_rows rows and cap_j indices are written.  The batch arguments must be
+ * those of the run.  Enqueued on `stream`; no host synchronisation.
+ */
+kmg_status kmg_batch_descriptors(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins, int32_t cloud,
+                                 float* fpfh, int64_t cap_rows, int32_t* j_idx, int64_t cap_j, void* ws,
+                                 size_t ws_bytes, void* stream);
 kmg_status kmg_batch_upload(const kmg_cloud* clouds, const kmg_match_out* outs, int32_t n_pairs, int64_t raw_cap,
                             int64_t nnz_cap, void* ws, size_t ws_bytes, void* stream);
 kmg_status kmg_batch_run(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins, int32_t prec,

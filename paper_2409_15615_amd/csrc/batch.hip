@@ -72,7 +72,35 @@ __global__ __launch_bounds__(256) void batch_init(DevStatus* st, const CloudDev*
     run_fill_jobs(fills);
 }
 
+// Copies cloud `cloud`'s descriptor rows (kept-space rows, zero outside J) and
+// its J list as kept indices of that cloud, at most the given capacities.
+__global__ __launch_bounds__(256) void batch_export(const CloudState* __restrict__ cs, int cloud,
+                                                    const float* __restrict__ fpfh, const int32_t* __restrict__ jlist,
+                                                    int D, float* __restrict__ fpfh_out, int64_t cap_rows,
+                                                    int32_t* __restrict__ j_out, int64_t cap_j) {
+    const CloudState c = cs[cloud];
+    const int64_t rows = c.kept_cnt < cap_rows ? c.kept_cnt : cap_rows;
+    const int64_t nj = c.j_cnt < cap_j ? c.j_cnt : cap_j;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const float* src = fpfh + static_cast<int64_t>(c.kept_off) * D;
+    for (int64_t t = t0; t < rows * D; t += gs) fpfh_out[t] = src[t];
+    for (int64_t i = t0; i < nj; i += gs) j_out[i] = jlist[c.j_off + i] - c.kept_off;
+}
+
 }  // namespace
+
+kmg_status batch_export_cloud(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int cloud, float* fpfh_out,
+                              int64_t cap_rows, int32_t* j_out, int64_t cap_j, void* ws, size_t ws_bytes,
+                              hipStream_t s) {
+    Carver c(ws, ws_bytes);
+    BatchWs w = carve_batch(c, n_pairs, raw_cap, nnz_cap, H);
+    if (!c.fits()) return KMG_ERR_WORKSPACE;
+    const int64_t most = std::max<int64_t>(cap_rows * 3 * H, cap_j);
+    batch_export<<<static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>((most + 255) / 256, 1), 1024)), 256, 0,
+                   s>>>(w.cs, cloud, w.fpfh, w.jlist, 3 * H, fpfh_out, cap_rows, j_out, cap_j);
+    return launch_status();
+}
 
 size_t batch_ws(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H) {
     Carver c(nullptr, 0);

@@ -149,6 +149,18 @@ KMG_EXPORT kmg_status kmg_register_batch(const kmg_cloud* clouds, const kmg_matc
     return kmg_batch_run(n_pairs, raw_cap, nnz_cap, clouds[0].params.n_bins, prec, counts, ws, ws_bytes, stream);
 }
 
+KMG_EXPORT kmg_status kmg_batch_descriptors(int32_t n_pairs, int64_t raw_cap, int64_t nnz_cap, int32_t n_bins,
+                                            int32_t cloud, float* fpfh, int64_t cap_rows, int32_t* j_idx,
+                                            int64_t cap_j, void* ws, size_t ws_bytes, void* stream) {
+    if (!ws || n_pairs < 1 || 2 * n_pairs > kmg::kMaxClouds) return KMG_ERR_ARG;
+    if (raw_cap < 0 || raw_cap > INT32_MAX / 2 || nnz_cap < 0 || nnz_cap > INT32_MAX) return KMG_ERR_ARG;
+    if (n_bins < 1 || 3 * n_bins > kmg::kMaxMatchDim || cloud < 0 || cloud >= 2 * n_pairs) return KMG_ERR_ARG;
+    if (cap_rows < 0 || cap_j < 0 || (cap_rows > 0 && !fpfh) || (cap_j > 0 && !j_idx)) return KMG_ERR_ARG;
+    if (ws_bytes < kmg::batch_ws(n_pairs, raw_cap, nnz_cap, n_bins)) return KMG_ERR_WORKSPACE;
+    return kmg::batch_export_cloud(n_pairs, raw_cap, nnz_cap, n_bins, cloud, fpfh, cap_rows, j_idx, cap_j, ws,
+                                   ws_bytes, as_stream(stream));
+}
+
 KMG_EXPORT kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, const float* desc_q,
                      const int32_t* rows_q, int64_t nq, int32_t dim, int32_t prec, int32_t* pairs, float* d1,
                      float* d2, int64_t cap, int64_t* n_pairs, int64_t* n_fallback, void* ws, size_t ws_bytes,

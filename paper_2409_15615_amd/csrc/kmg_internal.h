@@ -432,5 +432,8 @@ kmg_status batch_upload(const kmg_cloud* clouds, const kmg_match_out* outs, int 
                         int64_t nnz_cap, int H, void* ws, size_t ws_bytes, hipStream_t s);
 kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int prec, int64_t* counts, void* ws,
                      size_t ws_bytes, hipStream_t s);
+kmg_status batch_export_cloud(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int cloud, float* fpfh_out,
+                              int64_t cap_rows, int32_t* j_out, int64_t cap_j, void* ws, size_t ws_bytes,
+                              hipStream_t s);
 
 }  // namespace kmg

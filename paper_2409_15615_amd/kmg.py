@@ -97,6 +97,8 @@ def load():
     lib.kmg_batch_upload.restype = i32
     lib.kmg_batch_run.argtypes = [i32, i64, i64, i32, i32, vp, vp, sz, vp]
     lib.kmg_batch_run.restype = i32
+    lib.kmg_batch_descriptors.argtypes = [i32, i64, i64, i32, i32, vp, i64, vp, i64, vp, sz, vp]
+    lib.kmg_batch_descriptors.restype = i32
     lib.kmg_register_batch.argtypes = [cp, op, i32, i64, i64, i32, vp, vp, sz, vp]
     lib.kmg_register_batch.restype = i32
     i32p = C.POINTER(C.c_int32)
@@ -519,6 +521,18 @@ class Batch:
 
     def nnz(self):
         return int(self.counts[0, 7].item())
+
+    def descriptors(self, cloud, n_kept, n_j):
+        """kmg_batch_descriptors: cloud `cloud`'s kept-space FPFH rows (n_kept, 3H) and
+        its J list (own kept indices), copied out of the workspace on the current stream."""
+        lib = load()
+        D = 3 * self.n_bins
+        fp = torch.empty((max(n_kept, 1), D), dtype=torch.float32, device=self.device)
+        jj = torch.empty(max(n_j, 1), dtype=torch.int32, device=self.device)
+        _raise("kmg_batch_descriptors", lib.kmg_batch_descriptors(
+            self.n_active, self.raw_cap, self.nnz_cap, self.n_bins, int(cloud), _ptr(fp), int(n_kept), _ptr(jj),
+            int(n_j), _ptr(self.ws), self.ws.numel(), _stream()))
+        return fp[:n_kept], jj[:n_j]
 
 
 def register_batch(clouds, prec="fp32", nnz_per_point=48, out_cap=None):
