@@ -136,6 +136,41 @@ int32_t kmg_timing_work(int64_t* work, int32_t n);
 const char* kmg_stage_name(int32_t stage);
 
 /*
+ * Launch tuning.  Work-distribution choices of the hot-path kernels, picked
+ * per workload by the autotuner in paper_2409_15615_amd/tune.py (every value
+ * gives bit-identical outputs: they change how work is scheduled, never what
+ * is computed or the order of any floating-point sum).  Process-wide; read
+ * when a call enqueues its kernels, so a captured hipGraph keeps the shapes
+ * in force at capture time.  Not synchronised with concurrent calls.
+ *   search_waves    waves per block of the radius count and fill passes
+ *                   (Eq. A1): 2, 4 (default) or 8.
+ *   count_queries   queries per wavefront in the count pass: 1, 2 (default)
+ *                   or 4.
+ *   spfh_pair_mean  mean neighbour-list length up to which the SPFH pass
+ *                   (Eq. A2-A4) takes two points per wavefront (default 24;
+ *                   0 = never, 8192 = always).
+ *   fpfh_rows       SPFH rows in flight per lane in the FPFH sum (Eq. A5):
+ *                   4, 8 (default) or 16.
+ *   band_tile       partner chunks per distance tile of matching (a length
+ *                   of the planner's candidate set: 1..64, then four per
+ *                   octave up to 4096), used whenever its tiles fit; 0
+ *                   (default) = the planner's modelled choice.
+ *   reserved        must be 0.
+ * kmg_set_tuning(NULL) restores the defaults; unsupported values give
+ * KMG_ERR_ARG and leave the tuning unchanged.
+ */
+typedef struct {
+    int32_t search_waves;
+    int32_t count_queries;
+    int32_t spfh_pair_mean;
+    int32_t fpfh_rows;
+    int32_t band_tile;
+    int32_t reserved[3];
+} kmg_tuning;
+kmg_status kmg_set_tuning(const kmg_tuning* t);
+kmg_status kmg_get_tuning(kmg_tuning* t);
+
+/*
  * kmg_voxelize -- voxel downsampling of a raw cloud (Section III-A: the
  * method takes clouds voxelized with voxel size v).
  *

@@ -9,14 +9,17 @@
 // them; a feature set that lies within a guard band of a bin edge or of an
 // ill-conditioned frame, or near the a/b selection tie with the two role
 // assignments binning differently, is recomputed in FP64 with the operation
-// order of the plain definition, so the bins equal the FP64 definition's.  Bin counts are formed with one ballot + popcount per
-// (feature, bin): no atomics, deterministic.  SPFH values 100 * c / P_q are
-// kept in FP64 for the FPFH pass.
+// order of the plain definition, so the bins equal the FP64 definition's.
+// Bin counts are formed with one ballot + popcount per (feature, bin): no
+// atomics, deterministic.  The FPFH pass keeps the counts (uint16, 66 bytes
+// per row of 33) and 100 / P_q per point, not the FP64 SPFH values: the
+// gather of a neighbour's row moves a quarter of the bytes.
 //
 // FPFH: one wavefront per point q in J; lanes first compute the weights
-// 1 / ||a_k - a_q|| of a chunk of neighbours (FP64) and compact them into
-// LDS, then each lane owns descriptor bins and accumulates
-// (1 / w_k) * SPFH(k) over the chunk in ascending k, in FP64.
+// (1 / ||a_k - a_q||) (100 / P_k) of a chunk of neighbours (FP64) and compact
+// them into LDS, then each lane owns descriptor bins and accumulates weight x
+// count over the chunk in ascending k, in FP64 (the term (1 / w_k) SPFH(k) of
+// Eq. A5); the query's own SPFH value is 100 c / P_q, divided exactly.
 #include <math.h>
 
 #include "kmg_device.h"
@@ -28,7 +31,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kBatch = 8;          // SPFH rows loaded together in the FPFH sum
-constexpr int kBatchNarrow = 8;    // the same for rows of at most 64 values
 
 struct V3f {
     float x, y, z;
@@ -156,6 +158,11 @@ __device__ __attribute__((noinline)) BinsF64 bins_f64(V3f pq32, V3f nq32, V3f pk
     return r;
 }
 
+// SPFH value of a bin (Eq. A4): 100 * count / P_q in FP64, 0 when P_q = 0.
+__device__ __forceinline__ double spfh_value(int count, int P) {
+    return P > 0 ? (100.0 * static_cast<double>(count)) / static_cast<double>(P) : 0.0;
+}
+
 __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
     return kept_cloud ? kept_cloud[q] : 0;
 }
@@ -168,7 +175,7 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
 // The threshold is measured: the 64-pair batch (mean 22.5) runs 1.5x faster
 // in pairs, the LiDAR pair (mean 29, but a long tail of structure points next
 // to scattered outliers with a few neighbours) 8% slower.
-constexpr int kHalfListMean = 24;
+constexpr int kHalfListMean = 24;  // the default of tuning().spfh_pair_mean
 
 __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
                                                      int64_t stride, const int32_t* __restrict__ kept_cloud,
@@ -176,15 +183,16 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
                                                      int64_t nrm_stride, const uint8_t* __restrict__ flags,
                                                      const int32_t* __restrict__ off,
                                                      const int32_t* __restrict__ nbr, int H,
-                                                     double* __restrict__ spfh64, float* __restrict__ spfh_out,
-                                                     int32_t* __restrict__ Pq, int32_t* __restrict__ jflag,
-                                                     DevStatus* st) {
+                                                     uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
+                                                     int32_t* __restrict__ Pq, double* __restrict__ inv100,
+                                                     int32_t* __restrict__ jflag,
+                                                     int pair_mean, DevStatus* st) {
     constexpr int kHalf = kWave / 2;
     const int lane = lane_id();
     const int hf = lane / kHalf, hl = lane % kHalf, sh = kHalf * hf;
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz > kHalfListMean * m) return;        // long lists: spfh_kernel
+    if (st->nnz > pair_mean * m) return;            // long lists: spfh_kernel
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
     uint32_t n64 = 0, nedge = 0;
@@ -236,14 +244,15 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
             }
         }
         if (!live) continue;
-        double* row = spfh64 + q * D;
+        uint16_t* row = cnt16 + q * D;
         if (!has_b) {
             for (int t = hl; t < D; t += kHalf) {
-                row[t] = 0.0;
+                row[t] = 0;
                 if (spfh_out) spfh_out[q * D + t] = 0.0f;
             }
             if (hl == 0) {
                 Pq[q] = 0;
+                inv100[q] = 0.0;
                 jflag[q] = 0;
             }
             continue;
@@ -252,13 +261,13 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
         if (hl < H) {
             const int cs[3] = {c0, c1, c2};
             for (int l = 0; l < 3; ++l) {
-                const double val = (P > 0) ? (100.0 * static_cast<double>(cs[l])) / static_cast<double>(P) : 0.0;
-                row[l * H + hl] = val;
-                if (spfh_out) spfh_out[q * D + l * H + hl] = static_cast<float>(val);
+                row[l * H + hl] = static_cast<uint16_t>(cs[l]);
+                if (spfh_out) spfh_out[q * D + l * H + hl] = static_cast<float>(spfh_value(cs[l], P));
             }
         }
         if (hl == 0) {
             Pq[q] = P;
+            inv100[q] = P > 0 ? 100.0 / static_cast<double>(P) : 0.0;
             jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_j) ? 1 : 0;
         }
     }
@@ -277,24 +286,26 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                                                       int64_t nrm_stride, const uint8_t* __restrict__ flags,
                                                       const int32_t* __restrict__ off,
                                                       const int32_t* __restrict__ nbr, int H,
-                                                      double* __restrict__ spfh64, float* __restrict__ spfh_out,
-                                                      int32_t* __restrict__ Pq, int32_t* __restrict__ jflag,
-                                                      DevStatus* st) {
+                                                      uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
+                                                      int32_t* __restrict__ Pq, double* __restrict__ inv100,
+                                                     int32_t* __restrict__ jflag,
+                                                      int pair_mean, DevStatus* st) {
     const int lane = lane_id();
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz <= kHalfListMean * m) return;       // short lists: spfh_pairs
+    if (st->nnz <= pair_mean * m) return;           // short lists: spfh_pairs
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
     for (int64_t q = global_wave(); q < m; q += wave_count()) {
-        double* row = spfh64 + q * D;
+        uint16_t* row = cnt16 + q * D;
         if (!(flags[q] & 1)) {
             for (int t = lane; t < D; t += kWave) {
-                row[t] = 0.0;
+                row[t] = 0;
                 if (spfh_out) spfh_out[q * D + t] = 0.0f;
             }
             if (lane == 0) {
                 Pq[q] = 0;
+                inv100[q] = 0.0;
                 jflag[q] = 0;
             }
             continue;
@@ -344,13 +355,13 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
         if (lane < H) {
             const int cs[3] = {c0, c1, c2};
             for (int l = 0; l < 3; ++l) {
-                const double val = (P > 0) ? (100.0 * static_cast<double>(cs[l])) / static_cast<double>(P) : 0.0;
-                row[l * H + lane] = val;
-                if (spfh_out) spfh_out[q * D + l * H + lane] = static_cast<float>(val);
+                row[l * H + lane] = static_cast<uint16_t>(cs[l]);
+                if (spfh_out) spfh_out[q * D + l * H + lane] = static_cast<float>(spfh_value(cs[l], P));
             }
         }
         if (lane == 0) {
             Pq[q] = P;
+            inv100[q] = P > 0 ? 100.0 / static_cast<double>(P) : 0.0;
             jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_j) ? 1 : 0;
             if (n64) atomicAdd(&st->feat_fp64, n64);
             if (nedge) atomicAdd(&st->feat_edge, nedge);
@@ -363,14 +374,16 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
 // and l + 32.  The neighbours of a round of 32 are compacted in order into
 // the half's LDS list and their SPFH rows summed in that order, term by term
 // the sum fpfh_kernel forms.  The rows of the other kept points are zeroed.
+template <int kBatchNarrow>
 __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ xyz, int64_t stride, int64_t m_cap,
                                                      const uint8_t* __restrict__ flags,
                                                      const int32_t* __restrict__ jflag,
                                                      const int32_t* __restrict__ j_list,
                                                      const int32_t* __restrict__ off,
                                                      const int32_t* __restrict__ nbr, int H,
-                                                     const double* __restrict__ spfh64,
-                                                     const int32_t* __restrict__ Pq, float* __restrict__ fpfh,
+                                                     const uint16_t* __restrict__ cnt16,
+                                                     const int32_t* __restrict__ Pq,
+                                                     const double* __restrict__ inv100, float* __restrict__ fpfh,
                                                      const DevStatus* st) {
 #pragma clang fp contract(off)
     constexpr int kHalf = kWave / 2;
@@ -413,7 +426,8 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
                 k = nbr[b + base + hl];
                 const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
                 use = (k != q) && (flags[k] & 1);
-                w = 1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz));
+                // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k])
+                w = use ? (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k] : 0.0;
             }
             const uint32_t bm = static_cast<uint32_t>(ballot(use) >> sh);
             __builtin_amdgcn_wave_barrier();
@@ -430,9 +444,9 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
 #pragma unroll
                 for (int u = 0; u < kBatchNarrow; ++u) {
                     const int64_t r = j + u < nuse ? s_k[wv][hf][j + u] : q;
-                    const double* sk = spfh64 + r * D;
-                    v0[u] = sk[lb0];
-                    v1[u] = D > kHalf ? sk[lb1] : 0.0;
+                    const uint16_t* sk = cnt16 + r * D;
+                    v0[u] = static_cast<double>(sk[lb0]);
+                    v1[u] = D > kHalf ? static_cast<double>(sk[lb1]) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < kBatchNarrow; ++u) {
@@ -448,28 +462,30 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
         if (!live) continue;
         float* out = fpfh + q * D;
         const int P = Pq[q];
-        const double* sq = spfh64 + q * D;
+        const uint16_t* sq = cnt16 + q * D;
         if (P == 0) {
-            if (hl < D) out[hl] = static_cast<float>(sq[hl]);
-            if (hl + kHalf < D) out[hl + kHalf] = static_cast<float>(sq[hl + kHalf]);
+            if (hl < D) out[hl] = 0.0f;
+            if (hl + kHalf < D) out[hl + kHalf] = 0.0f;
             continue;
         }
         const double inv = 1.0 / static_cast<double>(P);
-        if (hl < D) out[hl] = static_cast<float>(sq[hl] + inv * acc0);
-        if (hl + kHalf < D) out[hl + kHalf] = static_cast<float>(sq[hl + kHalf] + inv * acc1);
+        if (hl < D) out[hl] = static_cast<float>(spfh_value(sq[hl], P) + inv * acc0);
+        if (hl + kHalf < D) out[hl + kHalf] = static_cast<float>(spfh_value(sq[hl + kHalf], P) + inv * acc1);
     }
 }
 
 // One wavefront per point of the J list (j_list[0 .. n_j), from the J scan);
 // the rows of the other kept points are zeroed by a grid-stride pass first.
+template <int kBatchNarrow>
 __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ xyz, int64_t stride, int64_t m_cap,
                                                       const uint8_t* __restrict__ flags,
                                                       const int32_t* __restrict__ jflag,
                                                       const int32_t* __restrict__ j_list,
                                                       const int32_t* __restrict__ off,
                                                       const int32_t* __restrict__ nbr, int H,
-                                                      const double* __restrict__ spfh64,
-                                                      const int32_t* __restrict__ Pq, float* __restrict__ fpfh,
+                                                      const uint16_t* __restrict__ cnt16,
+                                                      const int32_t* __restrict__ Pq,
+                                                     const double* __restrict__ inv100, float* __restrict__ fpfh,
                                                       const DevStatus* st) {
 #pragma clang fp contract(off)
     __shared__ int32_t s_k[kWaves][kWave];
@@ -498,7 +514,8 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
             const int k = nbr[t];
             const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
             const bool use = (base + lane < e) && (k != q) && (flags[k] & 1);
-            const double w = 1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz));
+            // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k])
+            const double w = use ? (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k] : 0.0;
             const uint64_t bm = ballot(use);
             __builtin_amdgcn_wave_barrier();
             if (use) {
@@ -516,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
                     double v0[kBatchNarrow];
 #pragma unroll
                     for (int u = 0; u < kBatchNarrow; ++u)
-                        v0[u] = spfh64[static_cast<int64_t>(s_k[wv][j + u]) * D + lb0];
+                        v0[u] = static_cast<double>(cnt16[static_cast<int64_t>(s_k[wv][j + u]) * D + lb0]);
 #pragma unroll
                     for (int u = 0; u < kBatchNarrow; ++u) acc0 = acc0 + s_w[wv][j + u] * v0[u];
                 }
@@ -525,9 +542,9 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
                 double v0[kBatch], v1[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j + u]) * D;
-                    v0[u] = sk[lb0];
-                    v1[u] = D > kWave ? sk[lb1] : 0.0;
+                    const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[wv][j + u]) * D;
+                    v0[u] = static_cast<double>(sk[lb0]);
+                    v1[u] = D > kWave ? static_cast<double>(sk[lb1]) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
@@ -538,21 +555,56 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
             }
             for (; j < nuse; ++j) {
                 const double wj = s_w[wv][j];
-                const double* sk = spfh64 + static_cast<int64_t>(s_k[wv][j]) * D;
-                acc0 = acc0 + wj * sk[lb0];
-                if (D > kWave) acc1 = acc1 + wj * sk[lb1];
+                const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[wv][j]) * D;
+                acc0 = acc0 + wj * static_cast<double>(sk[lb0]);
+                if (D > kWave) acc1 = acc1 + wj * static_cast<double>(sk[lb1]);
             }
         }
         const int P = Pq[q];
-        const double* sq = spfh64 + q * D;
+        const uint16_t* sq = cnt16 + q * D;
         if (P == 0) {
-            if (lane < D) out[lane] = static_cast<float>(sq[lane]);
-            if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave]);
+            if (lane < D) out[lane] = 0.0f;
+            if (lane + kWave < D) out[lane + kWave] = 0.0f;
             continue;
         }
         const double inv = 1.0 / static_cast<double>(P);
-        if (lane < D) out[lane] = static_cast<float>(sq[lane] + inv * acc0);
-        if (lane + kWave < D) out[lane + kWave] = static_cast<float>(sq[lane + kWave] + inv * acc1);
+        if (lane < D) out[lane] = static_cast<float>(spfh_value(sq[lane], P) + inv * acc0);
+        if (lane + kWave < D) out[lane + kWave] = static_cast<float>(spfh_value(sq[lane + kWave], P) + inv * acc1);
+    }
+}
+
+// The FPFH launch with kRows SPFH rows in flight per lane (4, 8 or 16; the
+// accumulation order, ascending neighbours, is the same for every choice).
+template <bool kPairs, int kRows>
+kmg_status fpfh_as(const float* xyz, int64_t stride, int64_t m_cap, const uint8_t* flags, const int32_t* jflag,
+                   const int32_t* j_idx, const int32_t* off, const int32_t* nbr, int H, const uint16_t* cnt16,
+                   const int32_t* Pq, const double* inv100, float* fpfh_out, const DevStatus* st, hipStream_t s) {
+    if (kPairs) {
+        fpfh_pairs<kRows><<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, jflag, j_idx,
+                                                                              off, nbr, H, cnt16, Pq, inv100, fpfh_out,
+                                                                              st);
+    } else {
+        fpfh_kernel<kRows><<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, jflag, j_idx, off,
+                                                                     nbr, H, cnt16, Pq, inv100, fpfh_out, st);
+    }
+    return launch_status();
+}
+
+template <bool kPairs>
+kmg_status launch_fpfh(int rows, const float* xyz, int64_t stride, int64_t m_cap, const uint8_t* flags,
+                       const int32_t* jflag, const int32_t* j_idx, const int32_t* off, const int32_t* nbr, int H,
+                       const uint16_t* cnt16, const int32_t* Pq, const double* inv100, float* fpfh_out,
+                       const DevStatus* st, hipStream_t s) {
+    switch (rows) {
+        case 4:
+            return fpfh_as<kPairs, 4>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+                                      fpfh_out, st, s);
+        case 16:
+            return fpfh_as<kPairs, 16>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+                                       fpfh_out, st, s);
+        default:
+            return fpfh_as<kPairs, 8>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+                                      fpfh_out, st, s);
     }
 }
 
@@ -611,7 +663,8 @@ __global__ void cloud_j_ranges(int n_clouds, int64_t m_cap, const int32_t* __res
 FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
     FeatWs w;
     const size_t mc = static_cast<size_t>(std::max<int64_t>(m_cap, 1));
-    w.spfh64 = c.take<double>(mc * 3 * H);
+    w.cnt16 = c.take<uint16_t>(mc * 3 * H);
+    w.inv100 = c.take<double>(mc);
     w.Pq = c.take<int32_t>(mc);
     w.jflag = c.take<int32_t>(mc);
     w.pos = c.take<int32_t>(mc);
@@ -624,16 +677,19 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
                       const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s,
                       bool cleared) {
     if (!cleared)
-        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)), s));
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)),
+                         s));
     if (m_cap > 0) {
         StageScope sc(ST_SPFH, s);
+        const int pair_mean = tuning().spfh_pair_mean;
         spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
-                                                              flags, off, nbr, H, w.spfh64, spfh_out, w.Pq, w.jflag,
-                                                              st);
+                                                              flags, off, nbr, H, w.cnt16, spfh_out, w.Pq, w.inv100,
+                                                              w.jflag, pair_mean, st);
         KMG_TRY(launch_status());
         spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
-                                                                       nrm_stride, flags, off, nbr, H, w.spfh64,
-                                                                       spfh_out, w.Pq, w.jflag, st);
+                                                                       nrm_stride, flags, off, nbr, H, w.cnt16,
+                                                                       spfh_out, w.Pq, w.inv100, w.jflag, pair_mean,
+                                                                       st);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
@@ -660,13 +716,12 @@ kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_
     if (m_cap > 0) {
         StageScope sc(ST_FPFH, s);
         if (3 * H <= kWave) {
-            fpfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, j_idx,
-                                                                           off, nbr, H, w.spfh64, w.Pq, fpfh_out, st);
+            KMG_TRY(launch_fpfh<true>(tuning().fpfh_rows, xyz, stride, m_cap, flags, w.jflag, j_idx, off, nbr, H,
+                                      w.cnt16, w.Pq, w.inv100, fpfh_out, st, s));
         } else {
-            fpfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, w.jflag, j_idx, off,
-                                                                  nbr, H, w.spfh64, w.Pq, fpfh_out, st);
+            KMG_TRY(launch_fpfh<false>(tuning().fpfh_rows, xyz, stride, m_cap, flags, w.jflag, j_idx, off, nbr, H,
+                                       w.cnt16, w.Pq, w.inv100, fpfh_out, st, s));
         }
-        KMG_TRY(launch_status());
     }
     return KMG_OK;
 }

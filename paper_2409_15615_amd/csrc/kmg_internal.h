@@ -304,7 +304,8 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
 
 // ---- features.hip ---------------------------------------------------------
 struct FeatWs {
-    double* spfh64;
+    uint16_t* cnt16;  // SPFH bin counts (Eq. A4 numerators), m x 3H
+    double* inv100;   // 100 / P_q (0 when P_q = 0)
     int32_t* Pq;
     int32_t* jflag;
     int32_t* pos;
@@ -425,6 +426,21 @@ size_t match_ws(int64_t np, int64_t nq, int dim);
 kmg_status match(const float* dp, const int32_t* rp, int64_t np, const float* dq, const int32_t* rq, int64_t nq,
                  int dim, int prec, int32_t* pairs, float* d1, float* d2, int64_t cap, int64_t* n_pairs_host,
                  int64_t* n_fallback_host, void* ws, size_t ws_bytes, hipStream_t s);
+
+// ---- tuning.hip -----------------------------------------------------------
+// Launch shapes that change how work is scheduled, never what is computed or in
+// which order floating-point terms are summed (every choice gives bit-identical
+// outputs); set process-wide by kmg_set_tuning, read at launch time.
+struct Tuning {
+    int search_waves = 4;     // waves per block of the radius count and fill passes (2, 4, 8)
+    int count_queries = 2;    // queries per wavefront in the count pass (1, 2, 4)
+    int spfh_pair_mean = 24;  // mean list length up to which SPFH takes two points per wavefront
+    int fpfh_rows = 8;        // SPFH rows in flight per lane in the FPFH sum (4, 8, 16)
+    int band_tile = 0;        // partner chunks per band tile; 0 = the tile-length model's choice
+};
+const Tuning& tuning();
+bool set_tuning(const Tuning& t);
+bool band_tile_candidate(int T);  // T is one of the band planner's candidate lengths
 
 // ---- batch.hip ------------------------------------------------------------
 size_t batch_ws(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H);

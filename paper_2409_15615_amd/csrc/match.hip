@@ -2051,6 +2051,16 @@ __host__ __device__ constexpr int tile_len_cand(int i) {
 }
 static_assert(tile_len_cand(kTileCands - 1) == 4096, "candidate lengths end at 4096");
 
+}  // namespace
+
+bool band_tile_candidate(int T) {
+    for (int i = 0; i < kTileCands; ++i)
+        if (tile_len_cand(i) == T) return true;
+    return false;
+}
+
+namespace {
+
 // Threads per candidate length when the plan counts tiles: 88 x 11 threads,
 // thread (i, k) sums ceil(L_w / T_i) over the waves w = k mod 11.  Beyond
 // kExactTileWaves waves (many rounds of tiles, where the count matters less
@@ -2067,7 +2077,7 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
                                                           const int32_t* __restrict__ wave_c0,
                                                           const int32_t* __restrict__ wave_len,
                                                           int32_t* __restrict__ wave_tile, int4* __restrict__ tinfo,
-                                                          int64_t tile_cap, DevStatus* st) {
+                                                          int64_t tile_cap, int forced_T, DevStatus* st) {
     __shared__ int64_t smem[kPlanThreads / kWave];
     __shared__ int s_cnt[kTileCands][kCandThreads];  // tiles of each candidate length, per stripe of waves
     __shared__ int s_lmax[kPlanThreads / kWave];
@@ -2128,6 +2138,7 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
                         ? len + kTileOverhead
                         : (static_cast<double>(tot_len) + static_cast<double>(tiles) * kTileOverhead) / kBandSlots +
                               0.5 * (len + kTileOverhead);
+                if (Ti == forced_T) t = -1.0;  // a length fixed by the tuning wins whenever its tiles fit
             }
             if (t < t_best) {
                 t_best = t;
@@ -2679,7 +2690,7 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
                                                                            w.skey, w.wave_c0, w.wave_len, st);
         KMG_TRY(launch_status());
         band_plan<<<1, kPlanThreads, 0, s>>>(w.plan, n_sets, w.wave_c0, w.wave_len, w.wave_tile, w.tinfo, w.tile_cap,
-                                             st);
+                                             tuning().band_tile, st);
         KMG_TRY(launch_status());
     }
     {

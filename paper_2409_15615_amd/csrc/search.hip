@@ -22,7 +22,6 @@ namespace kmg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSearchWaves = 4;  // waves (queries) per block in the count and fill passes
 constexpr int kNormalLanes = 4;  // lanes per point in the normal estimation
 
 struct Grid {
@@ -254,10 +253,9 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
 // of the 27, the group scans the cell counts, and the group's lanes test its
 // query's candidates G at a time; the memory round trips of the wavefront's
 // queries overlap.  Queries kCountGroups pw .. of the cell-sorted order go to
-// wave pw; writes |N(q)| to deg[q].
-constexpr int kCountGroups = 2;
-
-template <int kWaves>
+// wave pw; writes |N(q)| to deg[q].  kCountGroups (1, 2 or 4) and the waves
+// per block are launch choices (tuning).
+template <int kWaves, int kCountGroups>
 __global__ __launch_bounds__(kWaves* kWave) void radius_count2(const CloudDev* __restrict__ cl, Grid g,
                                                                const int32_t* __restrict__ kept_cloud,
                                                                int64_t m_cap, int32_t* __restrict__ deg, int use_rn,
@@ -616,6 +614,50 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
     }
 }
 
+template <int kWaves, int kGroups>
+kmg_status count_as(const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap, int32_t* deg, int use_rn,
+                    DevStatus* st, hipStream_t s) {
+    radius_count2<kWaves, kGroups><<<grid_cap((m_cap + kGroups - 1) / kGroups, kWaves), kWaves * kWave, 0, s>>>(
+        cl, g, kept_cloud, m_cap, deg, use_rn, st);
+    return launch_status();
+}
+
+template <int kWaves>
+kmg_status count_waves(int groups, const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap,
+                       int32_t* deg, int use_rn, DevStatus* st, hipStream_t s) {
+    switch (groups) {
+        case 1: return count_as<kWaves, 1>(cl, g, kept_cloud, m_cap, deg, use_rn, st, s);
+        case 4: return count_as<kWaves, 4>(cl, g, kept_cloud, m_cap, deg, use_rn, st, s);
+        default: return count_as<kWaves, 2>(cl, g, kept_cloud, m_cap, deg, use_rn, st, s);
+    }
+}
+
+kmg_status launch_count(int waves, int groups, const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap,
+                        int32_t* deg, int use_rn, DevStatus* st, hipStream_t s) {
+    switch (waves) {
+        case 2: return count_waves<2>(groups, cl, g, kept_cloud, m_cap, deg, use_rn, st, s);
+        case 8: return count_waves<8>(groups, cl, g, kept_cloud, m_cap, deg, use_rn, st, s);
+        default: return count_waves<4>(groups, cl, g, kept_cloud, m_cap, deg, use_rn, st, s);
+    }
+}
+
+template <int kWaves>
+kmg_status fill_as(const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap, const int32_t* off,
+                   int32_t* nbr, int64_t nbr_cap, int use_rn, DevStatus* st, hipStream_t s) {
+    radius_fill2<kWaves><<<grid_cap((m_cap + 1) / 2, kWaves), kWaves * kWave, 0, s>>>(cl, g, kept_cloud, m_cap, off,
+                                                                                     nbr, nbr_cap, use_rn, st);
+    return launch_status();
+}
+
+kmg_status launch_fill(int waves, const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap,
+                       const int32_t* off, int32_t* nbr, int64_t nbr_cap, int use_rn, DevStatus* st, hipStream_t s) {
+    switch (waves) {
+        case 2: return fill_as<2>(cl, g, kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st, s);
+        case 8: return fill_as<8>(cl, g, kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st, s);
+        default: return fill_as<4>(cl, g, kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st, s);
+    }
+}
+
 Grid grid_of(const SearchWs& w) {
     Grid g;
     g.pts = w.pts;
@@ -668,10 +710,9 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
         StageScope sc(ST_SEARCH_COUNT, s);
         if (!cleared) KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
         if (m_cap > 0) {
-            radius_count2<kSearchWaves><<<grid_cap((m_cap + kCountGroups - 1) / kCountGroups, kSearchWaves),
-                                         kSearchWaves * kWave, 0, s>>>(
-                cl, grid_of(w), kept_cloud, m_cap, w.deg, use_rn, st);
-            KMG_TRY(launch_status());
+            const Tuning& t = tuning();
+            KMG_TRY(launch_count(t.search_waves, t.count_queries, cl, grid_of(w), kept_cloud, m_cap, w.deg, use_rn,
+                                 st, s));
         }
         KMG_TRY(scan_exclusive(w.deg, off, m_cap + 1, &st->nnz, w.scan_tmp, s));
     }
@@ -685,9 +726,8 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
     if (m_cap <= 0) return KMG_OK;
     {
         StageScope sc(ST_SEARCH_FILL, s);
-        radius_fill2<kSearchWaves><<<grid_cap((m_cap + 1) / 2, kSearchWaves), kSearchWaves * kWave, 0, s>>>(
-            cl, grid_of(w), kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st);
-        KMG_TRY(launch_status());
+        KMG_TRY(launch_fill(tuning().search_waves, cl, grid_of(w), kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st,
+                            s));
         if (dense_pass) {
             radius_search<true, kMaxDegree, 1><<<grid_cap(m_cap, 1), kWave, 0, s>>>(
                 cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 1, use_rn, st);

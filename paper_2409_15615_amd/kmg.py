@@ -46,6 +46,20 @@ class KmgParams(C.Structure):
 MODE_FASTER_PFH, MODE_CLASSIC_FPFH = 0, 1
 
 
+class KmgTuning(C.Structure):
+    _fields_ = [
+        ("search_waves", C.c_int32),
+        ("count_queries", C.c_int32),
+        ("spfh_pair_mean", C.c_int32),
+        ("fpfh_rows", C.c_int32),
+        ("band_tile", C.c_int32),
+        ("reserved", C.c_int32 * 3),
+    ]
+
+
+TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile")
+
+
 class KmgCloud(C.Structure):
     _fields_ = [("xyz", C.c_void_p), ("n", C.c_int64), ("params", KmgParams)]
 
@@ -107,6 +121,10 @@ def load():
     lib.kmg_corr_graph.restype = i32
     lib.kmg_max_kcore.argtypes = [vp, vp, i32, vp, vp, i32p, i32p, vp, sz, vp]
     lib.kmg_max_kcore.restype = i32
+    lib.kmg_set_tuning.argtypes = [C.POINTER(KmgTuning)]
+    lib.kmg_set_tuning.restype = i32
+    lib.kmg_get_tuning.argtypes = [C.POINTER(KmgTuning)]
+    lib.kmg_get_tuning.restype = i32
     lib.kmg_timing_enable.argtypes = [i32]
     lib.kmg_timing_enable.restype = i32
     lib.kmg_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
@@ -117,6 +135,29 @@ def load():
     lib.kmg_stage_name.restype = C.c_char_p
     _lib = lib
     return lib
+
+
+def get_tuning() -> dict:
+    """kmg_get_tuning as a dict of the tunable fields."""
+    t = KmgTuning()
+    _raise("kmg_get_tuning", load().kmg_get_tuning(C.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+def set_tuning(values=None):
+    """kmg_set_tuning: fields not given keep their defaults; None restores all defaults."""
+    lib = load()
+    if values is None:
+        _raise("kmg_set_tuning", lib.kmg_set_tuning(None))
+        return
+    _raise("kmg_set_tuning", lib.kmg_set_tuning(None))
+    t = KmgTuning()
+    lib.kmg_get_tuning(C.byref(t))
+    for f, v in values.items():
+        if f not in TUNING_FIELDS:
+            raise ValueError(f"unknown tuning field {f}")
+        setattr(t, f, int(v))
+    _raise("kmg_set_tuning", lib.kmg_set_tuning(C.byref(t)))
 
 
 def make_params(voxel, r_normal, r_fpfh, tau_num=3, tau_lin=0.99, n_bins=11, viewpoint=(0.0, 0.0, 0.0),

@@ -1,0 +1,105 @@
+"""Autotune invariance: every launch shape of kmg_set_tuning gives bit-identical
+outputs (kept sets, neighbour lists, flags, normals, SPFH / FPFH, J lists,
+correspondences, d1, d2), in the per-stage calls and in the batch form, and the
+autotuner's choice gives the defaults' results."""
+
+import hashlib
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_15615_amd import kmg
+
+    kmg.load()
+    torch.cuda.set_device(0)
+    yield kmg
+    kmg.set_tuning(None)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def settings():
+    from paper_2409_15615_amd.tune import SPACE
+
+    out = [{}]
+    for f, vals in SPACE.items():
+        out += [{f: v} for v in vals]
+    out.append({"search_waves": 8, "count_queries": 4, "spfh_pair_mean": 0, "fpfh_rows": 16, "band_tile": 12})
+    out.append({"search_waves": 2, "count_queries": 1, "spfh_pair_mean": 8192, "fpfh_rows": 4, "band_tile": 64})
+    return out
+
+
+def digest(*tensors):
+    h = hashlib.sha256()
+    for t in tensors:
+        h.update(t.detach().cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+def test_per_stage_outputs_invariant(K):
+    d = synth.c1_pair(0)
+    p = d["params"]
+    prm = K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_tgt"])
+    prs = K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, d["vp_src"])
+    src, tgt = dev(d["src"]), dev(d["tgt"])
+    ref = None
+    for st in settings():
+        K.set_tuning(st)
+        a, b, mt = K.register_pair(src, tgt, prs, prm)
+        g = digest(a.normals.off, a.normals.idx, a.normals.normals, a.feats.flags, a.feats.fpfh, b.normals.idx,
+                   b.normals.normals, b.feats.fpfh, b.feats.j_idx, mt.pairs, mt.d1, mt.d2)
+        if ref is None:
+            ref = g
+        assert g == ref, st
+    K.set_tuning(None)
+
+
+def test_batch_outputs_invariant_and_autotuner(K):
+    from paper_2409_15615_amd.tune import autotune
+
+    pairs = [synth.c0_pair(0), synth.indoor_pair(2, 101, 3000), synth.lidar_pair(2, 103, 0.6, n_az=900)]
+    clouds = []
+    for d in pairs:
+        p = d["params"]
+        clouds += [(dev(d["src"]), K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins,
+                                                 d["vp_src"])),
+                   (dev(d["tgt"]), K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins,
+                                                 d["vp_tgt"]))]
+    K.set_tuning(None)
+    _, probe = K.register_batch(clouds)
+    b = K.Batch(len(pairs), probe.raw_cap, probe.nnz() + 4096, 11)
+    b.upload(clouds)
+
+    def fingerprint():
+        return digest(b.counts, b.pairs, b.d1, b.d2)
+
+    b.pairs.fill_(-1)
+    b.d1.fill_(-1.0)
+    b.d2.fill_(-1.0)
+    b.run()
+    ref = fingerprint()
+    for st in settings():
+        K.set_tuning(st)
+        b.counts.zero_()
+        b.pairs.fill_(-1)
+        b.run()
+        assert fingerprint() == ref, st
+    best, t_best, t_def, log = autotune(b.run, fingerprint, reps=2, rounds=1)
+    assert t_best <= t_def and len(log) > 5
+    b.run()
+    assert fingerprint() == ref
+    K.set_tuning(None)
+    print(f"autotuned {best}: {t_best:.3f} ms vs {t_def:.3f} ms with the defaults, {len(log)} settings timed")
