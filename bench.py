@@ -655,6 +655,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c1-batch", type=int, default=16,
+                    help="lidar: distinct pairs of the batched forms reported beside the single-pair value")
     ap.add_argument("--cpu-repeats", type=int, default=3, help="oracle runs at all host threads (median)")
     ap.add_argument("--cpu-repeats-one-thread", type=int, default=1, help="oracle runs on one thread")
     ap.add_argument("--item", type=int, default=0)
@@ -763,6 +765,51 @@ def main():
     same = (torch.equal(res.pairs, mt.pairs) and torch.equal(res_g.pairs, mt.pairs)
             and torch.equal(res.d1, mt.d1) and torch.equal(res.d2, mt.d2))
 
+    # batched forms: args.c1_batch distinct LiDAR pairs (item 0 is the pair above) in one
+    # graph-replayed kmg_batch_run, FP32 and BF16 candidate tiles, results compared
+    batched_forms = {}
+    if args.c1_batch > 1:
+        t_gen = time.perf_counter()
+        more = [d] + [synth.c1_pair(args.item + 1 + i) for i in range(args.c1_batch - 1)]
+        t_gen = time.perf_counter() - t_gen
+        bclouds = []
+        for e in more:
+            for xyz, vp in ((e["src"], e["vp_src"]), (e["tgt"], e["vp_tgt"])):
+                bclouds.append((torch.from_numpy(xyz).to(dev),
+                                kmg.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins, vp)))
+        _, bprobe = kmg.register_batch(bclouds)
+        bb = kmg.Batch(len(more), bprobe.raw_cap, bprobe.nnz() + 4096, p.n_bins, device=dev)
+        bb.upload(bclouds)
+        outs = {}
+        for prec in ("fp32", "bf16"):
+            def brun(prec=prec):
+                bb.run(prec)
+
+            sb = torch.cuda.Stream()
+            sb.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(sb):
+                brun()
+            torch.cuda.current_stream().wait_stream(sb)
+            sync()
+            gb = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gb):
+                brun()
+            for _ in range(2):
+                gb.replay()
+            nb = max(3, args.steps // 4)
+            tb, latb = timed(gb.replay, nb, sync)
+            rb = bb.results()
+            outs[prec] = [(x.pairs.cpu().numpy().tobytes(), x.d1.cpu().numpy().tobytes(),
+                           x.d2.cpu().numpy().tobytes()) for x in rb]
+            batched_forms[f"batch{len(more)}_{prec}"] = {
+                "pairs_per_s": round(len(more) * nb / tb, 3), "ms_per_batch": round(1e3 * tb / nb, 4),
+                "p50_ms_per_batch": round(statistics.median(latb), 4)}
+            del gb
+        first = (mt.pairs.cpu().numpy().tobytes(), mt.d1.cpu().numpy().tobytes(), mt.d2.cpu().numpy().tobytes())
+        batched_forms["identical_correspondences_bf16_vs_fp32"] = outs["fp32"] == outs["bf16"]
+        batched_forms["pair0_equal_to_single_pair"] = outs["fp32"][0] == first
+        batched_forms["generation_s"] = round(t_gen, 1)
+
     nj_p, nj_q = res.n_j
     dim = 3 * p.n_bins
     i_topk = names.index("match_topk")
@@ -808,6 +855,7 @@ def main():
             "graph": {"pairs_per_s": round(value, 3), "p50_ms": round(statistics.median(lat_graph), 4),
                       "p99_ms": round(pct(lat_graph, 0.99), 4)},
             "identical_correspondences": bool(same),
+            **batched_forms,
         },
         "stages_ms_per_step": stages,
         "roofline": {

@@ -155,6 +155,10 @@ const char* kmg_stage_name(int32_t stage);
  *                   of the planner's candidate set: 1..64, then four per
  *                   octave up to 4096), used whenever its tiles fit; 0
  *                   (default) = the planner's modelled choice.
+ *   fuse_features   1: SPFH and FPFH (Eq. A2-A5) in one persistent launch
+ *                   that takes work items from a queue, the FPFH of a cloud
+ *                   starting once every SPFH of that cloud is written
+ *                   (per-cloud readiness counters); 0 (default): two launches.
  *   reserved        must be 0.
  * kmg_set_tuning(NULL) restores the defaults; unsupported values give
  * KMG_ERR_ARG and leave the tuning unchanged.
@@ -165,7 +169,8 @@ typedef struct {
     int32_t spfh_pair_mean;
     int32_t fpfh_rows;
     int32_t band_tile;
-    int32_t reserved[3];
+    int32_t fuse_features;
+    int32_t reserved[2];
 } kmg_tuning;
 kmg_status kmg_set_tuning(const kmg_tuning* t);
 kmg_status kmg_get_tuning(kmg_tuning* t);

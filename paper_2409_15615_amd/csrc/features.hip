@@ -280,6 +280,89 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
     }
 }
 
+// SPFH of point q (Eq. A2-A4) by one wavefront: the body of spfh_kernel.
+__device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
+                                           int64_t stride, const int32_t* __restrict__ kept_cloud,
+                                           const float* __restrict__ nrm, int64_t nrm_stride,
+                                           const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
+                                           const int32_t* __restrict__ nbr, int H, uint16_t* __restrict__ cnt16,
+                                           float* __restrict__ spfh_out, int32_t* __restrict__ Pq,
+                                           double* __restrict__ inv100, int32_t* __restrict__ jflag, DevStatus* st,
+                                           int64_t q) {
+    const int lane = lane_id();
+    const int D = 3 * H;
+    const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
+    uint16_t* row = cnt16 + q * D;
+    if (!(flags[q] & 1)) {
+        for (int t = lane; t < D; t += kWave) {
+            row[t] = 0;
+            if (spfh_out) spfh_out[q * D + t] = 0.0f;
+        }
+        if (lane == 0) {
+            Pq[q] = 0;
+            inv100[q] = 0.0;
+            jflag[q] = 0;
+        }
+        return;
+    }
+    const V3f pq = {xyz[q], xyz[stride + q], xyz[s2 + q]};
+    const V3f nq = {nrm[q], nrm[nrm_stride + q], nrm[n2 + q]};
+    const int b = off[q], e = off[q + 1];
+    int n_valid = 0;
+    // lane h holds the counts of bin h for the three features
+    int c0 = 0, c1 = 0, c2 = 0;
+    uint32_t n64 = 0, nedge = 0;
+    for (int base = b; base < e; base += kWave) {
+        const int t = base + lane;
+        bool valid = false;
+        int bn[3] = {-1, -1, -1};
+        if (t < e) {
+            const int k = nbr[t];
+            valid = (flags[k] & 1) != 0;
+            if (valid && k != q) {
+                const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
+                const V3f nk = {nrm[k], nrm[nrm_stride + k], nrm[n2 + k]};
+                if (!bins_f32(pq, nq, pk, nk, H, bn)) {
+                    const BinsF64 r = bins_f64(pq, nq, pk, nk, H);
+                    bn[0] = r.b[0];
+                    bn[1] = r.b[1];
+                    bn[2] = r.b[2];
+                    ++n64;
+                    nedge += r.edge ? 1u : 0u;
+                }
+            }
+        }
+        n_valid += __popcll(ballot(valid));
+        for (int h = 0; h < H; ++h) {
+            const int a0 = __popcll(ballot(bn[0] == h));
+            const int a1 = __popcll(ballot(bn[1] == h));
+            const int a2 = __popcll(ballot(bn[2] == h));
+            if (lane == h) {
+                c0 += a0;
+                c1 += a1;
+                c2 += a2;
+            }
+        }
+    }
+    n64 = wave_sum(n64);
+    nedge = wave_sum(nedge);
+    const int P = n_valid - 1;
+    if (lane < H) {
+        const int cs[3] = {c0, c1, c2};
+        for (int l = 0; l < 3; ++l) {
+            row[l * H + lane] = static_cast<uint16_t>(cs[l]);
+            if (spfh_out) spfh_out[q * D + l * H + lane] = static_cast<float>(spfh_value(cs[l], P));
+        }
+    }
+    if (lane == 0) {
+        Pq[q] = P;
+        inv100[q] = P > 0 ? 100.0 / static_cast<double>(P) : 0.0;
+        jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_j) ? 1 : 0;
+        if (n64) atomicAdd(&st->feat_fp64, n64);
+        if (nedge) atomicAdd(&st->feat_edge, nedge);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
                                                       int64_t stride, const int32_t* __restrict__ kept_cloud,
                                                       int64_t m_cap, const float* __restrict__ nrm,
@@ -290,83 +373,12 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                                                       int32_t* __restrict__ Pq, double* __restrict__ inv100,
                                                      int32_t* __restrict__ jflag,
                                                       int pair_mean, DevStatus* st) {
-    const int lane = lane_id();
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     if (st->nnz <= pair_mean * m) return;           // short lists: spfh_pairs
-    const int D = 3 * H;
-    const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
-    for (int64_t q = global_wave(); q < m; q += wave_count()) {
-        uint16_t* row = cnt16 + q * D;
-        if (!(flags[q] & 1)) {
-            for (int t = lane; t < D; t += kWave) {
-                row[t] = 0;
-                if (spfh_out) spfh_out[q * D + t] = 0.0f;
-            }
-            if (lane == 0) {
-                Pq[q] = 0;
-                inv100[q] = 0.0;
-                jflag[q] = 0;
-            }
-            continue;
-        }
-        const V3f pq = {xyz[q], xyz[stride + q], xyz[s2 + q]};
-        const V3f nq = {nrm[q], nrm[nrm_stride + q], nrm[n2 + q]};
-        const int b = off[q], e = off[q + 1];
-        int n_valid = 0;
-        // lane h holds the counts of bin h for the three features
-        int c0 = 0, c1 = 0, c2 = 0;
-        uint32_t n64 = 0, nedge = 0;
-        for (int base = b; base < e; base += kWave) {
-            const int t = base + lane;
-            bool valid = false;
-            int bn[3] = {-1, -1, -1};
-            if (t < e) {
-                const int k = nbr[t];
-                valid = (flags[k] & 1) != 0;
-                if (valid && k != q) {
-                    const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
-                    const V3f nk = {nrm[k], nrm[nrm_stride + k], nrm[n2 + k]};
-                    if (!bins_f32(pq, nq, pk, nk, H, bn)) {
-                        const BinsF64 r = bins_f64(pq, nq, pk, nk, H);
-                        bn[0] = r.b[0];
-                        bn[1] = r.b[1];
-                        bn[2] = r.b[2];
-                        ++n64;
-                        nedge += r.edge ? 1u : 0u;
-                    }
-                }
-            }
-            n_valid += __popcll(ballot(valid));
-            for (int h = 0; h < H; ++h) {
-                const int a0 = __popcll(ballot(bn[0] == h));
-                const int a1 = __popcll(ballot(bn[1] == h));
-                const int a2 = __popcll(ballot(bn[2] == h));
-                if (lane == h) {
-                    c0 += a0;
-                    c1 += a1;
-                    c2 += a2;
-                }
-            }
-        }
-        n64 = wave_sum(n64);
-        nedge = wave_sum(nedge);
-        const int P = n_valid - 1;
-        if (lane < H) {
-            const int cs[3] = {c0, c1, c2};
-            for (int l = 0; l < 3; ++l) {
-                row[l * H + lane] = static_cast<uint16_t>(cs[l]);
-                if (spfh_out) spfh_out[q * D + l * H + lane] = static_cast<float>(spfh_value(cs[l], P));
-            }
-        }
-        if (lane == 0) {
-            Pq[q] = P;
-            inv100[q] = P > 0 ? 100.0 / static_cast<double>(P) : 0.0;
-            jflag[q] = (n_valid >= cl[cloud_of(kept_cloud, q)].tau_j) ? 1 : 0;
-            if (n64) atomicAdd(&st->feat_fp64, n64);
-            if (nedge) atomicAdd(&st->feat_edge, nedge);
-        }
-    }
+    for (int64_t q = global_wave(); q < m; q += wave_count())
+        spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
+                   jflag, st, q);
 }
 
 // FPFH of rows of at most 64 values over the J list, two points per
@@ -474,6 +486,88 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
     }
 }
 
+// FPFH of point q in J (Eq. A5) by one wavefront, with the wave's LDS lists
+// s_k / s_w: the body of fpfh_kernel.
+template <int kBatchNarrow>
+__device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_t stride,
+                                           const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
+                                           const int32_t* __restrict__ nbr, int H, const uint16_t* __restrict__ cnt16,
+                                           const int32_t* __restrict__ Pq, const double* __restrict__ inv100,
+                                           float* __restrict__ fpfh, int32_t* s_k, double* s_w, int64_t q) {
+#pragma clang fp contract(off)
+    const int lane = lane_id();
+    const int D = 3 * H;
+    const int64_t s2 = 2 * stride;
+    float* out = fpfh + q * D;
+    const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
+    const int b = off[q], e = off[q + 1];
+    // lanes own bins lane and lane + 64; lanes past D read bin D - 1 and are never stored
+    const int lb0 = min(lane, D - 1), lb1 = min(lane + kWave, D - 1);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int base = b; base < e; base += kWave) {
+        // every load is unconditional (indices clamped), the mask applies afterwards
+        const int t = min(base + lane, e - 1);
+        const int k = nbr[t];
+        const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
+        const bool use = (base + lane < e) && (k != q) && (flags[k] & 1);
+        // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k])
+        const double w = use ? (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k] : 0.0;
+        const uint64_t bm = ballot(use);
+        __builtin_amdgcn_wave_barrier();
+        if (use) {
+            const int at = lanes_below(bm);
+            s_k[at] = k;
+            s_w[at] = w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int nuse = __popcll(bm);
+        // SPFH rows in flight kBatchNarrow (rows of at most 64 values) or kBatch at a time,
+        // accumulated in ascending neighbour order
+        int j = 0;
+        if (D <= kWave) {
+            for (; j + kBatchNarrow <= nuse; j += kBatchNarrow) {
+                double v0[kBatchNarrow];
+#pragma unroll
+                for (int u = 0; u < kBatchNarrow; ++u)
+                    v0[u] = static_cast<double>(cnt16[static_cast<int64_t>(s_k[j + u]) * D + lb0]);
+#pragma unroll
+                for (int u = 0; u < kBatchNarrow; ++u) acc0 = acc0 + s_w[j + u] * v0[u];
+            }
+        }
+        for (; j + kBatch <= nuse; j += kBatch) {
+            double v0[kBatch], v1[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[j + u]) * D;
+                v0[u] = static_cast<double>(sk[lb0]);
+                v1[u] = D > kWave ? static_cast<double>(sk[lb1]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const double wj = s_w[j + u];
+                acc0 = acc0 + wj * v0[u];
+                acc1 = acc1 + wj * v1[u];
+            }
+        }
+        for (; j < nuse; ++j) {
+            const double wj = s_w[j];
+            const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[j]) * D;
+            acc0 = acc0 + wj * static_cast<double>(sk[lb0]);
+            if (D > kWave) acc1 = acc1 + wj * static_cast<double>(sk[lb1]);
+        }
+    }
+    const int P = Pq[q];
+    const uint16_t* sq = cnt16 + q * D;
+    if (P == 0) {
+        if (lane < D) out[lane] = 0.0f;
+        if (lane + kWave < D) out[lane + kWave] = 0.0f;
+        return;
+    }
+    const double inv = 1.0 / static_cast<double>(P);
+    if (lane < D) out[lane] = static_cast<float>(spfh_value(sq[lane], P) + inv * acc0);
+    if (lane + kWave < D) out[lane + kWave] = static_cast<float>(spfh_value(sq[lane + kWave], P) + inv * acc1);
+}
+
 // One wavefront per point of the J list (j_list[0 .. n_j), from the J scan);
 // the rows of the other kept points are zeroed by a grid-stride pass first.
 template <int kBatchNarrow>
@@ -485,9 +579,49 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
                                                       const int32_t* __restrict__ nbr, int H,
                                                       const uint16_t* __restrict__ cnt16,
                                                       const int32_t* __restrict__ Pq,
-                                                     const double* __restrict__ inv100, float* __restrict__ fpfh,
+                                                      const double* __restrict__ inv100, float* __restrict__ fpfh,
                                                       const DevStatus* st) {
-#pragma clang fp contract(off)
+    __shared__ int32_t s_k[kWaves][kWave];
+    __shared__ double s_w[kWaves][kWave];
+    const int wv = threadIdx.x / kWave;
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
+    const int D = 3 * H;
+    const int64_t gt = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
+        if (!jflag[t / D]) fpfh[t] = 0.0f;
+    const int64_t n_j = clamp_count(st->n_j, m);
+    for (int64_t g = global_wave(); g < n_j; g += wave_count())
+        fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nbr, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
+                                 j_list[g]);
+}
+
+// SPFH and FPFH in one persistent launch.  Wavefronts take work items from a
+// queue (one counter): first every SPFH item (kFuseChunk consecutive kept
+// points), then every FPFH item (the same chunks); the FPFH of q in cloud c
+// may start once every point of c has its SPFH, which a per-cloud readiness
+// counter tells: an SPFH item adds its points to their clouds' counters after
+// a release fence, an FPFH item waits (s_sleep polling, bounded) for its
+// cloud's counter to reach the cloud's kept count and then acquires.  Items
+// are handed out in order, so a waiting wavefront only ever waits for SPFH
+// items that running wavefronts hold.  Non-J rows of the FPFH are zeroed by
+// their FPFH items.  The same per-point bodies as spfh_kernel and fpfh_kernel:
+// bit-identical outputs.
+constexpr int kFuseChunk = 16;
+constexpr uint32_t kFuseSpinLimit = 1u << 22;
+
+__device__ __forceinline__ int64_t cloud_kept(const CloudState* cs, int c, int64_t m) {
+    return cs ? cs[c].kept_cnt : m;
+}
+
+template <int kBatchNarrow>
+__global__ __launch_bounds__(kBlock) void features_fused(
+    const CloudDev* __restrict__ cl, const float* __restrict__ xyz, int64_t stride,
+    const int32_t* __restrict__ kept_cloud, int64_t m_cap, const float* __restrict__ nrm, int64_t nrm_stride,
+    uint8_t* __restrict__ flags, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr, int H,
+    uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out, int32_t* __restrict__ Pq, double* __restrict__ inv100,
+    int32_t* __restrict__ jflag, float* __restrict__ fpfh, const CloudState* __restrict__ cs, uint32_t* queue,
+    int32_t* ready, DevStatus* st) {
     __shared__ int32_t s_k[kWaves][kWave];
     __shared__ double s_w[kWaves][kWave];
     const int wv = threadIdx.x / kWave;
@@ -495,81 +629,63 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     const int D = 3 * H;
-    const int64_t s2 = 2 * stride;
-    const int64_t gt = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
-        if (!jflag[t / D]) fpfh[t] = 0.0f;
-    const int64_t n_j = clamp_count(st->n_j, m);
-    for (int64_t g = global_wave(); g < n_j; g += wave_count()) {
-        const int64_t q = j_list[g];
-        float* out = fpfh + q * D;
-        const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
-        const int b = off[q], e = off[q + 1];
-        // lanes own bins lane and lane + 64; lanes past D read bin D - 1 and are never stored
-        const int lb0 = min(lane, D - 1), lb1 = min(lane + kWave, D - 1);
-        double acc0 = 0.0, acc1 = 0.0;
-        for (int base = b; base < e; base += kWave) {
-            // every load is unconditional (indices clamped), the mask applies afterwards
-            const int t = min(base + lane, e - 1);
-            const int k = nbr[t];
-            const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
-            const bool use = (base + lane < e) && (k != q) && (flags[k] & 1);
-            // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k])
-            const double w = use ? (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k] : 0.0;
-            const uint64_t bm = ballot(use);
-            __builtin_amdgcn_wave_barrier();
-            if (use) {
-                const int at = lanes_below(bm);
-                s_k[wv][at] = k;
-                s_w[wv][at] = w;
-            }
-            __builtin_amdgcn_wave_barrier();
-            const int nuse = __popcll(bm);
-            // SPFH rows in flight kBatchNarrow (rows of at most 64 values) or kBatch at a time,
-            // accumulated in ascending neighbour order
-            int j = 0;
-            if (D <= kWave) {
-                for (; j + kBatchNarrow <= nuse; j += kBatchNarrow) {
-                    double v0[kBatchNarrow];
-#pragma unroll
-                    for (int u = 0; u < kBatchNarrow; ++u)
-                        v0[u] = static_cast<double>(cnt16[static_cast<int64_t>(s_k[wv][j + u]) * D + lb0]);
-#pragma unroll
-                    for (int u = 0; u < kBatchNarrow; ++u) acc0 = acc0 + s_w[wv][j + u] * v0[u];
+    const int64_t n_chunks = (m + kFuseChunk - 1) / kFuseChunk;
+    int known = -1;  // a cloud whose SPFH this wavefront has seen complete (and acquired)
+    while (true) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(queue, 1u);
+        item = __shfl(item, 0, kWave);
+        if (item >= 2 * n_chunks) break;
+        if (item < n_chunks) {
+            const int64_t p0 = static_cast<int64_t>(item) * kFuseChunk;
+            const int64_t p1 = min(p0 + kFuseChunk, m);
+            for (int64_t q = p0; q < p1; ++q)
+                spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq,
+                           inv100, jflag, st, q);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0) {
+                // the chunk's points by cloud (a chunk rarely crosses a cloud boundary)
+                int c = cloud_of(kept_cloud, p0), n = 0;
+                for (int64_t q = p0; q < p1; ++q) {
+                    const int cq = cloud_of(kept_cloud, q);
+                    if (cq != c) {
+                        atomicAdd(ready + c, n);
+                        c = cq;
+                        n = 0;
+                    }
+                    ++n;
                 }
+                atomicAdd(ready + c, n);
             }
-            for (; j + kBatch <= nuse; j += kBatch) {
-                double v0[kBatch], v1[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[wv][j + u]) * D;
-                    v0[u] = static_cast<double>(sk[lb0]);
-                    v1[u] = D > kWave ? static_cast<double>(sk[lb1]) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const double wj = s_w[wv][j + u];
-                    acc0 = acc0 + wj * v0[u];
-                    acc1 = acc1 + wj * v1[u];
-                }
-            }
-            for (; j < nuse; ++j) {
-                const double wj = s_w[wv][j];
-                const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[wv][j]) * D;
-                acc0 = acc0 + wj * static_cast<double>(sk[lb0]);
-                if (D > kWave) acc1 = acc1 + wj * static_cast<double>(sk[lb1]);
-            }
-        }
-        const int P = Pq[q];
-        const uint16_t* sq = cnt16 + q * D;
-        if (P == 0) {
-            if (lane < D) out[lane] = 0.0f;
-            if (lane + kWave < D) out[lane + kWave] = 0.0f;
             continue;
         }
-        const double inv = 1.0 / static_cast<double>(P);
-        if (lane < D) out[lane] = static_cast<float>(spfh_value(sq[lane], P) + inv * acc0);
-        if (lane + kWave < D) out[lane + kWave] = static_cast<float>(spfh_value(sq[lane + kWave], P) + inv * acc1);
+        const int64_t p0 = static_cast<int64_t>(item - n_chunks) * kFuseChunk;
+        const int64_t p1 = min(p0 + kFuseChunk, m);
+        for (int64_t q = p0; q < p1; ++q) {
+            const int c = cloud_of(kept_cloud, q);
+            if (c != known) {
+                const int64_t need = cloud_kept(cs, c, m);
+                int ok = 0;
+                if (lane == 0) {
+                    uint32_t spins = 0;
+                    while (__hip_atomic_load(ready + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > kFuseSpinLimit) break;
+                    }
+                    ok = spins <= kFuseSpinLimit;
+                    if (!ok) atomicOr(&st->err_sync, 1);
+                }
+                ok = __shfl(ok, 0, kWave);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (ok) known = c;
+            }
+            if (jflag[q]) {
+                fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nbr, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
+                                         q);
+            } else {
+                for (int t = lane; t < D; t += kWave) fpfh[q * D + t] = 0.0f;
+            }
+        }
     }
 }
 
@@ -665,6 +781,8 @@ FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
     const size_t mc = static_cast<size_t>(std::max<int64_t>(m_cap, 1));
     w.cnt16 = c.take<uint16_t>(mc * 3 * H);
     w.inv100 = c.take<double>(mc);
+    w.queue = c.take<uint32_t>(1);
+    w.ready = c.take<int32_t>(kMaxClouds);
     w.Pq = c.take<int32_t>(mc);
     w.jflag = c.take<int32_t>(mc);
     w.pos = c.take<int32_t>(mc);
@@ -726,11 +844,63 @@ kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_
     return KMG_OK;
 }
 
+// SPFH and FPFH in the fused persistent launch, then the J list.
+template <int kRows>
+void launch_fused(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud, int64_t m_cap,
+                  const float* nrm, int64_t nrm_stride, uint8_t* flags, const int32_t* off, const int32_t* nbr, int H,
+                  const FeatWs& w, float* spfh_out, float* fpfh_out, const CloudState* cs, DevStatus* st,
+                  hipStream_t s) {
+    features_fused<kRows><<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
+                                                                      nrm_stride, flags, off, nbr, H, w.cnt16, spfh_out,
+                                                                      w.Pq, w.inv100, w.jflag, fpfh_out, cs, w.queue,
+                                                                      w.ready, st);
+}
+
+kmg_status features_fused_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
+                                const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
+                                const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                                uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
+                                hipStream_t s, bool cleared, MatchSet* sets) {
+    if (sets && !cs) return KMG_ERR_ARG;
+    if (!cleared)
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.jflag), 0u, static_cast<size_t>(std::max<int64_t>(m_cap, 1)),
+                         s));
+    KMG_TRY(fill_u32(w.queue, 0u, 1, s));
+    KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ready), 0u, static_cast<size_t>(std::max(n_clouds, 1)), s));
+    if (m_cap > 0) {
+        StageScope sc(ST_SPFH, s);  // SPFH and FPFH together
+        switch (tuning().fpfh_rows) {
+            case 4: launch_fused<4>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nbr, H, w,
+                                    spfh_out, fpfh_out, cs, st, s); break;
+            case 16: launch_fused<16>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nbr, H, w,
+                                      spfh_out, fpfh_out, cs, st, s); break;
+            default: launch_fused<8>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nbr, H, w,
+                                     spfh_out, fpfh_out, cs, st, s); break;
+        }
+        KMG_TRY(launch_status());
+    }
+    StageScope sc(ST_J_COMPACT, s);
+    KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
+    if (m_cap > 0 || sets) {
+        j_emit<<<std::max(grid_cap(m_cap, kBlock), 1u), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st, cs,
+                                                                      n_clouds, fpfh_out, sets);
+        KMG_TRY(launch_status());
+    }
+    if (cs && !sets) {
+        cloud_j_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(n_clouds, m_cap, w.pos, st, cs);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
 kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
                           hipStream_t s, bool cleared, MatchSet* sets) {
+    if (tuning().fuse_features)
+        return features_fused_batch(cl, n_clouds, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm,
+                                    nrm_stride, flags, spfh_out, fpfh_out, j_idx, cs, s, cleared, sets);
     KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm, nrm_stride, flags, spfh_out, s,
                        cleared));
     return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nbr, flags, fpfh_out, j_idx, cs, s, sets);

@@ -129,6 +129,8 @@ struct DevStatus {
     int32_t rank_items;       // norm-band matching: tile pairs of the cross ranking
     int32_t sort_items;       // norm-band matching: sorted tiles
     int64_t band_pairs;       // norm-band matching: query-row distances evaluated by the tiles
+    int32_t err_sync;         // a bounded wait inside a persistent kernel gave up (never expected)
+    int32_t pad1;
 };
 
 // Linear workspace allocator; with base == nullptr it only measures.
@@ -306,6 +308,8 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
 struct FeatWs {
     uint16_t* cnt16;  // SPFH bin counts (Eq. A4 numerators), m x 3H
     double* inv100;   // 100 / P_q (0 when P_q = 0)
+    uint32_t* queue;  // work queue of the fused SPFH / FPFH launch
+    int32_t* ready;   // per cloud: points whose SPFH is written (fused launch)
     int32_t* Pq;
     int32_t* jflag;
     int32_t* pos;
@@ -437,6 +441,7 @@ struct Tuning {
     int spfh_pair_mean = 24;  // mean list length up to which SPFH takes two points per wavefront
     int fpfh_rows = 8;        // SPFH rows in flight per lane in the FPFH sum (4, 8, 16)
     int band_tile = 0;        // partner chunks per band tile; 0 = the tile-length model's choice
+    int fuse_features = 0;    // 1: SPFH and FPFH in one persistent launch (per-cloud readiness counters)
 };
 const Tuning& tuning();
 bool set_tuning(const Tuning& t);

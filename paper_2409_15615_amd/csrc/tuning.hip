@@ -17,6 +17,7 @@ bool set_tuning(const Tuning& t) {
     if (t.spfh_pair_mean < 0 || t.spfh_pair_mean > kMaxDegree) return false;
     if (t.fpfh_rows != 4 && t.fpfh_rows != 8 && t.fpfh_rows != 16) return false;
     if (t.band_tile != 0 && !band_tile_candidate(t.band_tile)) return false;
+    if (t.fuse_features != 0 && t.fuse_features != 1) return false;
     g_tuning = t;
     return true;
 }
@@ -28,12 +29,13 @@ extern "C" {
 __attribute__((visibility("default"))) kmg_status kmg_set_tuning(const kmg_tuning* t) {
     kmg::Tuning v;  // defaults
     if (t) {
-        if (t->reserved[0] || t->reserved[1] || t->reserved[2]) return KMG_ERR_ARG;
+        if (t->reserved[0] || t->reserved[1]) return KMG_ERR_ARG;
         v.search_waves = t->search_waves;
         v.count_queries = t->count_queries;
         v.spfh_pair_mean = t->spfh_pair_mean;
         v.fpfh_rows = t->fpfh_rows;
         v.band_tile = t->band_tile;
+        v.fuse_features = t->fuse_features;
     }
     return kmg::set_tuning(v) ? KMG_OK : KMG_ERR_ARG;
 }
@@ -46,7 +48,8 @@ __attribute__((visibility("default"))) kmg_status kmg_get_tuning(kmg_tuning* t) 
     t->spfh_pair_mean = v.spfh_pair_mean;
     t->fpfh_rows = v.fpfh_rows;
     t->band_tile = v.band_tile;
-    t->reserved[0] = t->reserved[1] = t->reserved[2] = 0;
+    t->fuse_features = v.fuse_features;
+    t->reserved[0] = t->reserved[1] = 0;
     return KMG_OK;
 }
 

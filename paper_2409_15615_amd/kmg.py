@@ -53,11 +53,12 @@ class KmgTuning(C.Structure):
         ("spfh_pair_mean", C.c_int32),
         ("fpfh_rows", C.c_int32),
         ("band_tile", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("fuse_features", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
-TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile")
+TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile", "fuse_features")
 
 
 class KmgCloud(C.Structure):

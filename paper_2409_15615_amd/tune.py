@@ -25,6 +25,7 @@ SPACE = {
     "spfh_pair_mean": (0, 16, 24, 32, 8192),
     "fpfh_rows": (4, 8, 16),
     "band_tile": (0, 8, 12, 16, 20, 24, 32, 48, 64),
+    "fuse_features": (0, 1),
 }
 
 
