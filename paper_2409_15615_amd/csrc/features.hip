@@ -438,8 +438,9 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
                 k = nbr[b + base + hl];
                 const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
                 use = (k != q) && (flags[k] & 1);
-                // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k])
-                w = use ? (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k] : 0.0;
+                // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k]);
+                // 100 / P_k is loaded beside the coordinates (the weight of an unused lane is dropped)
+                w = (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k];
             }
             const uint32_t bm = static_cast<uint32_t>(ballot(use) >> sh);
             __builtin_amdgcn_wave_barrier();
@@ -510,8 +511,9 @@ __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_
         const int k = nbr[t];
         const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
         const bool use = (base + lane < e) && (k != q) && (flags[k] & 1);
-        // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k])
-        const double w = use ? (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k] : 0.0;
+        // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k]);
+        // 100 / P_k is loaded beside the coordinates (the weight of an unused lane is dropped)
+        const double w = (1.0 / sqrt(d2_exact(qx, qy, qz, kx, ky, kz))) * inv100[k];
         const uint64_t bm = ballot(use);
         __builtin_amdgcn_wave_barrier();
         if (use) {

@@ -121,4 +121,27 @@ __device__ __forceinline__ int cloud_of_raw(const CloudDev* cl, int n_clouds, in
 
 __device__ __forceinline__ int64_t clamp_count(int64_t v, int64_t cap) { return v < cap ? v : cap; }
 
+// Runs of equal keys on consecutive lanes (a lane with key kEmptyKey is a run
+// of its own).  The whole wavefront must be active.  head: this lane starts a
+// run; lead: the first lane of this lane's run; len: the run's lane count
+// (meaningful on the head).
+struct LaneRun {
+    bool head;
+    int lead;
+    int len;
+};
+__device__ __forceinline__ LaneRun lane_run(uint64_t key) {
+    const int lane = lane_id();
+    const uint64_t prev = __shfl_up(key, 1, kWave);
+    const bool head = lane == 0 || key == kEmptyKey || key != prev;
+    const uint64_t heads = ballot(head);
+    const uint64_t upto = lane == kWave - 1 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    LaneRun r;
+    r.head = head;
+    r.lead = 63 - __clzll(static_cast<long long>(heads & upto));
+    const uint64_t above = heads & ~upto;
+    r.len = (above ? __ffsll(static_cast<unsigned long long>(above)) - 1 : kWave) - lane;
+    return r;
+}
+
 }  // namespace kmg

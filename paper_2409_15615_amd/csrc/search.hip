@@ -40,6 +40,9 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
     return kept_cloud ? kept_cloud[q] : 0;
 }
 
+// Kept points in input order often share a cell: only the first lane of a run
+// of equal keys on consecutive lanes inserts the key and adds the run's length
+// to the cell's count; cell_scatter places a run the same way, in lane order.
 __global__ __launch_bounds__(kBlock) void cell_insert(const CloudDev* __restrict__ cl,
                                                       const float* __restrict__ xyz, int64_t stride,
                                                       const int32_t* __restrict__ kept_cloud, int64_t m_cap,
@@ -47,24 +50,32 @@ __global__ __launch_bounds__(kBlock) void cell_insert(const CloudDev* __restrict
                                                       int32_t* __restrict__ pslot, DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < m; p += gs) {
-        const int c = cloud_of(kept_cloud, p);
-        const double inv_c = cl[c].inv_cell;
-        const double kx = floor(static_cast<double>(xyz[p]) * inv_c);
-        const double ky = floor(static_cast<double>(xyz[stride + p]) * inv_c);
-        const double kz = floor(static_cast<double>(xyz[2 * stride + p]) * inv_c);
-        // keep one cell of headroom so that the 27-cell stencil stays packable
-        if (!key_in_range(kx - 1) || !key_in_range(kx + 1) || !key_in_range(ky - 1) || !key_in_range(ky + 1) ||
-            !key_in_range(kz - 1) || !key_in_range(kz + 1)) {
-            atomicOr(&st->err_range, 1);
-            pslot[p] = -1;
-            continue;
+    const int lane = lane_id();
+    // every lane of a wave runs the same rounds (the run detection shuffles)
+    for (int64_t p0 = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~(kWave - 1)); p0 < m; p0 += gs) {
+        const int64_t p = p0 + lane;
+        uint64_t key = kEmptyKey;
+        if (p < m) {
+            const int c = cloud_of(kept_cloud, p);
+            const double inv_c = cl[c].inv_cell;
+            const double kx = floor(static_cast<double>(xyz[p]) * inv_c);
+            const double ky = floor(static_cast<double>(xyz[stride + p]) * inv_c);
+            const double kz = floor(static_cast<double>(xyz[2 * stride + p]) * inv_c);
+            // keep one cell of headroom so that the 27-cell stencil stays packable
+            if (!key_in_range(kx - 1) || !key_in_range(kx + 1) || !key_in_range(ky - 1) || !key_in_range(ky + 1) ||
+                !key_in_range(kz - 1) || !key_in_range(kz + 1))
+                atomicOr(&st->err_range, 1);
+            else
+                key = pack_key(c, static_cast<int64_t>(kx), static_cast<int64_t>(ky), static_cast<int64_t>(kz));
         }
-        const uint64_t key =
-            pack_key(c, static_cast<int64_t>(kx), static_cast<int64_t>(ky), static_cast<int64_t>(kz));
-        const uint32_t h = hash_insert(keys, mask, key);
-        atomicAdd(cnt + h, 1);
-        pslot[p] = static_cast<int32_t>(h);
+        const LaneRun run = lane_run(key);
+        int h = -1;
+        if (run.head && key != kEmptyKey) {
+            h = static_cast<int>(hash_insert(keys, mask, key));
+            atomicAdd(cnt + h, run.len);
+        }
+        h = __shfl(h, run.lead, kWave);
+        if (p < m) pslot[p] = key == kEmptyKey ? -1 : h;
     }
 }
 
@@ -74,11 +85,16 @@ __global__ __launch_bounds__(kBlock) void cell_scatter(const float* __restrict__
                                                        float4* __restrict__ pts, const DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < m; p += gs) {
-        const int h = pslot[p];
-        if (h < 0) continue;
-        const int pos = start[h] + atomicAdd(fill + h, 1);
-        pts[pos] = make_float4(xyz[p], xyz[stride + p], xyz[2 * stride + p], __int_as_float(static_cast<int>(p)));
+    const int lane = lane_id();
+    for (int64_t p0 = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~(kWave - 1)); p0 < m; p0 += gs) {
+        const int64_t p = p0 + lane;
+        const int h = p < m ? pslot[p] : -1;
+        const LaneRun run = lane_run(h < 0 ? kEmptyKey : static_cast<uint64_t>(h));
+        int base = 0;
+        if (run.head && h >= 0) base = start[h] + atomicAdd(fill + h, run.len);
+        base = __shfl(base, run.lead, kWave);
+        if (h >= 0) pts[base + (lane - run.lead)] = make_float4(xyz[p], xyz[stride + p], xyz[2 * stride + p],
+                                                               __int_as_float(static_cast<int>(p)));
     }
 }
 

@@ -13,40 +13,45 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Consecutive raw points often share a voxel (a spinning scan lists its
+// points along each ring): only the first lane of a run of equal keys on
+// consecutive lanes inserts the key and takes the minimum (its index is the
+// run's smallest); the others take its slot by a shuffle.
 __global__ __launch_bounds__(kBlock) void voxel_insert(const CloudDev* __restrict__ cl, int n_clouds, int64_t n_cap,
                                                        uint64_t* keys, int32_t* mins, uint32_t mask,
                                                        int32_t* __restrict__ slot, DevStatus* st) {
     const int64_t n = clamp_count(st->n_raw, n_cap);
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < n_cap; t += stride) {
-        if (t >= n) {
-            slot[t] = -1;
-            continue;
+    const int lane = lane_id();
+    // every lane of a wave runs the same rounds (the run detection shuffles)
+    for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~(kWave - 1)); t0 < n_cap;
+         t0 += stride) {
+        const int64_t t = t0 + lane;
+        uint64_t key = kEmptyKey;
+        if (t < n) {
+            const int c = cloud_of_raw(cl, n_clouds, t);
+            const int64_t i = t - cl[c].raw_off;
+            const int64_t nc = cl[c].n_raw;
+            const float* raw = cl[c].raw;
+            const float x = raw[i], y = raw[nc + i], z = raw[2 * nc + i];
+            if (isfinite(x) && isfinite(y) && isfinite(z)) {
+                // IEEE FP64 division and floor: the same keys as any IEEE implementation.
+                const double v = cl[c].voxel;
+                const double kx = floor(static_cast<double>(x) / v);
+                const double ky = floor(static_cast<double>(y) / v);
+                const double kz = floor(static_cast<double>(z) / v);
+                if (!key_in_range(kx) || !key_in_range(ky) || !key_in_range(kz)) atomicOr(&st->err_range, 1);
+                else key = pack_key(c, static_cast<int64_t>(kx), static_cast<int64_t>(ky), static_cast<int64_t>(kz));
+            }
         }
-        const int c = cloud_of_raw(cl, n_clouds, t);
-        const int64_t i = t - cl[c].raw_off;
-        const int64_t nc = cl[c].n_raw;
-        const float* raw = cl[c].raw;
-        const float x = raw[i], y = raw[nc + i], z = raw[2 * nc + i];
-        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
-            slot[t] = -1;
-            continue;
+        const LaneRun run = lane_run(key);
+        int h = -1;
+        if (run.head && key != kEmptyKey) {
+            h = static_cast<int>(hash_insert(keys, mask, key));
+            atomicMin(mins + h, static_cast<int32_t>(t));
         }
-        // IEEE FP64 division and floor: the same keys as any IEEE implementation.
-        const double v = cl[c].voxel;
-        const double kx = floor(static_cast<double>(x) / v);
-        const double ky = floor(static_cast<double>(y) / v);
-        const double kz = floor(static_cast<double>(z) / v);
-        if (!key_in_range(kx) || !key_in_range(ky) || !key_in_range(kz)) {
-            atomicOr(&st->err_range, 1);
-            slot[t] = -1;
-            continue;
-        }
-        const uint64_t key =
-            pack_key(c, static_cast<int64_t>(kx), static_cast<int64_t>(ky), static_cast<int64_t>(kz));
-        const uint32_t h = hash_insert(keys, mask, key);
-        atomicMin(mins + h, static_cast<int32_t>(t));
-        slot[t] = static_cast<int32_t>(h);
+        h = __shfl(h, run.lead, kWave);
+        if (t < n_cap) slot[t] = key == kEmptyKey ? -1 : h;
     }
 }
 
