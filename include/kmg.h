@@ -159,6 +159,13 @@ const char* kmg_stage_name(int32_t stage);
  *                   that takes work items from a queue, the FPFH of a cloud
  *                   starting once every SPFH of that cloud is written
  *                   (per-cloud readiness counters); 0 (default): two launches.
+ *   xcd_split       bit 0 (SPFH, Eq. A2-A4) and bit 1 (FPFH, Eq. A5): deal
+ *                   the points to wavefronts XCD-aware (each of the eight
+ *                   XCDs takes one contiguous eighth of the points, balanced
+ *                   by neighbour-list volume, so that its L2 holds that
+ *                   eighth's neighbourhood) rather than in turn; 0..3,
+ *                   default 2 (measured: the FPFH gather reads its
+ *                   neighbours' rows and gains, the SPFH pass loses).
  *   reserved        must be 0.
  * kmg_set_tuning(NULL) restores the defaults; unsupported values give
  * KMG_ERR_ARG and leave the tuning unchanged.
@@ -170,7 +177,8 @@ typedef struct {
     int32_t fpfh_rows;
     int32_t band_tile;
     int32_t fuse_features;
-    int32_t reserved[2];
+    int32_t xcd_split;
+    int32_t reserved;
 } kmg_tuning;
 kmg_status kmg_set_tuning(const kmg_tuning* t);
 kmg_status kmg_get_tuning(kmg_tuning* t);

@@ -29,6 +29,10 @@ namespace kmg {
 namespace {
 
 constexpr int kBlock = 256;
+// Work of a point in the XCD split, in list entries: its fixed cost (the list
+// bounds, its own row and the dependent loads before the first neighbour) plus
+// one per neighbour.
+constexpr int64_t kItemWork = 32;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kBatch = 8;          // SPFH rows loaded together in the FPFH sum
 
@@ -170,33 +174,31 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
 // Lists of a mean of at most kHalfListMean entries per point: two points per
 // wavefront, one per half of 32 lanes (each lane one neighbour of its half's
 // point per round, bin counts from ballots split by half, lane h of a half
-// holding bin h).  Longer lists: spfh_kernel, one point per wavefront.  Each
-// kernel checks the mean and returns at once when the other one serves it.
-// The threshold is measured: the 64-pair batch (mean 22.5) runs 1.5x faster
-// in pairs, the LiDAR pair (mean 29, but a long tail of structure points next
-// to scattered outliers with a few neighbours) 8% slower.
+// holding bin h).  Longer lists: one point per wavefront.  spfh_kernel checks
+// the mean on the device and takes one form or the other.  The threshold is
+// measured: the 64-pair batch (mean 22.5) runs 1.5x faster in pairs, the
+// LiDAR pair (mean 29, but a long tail of structure points next to scattered
+// outliers with a few neighbours) 8% slower.
 constexpr int kHalfListMean = 24;  // the default of tuning().spfh_pair_mean
 
-__global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
-                                                     int64_t stride, const int32_t* __restrict__ kept_cloud,
-                                                     int64_t m_cap, const float* __restrict__ nrm,
-                                                     int64_t nrm_stride, const uint8_t* __restrict__ flags,
-                                                     const int32_t* __restrict__ off,
-                                                     const int32_t* __restrict__ nbr, int H,
-                                                     uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
-                                                     int32_t* __restrict__ Pq, double* __restrict__ inv100,
-                                                     int32_t* __restrict__ jflag,
-                                                     int pair_mean, DevStatus* st) {
+__device__ __forceinline__ void spfh_pairs(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
+                                           int64_t stride, const int32_t* __restrict__ kept_cloud, int64_t m,
+                                           const float* __restrict__ nrm, int64_t nrm_stride,
+                                           const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
+                                           const int32_t* __restrict__ nbr, int H, uint16_t* __restrict__ cnt16,
+                                           float* __restrict__ spfh_out, int32_t* __restrict__ Pq,
+                                           double* __restrict__ inv100, int32_t* __restrict__ jflag, int xcd,
+                                           DevStatus* st) {
     constexpr int kHalf = kWave / 2;
     const int lane = lane_id();
     const int hf = lane / kHalf, hl = lane % kHalf, sh = kHalf * hf;
-    const int64_t m = clamp_count(st->m_kept, m_cap);
-    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz > pair_mean * m) return;            // long lists: spfh_kernel
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
     uint32_t n64 = 0, nedge = 0;
-    for (int64_t pw = global_wave(); 2 * pw < m; pw += wave_count()) {
+    const XcdItems it = xcd ? xcd_items((m + 1) / 2, off[m] + kItemWork * m,
+                                        [&](int64_t i) { return off[2 * i] + kItemWork * 2 * i; })
+                            : cyclic_items((m + 1) / 2);
+    for (int64_t pw = it.first; pw < it.end; pw += it.stride) {
         const int64_t q = 2 * pw + hf;
         const bool live = q < m;
         const bool has_b = live && (flags[q] & 1);
@@ -363,6 +365,9 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
     }
 }
 
+// SPFH (Eq. A2-A4) of every kept point: two points per wavefront when the
+// mean list length is at most pair_mean, else one; xcd selects the XCD-aware
+// split of the points over the wavefronts.
 __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
                                                       int64_t stride, const int32_t* __restrict__ kept_cloud,
                                                       int64_t m_cap, const float* __restrict__ nrm,
@@ -371,12 +376,18 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                                                       const int32_t* __restrict__ nbr, int H,
                                                       uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
                                                       int32_t* __restrict__ Pq, double* __restrict__ inv100,
-                                                     int32_t* __restrict__ jflag,
-                                                      int pair_mean, DevStatus* st) {
+                                                      int32_t* __restrict__ jflag, int pair_mean, int xcd,
+                                                      DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz <= pair_mean * m) return;           // short lists: spfh_pairs
-    for (int64_t q = global_wave(); q < m; q += wave_count())
+    if (st->nnz <= pair_mean * m) {
+        spfh_pairs(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
+                   jflag, xcd, st);
+        return;
+    }
+    const XcdItems it = xcd ? xcd_items(m, off[m] + kItemWork * m, [&](int64_t i) { return off[i] + kItemWork * i; })
+                            : cyclic_items(m);
+    for (int64_t q = it.first; q < it.end; q += it.stride)
         spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
                    jflag, st, q);
 }
@@ -396,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
                                                      const uint16_t* __restrict__ cnt16,
                                                      const int32_t* __restrict__ Pq,
                                                      const double* __restrict__ inv100, float* __restrict__ fpfh,
-                                                     const DevStatus* st) {
+                                                     int xcd, const DevStatus* st) {
 #pragma clang fp contract(off)
     constexpr int kHalf = kWave / 2;
     __shared__ int32_t s_k[kWaves][2][kHalf];
@@ -413,7 +424,10 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
         if (!jflag[t / D]) fpfh[t] = 0.0f;
     const int64_t n_j = clamp_count(st->n_j, m);
-    for (int64_t pw = global_wave(); 2 * pw < n_j; pw += wave_count()) {
+    const XcdItems it = xcd ? xcd_items((n_j + 1) / 2, off[m] + kItemWork * n_j,
+                                        [&](int64_t i) { return off[j_list[2 * i]] + kItemWork * 2 * i; })
+                            : cyclic_items((n_j + 1) / 2);
+    for (int64_t pw = it.first; pw < it.end; pw += it.stride) {
         const bool live = 2 * pw + hf < n_j;
         const int64_t q = live ? j_list[2 * pw + hf] : 0;
         float qx = 0.f, qy = 0.f, qz = 0.f;
@@ -582,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
                                                       const uint16_t* __restrict__ cnt16,
                                                       const int32_t* __restrict__ Pq,
                                                       const double* __restrict__ inv100, float* __restrict__ fpfh,
-                                                      const DevStatus* st) {
+                                                      int xcd, const DevStatus* st) {
     __shared__ int32_t s_k[kWaves][kWave];
     __shared__ double s_w[kWaves][kWave];
     const int wv = threadIdx.x / kWave;
@@ -593,7 +607,10 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
         if (!jflag[t / D]) fpfh[t] = 0.0f;
     const int64_t n_j = clamp_count(st->n_j, m);
-    for (int64_t g = global_wave(); g < n_j; g += wave_count())
+    const XcdItems it = xcd ? xcd_items(n_j, off[m] + kItemWork * n_j,
+                                        [&](int64_t i) { return off[j_list[i]] + kItemWork * i; })
+                            : cyclic_items(n_j);
+    for (int64_t g = it.first; g < it.end; g += it.stride)
         fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nbr, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
                                  j_list[g]);
 }
@@ -700,10 +717,11 @@ kmg_status fpfh_as(const float* xyz, int64_t stride, int64_t m_cap, const uint8_
     if (kPairs) {
         fpfh_pairs<kRows><<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, jflag, j_idx,
                                                                               off, nbr, H, cnt16, Pq, inv100, fpfh_out,
-                                                                              st);
+                                                                              (tuning().xcd_split >> 1) & 1, st);
     } else {
         fpfh_kernel<kRows><<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, jflag, j_idx, off,
-                                                                     nbr, H, cnt16, Pq, inv100, fpfh_out, st);
+                                                                     nbr, H, cnt16, Pq, inv100, fpfh_out,
+                                                                     (tuning().xcd_split >> 1) & 1, st);
     }
     return launch_status();
 }
@@ -804,12 +822,7 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
         const int pair_mean = tuning().spfh_pair_mean;
         spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
                                                               flags, off, nbr, H, w.cnt16, spfh_out, w.Pq, w.inv100,
-                                                              w.jflag, pair_mean, st);
-        KMG_TRY(launch_status());
-        spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
-                                                                       nrm_stride, flags, off, nbr, H, w.cnt16,
-                                                                       spfh_out, w.Pq, w.inv100, w.jflag, pair_mean,
-                                                                       st);
+                                                              w.jflag, pair_mean, tuning().xcd_split & 1, st);
         KMG_TRY(launch_status());
     }
     return KMG_OK;

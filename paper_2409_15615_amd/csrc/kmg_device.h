@@ -42,6 +42,60 @@ __device__ __forceinline__ int global_wave() {
 }
 __device__ __forceinline__ int wave_count() { return static_cast<int>(gridDim.x * blockDim.x / kWave); }
 
+// XCD-aware split of items [0, n) over the wavefronts of a launch, balanced
+// by work.  The blocks of a launch are dealt to the eight XCDs in turn (block
+// b runs on XCD b % 8; the grid G is a multiple of 8), so XCD x takes the
+// items whose work prefix start(i) (non-decreasing, total `work`) lies in
+// [x work / 8, (x + 1) work / 8), and its wavefronts deal those out in turn
+// (item first + k stride).  Items in input order are spatially coherent (a
+// scan lists its points ring by ring), so each XCD's L2 then holds the
+// neighbourhood of its own eighth rather than of the whole cloud.
+constexpr int kXcds = 8;
+struct XcdItems {
+    int64_t first, end, stride;
+};
+// Wavefront index of the launch in the XCD-aware order: the waves of XCD x
+// (blocks b with b % 8 == x) take indices [x W / 8, (x + 1) W / 8) of the W
+// waves, in block order.
+__device__ __forceinline__ int64_t xcd_block_index() {
+    const int64_t G = gridDim.x;
+    const int64_t b = blockIdx.x;
+    return (G % kXcds == 0) ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
+}
+__device__ __forceinline__ int64_t xcd_wave_index() {
+    return xcd_block_index() * (blockDim.x / kWave) + threadIdx.x / kWave;
+}
+
+// The plain split: item i to wavefront i mod (wavefronts of the launch).
+__device__ __forceinline__ XcdItems cyclic_items(int64_t n) {
+    return XcdItems{static_cast<int64_t>(global_wave()), n, static_cast<int64_t>(wave_count())};
+}
+template <class F>
+__device__ __forceinline__ XcdItems xcd_items(int64_t n, int64_t work, F start) {
+    const int64_t G = gridDim.x;
+    const int64_t wpb = blockDim.x / kWave;
+    const int64_t wv = threadIdx.x / kWave;
+    if (G % kXcds != 0 || n <= 0) return XcdItems{blockIdx.x * wpb + wv, n, G * wpb};
+    const int64_t x = blockIdx.x % kXcds;
+    // first item whose start reaches t: a 64-way search by the wavefront
+    auto first_at = [&](int64_t t) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {  // uniform over the wave
+            const int64_t step = (hi - lo + kWave - 1) / kWave;
+            const int64_t probe = lo + (lane_id() + 1) * step - 1;
+            const bool b = probe < hi && start(probe) < t;
+            const int cnt = __popcll(ballot(b));
+            const int64_t nlo = lo + cnt * step;
+            hi = min(hi, lo + (cnt + 1) * step - 1);
+            lo = nlo;
+        }
+        return lo;
+    };
+    const int64_t b0 = x == 0 ? 0 : first_at((work * x) / kXcds);
+    const int64_t b1 = x == kXcds - 1 ? n : first_at((work * (x + 1)) / kXcds);
+    return XcdItems{b0 + (blockIdx.x / kXcds) * wpb + wv, b1, (G / kXcds) * wpb};
+}
+
 // 64-bit mixing function (the MurmurHash3 fmix64 finaliser).
 __device__ __forceinline__ uint32_t hash_key(uint64_t k) {
     k ^= k >> 33;

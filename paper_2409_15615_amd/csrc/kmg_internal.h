@@ -442,6 +442,7 @@ struct Tuning {
     int fpfh_rows = 8;        // SPFH rows in flight per lane in the FPFH sum (4, 8, 16)
     int band_tile = 0;        // partner chunks per band tile; 0 = the tile-length model's choice
     int fuse_features = 0;    // 1: SPFH and FPFH in one persistent launch (per-cloud readiness counters)
+    int xcd_split = 2;        // bit 0 SPFH, bit 1 FPFH: XCD-aware split of the points over the wavefronts
 };
 const Tuning& tuning();
 bool set_tuning(const Tuning& t);

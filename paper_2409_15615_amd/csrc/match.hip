@@ -498,12 +498,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
     __shared__ int s_tile;
     const int wv = threadIdx.x / kWave;
     const int total = st->err_capacity ? 0 : st->total_tiles;
-    while (true) {
-        if (threadIdx.x == 0) s_tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
-        __syncthreads();
-        const int tile = s_tile;
-        __syncthreads();
-        if (tile >= total) break;
+    // the first tile of every block is fixed (XCD-aware order), the rest come from the queue
+    // counted from kTopkBlocks: one round takes no atomic
+    for (int tile = static_cast<int>(xcd_block_index()); tile < total;) {
         const int c = find_set(n_sets, tile, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
         const SetPlan qc = plan[c];
         const SetPlan pc = plan[c ^ 1];
@@ -515,6 +512,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
         const int c_end = min(c_begin + cps, pc.chunks);
         const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
         tile_block<KS>(pk, dim, qc, pc, col0, c_begin, c_end, seg, part, lds);
+        if (total <= kTopkBlocks) break;  // uniform: every tile was a first tile
+        __syncthreads();                  // every thread has read s_tile
+        if (threadIdx.x == 0) s_tile = kTopkBlocks + static_cast<int>(atomicAdd(&st->tile_next, 1u));
+        __syncthreads();
+        tile = s_tile;
     }
 }
 
@@ -1282,12 +1284,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     __shared__ int s_tile;
     const int wv = threadIdx.x / kWave;
     const int total = st->err_capacity ? 0 : st->total_tiles;
-    while (true) {
-        if (threadIdx.x == 0) s_tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
-        __syncthreads();
-        const int tile = s_tile;
-        __syncthreads();
-        if (tile >= total) break;
+    // the first tile of every block is fixed (XCD-aware order), the rest come from the queue
+    // counted from kTopkBlocks: one round takes no atomic
+    for (int tile = static_cast<int>(xcd_block_index()); tile < total;) {
         const int c = find_set(n_sets, tile, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
         const SetPlan qc = plan[c];
         const SetPlan pc = plan[c ^ 1];
@@ -1300,6 +1299,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         const int col0 = cblk * kColsPerBlock + wv * kColsPerWave;
         tile_block_lp<T>(pk, lp_a, lp_nx, dim, qc, pc, pp[c >> 1], col0, c_begin, c_end, seg, part, lds_pk,
                          lds_rows);
+        if (total <= kTopkBlocks) break;  // uniform: every tile was a first tile
+        __syncthreads();                  // every thread has read s_tile
+        if (threadIdx.x == 0) s_tile = kTopkBlocks + static_cast<int>(atomicAdd(&st->tile_next, 1u));
+        __syncthreads();
+        tile = s_tile;
     }
 }
 
@@ -1599,7 +1603,11 @@ constexpr int kSortThreads = 256;
 constexpr int kRankGroupDiv = 8;       // a set of m tiles ranks against max(1, m / 8) B tiles per item
 constexpr int kBandTiles = 8192;         // band tiles the partial buffer holds beyond one per wave
 constexpr int kSeedRows = kWave;         // partner rows around the query's norm for R
-constexpr int kBandSlots = kTopkBlocks * kWavesPerBlock;  // wavefronts of the band tile kernel
+// Persistent grid of the band tile kernel: two blocks per CU, two waves per
+// SIMD (measured: four waves per SIMD, with tiles of half the length, take
+// twice as long).
+constexpr int kBandBlocks = 512;
+constexpr int kBandSlots = kBandBlocks * kWavesPerBlock;  // wavefronts of the band tile kernel
 
 // Block-wide exclusive scan of K int32 values per thread in one pass (two
 // barriers): v[k] <- the sum over lower threads, tot[k] <- the block total.
@@ -2224,13 +2232,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
     const int g = lane >> 4;
     const int l16 = lane & 15;
     const int total = st->err_capacity ? 0 : st->total_tiles;
-    while (true) {
-        int tile = 0;
-        if (lane == 0) tile = static_cast<int>(atomicAdd(&st->tile_next, 1u));
-        // uniform from here on: the tile's descriptor, plans and buffer resources live in
-        // scalar registers (a per-lane value would wrap every buffer load in a waterfall loop)
-        tile = __builtin_amdgcn_readfirstlane(tile);
-        if (tile >= total) break;
+    // The first tile of every wavefront is fixed, in the XCD-aware order (the waves of one XCD
+    // take one contiguous range of the tile list: adjacent bands, whose partner chunks then stay
+    // in that XCD's L2); only the tiles beyond one per wavefront come from the queue, counted
+    // from kBandSlots.  A plan of at most one round takes no atomic at all (a queue that every
+    // wavefront hits at once serialises on its one counter).
+    // uniform from here on: the tile's descriptor, plans and buffer resources live in scalar
+    // registers (a per-lane value would wrap every buffer load in a waterfall loop)
+    int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(xcd_wave_index()));
+    for (; tile < total;) {
         const int4 ti = tinfo[tile];
         const SetPlan qc = plan[ti.y];
         const SetPlan pc = plan[ti.y ^ 1];
@@ -2258,18 +2268,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
                 const_cast<double*>(pk + static_cast<int64_t>(pc.chunk_off) * kChunk), 0,
                 static_cast<int>(min(static_cast<int64_t>(pc.chunks) * kChunk * 8, static_cast<int64_t>(INT32_MAX))),
                 static_cast<int>(kBufferWord3));
-            double a[KS];
+            // two chunks in flight ahead of the products (a miss in L2 outlasts one chunk's products)
+            double a[KS], an[KS];
+            const int c_second = min(c_begin + 1, c_end - 1);
 #pragma unroll
             for (int s = 0; s < KS; ++s)
                 a[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
                                                        rows, ((c_begin * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                an[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                        rows, ((c_second * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
             for (int c = c_begin; c < c_end; ++c) {
-                const int cn = min(c + 1, c_end - 1);
-                double an[KS];
+                const int cnn = min(c + 2, c_end - 1);
+                double ann[KS];
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
-                    an[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                            rows, ((cn * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
+                    ann[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                             rows, ((cnn * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
                 __builtin_amdgcn_sched_barrier(0);
                 doublex4 acc[kTilesPerWave];
                 chunk_mfma<KS>(acc, a, bq);
@@ -2287,7 +2303,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int s = 0; s < KS; ++s) a[s] = an[s];
+                for (int s = 0; s < KS; ++s) {
+                    a[s] = an[s];
+                    an[s] = ann[s];
+                }
             }
         }
 #pragma unroll
@@ -2303,6 +2322,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
                 dst[3] = top[t][3];
             }
         }
+        if (total <= kBandSlots) break;  // uniform: every tile was a first tile
+        int next = 0;
+        if (lane == 0) next = kBandSlots + static_cast<int>(atomicAdd(&st->tile_next, 1u));
+        tile = __builtin_amdgcn_readfirstlane(next);
     }
 }
 
@@ -2696,11 +2719,11 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     {
         StageScope sc(ST_MATCH_TOPK, s);
         if (ks == 9) {
-            if (oside) band_tiles<9, 0><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
-            else band_tiles<9, 1><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            if (oside) band_tiles<9, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            else band_tiles<9, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
         } else {
-            if (oside) band_tiles<17, 0><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
-            else band_tiles<17, 1><<<kTopkBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            if (oside) band_tiles<17, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            else band_tiles<17, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
         }
         KMG_TRY(launch_status());
         timer_note_work(&st->band_pairs);

@@ -18,6 +18,7 @@ bool set_tuning(const Tuning& t) {
     if (t.fpfh_rows != 4 && t.fpfh_rows != 8 && t.fpfh_rows != 16) return false;
     if (t.band_tile != 0 && !band_tile_candidate(t.band_tile)) return false;
     if (t.fuse_features != 0 && t.fuse_features != 1) return false;
+    if (t.xcd_split < 0 || t.xcd_split > 3) return false;
     g_tuning = t;
     return true;
 }
@@ -29,13 +30,14 @@ extern "C" {
 __attribute__((visibility("default"))) kmg_status kmg_set_tuning(const kmg_tuning* t) {
     kmg::Tuning v;  // defaults
     if (t) {
-        if (t->reserved[0] || t->reserved[1]) return KMG_ERR_ARG;
+        if (t->reserved) return KMG_ERR_ARG;
         v.search_waves = t->search_waves;
         v.count_queries = t->count_queries;
         v.spfh_pair_mean = t->spfh_pair_mean;
         v.fpfh_rows = t->fpfh_rows;
         v.band_tile = t->band_tile;
         v.fuse_features = t->fuse_features;
+        v.xcd_split = t->xcd_split;
     }
     return kmg::set_tuning(v) ? KMG_OK : KMG_ERR_ARG;
 }
@@ -49,7 +51,8 @@ __attribute__((visibility("default"))) kmg_status kmg_get_tuning(kmg_tuning* t) 
     t->fpfh_rows = v.fpfh_rows;
     t->band_tile = v.band_tile;
     t->fuse_features = v.fuse_features;
-    t->reserved[0] = t->reserved[1] = 0;
+    t->xcd_split = v.xcd_split;
+    t->reserved = 0;
     return KMG_OK;
 }
 

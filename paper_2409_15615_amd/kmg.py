@@ -54,11 +54,13 @@ class KmgTuning(C.Structure):
         ("fpfh_rows", C.c_int32),
         ("band_tile", C.c_int32),
         ("fuse_features", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("xcd_split", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
-TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile", "fuse_features")
+TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile", "fuse_features",
+                 "xcd_split")
 
 
 class KmgCloud(C.Structure):

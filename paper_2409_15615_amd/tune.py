@@ -26,6 +26,7 @@ SPACE = {
     "fpfh_rows": (4, 8, 16),
     "band_tile": (0, 8, 12, 16, 20, 24, 32, 48, 64),
     "fuse_features": (0, 1),
+    "xcd_split": (0, 1, 2, 3),
 }
 
 

@@ -38,9 +38,9 @@ def settings():
     for f, vals in SPACE.items():
         out += [{f: v} for v in vals]
     out.append({"search_waves": 8, "count_queries": 4, "spfh_pair_mean": 0, "fpfh_rows": 16, "band_tile": 12,
-                "fuse_features": 1})
+                "fuse_features": 1, "xcd_split": 0})
     out.append({"search_waves": 2, "count_queries": 1, "spfh_pair_mean": 8192, "fpfh_rows": 4, "band_tile": 64,
-                "fuse_features": 0})
+                "fuse_features": 0, "xcd_split": 2})
     return out
 
 
