@@ -246,7 +246,7 @@ __device__ __forceinline__ void spfh_pairs(const CloudDev* __restrict__ cl, cons
             }
         }
         if (!live) continue;
-        uint16_t* row = cnt16 + q * D;
+        uint16_t* row = cnt16 + q * spfh_row(H);
         if (!has_b) {
             for (int t = hl; t < D; t += kHalf) {
                 row[t] = 0;
@@ -294,7 +294,7 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
     const int lane = lane_id();
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
-    uint16_t* row = cnt16 + q * D;
+    uint16_t* row = cnt16 + q * spfh_row(H);
     if (!(flags[q] & 1)) {
         for (int t = lane; t < D; t += kWave) {
             row[t] = 0;
@@ -410,8 +410,9 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
                                                      int xcd, const DevStatus* st) {
 #pragma clang fp contract(off)
     constexpr int kHalf = kWave / 2;
-    __shared__ int32_t s_k[kWaves][2][kHalf];
     __shared__ double s_w[kWaves][2][kHalf];
+    // the SPFH rows of a round of 32 neighbours, one per lane, R entries each (dynamic)
+    extern __shared__ uint4 s_dyn[];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     const int hf = lane / kHalf, hl = lane % kHalf, sh = kHalf * hf;
@@ -419,6 +420,9 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     const int D = 3 * H;
+    const int R = spfh_row(H);
+    const int R8 = R / 8;  // 16-byte pieces of a row
+    uint4* s_rows = s_dyn + (wv * 2 + hf) * kHalf * R8;
     const int64_t s2 = 2 * stride;
     const int64_t gt = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
@@ -459,28 +463,32 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
             const uint32_t bm = static_cast<uint32_t>(ballot(use) >> sh);
             __builtin_amdgcn_wave_barrier();
             if (use) {
+                // the lane's whole row in 16-byte pieces, every row of the round in flight at once
                 const int at = __popc(bm & below);
-                s_k[wv][hf][at] = k;
+                const uint4* src = reinterpret_cast<const uint4*>(cnt16 + static_cast<int64_t>(k) * R);
+                uint4* dst = s_rows + at * R8;
+                for (int i = 0; i < R8; ++i) dst[i] = src[i];
                 s_w[wv][hf][at] = w;
             }
             __builtin_amdgcn_wave_barrier();
             const int nuse = __popc(bm);
             const int numax = max(nuse, __shfl_xor(nuse, kHalf, kWave));
+            // the rows summed in ascending neighbour order, bin by bin from LDS
+            const uint16_t* rows = reinterpret_cast<const uint16_t*>(s_rows);
             for (int j = 0; j < numax; j += kBatchNarrow) {
-                double v0[kBatchNarrow], v1[kBatchNarrow];
+                double v0[kBatchNarrow], v1[kBatchNarrow], wj[kBatchNarrow];
 #pragma unroll
                 for (int u = 0; u < kBatchNarrow; ++u) {
-                    const int64_t r = j + u < nuse ? s_k[wv][hf][j + u] : q;
-                    const uint16_t* sk = cnt16 + r * D;
-                    v0[u] = static_cast<double>(sk[lb0]);
-                    v1[u] = D > kHalf ? static_cast<double>(sk[lb1]) : 0.0;
+                    const int r = min(j + u, kHalf - 1);
+                    v0[u] = static_cast<double>(rows[r * R + lb0]);
+                    v1[u] = static_cast<double>(rows[r * R + lb1]);
+                    wj[u] = s_w[wv][hf][r];
                 }
 #pragma unroll
                 for (int u = 0; u < kBatchNarrow; ++u) {
                     if (j + u < nuse) {
-                        const double wj = s_w[wv][hf][j + u];
-                        acc0 = acc0 + wj * v0[u];
-                        acc1 = acc1 + wj * v1[u];
+                        acc0 = acc0 + wj[u] * v0[u];
+                        acc1 = acc1 + wj[u] * v1[u];
                     }
                 }
             }
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
         if (!live) continue;
         float* out = fpfh + q * D;
         const int P = Pq[q];
-        const uint16_t* sq = cnt16 + q * D;
+        const uint16_t* sq = cnt16 + q * R;
         if (P == 0) {
             if (hl < D) out[hl] = 0.0f;
             if (hl + kHalf < D) out[hl + kHalf] = 0.0f;
@@ -512,6 +520,7 @@ __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_
 #pragma clang fp contract(off)
     const int lane = lane_id();
     const int D = 3 * H;
+    const int R = spfh_row(H);
     const int64_t s2 = 2 * stride;
     float* out = fpfh + q * D;
     const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
@@ -545,7 +554,7 @@ __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_
                 double v0[kBatchNarrow];
 #pragma unroll
                 for (int u = 0; u < kBatchNarrow; ++u)
-                    v0[u] = static_cast<double>(cnt16[static_cast<int64_t>(s_k[j + u]) * D + lb0]);
+                    v0[u] = static_cast<double>(cnt16[static_cast<int64_t>(s_k[j + u]) * R + lb0]);
 #pragma unroll
                 for (int u = 0; u < kBatchNarrow; ++u) acc0 = acc0 + s_w[j + u] * v0[u];
             }
@@ -554,7 +563,7 @@ __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_
             double v0[kBatch], v1[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[j + u]) * D;
+                const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[j + u]) * R;
                 v0[u] = static_cast<double>(sk[lb0]);
                 v1[u] = D > kWave ? static_cast<double>(sk[lb1]) : 0.0;
             }
@@ -567,13 +576,13 @@ __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_
         }
         for (; j < nuse; ++j) {
             const double wj = s_w[j];
-            const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[j]) * D;
+            const uint16_t* sk = cnt16 + static_cast<int64_t>(s_k[j]) * R;
             acc0 = acc0 + wj * static_cast<double>(sk[lb0]);
             if (D > kWave) acc1 = acc1 + wj * static_cast<double>(sk[lb1]);
         }
     }
     const int P = Pq[q];
-    const uint16_t* sq = cnt16 + q * D;
+    const uint16_t* sq = cnt16 + q * R;
     if (P == 0) {
         if (lane < D) out[lane] = 0.0f;
         if (lane + kWave < D) out[lane + kWave] = 0.0f;
@@ -715,7 +724,9 @@ kmg_status fpfh_as(const float* xyz, int64_t stride, int64_t m_cap, const uint8_
                    const int32_t* j_idx, const int32_t* off, const int32_t* nbr, int H, const uint16_t* cnt16,
                    const int32_t* Pq, const double* inv100, float* fpfh_out, const DevStatus* st, hipStream_t s) {
     if (kPairs) {
-        fpfh_pairs<kRows><<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, jflag, j_idx,
+        // dynamic LDS: one SPFH row per lane of the block
+        const size_t rows_lds = static_cast<size_t>(kBlock) * spfh_row(H) * sizeof(uint16_t);
+        fpfh_pairs<kRows><<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, rows_lds, s>>>(xyz, stride, m_cap, flags, jflag, j_idx,
                                                                               off, nbr, H, cnt16, Pq, inv100, fpfh_out,
                                                                               (tuning().xcd_split >> 1) & 1, st);
     } else {
@@ -799,7 +810,7 @@ __global__ void cloud_j_ranges(int n_clouds, int64_t m_cap, const int32_t* __res
 FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
     FeatWs w;
     const size_t mc = static_cast<size_t>(std::max<int64_t>(m_cap, 1));
-    w.cnt16 = c.take<uint16_t>(mc * 3 * H);
+    w.cnt16 = c.take<uint16_t>(mc * spfh_row(H));
     w.inv100 = c.take<double>(mc);
     w.queue = c.take<uint32_t>(1);
     w.ready = c.take<int32_t>(kMaxClouds);

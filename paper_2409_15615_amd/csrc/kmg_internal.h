@@ -305,8 +305,12 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
                              int32_t* n_normal, hipStream_t s, int use_rn = 0, bool with_normals = true);
 
 // ---- features.hip ---------------------------------------------------------
+// Row stride of the SPFH counts, in entries: 3H rounded up to a multiple of 8,
+// so that every row starts on a 16-byte boundary and is read with 16-byte loads.
+__host__ __device__ constexpr int spfh_row(int H) { return (3 * H + 7) & ~7; }
+
 struct FeatWs {
-    uint16_t* cnt16;  // SPFH bin counts (Eq. A4 numerators), m x 3H
+    uint16_t* cnt16;  // SPFH bin counts (Eq. A4 numerators), m rows of spfh_row(H) (3H used)
     double* inv100;   // 100 / P_q (0 when P_q = 0)
     uint32_t* queue;  // work queue of the fused SPFH / FPFH launch
     int32_t* ready;   // per cloud: points whose SPFH is written (fused launch)
