@@ -174,14 +174,16 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
 // Lists of a mean of at most kHalfListMean entries per point: two points per
 // wavefront, one per half of 32 lanes (each lane one neighbour of its half's
 // point per round, bin counts from ballots split by half, lane h of a half
-// holding bin h).  Longer lists: one point per wavefront.  spfh_kernel checks
-// the mean on the device and takes one form or the other.  The threshold is
-// measured: the 64-pair batch (mean 22.5) runs 1.5x faster in pairs, the
-// LiDAR pair (mean 29, but a long tail of structure points next to scattered
-// outliers with a few neighbours) 8% slower.
+// holding bin h).  Longer lists: spfh_kernel, one point per wavefront.  Each
+// kernel checks the mean and returns at once when the other one serves it
+// (one kernel holding both bodies was measured slower: its one-wave body runs
+// slower than alone, 64.7 -> 70.5 us for the pass on the LiDAR pair, more than
+// the launch it saves).  The threshold is measured: the 64-pair batch (mean
+// 22.5) runs 1.5x faster in pairs, the LiDAR pair (mean 29, but a long tail of
+// structure points next to scattered outliers with a few neighbours) 8% slower.
 constexpr int kHalfListMean = 24;  // the default of tuning().spfh_pair_mean
 
-__device__ __forceinline__ void spfh_pairs(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
+__device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
                                            int64_t stride, const int32_t* __restrict__ kept_cloud, int64_t m,
                                            const float* __restrict__ nrm, int64_t nrm_stride,
                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
@@ -365,9 +367,26 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
     }
 }
 
-// SPFH (Eq. A2-A4) of every kept point: two points per wavefront when the
-// mean list length is at most pair_mean, else one; xcd selects the XCD-aware
-// split of the points over the wavefronts.
+__global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
+                                                     int64_t stride, const int32_t* __restrict__ kept_cloud,
+                                                     int64_t m_cap, const float* __restrict__ nrm,
+                                                     int64_t nrm_stride, const uint8_t* __restrict__ flags,
+                                                     const int32_t* __restrict__ off,
+                                                     const int32_t* __restrict__ nbr, int H,
+                                                     uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
+                                                     int32_t* __restrict__ Pq, double* __restrict__ inv100,
+                                                     int32_t* __restrict__ jflag, int pair_mean, int xcd,
+                                                     DevStatus* st) {
+    const int64_t m = clamp_count(st->m_kept, m_cap);
+    if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
+    if (st->nnz > pair_mean * m) return;            // long lists: spfh_kernel
+    spfh_pairs_body(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
+                    jflag, xcd, st);
+}
+
+// SPFH (Eq. A2-A4) of every kept point when the mean list length exceeds
+// pair_mean, one point per wavefront; xcd selects the XCD-aware split of the
+// points over the wavefronts.
 __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict__ cl, const float* __restrict__ xyz,
                                                       int64_t stride, const int32_t* __restrict__ kept_cloud,
                                                       int64_t m_cap, const float* __restrict__ nrm,
@@ -380,11 +399,7 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                                                       DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz <= pair_mean * m) {
-        spfh_pairs(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
-                   jflag, xcd, st);
-        return;
-    }
+    if (st->nnz <= pair_mean * m) return;           // short lists: spfh_pairs
     const XcdItems it = xcd ? xcd_items(m, off[m] + kItemWork * m, [&](int64_t i) { return off[i] + kItemWork * i; })
                             : cyclic_items(m);
     for (int64_t q = it.first; q < it.end; q += it.stride)
@@ -834,6 +849,11 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
         spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
                                                               flags, off, nbr, H, w.cnt16, spfh_out, w.Pq, w.inv100,
                                                               w.jflag, pair_mean, tuning().xcd_split & 1, st);
+        KMG_TRY(launch_status());
+        spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
+                                                                       nrm_stride, flags, off, nbr, H, w.cnt16,
+                                                                       spfh_out, w.Pq, w.inv100, w.jflag, pair_mean,
+                                                                       tuning().xcd_split & 1, st);
         KMG_TRY(launch_status());
     }
     return KMG_OK;
