@@ -149,8 +149,10 @@ const char* kmg_stage_name(int32_t stage);
  *   spfh_pair_mean  mean neighbour-list length up to which the SPFH pass
  *                   (Eq. A2-A4) takes two points per wavefront (default 24;
  *                   0 = never, 8192 = always).
- *   fpfh_rows       SPFH rows in flight per lane in the FPFH sum (Eq. A5):
- *                   4, 8 (default) or 16.
+ *   fpfh_rows       SPFH rows per unrolled step of the FPFH sum (Eq. A5):
+ *                   rows read from LDS per step where two J points share a
+ *                   wavefront (3H <= 64), rows in flight per lane otherwise;
+ *                   1, 2 (default), 4, 8 or 16.
  *   band_tile       partner chunks per distance tile of matching (a length
  *                   of the planner's candidate set: 1..64, then four per
  *                   octave up to 4096), used whenever its tiles fit; 0

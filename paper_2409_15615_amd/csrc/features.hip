@@ -758,6 +758,12 @@ kmg_status launch_fpfh(int rows, const float* xyz, int64_t stride, int64_t m_cap
                        const uint16_t* cnt16, const int32_t* Pq, const double* inv100, float* fpfh_out,
                        const DevStatus* st, hipStream_t s) {
     switch (rows) {
+        case 1:
+            return fpfh_as<kPairs, 1>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+                                      fpfh_out, st, s);
+        case 2:
+            return fpfh_as<kPairs, 2>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+                                      fpfh_out, st, s);
         case 4:
             return fpfh_as<kPairs, 4>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
                                       fpfh_out, st, s);

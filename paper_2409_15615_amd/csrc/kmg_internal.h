@@ -443,7 +443,7 @@ struct Tuning {
     int search_waves = 4;     // waves per block of the radius count and fill passes (2, 4, 8)
     int count_queries = 2;    // queries per wavefront in the count pass (1, 2, 4)
     int spfh_pair_mean = 24;  // mean list length up to which SPFH takes two points per wavefront
-    int fpfh_rows = 8;        // SPFH rows in flight per lane in the FPFH sum (4, 8, 16)
+    int fpfh_rows = 2;        // SPFH rows per unrolled step of the FPFH sum (1, 2, 4, 8, 16)
     int band_tile = 0;        // partner chunks per band tile; 0 = the tile-length model's choice
     int fuse_features = 0;    // 1: SPFH and FPFH in one persistent launch (per-cloud readiness counters)
     int xcd_split = 2;        // bit 0 SPFH, bit 1 FPFH: XCD-aware split of the points over the wavefronts

@@ -15,7 +15,8 @@ bool set_tuning(const Tuning& t) {
     if (t.search_waves != 2 && t.search_waves != 4 && t.search_waves != 8) return false;
     if (t.count_queries != 1 && t.count_queries != 2 && t.count_queries != 4) return false;
     if (t.spfh_pair_mean < 0 || t.spfh_pair_mean > kMaxDegree) return false;
-    if (t.fpfh_rows != 4 && t.fpfh_rows != 8 && t.fpfh_rows != 16) return false;
+    if (t.fpfh_rows != 1 && t.fpfh_rows != 2 && t.fpfh_rows != 4 && t.fpfh_rows != 8 && t.fpfh_rows != 16)
+        return false;
     if (t.band_tile != 0 && !band_tile_candidate(t.band_tile)) return false;
     if (t.fuse_features != 0 && t.fuse_features != 1) return false;
     if (t.xcd_split < 0 || t.xcd_split > 3) return false;

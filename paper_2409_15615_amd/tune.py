@@ -23,7 +23,7 @@ SPACE = {
     "search_waves": (2, 4, 8),
     "count_queries": (1, 2, 4),
     "spfh_pair_mean": (0, 16, 24, 32, 8192),
-    "fpfh_rows": (4, 8, 16),
+    "fpfh_rows": (1, 2, 4, 8, 16),
     "band_tile": (0, 8, 12, 16, 20, 24, 32, 48, 64),
     "fuse_features": (0, 1),
     "xcd_split": (0, 1, 2, 3),
