@@ -173,9 +173,10 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
 
 // Lists of a mean of at most kHalfListMean entries per point: two points per
 // wavefront, one per half of 32 lanes (each lane one neighbour of its half's
-// point per round, bin counts from ballots split by half, lane h of a half
-// holding bin h).  Longer lists: spfh_kernel, one point per wavefront.  Each
-// kernel checks the mean and returns at once when the other one serves it
+// point per round, adding its three bins to the half's LDS histogram with
+// integer atomics; lane h of a half then reads bin h).  Longer lists:
+// spfh_kernel, one point per wavefront.  Each kernel checks the mean and
+// returns at once when the other one serves it
 // (one kernel holding both bodies was measured slower: its one-wave body runs
 // slower than alone, 64.7 -> 70.5 us for the pass on the LiDAR pair, more than
 // the launch it saves).  The threshold is measured: the 64-pair batch (mean
@@ -190,7 +191,7 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
                                            const int32_t* __restrict__ nbr, int H, uint16_t* __restrict__ cnt16,
                                            float* __restrict__ spfh_out, int32_t* __restrict__ Pq,
                                            double* __restrict__ inv100, int32_t* __restrict__ jflag, int xcd,
-                                           DevStatus* st) {
+                                           DevStatus* st, uint32_t* s_hist) {
     constexpr int kHalf = kWave / 2;
     const int lane = lane_id();
     const int hf = lane / kHalf, hl = lane % kHalf, sh = kHalf * hf;
@@ -215,7 +216,10 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
         const int len = e - b;
         const int lmax = max(len, __shfl_xor(len, kHalf, kWave));
         int n_valid = 0;
-        int c0 = 0, c1 = 0, c2 = 0;
+        // the half's histogram in LDS (3H counters), one atomic per lane and feature
+        uint32_t* hist = s_hist + hf * 3 * kMaxBins;
+        for (int t = hl; t < D; t += kHalf) hist[t] = 0u;
+        __builtin_amdgcn_wave_barrier();
         for (int base = 0; base < lmax; base += kHalf) {
             bool valid = false;
             int bn[3] = {-1, -1, -1};
@@ -236,17 +240,21 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
                 }
             }
             n_valid += __popc(static_cast<uint32_t>(ballot(valid) >> sh));
-            for (int h = 0; h < H; ++h) {
-                const int a0 = __popc(static_cast<uint32_t>(ballot(bn[0] == h) >> sh));
-                const int a1 = __popc(static_cast<uint32_t>(ballot(bn[1] == h) >> sh));
-                const int a2 = __popc(static_cast<uint32_t>(ballot(bn[2] == h) >> sh));
-                if (hl == h) {
-                    c0 += a0;
-                    c1 += a1;
-                    c2 += a2;
-                }
+            if (bn[0] >= 0) {
+                atomicAdd(hist + bn[0], 1u);
+                atomicAdd(hist + H + bn[1], 1u);
+                atomicAdd(hist + 2 * H + bn[2], 1u);
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        // lane h of a half holds the counts of bin h for the three features
+        int c0 = 0, c1 = 0, c2 = 0;
+        if (hl < H) {
+            c0 = static_cast<int>(hist[hl]);
+            c1 = static_cast<int>(hist[H + hl]);
+            c2 = static_cast<int>(hist[2 * H + hl]);
+        }
+        __builtin_amdgcn_wave_barrier();  // the histogram is free for the next pair of points
         if (!live) continue;
         uint16_t* row = cnt16 + q * spfh_row(H);
         if (!has_b) {
@@ -292,7 +300,7 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
                                            const int32_t* __restrict__ nbr, int H, uint16_t* __restrict__ cnt16,
                                            float* __restrict__ spfh_out, int32_t* __restrict__ Pq,
                                            double* __restrict__ inv100, int32_t* __restrict__ jflag, DevStatus* st,
-                                           int64_t q) {
+                                           int64_t q, uint32_t* s_hist) {
     const int lane = lane_id();
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
@@ -312,9 +320,10 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
     const V3f pq = {xyz[q], xyz[stride + q], xyz[s2 + q]};
     const V3f nq = {nrm[q], nrm[nrm_stride + q], nrm[n2 + q]};
     const int b = off[q], e = off[q + 1];
+    // the wavefront's histogram in LDS (3H counters), one atomic per lane and feature
+    for (int t = lane; t < D; t += kWave) s_hist[t] = 0u;
+    __builtin_amdgcn_wave_barrier();
     int n_valid = 0;
-    // lane h holds the counts of bin h for the three features
-    int c0 = 0, c1 = 0, c2 = 0;
     uint32_t n64 = 0, nedge = 0;
     for (int base = b; base < e; base += kWave) {
         const int t = base + lane;
@@ -337,17 +346,21 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
             }
         }
         n_valid += __popcll(ballot(valid));
-        for (int h = 0; h < H; ++h) {
-            const int a0 = __popcll(ballot(bn[0] == h));
-            const int a1 = __popcll(ballot(bn[1] == h));
-            const int a2 = __popcll(ballot(bn[2] == h));
-            if (lane == h) {
-                c0 += a0;
-                c1 += a1;
-                c2 += a2;
-            }
+        if (bn[0] >= 0) {
+            atomicAdd(s_hist + bn[0], 1u);
+            atomicAdd(s_hist + H + bn[1], 1u);
+            atomicAdd(s_hist + 2 * H + bn[2], 1u);
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    // lane h holds the counts of bin h for the three features
+    int c0 = 0, c1 = 0, c2 = 0;
+    if (lane < H) {
+        c0 = static_cast<int>(s_hist[lane]);
+        c1 = static_cast<int>(s_hist[H + lane]);
+        c2 = static_cast<int>(s_hist[2 * H + lane]);
+    }
+    __builtin_amdgcn_wave_barrier();  // the histogram is free for the wavefront's next point
     n64 = wave_sum(n64);
     nedge = wave_sum(nedge);
     const int P = n_valid - 1;
@@ -380,8 +393,9 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     if (st->nnz > pair_mean * m) return;            // long lists: spfh_kernel
+    __shared__ uint32_t s_hist[kWaves][2 * 3 * kMaxBins];
     spfh_pairs_body(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
-                    jflag, xcd, st);
+                    jflag, xcd, st, s_hist[threadIdx.x / kWave]);
 }
 
 // SPFH (Eq. A2-A4) of every kept point when the mean list length exceeds
@@ -402,9 +416,10 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
     if (st->nnz <= pair_mean * m) return;           // short lists: spfh_pairs
     const XcdItems it = xcd ? xcd_items(m, off[m] + kItemWork * m, [&](int64_t i) { return off[i] + kItemWork * i; })
                             : cyclic_items(m);
+    __shared__ uint32_t s_hist[kWaves][3 * kMaxBins];
     for (int64_t q = it.first; q < it.end; q += it.stride)
         spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
-                   jflag, st, q);
+                   jflag, st, q, s_hist[threadIdx.x / kWave]);
 }
 
 // FPFH of rows of at most 64 values over the J list, two points per
@@ -667,6 +682,7 @@ __global__ __launch_bounds__(kBlock) void features_fused(
     int32_t* ready, DevStatus* st) {
     __shared__ int32_t s_k[kWaves][kWave];
     __shared__ double s_w[kWaves][kWave];
+    __shared__ uint32_t s_hist[kWaves][3 * kMaxBins];
     const int wv = threadIdx.x / kWave;
     const int lane = lane_id();
     const int64_t m = clamp_count(st->m_kept, m_cap);
@@ -684,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void features_fused(
             const int64_t p1 = min(p0 + kFuseChunk, m);
             for (int64_t q = p0; q < p1; ++q)
                 spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq,
-                           inv100, jflag, st, q);
+                           inv100, jflag, st, q, s_hist[wv]);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (lane == 0) {
                 // the chunk's points by cloud (a chunk rarely crosses a cloud boundary)
