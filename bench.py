@@ -55,12 +55,16 @@ TILE_TRAFFIC = {
     "fetch_scale": 262144.0 / 131085.2,
     "write_kib": 4007.1,
     "write_scale": 262144.0 / 262144.0,
+    # the matching form the counters were taken with (the launch holds one direction in form 0)
+    "match_form": 0,
 }
 
 
-def tile_traffic_bytes():
+def tile_traffic_bytes(match_form=0):
     import hashlib
 
+    if match_form != TILE_TRAFFIC["match_form"]:
+        return None
     path = os.path.join(ROOT, TILE_TRAFFIC["source"])
     with open(path, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != TILE_TRAFFIC["sha256"]:
@@ -85,6 +89,49 @@ def timed(fn, steps, sync):
         lat.append((time.perf_counter() - ts) * 1e3)
     t1 = time.perf_counter()
     return t1 - t0, lat
+
+
+def batch_fingerprint(batch):
+    """Digests of a batch's results for the autotuner's invariance check: pair counts,
+    sizes and statuses (counts without column 5, the exact re-scans, a work statistic
+    that depends on the matching form), correspondences, d1, d2."""
+    import hashlib
+
+    counts = batch.counts.clone()
+    counts[:, 5] = 0
+    return tuple(hashlib.sha256(t.cpu().numpy().tobytes()).hexdigest()[:16]
+                 for t in (counts, batch.pairs, batch.d1, batch.d2))
+
+
+def back_to_back(fn, steps, sync):
+    """Seconds for `steps` calls of fn issued back to back, bracketed by synchronisations
+    (the throughput measure; timed() adds a synchronisation per call for latencies)."""
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def tune_for(kmg, run, fingerprint, args, graph_inner):
+    """The launch tuning of one workload: forced by --tuning, the defaults with
+    --no-autotune, else picked by the autotuner on graph replays of run()."""
+    import json as _json
+
+    from paper_2409_15615_amd.tune import autotune
+
+    t0 = time.perf_counter()
+    if args.tuning:
+        kmg.set_tuning(_json.loads(args.tuning))
+        return {"setting": kmg.get_tuning(), "autotuned": False, "forced": True}
+    if args.no_autotune:
+        kmg.set_tuning(None)
+        return {"setting": kmg.get_tuning(), "autotuned": False}
+    best, t_best, t_def, log = autotune(run, fingerprint, reps=5, rounds=2, graph=True, inner=graph_inner,
+                                        min_gain=0.003)
+    return {"setting": best, "autotuned": True, "tuned_ms": round(t_best, 4), "default_ms": round(t_def, 4),
+            "settings_timed": len(log), "tuning_s": round(time.perf_counter() - t0, 1)}
 
 
 def read_stages(lib, steps):
@@ -227,19 +274,14 @@ def run_batch64(args, lib, kmg, torch, synth, dev):
     from paper_2409_15615_amd.tune import autotune
 
     def fingerprint():
-        import hashlib
-
-        h = hashlib.sha256()
-        for t in (batch.counts, batch.pairs, batch.d1, batch.d2):
-            h.update(t.cpu().numpy().tobytes())
-        return h.hexdigest()
+        return batch_fingerprint(batch)
 
     t_tune = time.perf_counter()
     if args.no_autotune:
         kmg.set_tuning(None)
         tuned = {"setting": kmg.get_tuning(), "autotuned": False}
     else:
-        best, t_best, t_def, log = autotune(batched, fingerprint, reps=3, rounds=2)
+        best, t_best, t_def, log = autotune(batched, fingerprint, reps=3, rounds=2, min_gain=0.003)
         tuned = {"setting": best, "autotuned": True, "tuned_ms": round(t_best, 3), "default_ms": round(t_def, 3),
                  "settings_timed": len(log), "tuning_s": round(time.perf_counter() - t_tune, 1)}
     for _ in range(2):
@@ -669,7 +711,11 @@ def main():
                          "with FP64, FP16 and BF16 candidate tiles; classic: the LiDAR pair with classical FPFH "
                          "(three searches, no filters) beside Faster-PFH, per-stage form")
     ap.add_argument("--requests", type=int, default=2000, help="serve: timed requests per rate (after 200 warm-up)")
-    ap.add_argument("--no-autotune", action="store_true", help="batch64: time the default launch shapes")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="lidar, batch64: time the default launch shapes (no autotuning)")
+    ap.add_argument("--tuning", default="", metavar="JSON",
+                    help="lidar: time this launch tuning (kmg_set_tuning fields) instead of autotuning, "
+                         "e.g. for counter passes")
     ap.add_argument("--max-wait-ms", type=float, default=2.0, help="serve: batching window of the oldest request")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the JSON line, run a streaming add over MIB MiB (read MIB, write MIB) three "
@@ -712,6 +758,19 @@ def main():
     tgt = torch.from_numpy(d["tgt"]).to(dev)
     sync = torch.cuda.synchronize
 
+    # the pair as a one-pair batch; the launch tuning of this workload (autotuned on graph
+    # replays, results checked identical for every setting) is in force for every form below
+    clouds = [(src, ps), (tgt, pt)]
+    _, probe = kmg.register_batch(clouds, prec=args.prec)
+    batch = kmg.Batch(1, probe.raw_cap, probe.nnz() + 4096, p.n_bins, device=dev)
+    batch.upload(clouds)
+
+    def batched():
+        batch.run(args.prec)
+
+    tuned = tune_for(kmg, batched, lambda: batch_fingerprint(batch), args, graph_inner=20)
+    match_form = int(kmg.get_tuning()["match_form"])
+
     # plain form
     ws = kmg.Workspace(dev)
     state = {}
@@ -725,14 +784,6 @@ def main():
     a, b, mt = state["plain"]
 
     # batched form (one pair per batch), stage timing over its timed steps
-    clouds = [(src, ps), (tgt, pt)]
-    _, probe = kmg.register_batch(clouds, prec=args.prec)
-    batch = kmg.Batch(1, probe.raw_cap, probe.nnz() + 4096, p.n_bins, device=dev)
-    batch.upload(clouds)
-
-    def batched():
-        batch.run(args.prec)
-
     for _ in range(args.warmup):
         batched()
     lib.kmg_timing_enable(1)
@@ -759,7 +810,8 @@ def main():
         batched()
     for _ in range(args.warmup):
         g.replay()
-    t_graph, lat_graph = timed(g.replay, args.steps, sync)
+    t_graph = back_to_back(g.replay, args.steps, sync)
+    _, lat_graph = timed(g.replay, args.steps, sync)
     res_g = batch.results()[0]
 
     same = (torch.equal(res.pairs, mt.pairs) and torch.equal(res_g.pairs, mt.pairs)
@@ -780,6 +832,9 @@ def main():
         _, bprobe = kmg.register_batch(bclouds)
         bb = kmg.Batch(len(more), bprobe.raw_cap, bprobe.nnz() + 4096, p.n_bins, device=dev)
         bb.upload(bclouds)
+
+        btuned = tune_for(kmg, lambda: bb.run("fp32"), lambda: batch_fingerprint(bb), args, graph_inner=2)
+        batched_forms[f"batch{len(more)}_tuning"] = btuned
         outs = {}
         for prec in ("fp32", "bf16"):
             def brun(prec=prec):
@@ -797,7 +852,8 @@ def main():
             for _ in range(2):
                 gb.replay()
             nb = max(3, args.steps // 4)
-            tb, latb = timed(gb.replay, nb, sync)
+            tb = back_to_back(gb.replay, nb, sync)
+            _, latb = timed(gb.replay, nb, sync)
             rb = bb.results()
             outs[prec] = [(x.pairs.cpu().numpy().tobytes(), x.d1.cpu().numpy().tobytes(),
                            x.d2.cpu().numpy().tobytes()) for x in rb]
@@ -814,8 +870,9 @@ def main():
     dim = 3 * p.n_bins
     i_topk = names.index("match_topk")
     topk_avg_s = ms[i_topk] / max(1, ln[i_topk]) / 1e3
-    dense = 2.0 * nj_p * nj_q * dim  # every query against every row, first direction
-    # what the band tiles of the first direction evaluate (the matching back is its own stage)
+    # every query against every row, in the directions the band tile launch covers
+    dense = 2.0 * nj_p * nj_q * dim * (2 if match_form == 1 else 1)
+    # what the band tiles of that launch evaluate (in form 0 the matching back is its own stage)
     flops_per_launch = 2.0 * dim * band_pairs if band_pairs > 0 else dense
     achieved = flops_per_launch / topk_avg_s / 1e12 if topk_avg_s > 0 else 0.0
 
@@ -843,7 +900,9 @@ def main():
             "correspondences": int(res.pairs.shape[0]),
             "exact_rescans": int(res.n_fallback),
             "precision": args.prec,
-            "form": "graph-replayed kmg_batch_run, one pair per step",
+            "form": "graph-replayed kmg_batch_run, one pair per replay; value from back-to-back replays "
+                    "(synchronised before and after), p50/p99 from replays synchronised one at a time; "
+                    "launch tuning autotuned on this pair (see tuning)",
         },
         "p50_ms": round(statistics.median(lat_graph), 4),
         "p99_ms": round(pct(lat_graph, 0.99), 4),
@@ -858,15 +917,19 @@ def main():
             **batched_forms,
         },
         "stages_ms_per_step": stages,
+        "tuning": tuned,
         "roofline": {
-            "kernel": "band_tiles (FP64 MFMA distance tiles over the norm bands + top-4 epilogue), the "
-                      "persistent launch of the first matching direction (smaller set as queries)",
+            "kernel": ("band_tiles (FP64 MFMA distance tiles over the norm bands + top-4 epilogue), the "
+                       "persistent launch of the first matching direction (smaller set as queries)")
+                      if match_form == 0 else
+                      ("band_tiles (FP64 MFMA distance tiles over the norm bands + top-4 epilogue), the "
+                       "persistent launch of both matching directions in full"),
             "bound": "mfma",
             "achieved": round(achieved, 4),
             "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 5),
-            "traffic": tile_traffic_bytes(),
+            "traffic": tile_traffic_bytes(match_form),
             "avg_launch_ms": round(topk_avg_s * 1e3, 5),
             "flops_per_launch": flops_per_launch,
             "band_fraction": round(flops_per_launch / dense, 4),

@@ -168,7 +168,13 @@ const char* kmg_stage_name(int32_t stage);
  *                   eighth's neighbourhood) rather than in turn; 0..3,
  *                   default 2 (measured: the FPFH gather reads its
  *                   neighbours' rows and gains, the SPFH pass loses).
- *   reserved        must be 0.
+ *   match_form      FP64 matching (Section III-C reciprocity test) of a batch
+ *                   that fits the one-sided form: 0 (default) matches the
+ *                   smaller set of each pair against the larger, then only
+ *                   the rows that are some query's nearest neighbour back;
+ *                   1 matches both directions in full in one band pass (more
+ *                   distance tiles, fewer launches).  The same
+ *                   correspondences, d1 and d2 either way.
  * kmg_set_tuning(NULL) restores the defaults; unsupported values give
  * KMG_ERR_ARG and leave the tuning unchanged.
  */
@@ -180,7 +186,7 @@ typedef struct {
     int32_t band_tile;
     int32_t fuse_features;
     int32_t xcd_split;
-    int32_t reserved;
+    int32_t match_form;
 } kmg_tuning;
 kmg_status kmg_set_tuning(const kmg_tuning* t);
 kmg_status kmg_get_tuning(kmg_tuning* t);
@@ -313,7 +319,8 @@ kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, con
  *
  * counts [out, DEVICE] int64[8 * n_pairs]: per pair, 0 correspondences,
  * 1 kept source points, 2 kept target points, 3 |J| source, 4 |J| target,
- * 5 queries re-scanned exactly, 6 status (a kmg_status; KMG_ERR_WORKSPACE
+ * 5 queries re-scanned exactly (a work statistic: it depends on the matching
+ * form of the launch tuning, the other entries do not), 6 status (a kmg_status; KMG_ERR_WORKSPACE
  * when the batch's neighbour entries exceed nnz_cap, KMG_ERR_CAPACITY when
  * outs[i].cap is too small), 7 neighbour entries of the whole batch.
  *

@@ -447,6 +447,7 @@ struct Tuning {
     int band_tile = 0;        // partner chunks per band tile; 0 = the tile-length model's choice
     int fuse_features = 0;    // 1: SPFH and FPFH in one persistent launch (per-cloud readiness counters)
     int xcd_split = 2;        // bit 0 SPFH, bit 1 FPFH: XCD-aware split of the points over the wavefronts
+    int match_form = 0;       // 0: one-sided matching then the image back; 1: both directions in one pass
 };
 const Tuning& tuning();
 bool set_tuning(const Tuning& t);

@@ -1493,6 +1493,95 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
     if (blockIdx.x == 0 && threadIdx.x == 0 && st2->err_capacity) st->err_capacity = 1;
 }
 
+// ------------------------------------------- both directions in full --
+//
+// Each pair as four sets, (set 2i as queries, set 2i+1 rows only) and (set
+// 2i+1 as queries, set 2i rows only), matched in one band pass: no second pass
+// over the image, at the price of matching every row of the larger set back.
+// A pair (j, i) is mutual when j's nearest neighbour is i and i's is j.
+
+__global__ void both_sets(const MatchSet* __restrict__ sets, int n_sets, MatchSet* __restrict__ out,
+                          DevStatus* st2) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_sets) {
+        MatchSet q = sets[t];
+        q.flags &= ~kSetRowsOnly;
+        MatchSet r = sets[t ^ 1];
+        r.flags |= kSetRowsOnly;
+        out[2 * t] = q;
+        out[2 * t + 1] = r;
+    }
+    if (t < static_cast<int>(sizeof(DevStatus) / 4)) reinterpret_cast<uint32_t*>(st2)[t] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void mutual_both(const SetPlan* __restrict__ plan, int n_sets2,
+                                                      const int32_t* __restrict__ nn, int64_t q_cap,
+                                                      int32_t* __restrict__ flag, const DevStatus* st2) {
+    const int64_t total = st2->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < q_cap; slot += gs) {
+        int f = 0;
+        if (slot < total) {
+            const int c = find_set(n_sets2, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+            if ((c & 3) == 0 && c + 2 < n_sets2) {  // the first set of a pair as queries
+                const int j = nn[slot];
+                f = (j >= 0 && nn[plan[c + 2].q_off + j] == slot - plan[c].q_off) ? 1 : 0;
+            }
+        }
+        flag[slot] = f;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void emit_both(const MatchSet* __restrict__ sets,
+                                                    const SetPlan* __restrict__ plan, int n_sets2,
+                                                    const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                                                    const int32_t* __restrict__ nn, const double* __restrict__ best,
+                                                    const double* __restrict__ second,
+                                                    const PairOutDev* __restrict__ outs, const DevStatus* st,
+                                                    const DevStatus* st2, int64_t* counts, int stride,
+                                                    const CloudState* cs, int64_t nnz_cap) {
+    const int64_t total = st2->total_queries;
+    const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (4 * tid + 3 < n_sets2) {
+        const int i = static_cast<int>(tid);
+        const int64_t a = plan[4 * i].q_off, b = plan[4 * i + 1].q_off;
+        const int64_t pa = a < total ? pos[a] : st2->pairs_total;
+        const int64_t pb = b < total ? pos[b] : st2->pairs_total;
+        int64_t* o = counts + static_cast<int64_t>(i) * stride;
+        o[0] = pb - pa;
+        o[5] = plan[4 * i].n_fb + plan[4 * i + 2].n_fb;
+        if (cs) {
+            o[1] = cs[2 * i].kept_cnt;
+            o[2] = cs[2 * i + 1].kept_cnt;
+            o[3] = cs[2 * i].j_cnt;
+            o[4] = cs[2 * i + 1].j_cnt;
+            o[7] = st->nnz;
+            int64_t status = KMG_OK;
+            if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
+            else if (st->err_capacity || st2->err_capacity || st->nnz > nnz_cap) status = KMG_ERR_WORKSPACE;
+            else if (o[0] > outs[i].cap) status = KMG_ERR_CAPACITY;
+            o[6] = status;
+        }
+    }
+    for (int64_t slot = tid; slot < total; slot += gs) {
+        if (!flag[slot]) continue;
+        const int c = find_set(n_sets2, slot, [&](int s) { return static_cast<int64_t>(plan[s].q_off); });
+        const int pr = c >> 2;
+        const PairOutDev o = outs[pr];
+        const int64_t at = pos[slot] - pos[plan[c].q_off];
+        if (at >= o.cap) continue;
+        const int j = static_cast<int>(slot - plan[c].q_off);
+        const int i = nn[slot];
+        const MatchSet& a = sets[2 * pr];
+        const MatchSet& b = sets[2 * pr + 1];
+        o.pairs[2 * at] = (a.rows ? a.rows[j] : j) - a.row_base;
+        o.pairs[2 * at + 1] = (b.rows ? b.rows[i] : i) - b.row_base;
+        o.d1[at] = static_cast<float>(sqrt(best[slot]));
+        o.d2[at] = static_cast<float>(sqrt(second[slot]));
+    }
+}
+
 // ------------------------------------------------------ one-sided form --
 //
 // A row can only be in a mutual pair if it is the nearest neighbour of some
@@ -2518,10 +2607,34 @@ kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs
 
 kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
 
+// Both directions in full in one band pass (the four-set form above).
+kmg_status match_both(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
+                      const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s,
+                      const CloudState* cs, int64_t nnz_cap) {
+    both_sets<<<grid_for(std::max<int64_t>(n_sets, sizeof(DevStatus) / 4), 64), 64, 0, s>>>(sets, n_sets, w.rr.sets,
+                                                                                           w.rr.st);
+    KMG_TRY(launch_status());
+    Carver c2(w.rr.region, w.rr.region_bytes);
+    const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
+    if (!c2.fits()) return KMG_ERR_WORKSPACE;
+    KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
+    StageScope sc(ST_MATCH_MUTUAL, s);
+    mutual_both<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w2.nn, w2.q_cap, w2.flag,
+                                                              w.rr.st);
+    KMG_TRY(launch_status());
+    KMG_TRY(scan_exclusive(w2.flag, w2.pos, w2.q_cap, &w.rr.st->pairs_total, w2.scan_tmp, s));
+    emit_both<<<std::max(grid_cap(w2.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
+        sets, w2.plan, 2 * n_sets, w2.flag, w2.pos, w2.nn, w2.best, w2.second, outs, st, w.rr.st, counts,
+        counts_stride, cs, nnz_cap);
+    return launch_status();
+}
+
 kmg_status match_batch(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                        const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s,
                        const CloudState* cs, int64_t nnz_cap) {
     if (n_sets < 2 || n_sets > kMaxClouds) return KMG_ERR_ARG;
+    if (tuning().match_form == 1 && w.one_sided && prec != KMG_FP16 && prec != KMG_BF16)
+        return match_both(sets, n_sets, dim, st, w, outs, counts, counts_stride, s, cs, nnz_cap);
     // one-sided form when the workspace holds the second plan, else both directions in full
     const MatchSet* first = w.one_sided ? w.one_sided : sets;
     if (prec == KMG_FP16 || prec == KMG_BF16) {

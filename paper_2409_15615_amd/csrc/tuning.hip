@@ -20,6 +20,7 @@ bool set_tuning(const Tuning& t) {
     if (t.band_tile != 0 && !band_tile_candidate(t.band_tile)) return false;
     if (t.fuse_features != 0 && t.fuse_features != 1) return false;
     if (t.xcd_split < 0 || t.xcd_split > 3) return false;
+    if (t.match_form != 0 && t.match_form != 1) return false;
     g_tuning = t;
     return true;
 }
@@ -31,7 +32,6 @@ extern "C" {
 __attribute__((visibility("default"))) kmg_status kmg_set_tuning(const kmg_tuning* t) {
     kmg::Tuning v;  // defaults
     if (t) {
-        if (t->reserved) return KMG_ERR_ARG;
         v.search_waves = t->search_waves;
         v.count_queries = t->count_queries;
         v.spfh_pair_mean = t->spfh_pair_mean;
@@ -39,6 +39,7 @@ __attribute__((visibility("default"))) kmg_status kmg_set_tuning(const kmg_tunin
         v.band_tile = t->band_tile;
         v.fuse_features = t->fuse_features;
         v.xcd_split = t->xcd_split;
+        v.match_form = t->match_form;
     }
     return kmg::set_tuning(v) ? KMG_OK : KMG_ERR_ARG;
 }
@@ -53,7 +54,7 @@ __attribute__((visibility("default"))) kmg_status kmg_get_tuning(kmg_tuning* t) 
     t->band_tile = v.band_tile;
     t->fuse_features = v.fuse_features;
     t->xcd_split = v.xcd_split;
-    t->reserved = 0;
+    t->match_form = v.match_form;
     return KMG_OK;
 }
 

@@ -55,12 +55,12 @@ class KmgTuning(C.Structure):
         ("band_tile", C.c_int32),
         ("fuse_features", C.c_int32),
         ("xcd_split", C.c_int32),
-        ("reserved", C.c_int32),
+        ("match_form", C.c_int32),
     ]
 
 
 TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile", "fuse_features",
-                 "xcd_split")
+                 "xcd_split", "match_form")
 
 
 class KmgCloud(C.Structure):

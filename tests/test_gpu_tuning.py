@@ -38,10 +38,18 @@ def settings():
     for f, vals in SPACE.items():
         out += [{f: v} for v in vals]
     out.append({"search_waves": 8, "count_queries": 4, "spfh_pair_mean": 0, "fpfh_rows": 16, "band_tile": 12,
-                "fuse_features": 1, "xcd_split": 0})
+                "fuse_features": 1, "xcd_split": 0, "match_form": 1})
     out.append({"search_waves": 2, "count_queries": 1, "spfh_pair_mean": 8192, "fpfh_rows": 4, "band_tile": 64,
                 "fuse_features": 0, "xcd_split": 2})
     return out
+
+
+def results_only(counts):
+    """The batch counts without column 5 (exact re-scans: a work statistic that
+    depends on the matching form)."""
+    c = counts.clone()
+    c[:, 5] = 0
+    return c
 
 
 def digest(*tensors):
@@ -86,7 +94,7 @@ def test_batch_outputs_invariant_and_autotuner(K):
     b.upload(clouds)
 
     def fingerprint():
-        return digest(b.counts, b.pairs, b.d1, b.d2)
+        return digest(results_only(b.counts), b.pairs, b.d1, b.d2)
 
     b.pairs.fill_(-1)
     b.d1.fill_(-1.0)
@@ -105,3 +113,36 @@ def test_batch_outputs_invariant_and_autotuner(K):
     assert fingerprint() == ref
     K.set_tuning(None)
     print(f"autotuned {best}: {t_best:.3f} ms vs {t_def:.3f} ms with the defaults, {len(log)} settings timed")
+
+
+def test_match_forms_on_lidar_batch(K):
+    """The one-sided matching and both directions in full give the same
+    correspondences, d1 and d2 on a batch of LiDAR pairs (whose ties send some
+    queries to the exact scan, in different numbers in the two forms)."""
+    pairs = [synth.c1_pair(i) for i in range(8)]
+    clouds = []
+    for d in pairs:
+        p = d["params"]
+        for key, vp in (("src", d["vp_src"]), ("tgt", d["vp_tgt"])):
+            clouds.append((dev(d[key]), K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins,
+                                                      vp)))
+    K.set_tuning(None)
+    _, probe = K.register_batch(clouds)
+    b = K.Batch(len(pairs), probe.raw_cap, probe.nnz() + 4096, 11)
+    b.upload(clouds)
+    out = {}
+    for form in (0, 1):
+        K.set_tuning({"match_form": form})
+        b.counts.zero_()
+        b.pairs.fill_(-1)
+        b.d1.fill_(-1.0)
+        b.d2.fill_(-1.0)
+        b.run()
+        torch.cuda.synchronize()
+        out[form] = (results_only(b.counts).cpu(), b.counts[:, 5].cpu(), b.pairs.cpu().clone(), b.d1.cpu().clone(),
+                     b.d2.cpu().clone())
+    K.set_tuning(None)
+    assert int(out[0][0][:, 6].abs().sum()) == 0  # every pair KMG_OK
+    for k in (0, 2, 3, 4):
+        assert torch.equal(out[0][k], out[1][k]), k
+    print("exact re-scans per pair: one-sided", out[0][1].tolist(), "both directions", out[1][1].tolist())
