@@ -41,22 +41,21 @@ METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency v
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the first-direction band tile kernel, from two rocprofv3
-# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 14 launches on
-# this workload), each scaled by what the same counter reads for a streaming add of
-# 256 MiB in and 256 MiB out (FETCH_SIZE 131085.2 KiB -> x2.0, WRITE_SIZE
-# 262144 KiB -> x1.0).  The figures hold for the matcher source with this SHA-256
-# only; after any change to it the field is reported as null until the counters
-# are taken again.
+# HBM bytes per launch of the band tile kernel on the LiDAR pair under the matching
+# form the autotuner picks for it (both directions in one launch, band_tiles<9, 1>), from
+# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the 16
+# launches of that form), each scaled by what the same counter reads for a streaming add
+# of 256 MiB in and 256 MiB out (FETCH_SIZE 131085.1 KiB -> x2.0, WRITE_SIZE 262144 KiB
+# -> x1.0).  The figures hold for the matcher source with this SHA-256 and that matching
+# form only; otherwise the field is reported as null until the counters are taken again.
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
-    "sha256": "d3e0ec6c932901578ed22b0d65cc1b2d0ab6697b7c5cae5b16bc0511bb253410",
-    "fetch_kib": 16083.9,
-    "fetch_scale": 262144.0 / 131085.2,
-    "write_kib": 4007.1,
+    "sha256": "5166418519ffbecf3e206e1328589914095aa0fcf5baf6c646adca4c3b966628",
+    "fetch_kib": 24886.3,
+    "fetch_scale": 262144.0 / 131085.1,
+    "write_kib": 3990.2,
     "write_scale": 262144.0 / 262144.0,
-    # the matching form the counters were taken with (the launch holds one direction in form 0)
-    "match_form": 0,
+    "match_form": 1,
 }
 
 
