@@ -2017,64 +2017,141 @@ __device__ __forceinline__ double wave_max_d(double v) {
     return v;
 }
 
-// One wavefront per query slot: R^2 = the second smallest exact distance
-// (the plain FP64 sum in dimension order, as exact_d2) to the kSeedRows
-// partner rows around the query's norm key in the partner's packed order, read
-// from the packed chunks; infinite when the partner has fewer than two rows.
-__global__ __launch_bounds__(kBlock) void band_seeds(const MatchSet* __restrict__ sets,
-                                                     const SetPlan* __restrict__ plan, int n_sets, int dim, int kp,
-                                                     const double* __restrict__ pk, const double* __restrict__ n2,
-                                                     const uint32_t* __restrict__ skey, double* __restrict__ r2,
-                                                     const DevStatus* st) {
+// As wave_search, by each group of 16 lanes for its own prefix predicate (the
+// four groups of a wavefront search at once; a group with n = 0 idles).
+template <class F>
+__device__ __forceinline__ int group_search16(int n, F below) {
+    const int gl = lane_id() & 15;
+    const int sh = lane_id() & ~15;
+    int lo = 0, hi = n;
+    while (ballot(lo < hi)) {  // uniform over the wave
+        const bool open = lo < hi;
+        const int stride = open ? (hi - lo + 15) / 16 : 1;
+        const int probe = lo + (gl + 1) * stride - 1;
+        const bool b = open && probe < hi && below(probe);
+        const int cnt = __popcll((ballot(b) >> sh) & 0xffffull);
+        if (open) {
+            const int nlo = lo + cnt * stride;
+            hi = min(hi, lo + (cnt + 1) * stride - 1);
+            lo = nlo;
+        }
+    }
+    return lo;
+}
+
+// R^2 of each query slot = the second smallest exact distance (the plain FP64
+// sum in dimension order, as exact_d2) to the kSeedRows partner rows around
+// the query's norm key in the partner's packed order; infinite when the
+// partner has fewer than two rows.  A group of 16 lanes takes one query (four
+// per wavefront, whose chains of dependent loads overlap), each lane four rows
+// of the window.  The query's own values are loaded before the search, which
+// they do not depend on.
+template <int KS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void band_seeds(
+    const MatchSet* __restrict__ sets, const SetPlan* __restrict__ plan, int n_sets, int dim,
+    const double* __restrict__ pk, const double* __restrict__ n2, const uint32_t* __restrict__ skey,
+    double* __restrict__ r2, const DevStatus* st) {
 #pragma clang fp contract(off)
+    constexpr int kp = 4 * KS;
+    constexpr int kG = 16;                   // lanes per query
+    constexpr int kRows = kSeedRows / kG;    // rows per lane
+    constexpr int kYv = (kp + kG - 1) / kG;  // query values per lane
     const int lane = lane_id();
+    const int gl = lane & (kG - 1);
     // the queries only: index g = 64 (query wave) + position, rows-only sets have no waves
     const int64_t total = static_cast<int64_t>(st->total_waves) * kBandWave;
-    const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-    for (int64_t g = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; g < total; g += gw) {
-        const int64_t wq = g / kBandWave;
-        const int c = find_set(n_sets, wq, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
-        const int jq = static_cast<int>(wq - plan[c].wave_off) * kBandWave + static_cast<int>(g % kBandWave);
-        if (jq >= plan[c].n) continue;  // uniform over the wave: the last wave's padding
-        const int64_t slot = plan[c].q_off + jq;
-        const int p = c ^ 1;
-        const int np = p < n_sets ? plan[p].n : 0;
-        if (np < 2) {
-            if (lane == 0) r2[slot] = INFINITY;
-            continue;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / kG);
+    for (int64_t base = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave * (kWave / kG);
+         base < total; base += stride) {  // uniform over the wave
+        const int64_t g = base + lane / kG;
+        bool live = g < total;
+        int c = 0, jq = 0, np = 0;
+        int64_t slot = 0;
+        if (live) {
+            const int64_t wq = g / kBandWave;
+            c = find_set(n_sets, wq, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+            jq = static_cast<int>(wq - plan[c].wave_off) * kBandWave + static_cast<int>(g % kBandWave);
+            live = jq < plan[c].n;  // the last wave's padding
         }
-        const SetPlan pc = plan[p];
-        const uint32_t kq = norm_key(n2[slot]);
-        const uint32_t* pkey = skey + pc.q_off;
-        const int at = wave_search(np, [&](int pos) { return pkey[pos] < kq; });
-        const int nw = min(np, kSeedRows);
-        const int w0 = min(max(at - nw / 2, 0), np - nw);
-        // lane L < dim holds the query's value L
-        const float* y = set_row(sets[c], static_cast<int>(slot - plan[c].q_off), dim);
-        const float yv = lane < dim ? y[lane] : 0.0f;
-        const int pos = w0 + min(lane, nw - 1);
-        const double* xr = pk + (static_cast<int64_t>(pc.chunk_off + pos / kTileRows) * kp) * kTileRows + pos % kTileRows;
-        double acc = 0.0;
-        int k = 0;
-        for (; k + 8 <= dim; k += 8) {
-            double xs[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) xs[u] = xr[(k + u) * kTileRows];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const double df = xs[u] - static_cast<double>(__shfl(yv, k + u, kWave));
-                acc = acc + df * df;
+        if (live) {
+            slot = plan[c].q_off + jq;
+            np = (c ^ 1) < n_sets ? plan[c ^ 1].n : 0;
+            if (np < 2) {
+                if (gl == 0) r2[slot] = INFINITY;
+                live = false;
             }
         }
-        for (; k < dim; ++k) {
-            const double df = xr[k * kTileRows] - static_cast<double>(__shfl(yv, k, kWave));
-            acc = acc + df * df;
+        float yv[kYv];  // lane gl holds the query's values gl, gl + 16, ...
+        {
+            const float* y = live ? set_row(sets[c], jq, dim) : nullptr;
+#pragma unroll
+            for (int j = 0; j < kYv; ++j) yv[j] = (live && j * kG + gl < dim) ? y[j * kG + gl] : 0.0f;
         }
-        const double d = lane < nw ? acc : INFINITY;
-        const double m1 = wave_min_d(d);
-        const int n_eq = __popcll(ballot(d == m1));
-        const double m2 = n_eq >= 2 ? m1 : wave_min_d(d == m1 ? INFINITY : d);
-        if (lane == 0) r2[slot] = m2;
+        int64_t chunk_off = 0;
+        uint32_t kq = 0;
+        const uint32_t* pkey = skey;
+        if (live) {
+            const SetPlan pc = plan[c ^ 1];
+            chunk_off = pc.chunk_off;
+            kq = norm_key(n2[slot]);
+            pkey = skey + pc.q_off;
+        }
+        const int at = group_search16(live ? np : 0, [&](int pos) { return pkey[pos] < kq; });
+        const int nw = min(np, kSeedRows);
+        const int w0 = min(max(at - nw / 2, 0), np - nw);
+        const double* xr[kRows];
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            const int pos = live ? w0 + min(j * kG + gl, nw - 1) : 0;
+            xr[j] = pk + (chunk_off + pos / kTileRows) * kp * kTileRows + pos % kTileRows;
+        }
+        double acc[kRows];
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) acc[j] = 0.0;
+#pragma unroll
+        for (int kb = 0; kb < kp; kb += 2) {
+            if (kb < dim) {  // uniform; the row holds kp values, those past dim are loaded, not used
+                double xs[kRows][2];
+#pragma unroll
+                for (int j = 0; j < kRows; ++j)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) xs[j][u] = xr[j][(kb + u) * kTileRows];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int k = kb + u;
+                    if (k < dim) {
+                        const double yk = static_cast<double>(__shfl(yv[k / kG], k % kG, kG));
+#pragma unroll
+                        for (int j = 0; j < kRows; ++j) {
+                            const double df = xs[j][u] - yk;
+                            acc[j] = acc[j] + df * df;
+                        }
+                    }
+                }
+            }
+        }
+        double d[kRows];
+        double m1 = INFINITY;
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            d[j] = (live && j * kG + gl < nw) ? acc[j] : INFINITY;
+            m1 = fmin(m1, d[j]);
+        }
+#pragma unroll
+        for (int o = 1; o < kG; o <<= 1) m1 = fmin(m1, __shfl_xor(m1, o, kG));
+        int n_eq = 0;
+        double m2 = INFINITY;
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            n_eq += d[j] == m1 ? 1 : 0;
+            m2 = d[j] == m1 ? m2 : fmin(m2, d[j]);
+        }
+#pragma unroll
+        for (int o = 1; o < kG; o <<= 1) {
+            n_eq += __shfl_xor(n_eq, o, kG);
+            m2 = fmin(m2, __shfl_xor(m2, o, kG));
+        }
+        if (live && gl == 0) r2[slot] = n_eq >= 2 ? m1 : m2;
     }
 }
 
@@ -2808,8 +2885,11 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
         unsigned long long* sorted = reinterpret_cast<unsigned long long*>(w.best);
         for (int role = 1; role >= 0; --role) {  // partners first: the seeds need their order
             if (role == 0) {
-                band_seeds<<<grid_cap(w.q_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, w.pk,
-                                                                                w.n2, w.skey, w.r2, st);
+                const unsigned gs = grid_cap(w.q_cap * 16, kBlock);
+                if (ks == 9)
+                    band_seeds<9><<<gs, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.pk, w.n2, w.skey, w.r2, st);
+                else
+                    band_seeds<17><<<gs, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.pk, w.n2, w.skey, w.r2, st);
                 KMG_TRY(launch_status());
             }
             tile_sort<<<grid_cap((w.q_cap / kSortTile + n_sets + 1) * kBlock, kBlock), kSortTile, 0, s>>>(
