@@ -2155,18 +2155,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
 }
 
-// One wavefront per query wave: the band of norms its queries need,
-// [nu - R - m, nu + R + m] over the wave with m = 2^-38 (nu + R) for the
-// rounding of the norms and distances, and the partner chunks that can hold a
-// squared norm in [lo^2 (1 - 2^-50), hi^2 (1 + 2^-50)], found on the chunks'
-// first and last sort keys (a key k holds squared norms in [dec(k), dec(k + 1))).
+// One wavefront per query wave: the band of norms each 16-query tile of the
+// wave needs, [nu - R - m, nu + R + m] over the tile's queries with
+// m = 2^-38 (nu + R) for the rounding of the norms and distances, and the
+// partner chunks that can hold a squared norm in [lo^2 (1 - 2^-50),
+// hi^2 (1 + 2^-50)], found on the chunks' first and last sort keys (a key k
+// holds squared norms in [dec(k), dec(k + 1))); the wave's range is the union
+// of its tiles' ranges.
 __global__ __launch_bounds__(kBlock) void band_waves(const MatchSet* __restrict__ sets,
                                                      const SetPlan* __restrict__ plan, int n_sets,
                                                      const double* __restrict__ n2, const double* __restrict__ r2,
                                                      const int32_t* __restrict__ perm,
                                                      const uint32_t* __restrict__ skey,
                                                      int32_t* __restrict__ wave_c0, int32_t* __restrict__ wave_len,
-                                                     const DevStatus* st) {
+                                                     int2* __restrict__ wave_sub, const DevStatus* st) {
     const int lane = lane_id();
     const int64_t total = st->total_waves;
     const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
@@ -2186,29 +2188,44 @@ __global__ __launch_bounds__(kBlock) void band_waves(const MatchSet* __restrict_
             lo = nu - R - m;
             hi = nu + R + m;
         }
-        lo = wave_min_d(lo);
-        hi = wave_max_d(hi);
+        // the band of each 16-query tile of the wave (lanes 16 t .. 16 t + 15); the wave's
+        // band is their union
+#pragma unroll
+        for (int d = 1; d < kTileCols; d <<= 1) {
+            lo = fmin(lo, __shfl_xor(lo, d, kWave));
+            hi = fmax(hi, __shfl_xor(hi, d, kWave));
+        }
+        const bool live = np > 0 && lo <= hi;
         int k0 = 0, k1 = 0;
-        if (np > 0 && lo <= hi) {
+        if (ballot(live)) {  // uniform over the wave
             const SetPlan pc = plan[p];
             const uint32_t* pkey = skey + pc.q_off;
             const int pch = pc.chunks;
-            if (lo > 0.0) {
-                // chunks whose last key is below that of lo^2 hold only squared norms below it
-                const uint32_t klo = norm_key(lo * lo * (1.0 - 0x1p-50));
-                k0 = wave_search(pch, [&](int k) { return pkey[min(k * kTileRows + kTileRows - 1, np - 1)] < klo; });
-            }
-            if (hi == INFINITY) {
-                k1 = pch;
-            } else {
-                // chunks whose first key is above that of hi^2 hold only squared norms above it
-                const uint32_t khi = norm_key(hi * hi * (1.0 + 0x1p-50));
-                k1 = wave_search(pch, [&](int k) { return pkey[k * kTileRows] <= khi; });
+            // chunks whose last key is below that of lo^2 hold only squared norms below it
+            const uint32_t klo = norm_key(lo > 0.0 ? lo * lo * (1.0 - 0x1p-50) : 0.0);
+            const int s0 = group_search16(live && lo > 0.0 ? pch : 0, [&](int k) {
+                return pkey[min(k * kTileRows + kTileRows - 1, np - 1)] < klo;
+            });
+            // chunks whose first key is above that of hi^2 hold only squared norms above it
+            const uint32_t khi = norm_key(hi == INFINITY ? 0.0 : hi * hi * (1.0 + 0x1p-50));
+            const int s1 = group_search16(live && hi != INFINITY ? pch : 0,
+                                          [&](int k) { return pkey[k * kTileRows] <= khi; });
+            if (live) {
+                k0 = s0;
+                k1 = hi == INFINITY ? pch : max(s1, s0);
             }
         }
+        if ((lane & (kTileCols - 1)) == 0) wave_sub[w * kTilesPerWave + lane / kTileCols] = make_int2(k0, k1);
+        // the union: the smallest start and the largest end of the non-empty tile ranges
+        int u0 = k1 > k0 ? k0 : INT_MAX, u1 = k1 > k0 ? k1 : 0;
+#pragma unroll
+        for (int d = kTileCols; d < kWave; d <<= 1) {
+            u0 = min(u0, __shfl_xor(u0, d, kWave));
+            u1 = max(u1, __shfl_xor(u1, d, kWave));
+        }
         if (lane == 0) {
-            wave_c0[w] = k0;
-            wave_len[w] = k1 > k0 ? k1 - k0 : 0;
+            wave_c0[w] = u1 > 0 ? u0 : 0;
+            wave_len[w] = u1 > 0 ? u1 - u0 : 0;
         }
     }
 }
@@ -2250,6 +2267,7 @@ static_assert(kTileCands * kCandThreads <= kPlanThreads, "one thread per (candid
 __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restrict__ plan, int n_sets,
                                                           const int32_t* __restrict__ wave_c0,
                                                           const int32_t* __restrict__ wave_len,
+                                                          const int2* __restrict__ wave_sub,
                                                           int32_t* __restrict__ wave_tile, int4* __restrict__ tinfo,
                                                           int64_t tile_cap, int forced_T, DevStatus* st) {
     __shared__ int64_t smem[kPlanThreads / kWave];
@@ -2330,7 +2348,7 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
     const int T = s_T;
     __shared__ int s_off[kPlanThreads], s_c0[kPlanThreads], s_len[kPlanThreads], s_set[kPlanThreads];
     int64_t carry = 0;
-    int64_t pairs = 0;  // query-row distances of the tiles (real queries and rows)
+    int64_t pairs = 0;  // query-row products of the tiles (real queries and rows)
     for (int base = 0; base < W; base += kPlanThreads) {
         const int w = base + static_cast<int>(threadIdx.x);
         const int L = w < W ? wave_len[w] : 0;
@@ -2343,9 +2361,14 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
             c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
             c0 = wave_c0[w];
             if (L > 0) {
+                // each 16-query tile over its own chunk range
                 const int nq = min(kBandWave, plan[c].n - (w - plan[c].wave_off) * kBandWave);
                 const int np = plan[c ^ 1].n;
-                pairs += static_cast<int64_t>(nq) * (min((c0 + L) * kTileRows, np) - c0 * kTileRows);
+                for (int t = 0; t < kTilesPerWave; ++t) {
+                    const int2 r = wave_sub[static_cast<int64_t>(w) * kTilesPerWave + t];
+                    const int nq_t = min(kTileCols, max(0, nq - t * kTileCols));
+                    if (r.y > r.x) pairs += static_cast<int64_t>(nq_t) * (min(r.y * kTileRows, np) - r.x * kTileRows);
+                }
             }
         }
         s_off[threadIdx.x] = static_cast<int>(rel);
@@ -2382,16 +2405,32 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
     }
 }
 
+// As absorb, skipped when no lane's four scores undercut its fourth best (the
+// encoded scores are unique, so such a merge leaves top as it is).
+__device__ __forceinline__ void absorb_some(double* top, const doublex4& acc, unsigned row0, unsigned keep) {
+    double w0 = encode(acc[0], keep, row0), w1 = encode(acc[1], keep, row0 + 4u);
+    double w2 = encode(acc[2], keep, row0 + 8u), w3 = encode(acc[3], keep, row0 + 12u);
+    if (ballot(fmin(fmin(w0, w1), fmin(w2, w3)) < top[3])) {
+        sort4(w0, w1, w2, w3);
+        merge4(top, w0, w1, w2, w3);
+    }
+}
+
 // Band tiles: each wavefront pulls tiles (64 queries of one wave against a
 // range of partner chunks) from an atomic queue.  The partner chunk operands
-// come straight from memory with raw buffer loads, one chunk ahead of the
-// products; the waves share no data, so there is no barrier.
+// come straight from memory with raw buffer loads, ahead of the products; the
+// waves share no data, so there is no barrier.  Each 16-query tile of the wave
+// needs only the chunks of its own band: the four tiles take the chunks every
+// one of them needs together (four products per chunk operand), and each tile
+// takes the rest of its own band alone.  Every tile meets each of its chunks
+// once, and a tile's product does not depend on the others', so the lists are
+// those of the four tiles over their own bands.
 // kBack only names the launch: 0 for the first direction, 1 for the matching
 // back and FP64 re-runs (so that profiles tell them apart).
 template <int KS, int kBack>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 ? 2 : 1))) void band_tiles(
     const SetPlan* __restrict__ plan, const double* __restrict__ pk, int dim, const int4* __restrict__ tinfo,
-    double* __restrict__ part, DevStatus* st) {
+    const int2* __restrict__ wave_sub, double* __restrict__ part, DevStatus* st) {
     constexpr int kp = 4 * KS;
     constexpr int kChunk = kp * kTileRows;
     const int lane = lane_id();
@@ -2411,6 +2450,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
         const SetPlan qc = plan[ti.y];
         const SetPlan pc = plan[ti.y ^ 1];
         const int col0 = (ti.x - qc.wave_off) * kBandWave;
+        // the tiles' own chunk ranges within this tile's [c_begin, c_end), and the part
+        // all of the tiles with a band share (tiles without queries have empty ranges)
+        const int c_begin = ti.z, c_end = ti.w;
+        int2 own[kTilesPerWave];
+        int core0 = c_begin, core1 = c_end;
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) {
+            const int2 r = wave_sub[static_cast<int64_t>(ti.x) * kTilesPerWave + t];
+            own[t] = make_int2(max(r.x, c_begin), min(r.y, c_end));
+            if (r.y > r.x) {
+                core0 = max(core0, r.x);
+                core1 = min(core1, r.y);
+            }
+        }
         double bq[kTilesPerWave][KS];
 #pragma unroll
         for (int t = 0; t < kTilesPerWave; ++t) {
@@ -2428,50 +2481,61 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
 #pragma unroll
         for (int t = 0; t < kTilesPerWave; ++t) top[t][0] = top[t][1] = top[t][2] = top[t][3] = INFINITY;
         const unsigned keep = keep_mask(row_bits(pc.chunks));
-        const int c_begin = ti.z, c_end = ti.w;
-        if (c_begin < c_end) {  // uniform over the wave
-            const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<double*>(pk + static_cast<int64_t>(pc.chunk_off) * kChunk), 0,
-                static_cast<int>(min(static_cast<int64_t>(pc.chunks) * kChunk * 8, static_cast<int64_t>(INT32_MAX))),
-                static_cast<int>(kBufferWord3));
+        const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double*>(pk + static_cast<int64_t>(pc.chunk_off) * kChunk), 0,
+            static_cast<int>(min(static_cast<int64_t>(pc.chunks) * kChunk * 8, static_cast<int64_t>(INT32_MAX))),
+            static_cast<int>(kBufferWord3));
+        const auto load_chunk = [&](double* dst, int c) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                dst[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                        rows, ((c * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
+        };
+        const bool has_core = core0 < core1;  // uniform over the wave
+        if (has_core) {
             // two chunks in flight ahead of the products (a miss in L2 outlasts one chunk's products)
             double a[KS], an[KS];
-            const int c_second = min(c_begin + 1, c_end - 1);
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-                a[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                       rows, ((c_begin * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
-#pragma unroll
-            for (int s = 0; s < KS; ++s)
-                an[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                        rows, ((c_second * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
-            for (int c = c_begin; c < c_end; ++c) {
-                const int cnn = min(c + 2, c_end - 1);
+            load_chunk(a, core0);
+            load_chunk(an, min(core0 + 1, core1 - 1));
+            for (int c = core0; c < core1; ++c) {
                 double ann[KS];
-#pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    ann[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                             rows, ((cnn * kChunk) + s * 4 * kTileRows + lane) * 8, 0, 0));
+                load_chunk(ann, min(c + 2, core1 - 1));
                 __builtin_amdgcn_sched_barrier(0);
                 doublex4 acc[kTilesPerWave];
                 chunk_mfma<KS>(acc, a, bq);
                 const unsigned row0 = static_cast<unsigned>(c * kTileRows + g);
 #pragma unroll
-                for (int t = 0; t < kTilesPerWave; ++t) {
-                    // the merge is skipped when no lane's four scores undercut its fourth best
-                    // (the encoded scores are unique, so such a merge leaves top as it is)
-                    double w0 = encode(acc[t][0], keep, row0), w1 = encode(acc[t][1], keep, row0 + 4u);
-                    double w2 = encode(acc[t][2], keep, row0 + 8u), w3 = encode(acc[t][3], keep, row0 + 12u);
-                    if (ballot(fmin(fmin(w0, w1), fmin(w2, w3)) < top[t][3])) {
-                        sort4(w0, w1, w2, w3);
-                        merge4(top[t], w0, w1, w2, w3);
-                    }
-                }
+                for (int t = 0; t < kTilesPerWave; ++t) absorb_some(top[t], acc[t], row0, keep);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                     a[s] = an[s];
                     an[s] = ann[s];
+                }
+            }
+        }
+        // each tile alone over its range outside the shared part, one chunk in flight ahead
+#pragma unroll
+        for (int t = 0; t < kTilesPerWave; ++t) {
+            const int e1 = own[t].y;
+            const auto after = [&](int c) { return (has_core && c >= core0 && c < core1) ? core1 : c; };
+            int c = after(own[t].x);
+            if (c < e1) {  // uniform over the wave
+                double a[KS];
+                load_chunk(a, c);
+                while (c < e1) {
+                    const int cn = after(c + 1);
+                    double an[KS];
+                    load_chunk(an, min(cn, e1 - 1));
+                    __builtin_amdgcn_sched_barrier(0);
+                    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bq[t][s], acc, 0, 0, 0);
+                    absorb_some(top[t], acc, static_cast<unsigned>(c * kTileRows + g), keep);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) a[s] = an[s];
+                    c = cn;
                 }
             }
         }
@@ -2651,6 +2715,7 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     w.skey = c.take<uint32_t>(static_cast<size_t>(w.q_cap));
     w.wave_c0 = c.take<int32_t>(static_cast<size_t>(w.wave_cap));
     w.wave_len = c.take<int32_t>(static_cast<size_t>(w.wave_cap));
+    w.wave_sub = c.take<int2>(static_cast<size_t>(w.wave_cap) * kTilesPerWave);
     w.wave_tile = c.take<int32_t>(static_cast<size_t>(w.wave_cap + 1));
     w.tinfo = c.take<int4>(static_cast<size_t>(w.tile_cap));
     w.rr = RerunWs{};
@@ -2903,20 +2968,21 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
             KMG_TRY(launch_status());
         }
         band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2, w.perm,
-                                                                           w.skey, w.wave_c0, w.wave_len, st);
+                                                                           w.skey, w.wave_c0, w.wave_len, w.wave_sub,
+                                                                           st);
         KMG_TRY(launch_status());
-        band_plan<<<1, kPlanThreads, 0, s>>>(w.plan, n_sets, w.wave_c0, w.wave_len, w.wave_tile, w.tinfo, w.tile_cap,
-                                             tuning().band_tile, st);
+        band_plan<<<1, kPlanThreads, 0, s>>>(w.plan, n_sets, w.wave_c0, w.wave_len, w.wave_sub, w.wave_tile, w.tinfo,
+                                             w.tile_cap, tuning().band_tile, st);
         KMG_TRY(launch_status());
     }
     {
         StageScope sc(ST_MATCH_TOPK, s);
         if (ks == 9) {
-            if (oside) band_tiles<9, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
-            else band_tiles<9, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            if (oside) band_tiles<9, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
+            else band_tiles<9, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
         } else {
-            if (oside) band_tiles<17, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
-            else band_tiles<17, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.part, st);
+            if (oside) band_tiles<17, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
+            else band_tiles<17, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
         }
         KMG_TRY(launch_status());
         timer_note_work(&st->band_pairs);
