@@ -41,28 +41,29 @@ METRIC = "registration pairs/s (Faster-PFH+matching) @25k pts; p50/p99 latency v
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the band tile kernel on the LiDAR pair under the matching
-# form the autotuner picks for it (both directions in one launch, band_tiles<9, 1>), from
-# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of the 16
-# launches of that form), each scaled by what the same counter reads for a streaming add
-# of 256 MiB in and 256 MiB out (FETCH_SIZE 131085.1 KiB -> x2.0, WRITE_SIZE 262144 KiB
-# -> x1.0).  The figures hold for the matcher source with this SHA-256 and that matching
-# form only; otherwise the field is reported as null until the counters are taken again.
+# HBM bytes per launch of the band tile kernel on the LiDAR pair under the launch
+# tuning the autotuner picks for it (both matching directions in one launch,
+# band_tiles<9, 1>, tiles of 16 chunks), from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch, mean of the 16 launches of that form), each scaled by what
+# the same counter reads for a streaming add of 256 MiB in and 256 MiB out (FETCH_SIZE
+# 131085.3 KiB -> x2.0, WRITE_SIZE 262144 KiB -> x1.0).  The figures hold for the matcher
+# source with this SHA-256 and those tuning fields only; otherwise the field is reported as
+# null until the counters are taken again.
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
-    "sha256": "5166418519ffbecf3e206e1328589914095aa0fcf5baf6c646adca4c3b966628",
-    "fetch_kib": 24886.3,
-    "fetch_scale": 262144.0 / 131085.1,
-    "write_kib": 3990.2,
+    "sha256": "de208490cb61987ba5edd74bf088a481b34c85fd8df001cec3233cef7aa44320",
+    "fetch_kib": 67346.1,
+    "fetch_scale": 262144.0 / 131085.3,
+    "write_kib": 11856.7,
     "write_scale": 262144.0 / 262144.0,
-    "match_form": 1,
+    "tuning": {"match_form": 1, "band_tile": 16},
 }
 
 
-def tile_traffic_bytes(match_form=0):
+def tile_traffic_bytes(setting):
     import hashlib
 
-    if match_form != TILE_TRAFFIC["match_form"]:
+    if any(setting.get(k) != v for k, v in TILE_TRAFFIC["tuning"].items()):
         return None
     path = os.path.join(ROOT, TILE_TRAFFIC["source"])
     with open(path, "rb") as f:
@@ -928,7 +929,7 @@ def main():
             "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 5),
-            "traffic": tile_traffic_bytes(match_form),
+            "traffic": tile_traffic_bytes(kmg.get_tuning()),
             "avg_launch_ms": round(topk_avg_s * 1e3, 5),
             "flops_per_launch": flops_per_launch,
             "band_fraction": round(flops_per_launch / dense, 4),
