@@ -125,7 +125,8 @@ int32_t kmg_version(void);
  * returns the number of stages; kmg_stage_name(i) names stage i (static
  * storage).  kmg_timing_work copies up to n per-stage work counts of the
  * stage's last timed launch (for match_topk and match_image with the norm
- * bands: query-row distances the tiles evaluated; 0 where a stage counts
+ * bands: query-row products the tiles evaluated, each 16-query tile over its
+ * own chunk range; 0 where a stage counts
  * none, -1 if the count could not be read) and returns the number of stages;
  * it reads device memory of the last call's workspace, which must still be
  * allocated.

@@ -128,7 +128,7 @@ struct DevStatus {
     int32_t band_step;        // norm-band matching: chunks per tile
     int32_t rank_items;       // norm-band matching: tile pairs of the cross ranking
     int32_t sort_items;       // norm-band matching: sorted tiles
-    int64_t band_pairs;       // norm-band matching: query-row distances evaluated by the tiles
+    int64_t band_pairs;       // norm-band matching: query-row products evaluated by the tiles
     int32_t err_sync;         // a bounded wait inside a persistent kernel gave up (never expected)
     int32_t pad1;
 };
