@@ -1498,21 +1498,8 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
 // Each pair as four sets, (set 2i as queries, set 2i+1 rows only) and (set
 // 2i+1 as queries, set 2i rows only), matched in one band pass: no second pass
 // over the image, at the price of matching every row of the larger set back.
-// A pair (j, i) is mutual when j's nearest neighbour is i and i's is j.
-
-__global__ void both_sets(const MatchSet* __restrict__ sets, int n_sets, MatchSet* __restrict__ out,
-                          DevStatus* st2) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n_sets) {
-        MatchSet q = sets[t];
-        q.flags &= ~kSetRowsOnly;
-        MatchSet r = sets[t ^ 1];
-        r.flags |= kSetRowsOnly;
-        out[2 * t] = q;
-        out[2 * t + 1] = r;
-    }
-    if (t < static_cast<int>(sizeof(DevStatus) / 4)) reinterpret_cast<uint32_t*>(st2)[t] = 0u;
-}
+// A pair (j, i) is mutual when j's nearest neighbour is i and i's is j.  The
+// band planner writes the four sets (plan_band with `both`).
 
 __global__ __launch_bounds__(kBlock) void mutual_both(const SetPlan* __restrict__ plan, int n_sets2,
                                                       const int32_t* __restrict__ nn, int64_t q_cap,
@@ -1727,33 +1714,12 @@ __device__ __forceinline__ void block_scan_k(int* v, int* tot, int* smem /* K x 
     __syncthreads();
 }
 
-// With `oside`, the sets are first made one-sided (the larger set of each
-// pair, the second on a tie, becomes rows-only) and written there; the
-// kernels after the planner then read oside.
-__global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
-                                                         SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside,
-                                                         int64_t* __restrict__ fb_total, int32_t* __restrict__ grp_done,
-                                                         int64_t n_grp) {
-    __shared__ int s_scan[5 * (kPlanThreads / kWave)];
-    for (int64_t g = threadIdx.x; g < n_grp; g += kPlanThreads) grp_done[g] = 0;  // for the exact scans
-    const int c = threadIdx.x;
-    const bool live = c < n_sets;
-    const bool paired = live && (c ^ 1) < n_sets;
-    int n = live ? *sets[c].n : 0;
-    const int n_other = paired ? *sets[c ^ 1].n : 0;
-    bool rows_only = live && (sets[c].flags & kSetRowsOnly);
-    bool other_rows = paired && (sets[c ^ 1].flags & kSetRowsOnly);
-    if (oside) {
-        if (paired) {
-            rows_only = (c & 1) ? n >= n_other : n > n_other;
-            other_rows = !rows_only;
-        }
-        if (live) {
-            MatchSet m = sets[c];
-            m.flags = rows_only ? (m.flags | kSetRowsOnly) : (m.flags & ~kSetRowsOnly);
-            oside[c] = m;
-        }
-    }
+// The plan of one set per thread (thread c: set c, n rows, its partner n_other
+// rows): slots, chunks, query waves, sort tiles and cross-rank items by block
+// scans, and the status counts of the pass.
+__device__ __forceinline__ void plan_sets_band(int c, bool live, bool paired, int n, int n_other, bool rows_only,
+                                               bool other_rows, int kp, SetPlan* plan, DevStatus* st,
+                                               int64_t* fb_total, int* s_scan) {
     // rows that no query is matched against need neither slots nor packing
     if (rows_only && (!paired || other_rows || n_other == 0)) n = 0;
     const int chunks = (n + kTileRows - 1) / kTileRows;
@@ -1796,6 +1762,57 @@ __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __rest
         st->band_step = 0;
         *fb_total = 0;  // the re-score counts the uncertified queries from zero
     }
+}
+
+// With `oside`, the sets are first made one-sided (the larger set of each
+// pair, the second on a tie, becomes rows-only) and written there; the
+// kernels after the planner then read oside.  With `both` as well, the
+// n_sets / 2 input sets are expanded there into the sets of both directions
+// in full, and the status block of that pass is cleared first.
+__global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
+                                                         SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside,
+                                                         int both, int64_t* __restrict__ fb_total,
+                                                         int32_t* __restrict__ grp_done, int64_t n_grp) {
+    __shared__ int s_scan[5 * (kPlanThreads / kWave)];
+    for (int64_t g = threadIdx.x; g < n_grp; g += kPlanThreads) grp_done[g] = 0;  // for the exact scans
+    const int c = threadIdx.x;
+    const bool live = c < n_sets;
+    const bool paired = live && (c ^ 1) < n_sets;
+    if (both) {
+        // both directions in full: the n_sets / 2 input sets become set 2t (t as queries) and
+        // set 2t + 1 (t's partner as rows only), planned on a status block of their own
+        for (int k = c; k < static_cast<int>(sizeof(DevStatus) / 4); k += kPlanThreads)
+            reinterpret_cast<uint32_t*>(st)[k] = 0u;
+        __syncthreads();
+        const int t = c >> 1;
+        MatchSet m;
+        int n = 0, n_other = 0;
+        if (live) {
+            m = sets[(c & 1) ? (t ^ 1) : t];
+            m.flags = (c & 1) ? (m.flags | kSetRowsOnly) : (m.flags & ~kSetRowsOnly);
+            oside[c] = m;
+            n = *m.n;
+            n_other = *sets[(c & 1) ? t : (t ^ 1)].n;
+        }
+        plan_sets_band(c, live, live, n, n_other, live && (c & 1), live && !(c & 1), kp, plan, st, fb_total, s_scan);
+        return;
+    }
+    int n = live ? *sets[c].n : 0;
+    const int n_other = paired ? *sets[c ^ 1].n : 0;
+    bool rows_only = live && (sets[c].flags & kSetRowsOnly);
+    bool other_rows = paired && (sets[c ^ 1].flags & kSetRowsOnly);
+    if (oside) {
+        if (paired) {
+            rows_only = (c & 1) ? n >= n_other : n > n_other;
+            other_rows = !rows_only;
+        }
+        if (live) {
+            MatchSet m = sets[c];
+            m.flags = rows_only ? (m.flags | kSetRowsOnly) : (m.flags & ~kSetRowsOnly);
+            oside[c] = m;
+        }
+    }
+    plan_sets_band(c, live, paired, n, n_other, rows_only, other_rows, kp, plan, st, fb_total, s_scan);
 }
 
 // 32-bit sort key of a slot.  Partners: the top 32 bits of the squared norm's
@@ -2739,9 +2756,11 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
 kmg_status match_lp(const MatchSet* sets, int n_sets, int dim, int prec, DevStatus* st, const MatchWs& w,
                     hipStream_t s);
 kmg_status match_fp64(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s);
-// With oside, the sets are made one-sided by the planner and written there.
+// With oside, the sets are made one-sided by the planner and written there;
+// with both as well, the n_sets / 2 input sets are expanded there into the
+// n_sets sets of both directions in full (and st is cleared first).
 kmg_status match_band(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s,
-                      MatchSet* oside = nullptr);
+                      MatchSet* oside = nullptr, bool both = false);
 kmg_status exact_fallback(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                           hipStream_t s);
 kmg_status exact_listed(const MatchSet* sets, int n_sets, int dim, const MatchWs& w, hipStream_t s,
@@ -2753,13 +2772,11 @@ kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st,
 kmg_status match_both(const MatchSet* sets, int n_sets, int dim, DevStatus* st, const MatchWs& w,
                       const PairOutDev* outs, int64_t* counts, int counts_stride, hipStream_t s,
                       const CloudState* cs, int64_t nnz_cap) {
-    both_sets<<<grid_for(std::max<int64_t>(n_sets, sizeof(DevStatus) / 4), 64), 64, 0, s>>>(sets, n_sets, w.rr.sets,
-                                                                                           w.rr.st);
-    KMG_TRY(launch_status());
     Carver c2(w.rr.region, w.rr.region_bytes);
     const MatchWs w2 = carve_match(c2, 2 * n_sets, 2 * w.q_cap, dim, false);
     if (!c2.fits()) return KMG_ERR_WORKSPACE;
-    KMG_TRY(match_band(w.rr.sets, 2 * n_sets, dim, w.rr.st, w2, s));
+    // the planner writes the four sets of each pair to rr.sets and clears rr.st
+    KMG_TRY(match_band(sets, 2 * n_sets, dim, w.rr.st, w2, s, w.rr.sets, true));
     StageScope sc(ST_MATCH_MUTUAL, s);
     mutual_both<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w2.nn, w2.q_cap, w2.flag,
                                                               w.rr.st);
@@ -2935,14 +2952,14 @@ kmg_status match_back(const MatchSet* sets1, int n_sets, int dim, DevStatus* st,
 // bounds, queries ranked by (class, norm) and packed, bands, band tiles, exact
 // re-score and certificate, exact scans for the rest.
 kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* st, const MatchWs& w, hipStream_t s,
-                      MatchSet* oside) {
+                      MatchSet* oside, bool both) {
     const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     if (ks != 9 && ks != 17) return KMG_ERR_ARG;
     const MatchSet* sets = oside ? oside : sets_in;
     {
         StageScope sc(ST_MATCH_PACK, s);
-        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, w.fb_total, w.grp_done,
-                                             w.n_grp);
+        plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, both ? 1 : 0, w.fb_total,
+                                             w.grp_done, w.n_grp);
         KMG_TRY(launch_status());
         row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
