@@ -2442,8 +2442,9 @@ __device__ __forceinline__ void absorb_some(double* top, const doublex4& acc, un
 // takes the rest of its own band alone.  Every tile meets each of its chunks
 // once, and a tile's product does not depend on the others', so the lists are
 // those of the four tiles over their own bands.
-// kBack only names the launch: 0 for the first direction, 1 for the matching
-// back and FP64 re-runs (so that profiles tell them apart).
+// kBack only names the launch: 0 for the first direction of the one-sided
+// form, 1 for the matching back, the FP64 re-runs and both directions in full
+// (so that profiles tell them apart).
 template <int KS, int kBack>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 ? 2 : 1))) void band_tiles(
     const SetPlan* __restrict__ plan, const double* __restrict__ pk, int dim, const int4* __restrict__ tinfo,
@@ -2956,6 +2957,7 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     const int ks = w.kp / 4;  // 9 or 17: the packed depth equals the kernel's 4 KS
     if (ks != 9 && ks != 17) return KMG_ERR_ARG;
     const MatchSet* sets = oside ? oside : sets_in;
+    const bool first = oside && !both;  // the launch name: the one-sided first direction, or the rest
     {
         StageScope sc(ST_MATCH_PACK, s);
         plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, both ? 1 : 0, w.fb_total,
@@ -2995,10 +2997,10 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     {
         StageScope sc(ST_MATCH_TOPK, s);
         if (ks == 9) {
-            if (oside) band_tiles<9, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
+            if (first) band_tiles<9, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
             else band_tiles<9, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
         } else {
-            if (oside) band_tiles<17, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
+            if (first) band_tiles<17, 0><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
             else band_tiles<17, 1><<<kBandBlocks, kBlock, 0, s>>>(w.plan, w.pk, dim, w.tinfo, w.wave_sub, w.part, st);
         }
         KMG_TRY(launch_status());
