@@ -101,3 +101,24 @@ def test_lidar_descriptors_with_rows(K, orc):
     np.testing.assert_array_equal(pairs, np.stack([js[mm["pairs"][:, 0]], jt[mm["pairs"][:, 1]]], 1)
                                   if len(mm["pairs"]) else pairs)
     np.testing.assert_array_equal(out.d1.cpu().numpy(), mm["d1"].astype(np.float32))
+
+
+@pytest.mark.parametrize("tuning", [None, {"band_tile": 4}, {"match_form": 1, "band_tile": 16}])
+def test_disjoint_tile_bands(K, orc, tuning):
+    # query norms over six decades, each query with a near twin among the rows (small R): the
+    # four 16-query tiles of a wave need disjoint chunk ranges, so no chunk is shared by all
+    # four and every tile runs its own range alone
+    rng = np.random.default_rng(11)
+    n = 1024
+    base = rng.gamma(0.7, 1.0, (n, 33))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    X = base * (10.0 ** np.linspace(0.0, 6.0, n))[:, None]
+    twins = X * (1 + 1e-3 * rng.standard_normal((n, 33)))
+    filler = rng.gamma(0.7, 1.0, (1000, 33)) * (10.0 ** rng.uniform(0.0, 6.0, (1000, 1)))
+    Y = np.abs(np.concatenate([twins, filler]))[rng.permutation(n + 1000)]
+    try:
+        K.set_tuning(tuning)
+        check(K, orc, X.astype(np.float32), Y.astype(np.float32))
+        check(K, orc, Y.astype(np.float32), X.astype(np.float32))
+    finally:
+        K.set_tuning(None)
