@@ -929,7 +929,7 @@ def main():
             "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 5),
-            "traffic": tile_traffic_bytes(kmg.get_tuning()),
+            "traffic": tile_traffic_bytes(tuned["setting"]),
             "avg_launch_ms": round(topk_avg_s * 1e3, 5),
             "flops_per_launch": flops_per_launch,
             "band_fraction": round(flops_per_launch / dense, 4),
