@@ -2581,13 +2581,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 9 
 // tiles, and candidates are packed partner positions mapped back through perm.
 __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restrict__ sets, SetPlan* plan, int n_sets,
                                                        int dim, const double* __restrict__ part,
-                                                       const double* __restrict__ n2, const int32_t* __restrict__ rank,
-                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ n2, const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ wave_tile, int32_t* __restrict__ nn,
                                                        double* __restrict__ best, double* __restrict__ second,
                                                        int32_t* __restrict__ failed, int32_t* __restrict__ fb_list,
                                                        int64_t* __restrict__ fb_total, DevStatus* st) {
-    // the queries only: index g = 64 (query wave) + position (scatter_pack clears the
+    // the queries only: index g = 64 (query wave) + packed position (scatter_pack clears the
     // flags of the rows-only slots)
     const int64_t total = static_cast<int64_t>(st->total_waves) * kBandWave;
     const bool no_tiles = st->err_capacity != 0;  // the results are void; the flags stay well defined
@@ -2598,13 +2597,17 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
         const int64_t wq = g / kBandWave;
         const int c = find_set(n_sets, wq, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
         const SetPlan qc = plan[c];
-        const int j = static_cast<int>(wq - qc.wave_off) * kBandWave + static_cast<int>(g % kBandWave);
-        if (j >= qc.n) continue;  // the last wave's padding (uniform over the quad)
-        const int64_t slot = qc.q_off + j;
+        // g runs over the packed (sorted) positions: the quads of a wave read adjacent columns
+        // of the same tile lists, and the query's slot comes from perm beside those loads
+        const int pos = static_cast<int>(wq - qc.wave_off) * kBandWave + static_cast<int>(g % kBandWave);
+        if (pos >= qc.n) continue;  // the last wave's padding (uniform over the quad)
         if (no_tiles) {
-            if (q == 0) failed[slot] = 0;
+            if (q == 0) failed[qc.q_off + pos] = 0;  // every slot of the set once
             continue;
         }
+        const int j = perm[qc.q_off + pos];
+        if (j < 0 || j >= qc.n) continue;  // never: the ranks are a permutation
+        const int64_t slot = qc.q_off + j;
         const int p = c ^ 1;
         const int np = p < n_sets ? plan[p].n : 0;
         if (np == 0) {
@@ -2616,8 +2619,7 @@ __global__ __launch_bounds__(kBlock) void rescore_band(const MatchSet* __restric
             }
             continue;
         }
-        const int pos = min(max(rank[slot], 0), qc.n - 1);
-        const int w = qc.wave_off + pos / kBandWave;
+        const int w = static_cast<int>(wq);
         const int col = pos % kBandWave;
         const int t0 = wave_tile[w], t1 = wave_tile[w + 1];
         double top[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
@@ -3009,9 +3011,8 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     {
         StageScope sc(ST_MATCH_RESCORE, s);
         rescore_band<<<grid_cap(w.q_cap * kQuad, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.part, w.n2,
-                                                                          w.rank, w.perm, w.wave_tile, w.nn, w.best,
-                                                                          w.second, w.flag, w.fb_list, w.fb_total,
-                                                                          st);
+                                                                          w.perm, w.wave_tile, w.nn, w.best, w.second,
+                                                                          w.flag, w.fb_list, w.fb_total, st);
         KMG_TRY(launch_status());
         KMG_TRY(exact_listed(sets, n_sets, dim, w, s, true));
     }
