@@ -2302,10 +2302,20 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
     }
     int64_t tot_len;
     block_excl_scan64(len_sum, smem, tot_len);
+    // a length fixed by the tuning is taken whenever its tiles fit: counted first, the
+    // model below is then not needed
+    bool forced_fits = false;
+    if (forced_T > 0) {
+        int64_t cnt = 0;
+        for (int w = threadIdx.x; w < W; w += kPlanThreads) cnt += (wave_len[w] + forced_T - 1) / forced_T;
+        int64_t tiles;
+        block_excl_scan64(cnt, smem, tiles);
+        forced_fits = tiles <= tile_cap;
+    }
     // exact tile counts sum_w ceil(L_w / T) of every candidate length; the quotient
     // from a float reciprocal, corrected to the exact one (L + T - 1 < 2^24)
     const bool exact = W <= kExactTileWaves;
-    if (exact && threadIdx.x < kTileCands * kCandThreads) {
+    if (!forced_fits && exact && threadIdx.x < kTileCands * kCandThreads) {
         const int i = threadIdx.x / kCandThreads, k = threadIdx.x % kCandThreads;
         const int T = tile_len_cand(i);
         const float inv = 1.0f / static_cast<float>(T);
@@ -2325,7 +2335,9 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
     __syncthreads();
     // wave 0: the modelled time of each candidate (lanes L and L + 64), the least wins,
     // the shorter length on a tie
-    if (wv == 0) {
+    if (forced_fits) {
+        if (threadIdx.x == 0) s_T = forced_T;
+    } else if (wv == 0) {
         int lm = 0;
         for (int k = 0; k < kPlanThreads / kWave; ++k) lm = max(lm, s_lmax[k]);
         double t_best = INFINITY;
@@ -2393,19 +2405,26 @@ __global__ __launch_bounds__(kPlanThreads) void band_plan(const SetPlan* __restr
         s_len[threadIdx.x] = L;
         s_set[threadIdx.x] = c;
         __syncthreads();
-        // the round's tiles, one per thread: the owning wave is the last whose first tile is <= t
+        // the round's tiles, a contiguous run per thread: the owning wave of the run's first
+        // tile is the last whose first tile is <= it, and the run walks on from there
         const int in_round = min(kPlanThreads, W - base);
-        for (int64_t t = threadIdx.x; t < round_total; t += kPlanThreads) {
-            if (carry + t >= tile_cap) break;
+        const int64_t per = (round_total + kPlanThreads - 1) / kPlanThreads;
+        const int64_t t_begin = min(round_total, static_cast<int64_t>(threadIdx.x) * per);
+        const int64_t t_end = min(round_total, t_begin + per);
+        if (t_begin < t_end) {
             int lo = 0, hi = in_round - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= t) lo = mid;
+                if (s_off[mid] <= t_begin) lo = mid;
                 else hi = mid - 1;
             }
-            const int k = static_cast<int>(t - s_off[lo]);
-            const int a = s_c0[lo] + k * T;
-            tinfo[carry + t] = make_int4(base + lo, s_set[lo], a, min(a + T, s_c0[lo] + s_len[lo]));
+            for (int64_t t = t_begin; t < t_end; ++t) {
+                if (carry + t >= tile_cap) break;
+                while (lo + 1 < in_round && s_off[lo + 1] <= t) ++lo;  // waves without tiles are passed over
+                const int k = static_cast<int>(t - s_off[lo]);
+                const int a = s_c0[lo] + k * T;
+                tinfo[carry + t] = make_int4(base + lo, s_set[lo], a, min(a + T, s_c0[lo] + s_len[lo]));
+            }
         }
         __syncthreads();
         carry += round_total;
