@@ -379,6 +379,7 @@ struct MatchWs {
     int32_t* wave_c0;     // norm-band matching: first partner chunk of every query wave's band
     int32_t* wave_len;    // norm-band matching: chunks in the band
     int2* wave_sub;       // norm-band matching: chunk range of each 16-query tile of every wave
+    int32_t* chist;       // norm-band matching, both directions: class histogram of every query sort tile
     int32_t* wave_tile;   // norm-band matching: first tile of every wave (wave_cap + 1 entries)
     int4* tinfo;          // norm-band matching: per tile {wave, set, first chunk, end chunk}
     int64_t wave_cap;

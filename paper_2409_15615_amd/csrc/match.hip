@@ -1940,6 +1940,134 @@ __global__ __launch_bounds__(kSortThreads) void cross_rank(const MatchSet* __res
     }
 }
 
+// Both directions in full: the query set of a cloud is ordered by (class of R,
+// norm) as a stable partition by class of the norm order that the rows-only
+// set of the same cloud already has (the partners' ordering), in place of
+// tile_sort and cross_rank.  Any order of the queries gives the same results;
+// this one keeps each class in norm order.  A query set whose cloud has no
+// ordered rows set (its partner cloud has no queries) keeps the slot order.
+__device__ __forceinline__ int band_class(double r2) {
+    const int e = static_cast<int>((static_cast<unsigned long long>(__double_as_longlong(r2)) >> 52) & 0x7ffull);
+    return min(max(e - 1023 + 256, 0), 511) >> 1;
+}
+constexpr int kClasses = 256;
+
+// The rows-only set of query set c's own cloud (sets 2t: cloud t as queries,
+// 2t + 1: cloud t^1 as rows), or -1 when it holds no ordered copy.
+__device__ __forceinline__ int same_cloud_rows(const SetPlan* plan, int n_sets, int c) {
+    const int cr = 2 * ((c >> 1) ^ 1) + 1;
+    return (cr < n_sets && plan[cr].n == plan[c].n) ? cr : -1;
+}
+
+// Class histogram of every sort tile of the query sets, in the norm order.
+__global__ __launch_bounds__(kSortTile) void class_hist(const MatchSet* __restrict__ sets,
+                                                        const SetPlan* __restrict__ plan, int n_sets,
+                                                        const double* __restrict__ r2,
+                                                        const int32_t* __restrict__ perm, int32_t* __restrict__ hist,
+                                                        const DevStatus* st) {
+    __shared__ int s_h[kClasses];
+    const int r = threadIdx.x;
+    const int64_t total = st->sort_items;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_set(n_sets, item, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the block
+        const int cr = same_cloud_rows(plan, n_sets, c);
+        if (cr < 0) continue;
+        const SetPlan pc = plan[c];
+        const int e0 = static_cast<int>(item - pc.tile_off) * kSortTile;
+        const int cnt = min(kSortTile, pc.n - e0);
+        if (r < kClasses) s_h[r] = 0;
+        __syncthreads();
+        if (r < cnt) {
+            const int j = perm[plan[cr].q_off + e0 + r];
+            if (j >= 0 && j < pc.n) atomicAdd(&s_h[band_class(r2[pc.q_off + j])], 1);  // (a valid order: always)
+        }
+        __syncthreads();
+        if (r < kClasses) hist[item * kClasses + r] = s_h[r];
+        __syncthreads();  // s_h is free for the next item
+    }
+}
+
+// rank[slot] = class offset + the class's count in earlier tiles + its count
+// earlier in this tile (waves in order, lanes in order within a wave).
+__global__ __launch_bounds__(kSortTile) void class_rank(const MatchSet* __restrict__ sets,
+                                                        const SetPlan* __restrict__ plan, int n_sets,
+                                                        const double* __restrict__ r2,
+                                                        const int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ hist, int32_t* __restrict__ rank,
+                                                        const DevStatus* st) {
+    constexpr int kWaves = kSortTile / kWave;
+    __shared__ int s_tot[kClasses], s_off[kClasses];
+    __shared__ int s_wcnt[kWaves][kClasses];
+    const int r = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = r / kWave;
+    const int64_t total = st->sort_items;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_set(n_sets, item, [&](int s) { return static_cast<int64_t>(plan[s].tile_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the block
+        const int cr = same_cloud_rows(plan, n_sets, c);
+        const SetPlan pc = plan[c];
+        const int e0 = static_cast<int>(item - pc.tile_off) * kSortTile;
+        const int cnt = min(kSortTile, pc.n - e0);
+        if (cr < 0) {
+            if (r < cnt) rank[pc.q_off + e0 + r] = e0 + r;
+            continue;
+        }
+        const int jp = r < cnt ? perm[plan[cr].q_off + e0 + r] : -1;
+        const bool ok = jp >= 0 && jp < pc.n;  // (a valid order: always)
+        const int j = ok ? jp : 0;
+        const int cls = ok ? band_class(r2[pc.q_off + j]) : -1;
+        // the set's class totals and the counts of its tiles before this one
+        const int nt = (pc.n + kSortTile - 1) / kSortTile;
+        const int me = static_cast<int>(item - pc.tile_off);
+        if (r < kClasses) {
+            int tot = 0, pre = 0;
+            for (int t = 0; t < nt; ++t) {
+                const int h = hist[(static_cast<int64_t>(pc.tile_off) + t) * kClasses + r];
+                tot += h;
+                pre += t < me ? h : 0;
+            }
+            s_tot[r] = tot;
+            s_off[r] = pre;
+        }
+        for (int k = r; k < kWaves * kClasses; k += kSortTile) (&s_wcnt[0][0])[k] = 0;
+        __syncthreads();
+        if (r < kWave) {  // wave 0: exclusive scan of the class totals, four classes per lane
+            int v[kClasses / kWave], sum = 0;
+#pragma unroll
+            for (int u = 0; u < kClasses / kWave; ++u) {
+                v[u] = s_tot[r * (kClasses / kWave) + u];
+                sum += v[u];
+            }
+            int run = wave_incl_scan(sum) - sum;
+#pragma unroll
+            for (int u = 0; u < kClasses / kWave; ++u) {
+                s_off[r * (kClasses / kWave) + u] += run;
+                run += v[u];
+            }
+        }
+        // the element's place among the earlier elements of its class in its wave
+        int in_wave = 0;
+        unsigned long long pending = ballot(cls >= 0);
+        while (pending) {  // uniform over the wave: one round per class present
+            const int lead = __ffsll(static_cast<long long>(pending)) - 1;
+            const int lc = __shfl(cls, lead, kWave);
+            const unsigned long long m = ballot(cls == lc);
+            if (cls == lc) in_wave = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == lead) s_wcnt[wv][lc] = __popcll(m);
+            pending &= ~m;
+        }
+        __syncthreads();
+        if (cls >= 0) {
+            int before = 0;
+            for (int w = 0; w < wv; ++w) before += s_wcnt[w][cls];
+            rank[pc.q_off + j] = s_off[cls] + before + in_wave;
+        }
+        __syncthreads();  // the LDS tables are free for the next item
+    }
+}
+
 // Packs the rows of the sets of one role at their ranks (layout of pack_rows:
 // k-major chunks of 16 rows, the squared norm at k = dim, padding rows scored
 // kPadScore) and records perm[q_off + position] = local row (and, for
@@ -2755,6 +2883,8 @@ MatchWs carve_match(Carver& c, int n_sets, int64_t q_cap, int dim, bool rerun) {
     w.wave_c0 = c.take<int32_t>(static_cast<size_t>(w.wave_cap));
     w.wave_len = c.take<int32_t>(static_cast<size_t>(w.wave_cap));
     w.wave_sub = c.take<int2>(static_cast<size_t>(w.wave_cap) * kTilesPerWave);
+    // class histograms of the query sort tiles (at most q_cap / kSortTile + n_sets of them)
+    w.chist = c.take<int32_t>(static_cast<size_t>(w.q_cap / kSortTile + n_sets + 1) * kClasses);
     w.wave_tile = c.take<int32_t>(static_cast<size_t>(w.wave_cap + 1));
     w.tinfo = c.take<int4>(static_cast<size_t>(w.tile_cap));
     w.rr = RerunWs{};
@@ -2997,11 +3127,18 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
                     band_seeds<17><<<gs, kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.pk, w.n2, w.skey, w.r2, st);
                 KMG_TRY(launch_status());
             }
-            tile_sort<<<grid_cap((w.q_cap / kSortTile + n_sets + 1) * kBlock, kBlock), kSortTile, 0, s>>>(
-                sets, w.plan, n_sets, role, w.n2, w.r2, sorted, w.rank, st);
-            KMG_TRY(launch_status());
-            cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
-            KMG_TRY(launch_status());
+            const unsigned gt = grid_cap((w.q_cap / kSortTile + n_sets + 1) * kBlock, kBlock);
+            if (both && role == 0) {  // the queries: a partition by class of their cloud's norm order
+                class_hist<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, w.r2, w.perm, w.chist, st);
+                KMG_TRY(launch_status());
+                class_rank<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, w.r2, w.perm, w.chist, w.rank, st);
+                KMG_TRY(launch_status());
+            } else {
+                tile_sort<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, role, w.n2, w.r2, sorted, w.rank, st);
+                KMG_TRY(launch_status());
+                cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
+                KMG_TRY(launch_status());
+            }
             scatter_pack<<<grid_cap(w.q_cap * 4, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
                                                                              w.n2, w.rank, w.pk, w.perm, w.skey, w.flag,
                                                                              st);
