@@ -1988,14 +1988,15 @@ __global__ __launch_bounds__(kSortTile) void class_hist(const MatchSet* __restri
     }
 }
 
-// rank[slot] = class offset + the class's count in earlier tiles + its count
-// earlier in this tile (waves in order, lanes in order within a wave).
+// perm[position] = the query's slot, with position = class offset + the
+// class's count in earlier tiles + its count earlier in this tile (waves in
+// order, lanes in order within a wave).  The reads of the rows set's part of
+// perm and the writes of the query set's part never overlap; gather_pack then
+// packs the queries in that order.
 __global__ __launch_bounds__(kSortTile) void class_rank(const MatchSet* __restrict__ sets,
                                                         const SetPlan* __restrict__ plan, int n_sets,
-                                                        const double* __restrict__ r2,
-                                                        const int32_t* __restrict__ perm,
-                                                        const int32_t* __restrict__ hist, int32_t* __restrict__ rank,
-                                                        const DevStatus* st) {
+                                                        const double* __restrict__ r2, int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ hist, const DevStatus* st) {
     constexpr int kWaves = kSortTile / kWave;
     __shared__ int s_tot[kClasses], s_off[kClasses];
     __shared__ int s_wcnt[kWaves][kClasses];
@@ -2011,7 +2012,7 @@ __global__ __launch_bounds__(kSortTile) void class_rank(const MatchSet* __restri
         const int e0 = static_cast<int>(item - pc.tile_off) * kSortTile;
         const int cnt = min(kSortTile, pc.n - e0);
         if (cr < 0) {
-            if (r < cnt) rank[pc.q_off + e0 + r] = e0 + r;
+            if (r < cnt) perm[pc.q_off + e0 + r] = e0 + r;
             continue;
         }
         const int jp = r < cnt ? perm[plan[cr].q_off + e0 + r] : -1;
@@ -2062,9 +2063,60 @@ __global__ __launch_bounds__(kSortTile) void class_rank(const MatchSet* __restri
         if (cls >= 0) {
             int before = 0;
             for (int w = 0; w < wv; ++w) before += s_wcnt[w][cls];
-            rank[pc.q_off + j] = s_off[cls] + before + in_wave;
+            perm[pc.q_off + s_off[cls] + before + in_wave] = j;
         }
         __syncthreads();  // the LDS tables are free for the next item
+    }
+}
+
+// The query sets' packed chunks once perm holds their order (both directions
+// in full): one wavefront per chunk, lane 4 r + q writing quarter q of the kp
+// values of the chunk's row r, so that the 16 lanes of a quarter write whole
+// 128-byte lines (scatter_pack writes each slot's values where its rank puts
+// them, one value per line); padding rows as scatter_pack writes them.
+__global__ __launch_bounds__(kBlock) void gather_pack(const MatchSet* __restrict__ sets,
+                                                      const SetPlan* __restrict__ plan, int n_sets, int dim, int kp,
+                                                      const double* __restrict__ n2,
+                                                      const int32_t* __restrict__ perm, double* __restrict__ pk,
+                                                      DevStatus* st) {
+    const int ks = kp / 4;
+    const int lane = lane_id();
+    const int r = lane >> 2, q = lane & 3;
+    const int64_t total = st->total_chunks;
+    const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t g = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; g < total; g += gw) {
+        const int c = find_set(n_sets, g, [&](int s) { return static_cast<int64_t>(plan[s].chunk_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the wave
+        const SetPlan pc = plan[c];
+        const int pos = static_cast<int>(g - pc.chunk_off) * kTileRows + r;
+        double* dst = pk + g * kp * kTileRows + r;
+        const int k0 = q * ks;
+        if (pos < pc.n) {
+            const int j = perm[pc.q_off + pos];
+            if (j < 0 || j >= pc.n) {  // never: the order is a permutation
+                st->err_capacity = 1;
+                continue;
+            }
+            const float* x = set_row(sets[c], j, dim);
+            double v[17];
+#pragma unroll
+            for (int u = 0; u < 17; ++u) {
+                const int k = k0 + u;
+                v[u] = (u < ks && k < dim) ? static_cast<double>(x[k]) : 0.0;
+            }
+            const double nn = n2[pc.q_off + j];
+#pragma unroll
+            for (int u = 0; u < 17; ++u) {
+                const int k = k0 + u;
+                if (u < ks) dst[k * kTileRows] = k == dim ? nn : v[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 17; ++u) {
+                const int k = k0 + u;
+                if (u < ks) dst[k * kTileRows] = k == dim ? kPadScore : 0.0;
+            }
+        }
     }
 }
 
@@ -3131,7 +3183,7 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
             if (both && role == 0) {  // the queries: a partition by class of their cloud's norm order
                 class_hist<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, w.r2, w.perm, w.chist, st);
                 KMG_TRY(launch_status());
-                class_rank<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, w.r2, w.perm, w.chist, w.rank, st);
+                class_rank<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, w.r2, w.perm, w.chist, st);
                 KMG_TRY(launch_status());
             } else {
                 tile_sort<<<gt, kSortTile, 0, s>>>(sets, w.plan, n_sets, role, w.n2, w.r2, sorted, w.rank, st);
@@ -3139,9 +3191,14 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
                 cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
                 KMG_TRY(launch_status());
             }
-            scatter_pack<<<grid_cap(w.q_cap * 4, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
-                                                                             w.n2, w.rank, w.pk, w.perm, w.skey, w.flag,
-                                                                             st);
+            if (both && role == 0) {  // perm holds the queries' order: their chunks are gathered
+                gather_pack<<<grid_cap((w.chunk_cap) * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim,
+                                                                                        w.kp, w.n2, w.perm, w.pk, st);
+            } else {
+                scatter_pack<<<grid_cap(w.q_cap * 4, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
+                                                                                 w.n2, w.rank, w.pk, w.perm, w.skey,
+                                                                                 w.flag, st);
+            }
             KMG_TRY(launch_status());
         }
         band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2, w.perm,
