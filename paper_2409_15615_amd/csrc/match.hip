@@ -1501,9 +1501,14 @@ __global__ __launch_bounds__(kBlock) void rerun_scatter(const SetPlan* __restric
 // A pair (j, i) is mutual when j's nearest neighbour is i and i's is j.  The
 // band planner writes the four sets (plan_band with `both`).
 
+// The flags also come summed per scan tile (tile_sums, cleared by the planner):
+// a wavefront's 64 slots lie in one tile, so one atomic per wavefront that
+// found a pair.
+static_assert(kScanTile % kWave == 0 && kBlock % kWave == 0, "a wavefront's slots lie in one scan tile");
 __global__ __launch_bounds__(kBlock) void mutual_both(const SetPlan* __restrict__ plan, int n_sets2,
                                                       const int32_t* __restrict__ nn, int64_t q_cap,
-                                                      int32_t* __restrict__ flag, const DevStatus* st2) {
+                                                      int32_t* __restrict__ flag, int64_t* __restrict__ tile_sums,
+                                                      const DevStatus* st2) {
     const int64_t total = st2->total_queries;
     const int64_t gs = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t slot = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; slot < q_cap; slot += gs) {
@@ -1516,6 +1521,9 @@ __global__ __launch_bounds__(kBlock) void mutual_both(const SetPlan* __restrict_
             }
         }
         flag[slot] = f;
+        const int cnt = __popcll(ballot(f != 0));
+        if (lane_id() == 0 && cnt) atomicAdd(reinterpret_cast<unsigned long long*>(tile_sums + slot / kScanTile),
+                                             static_cast<unsigned long long>(cnt));
     }
 }
 
@@ -1772,9 +1780,12 @@ __device__ __forceinline__ void plan_sets_band(int c, bool live, bool paired, in
 __global__ __launch_bounds__(kPlanThreads) void plan_band(const MatchSet* __restrict__ sets, int n_sets, int kp,
                                                          SetPlan* plan, DevStatus* st, MatchSet* __restrict__ oside,
                                                          int both, int64_t* __restrict__ fb_total,
-                                                         int32_t* __restrict__ grp_done, int64_t n_grp) {
+                                                         int32_t* __restrict__ grp_done, int64_t n_grp,
+                                                         int64_t* __restrict__ scan_tmp, int64_t n_tmp) {
     __shared__ int s_scan[5 * (kPlanThreads / kWave)];
     for (int64_t g = threadIdx.x; g < n_grp; g += kPlanThreads) grp_done[g] = 0;  // for the exact scans
+    if (both)  // the tile sums of the mutual flags, accumulated by mutual_both
+        for (int64_t g = threadIdx.x; g < n_tmp; g += kPlanThreads) scan_tmp[g] = 0;
     const int c = threadIdx.x;
     const bool live = c < n_sets;
     const bool paired = live && (c ^ 1) < n_sets;
@@ -2983,9 +2994,9 @@ kmg_status match_both(const MatchSet* sets, int n_sets, int dim, DevStatus* st, 
     KMG_TRY(match_band(sets, 2 * n_sets, dim, w.rr.st, w2, s, w.rr.sets, true));
     StageScope sc(ST_MATCH_MUTUAL, s);
     mutual_both<<<grid_cap(w2.q_cap, kBlock), kBlock, 0, s>>>(w2.plan, 2 * n_sets, w2.nn, w2.q_cap, w2.flag,
-                                                              w.rr.st);
+                                                              w2.scan_tmp, w.rr.st);
     KMG_TRY(launch_status());
-    KMG_TRY(scan_exclusive(w2.flag, w2.pos, w2.q_cap, &w.rr.st->pairs_total, w2.scan_tmp, s));
+    KMG_TRY(scan_exclusive_summed(w2.flag, w2.pos, w2.q_cap, &w.rr.st->pairs_total, w2.scan_tmp, s));
     emit_both<<<std::max(grid_cap(w2.q_cap, kBlock), grid_for(n_sets, kBlock)), kBlock, 0, s>>>(
         sets, w2.plan, 2 * n_sets, w2.flag, w2.pos, w2.nn, w2.best, w2.second, outs, st, w.rr.st, counts,
         counts_stride, cs, nnz_cap);
@@ -3164,7 +3175,8 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
     {
         StageScope sc(ST_MATCH_PACK, s);
         plan_band<<<1, kPlanThreads, 0, s>>>(sets_in, n_sets, w.kp, w.plan, st, oside, both ? 1 : 0, w.fb_total,
-                                             w.grp_done, w.n_grp);
+                                             w.grp_done, w.n_grp, w.scan_tmp,
+                                             static_cast<int64_t>(scan_temp_elems(w.q_cap)));
         KMG_TRY(launch_status());
         row_norms<<<grid_cap(w.q_cap, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.n2, st, nullptr);
         KMG_TRY(launch_status());
