@@ -51,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 # null until the counters are taken again.
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
-    "sha256": "770c1ac68c739d96eea7bc501eb584b2271728da62448c2299a667d6070bed5f",
-    "fetch_kib": 67330.3,
+    "sha256": "456f0e261b97f36ca8106e534216b244f070b58b606a9b976ce27a76eb938207",
+    "fetch_kib": 67601.4,
     "fetch_scale": 262144.0 / 131085.1,
-    "write_kib": 11856.7,
+    "write_kib": 11850.6,
     "write_scale": 262144.0 / 262144.0,
     "tuning": {"match_form": 1, "band_tile": 16},
 }
