@@ -122,3 +122,21 @@ def test_disjoint_tile_bands(K, orc, tuning):
         check(K, orc, Y.astype(np.float32), X.astype(np.float32))
     finally:
         K.set_tuning(None)
+
+
+@pytest.mark.parametrize("shape", [(0, 50), (50, 0), (1, 40), (40, 1), (2, 3), (65, 64), (1100, 700)])
+def test_both_directions_small_and_empty(K, orc, shape):
+    # both directions in full: a cloud whose partner has no rows keeps its slot order (its
+    # rows-only copy is empty), every other query set is ordered from its cloud's sorted copy
+    rng = np.random.default_rng(13 * shape[0] + shape[1])
+    X = rng.gamma(0.7, 10.0, (shape[0], 33)).astype(np.float32)
+    Y = rng.gamma(0.7, 10.0, (shape[1], 33)).astype(np.float32)
+    try:
+        K.set_tuning({"match_form": 1, "band_tile": 16})
+        if min(shape) == 0:
+            out = K.match(dev(X), dev(Y))
+            assert out.pairs.shape[0] == 0
+        else:
+            check(K, orc, X, Y)
+    finally:
+        K.set_tuning(None)
