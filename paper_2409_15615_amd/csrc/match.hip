@@ -2081,52 +2081,45 @@ __global__ __launch_bounds__(kSortTile) void class_rank(const MatchSet* __restri
 }
 
 // The query sets' packed chunks once perm holds their order (both directions
-// in full): one wavefront per chunk, lane 4 r + q writing quarter q of the kp
-// values of the chunk's row r, so that the 16 lanes of a quarter write whole
-// 128-byte lines (scatter_pack writes each slot's values where its rank puts
-// them, one value per line); padding rows as scatter_pack writes them.
-__global__ __launch_bounds__(kBlock) void gather_pack(const MatchSet* __restrict__ sets,
-                                                      const SetPlan* __restrict__ plan, int n_sets, int dim, int kp,
-                                                      const double* __restrict__ n2,
-                                                      const int32_t* __restrict__ perm, double* __restrict__ pk,
-                                                      DevStatus* st) {
+// in full), so that the 16 lanes of a quarter write whole 128-byte lines
+// (scatter_pack writes each slot's values where its rank puts them, one value
+// per line); padding rows as scatter_pack writes them.  pack_band_waves runs
+// it for the chunks of each query wave before the wave's bands.
+// One query chunk g (global chunk index, of query set c) packed by one
+// wavefront: lane 4 r + q writes quarter q of the kp values of row r.
+__device__ __forceinline__ void pack_chunk(const MatchSet* __restrict__ sets, const SetPlan& pc, int c, int dim,
+                                           int kp, const double* __restrict__ n2, const int32_t* __restrict__ perm,
+                                           double* __restrict__ pk, DevStatus* st, int64_t g) {
     const int ks = kp / 4;
     const int lane = lane_id();
     const int r = lane >> 2, q = lane & 3;
-    const int64_t total = st->total_chunks;
-    const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-    for (int64_t g = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; g < total; g += gw) {
-        const int c = find_set(n_sets, g, [&](int s) { return static_cast<int64_t>(plan[s].chunk_off); });
-        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the wave
-        const SetPlan pc = plan[c];
-        const int pos = static_cast<int>(g - pc.chunk_off) * kTileRows + r;
-        double* dst = pk + g * kp * kTileRows + r;
-        const int k0 = q * ks;
-        if (pos < pc.n) {
-            const int j = perm[pc.q_off + pos];
-            if (j < 0 || j >= pc.n) {  // never: the order is a permutation
-                st->err_capacity = 1;
-                continue;
-            }
-            const float* x = set_row(sets[c], j, dim);
-            double v[17];
+    const int pos = static_cast<int>(g - pc.chunk_off) * kTileRows + r;
+    double* dst = pk + g * kp * kTileRows + r;
+    const int k0 = q * ks;
+    if (pos < pc.n) {
+        const int j = perm[pc.q_off + pos];
+        if (j < 0 || j >= pc.n) {  // never: the order is a permutation
+            st->err_capacity = 1;
+            return;
+        }
+        const float* x = set_row(sets[c], j, dim);
+        double v[17];
 #pragma unroll
-            for (int u = 0; u < 17; ++u) {
-                const int k = k0 + u;
-                v[u] = (u < ks && k < dim) ? static_cast<double>(x[k]) : 0.0;
-            }
-            const double nn = n2[pc.q_off + j];
+        for (int u = 0; u < 17; ++u) {
+            const int k = k0 + u;
+            v[u] = (u < ks && k < dim) ? static_cast<double>(x[k]) : 0.0;
+        }
+        const double nn = n2[pc.q_off + j];
 #pragma unroll
-            for (int u = 0; u < 17; ++u) {
-                const int k = k0 + u;
-                if (u < ks) dst[k * kTileRows] = k == dim ? nn : v[u];
-            }
-        } else {
+        for (int u = 0; u < 17; ++u) {
+            const int k = k0 + u;
+            if (u < ks) dst[k * kTileRows] = k == dim ? nn : v[u];
+        }
+    } else {
 #pragma unroll
-            for (int u = 0; u < 17; ++u) {
-                const int k = k0 + u;
-                if (u < ks) dst[k * kTileRows] = k == dim ? kPadScore : 0.0;
-            }
+        for (int u = 0; u < 17; ++u) {
+            const int k = k0 + u;
+            if (u < ks) dst[k * kTileRows] = k == dim ? kPadScore : 0.0;
         }
     }
 }
@@ -2370,6 +2363,68 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // hi^2 (1 + 2^-50)], found on the chunks' first and last sort keys (a key k
 // holds squared norms in [dec(k), dec(k + 1))); the wave's range is the union
 // of its tiles' ranges.
+__device__ __forceinline__ void wave_band(const SetPlan* __restrict__ plan, int n_sets,
+                                          const double* __restrict__ n2, const double* __restrict__ r2,
+                                          const int32_t* __restrict__ perm, const uint32_t* __restrict__ skey,
+                                          int32_t* __restrict__ wave_c0, int32_t* __restrict__ wave_len,
+                                          int2* __restrict__ wave_sub, int64_t w) {
+    const int lane = lane_id();
+    const int c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+    const SetPlan qc = plan[c];
+    const int p = c ^ 1;
+    const int np = p < n_sets ? plan[p].n : 0;
+    const int pos = static_cast<int>(w - qc.wave_off) * kBandWave + lane;
+    double lo = INFINITY, hi = -INFINITY;
+    const int jq = pos < qc.n ? perm[qc.q_off + pos] : -1;
+    if (jq >= 0 && jq < qc.n) {
+        const int64_t sl = qc.q_off + jq;
+        const double nu = sqrt(n2[sl]);
+        const double R = sqrt(r2[sl]);
+        const double m = 0x1p-38 * (nu + R);
+        lo = nu - R - m;
+        hi = nu + R + m;
+    }
+    // the band of each 16-query tile of the wave (lanes 16 t .. 16 t + 15); the wave's
+    // band is their union
+#pragma unroll
+    for (int d = 1; d < kTileCols; d <<= 1) {
+        lo = fmin(lo, __shfl_xor(lo, d, kWave));
+        hi = fmax(hi, __shfl_xor(hi, d, kWave));
+    }
+    const bool live = np > 0 && lo <= hi;
+    int k0 = 0, k1 = 0;
+    if (ballot(live)) {  // uniform over the wave
+        const SetPlan pc = plan[p];
+        const uint32_t* pkey = skey + pc.q_off;
+        const int pch = pc.chunks;
+        // chunks whose last key is below that of lo^2 hold only squared norms below it
+        const uint32_t klo = norm_key(lo > 0.0 ? lo * lo * (1.0 - 0x1p-50) : 0.0);
+        const int s0 = group_search16(live && lo > 0.0 ? pch : 0, [&](int k) {
+            return pkey[min(k * kTileRows + kTileRows - 1, np - 1)] < klo;
+        });
+        // chunks whose first key is above that of hi^2 hold only squared norms above it
+        const uint32_t khi = norm_key(hi == INFINITY ? 0.0 : hi * hi * (1.0 + 0x1p-50));
+        const int s1 = group_search16(live && hi != INFINITY ? pch : 0,
+                                      [&](int k) { return pkey[k * kTileRows] <= khi; });
+        if (live) {
+            k0 = s0;
+            k1 = hi == INFINITY ? pch : max(s1, s0);
+        }
+    }
+    if ((lane & (kTileCols - 1)) == 0) wave_sub[w * kTilesPerWave + lane / kTileCols] = make_int2(k0, k1);
+    // the union: the smallest start and the largest end of the non-empty tile ranges
+    int u0 = k1 > k0 ? k0 : INT_MAX, u1 = k1 > k0 ? k1 : 0;
+#pragma unroll
+    for (int d = kTileCols; d < kWave; d <<= 1) {
+        u0 = min(u0, __shfl_xor(u0, d, kWave));
+        u1 = max(u1, __shfl_xor(u1, d, kWave));
+    }
+    if (lane == 0) {
+        wave_c0[w] = u1 > 0 ? u0 : 0;
+        wave_len[w] = u1 > 0 ? u1 - u0 : 0;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void band_waves(const MatchSet* __restrict__ sets,
                                                      const SetPlan* __restrict__ plan, int n_sets,
                                                      const double* __restrict__ n2, const double* __restrict__ r2,
@@ -2377,64 +2432,35 @@ __global__ __launch_bounds__(kBlock) void band_waves(const MatchSet* __restrict_
                                                      const uint32_t* __restrict__ skey,
                                                      int32_t* __restrict__ wave_c0, int32_t* __restrict__ wave_len,
                                                      int2* __restrict__ wave_sub, const DevStatus* st) {
-    const int lane = lane_id();
     const int64_t total = st->total_waves;
     const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-    for (int64_t w = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; w < total; w += gw) {
-        const int c = find_set(n_sets, w, [&](int s) { return static_cast<int64_t>(plan[s].wave_off); });
+    for (int64_t w = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; w < total; w += gw)
+        wave_band(plan, n_sets, n2, r2, perm, skey, wave_c0, wave_len, wave_sub, w);
+}
+
+// Both directions in full: one wavefront per query chunk packs it, and the
+// wavefront of the first chunk of each query wave also finds the wave's bands
+// (band_waves' work), in one launch.
+__global__ __launch_bounds__(kBlock) void pack_band_waves(const MatchSet* __restrict__ sets,
+                                                          const SetPlan* __restrict__ plan, int n_sets, int dim,
+                                                          int kp, const double* __restrict__ n2,
+                                                          const double* __restrict__ r2,
+                                                          const int32_t* __restrict__ perm,
+                                                          const uint32_t* __restrict__ skey, double* __restrict__ pk,
+                                                          int32_t* __restrict__ wave_c0,
+                                                          int32_t* __restrict__ wave_len, int2* __restrict__ wave_sub,
+                                                          DevStatus* st) {
+    const int64_t total = st->total_chunks;
+    const int64_t gw = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t g = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; g < total; g += gw) {
+        const int c = find_set(n_sets, g, [&](int s) { return static_cast<int64_t>(plan[s].chunk_off); });
+        if (sets[c].flags & kSetRowsOnly) continue;  // uniform over the wave
         const SetPlan qc = plan[c];
-        const int p = c ^ 1;
-        const int np = p < n_sets ? plan[p].n : 0;
-        const int pos = static_cast<int>(w - qc.wave_off) * kBandWave + lane;
-        double lo = INFINITY, hi = -INFINITY;
-        const int jq = pos < qc.n ? perm[qc.q_off + pos] : -1;
-        if (jq >= 0 && jq < qc.n) {
-            const int64_t sl = qc.q_off + jq;
-            const double nu = sqrt(n2[sl]);
-            const double R = sqrt(r2[sl]);
-            const double m = 0x1p-38 * (nu + R);
-            lo = nu - R - m;
-            hi = nu + R + m;
-        }
-        // the band of each 16-query tile of the wave (lanes 16 t .. 16 t + 15); the wave's
-        // band is their union
-#pragma unroll
-        for (int d = 1; d < kTileCols; d <<= 1) {
-            lo = fmin(lo, __shfl_xor(lo, d, kWave));
-            hi = fmax(hi, __shfl_xor(hi, d, kWave));
-        }
-        const bool live = np > 0 && lo <= hi;
-        int k0 = 0, k1 = 0;
-        if (ballot(live)) {  // uniform over the wave
-            const SetPlan pc = plan[p];
-            const uint32_t* pkey = skey + pc.q_off;
-            const int pch = pc.chunks;
-            // chunks whose last key is below that of lo^2 hold only squared norms below it
-            const uint32_t klo = norm_key(lo > 0.0 ? lo * lo * (1.0 - 0x1p-50) : 0.0);
-            const int s0 = group_search16(live && lo > 0.0 ? pch : 0, [&](int k) {
-                return pkey[min(k * kTileRows + kTileRows - 1, np - 1)] < klo;
-            });
-            // chunks whose first key is above that of hi^2 hold only squared norms above it
-            const uint32_t khi = norm_key(hi == INFINITY ? 0.0 : hi * hi * (1.0 + 0x1p-50));
-            const int s1 = group_search16(live && hi != INFINITY ? pch : 0,
-                                          [&](int k) { return pkey[k * kTileRows] <= khi; });
-            if (live) {
-                k0 = s0;
-                k1 = hi == INFINITY ? pch : max(s1, s0);
-            }
-        }
-        if ((lane & (kTileCols - 1)) == 0) wave_sub[w * kTilesPerWave + lane / kTileCols] = make_int2(k0, k1);
-        // the union: the smallest start and the largest end of the non-empty tile ranges
-        int u0 = k1 > k0 ? k0 : INT_MAX, u1 = k1 > k0 ? k1 : 0;
-#pragma unroll
-        for (int d = kTileCols; d < kWave; d <<= 1) {
-            u0 = min(u0, __shfl_xor(u0, d, kWave));
-            u1 = max(u1, __shfl_xor(u1, d, kWave));
-        }
-        if (lane == 0) {
-            wave_c0[w] = u1 > 0 ? u0 : 0;
-            wave_len[w] = u1 > 0 ? u1 - u0 : 0;
-        }
+        const int local = static_cast<int>(g - qc.chunk_off);
+        pack_chunk(sets, qc, c, dim, kp, n2, perm, pk, st, g);
+        if (local % (kBandWave / kTileRows) == 0)
+            wave_band(plan, n_sets, n2, r2, perm, skey, wave_c0, wave_len, wave_sub,
+                      qc.wave_off + local / (kBandWave / kTileRows));
     }
 }
 
@@ -3203,9 +3229,10 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
                 cross_rank<<<kPersistBlocks, kSortThreads, 0, s>>>(sets, w.plan, n_sets, role, sorted, w.rank, st);
                 KMG_TRY(launch_status());
             }
-            if (both && role == 0) {  // perm holds the queries' order: their chunks are gathered
-                gather_pack<<<grid_cap((w.chunk_cap) * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim,
-                                                                                        w.kp, w.n2, w.perm, w.pk, st);
+            if (both && role == 0) {  // perm holds the queries' order: each wave packs its chunks, then its bands
+                pack_band_waves<<<grid_cap(w.chunk_cap * kWave, kBlock), kBlock, 0, s>>>(
+                    sets, w.plan, n_sets, dim, w.kp, w.n2, w.r2, w.perm, w.skey, w.pk, w.wave_c0, w.wave_len,
+                    w.wave_sub, st);
             } else {
                 scatter_pack<<<grid_cap(w.q_cap * 4, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, dim, w.kp, role,
                                                                                  w.n2, w.rank, w.pk, w.perm, w.skey,
@@ -3213,10 +3240,12 @@ kmg_status match_band(const MatchSet* sets_in, int n_sets, int dim, DevStatus* s
             }
             KMG_TRY(launch_status());
         }
-        band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2, w.perm,
-                                                                           w.skey, w.wave_c0, w.wave_len, w.wave_sub,
-                                                                           st);
-        KMG_TRY(launch_status());
+        if (!both) {  // (both directions in full: pack_band_waves found the bands)
+            band_waves<<<grid_cap(w.wave_cap * kWave, kBlock), kBlock, 0, s>>>(sets, w.plan, n_sets, w.n2, w.r2,
+                                                                               w.perm, w.skey, w.wave_c0, w.wave_len,
+                                                                               w.wave_sub, st);
+            KMG_TRY(launch_status());
+        }
         band_plan<<<1, kPlanThreads, 0, s>>>(w.plan, n_sets, w.wave_c0, w.wave_len, w.wave_sub, w.wave_tile, w.tinfo,
                                              w.tile_cap, tuning().band_tile, st);
         KMG_TRY(launch_status());
