@@ -176,6 +176,14 @@ const char* kmg_stage_name(int32_t stage);
  *                   1 matches both directions in full in one band pass (more
  *                   distance tiles, fewer launches).  The same
  *                   correspondences, d1 and d2 either way.
+ *   search_form     radius search (Eq. A1) of a batch (kmg_batch_run):
+ *                   0 (default) a count pass, the offsets, then the fill
+ *                   pass; 1 one search pass that writes |N(q)| and each list
+ *                   into a row of a pad in the workspace (32 entries per raw
+ *                   point, shared evenly by the kept points), the offsets,
+ *                   then the rows are copied to their places by the normal
+ *                   estimation (longer lists are searched again by the
+ *                   dense pass).  The same lists either way.
  * kmg_set_tuning(NULL) restores the defaults; unsupported values give
  * KMG_ERR_ARG and leave the tuning unchanged.
  */
@@ -188,6 +196,7 @@ typedef struct {
     int32_t fuse_features;
     int32_t xcd_split;
     int32_t match_form;
+    int32_t search_form;
 } kmg_tuning;
 kmg_status kmg_set_tuning(const kmg_tuning* t);
 kmg_status kmg_get_tuning(kmg_tuning* t);

@@ -12,6 +12,9 @@ namespace {
 // counts[i * 8 + k]: 0 correspondences, 1-2 kept points, 3-4 |J|, 5 exact
 // re-scans, 6 status, 7 neighbour entries of the batch.
 constexpr int kCountsStride = 8;
+// Pad entries per raw point for the list-first search (rows of about 120
+// entries when a quarter of the points are kept).
+constexpr int64_t kPadPerRaw = 32;
 
 struct BatchWs {
     DevStatus* st;
@@ -26,6 +29,9 @@ struct BatchWs {
     SearchWs srch;
     int32_t* off;
     int32_t* nbr;
+    int32_t* pad;     // list-first search: rows of the lists before they are placed
+    int64_t pad_cap;
+    int32_t* long_q;  // list-first search: the queries whose lists exceed a row
     float* nrm;
     uint8_t* flags;
     FeatWs feat;
@@ -50,6 +56,9 @@ BatchWs carve_batch(Carver& c, int n_pairs, int64_t raw_cap, int64_t nnz_cap, in
     w.srch = carve_search(c, raw_cap);
     w.off = c.take<int32_t>(rc + 1);
     w.nbr = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz_cap, 1)));
+    w.pad_cap = static_cast<int64_t>(rc) * kPadPerRaw;
+    w.pad = c.take<int32_t>(static_cast<size_t>(w.pad_cap));
+    w.long_q = c.take<int32_t>(rc);
     w.nrm = c.take<float>(3 * rc);
     w.flags = c.take<uint8_t>(rc);
     w.feat = carve_feat(c, raw_cap, H);
@@ -156,10 +165,15 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
     KMG_TRY(launch_status());
     KMG_TRY(voxelize_batch(w.cl, C, raw_cap, w.st, w.vox, raw_cap, raw_cap, w.kept_idx, w.kept_xyz, w.kept_cloud,
                            w.cs, s, true));
-    KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s, true, 0,
-                               true));
-    KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch, w.off,
-                              w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
+    if (tuning().search_form == 1) {
+        KMG_TRY(search_lists_first(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, w.st, w.srch, w.off,
+                                   w.nbr, w.pad, w.pad_cap, w.long_q, w.nrm, raw_cap, w.flags, s));
+    } else {
+        KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s, true,
+                                   0, true));
+        KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch,
+                                  w.off, w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
+    }
     // the J list emission also writes the clouds' J ranges and matching sets
     KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, w.nbr,
                            w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, w.cs, s, true, w.sets));

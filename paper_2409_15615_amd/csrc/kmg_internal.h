@@ -108,7 +108,7 @@ struct DevStatus {
     int32_t err_range;        // a key left the packable range
     int32_t dense;            // bit 0: some |N(q)| > kListSmall; bit 1: some |N(q)| > kMaxDegree
     int32_t err_capacity;     // a capacity bound was exceeded (CSR or partials)
-    int32_t pad0;
+    int32_t n_long;           // list-first search: lists longer than a pad row
     int64_t n_raw;            // raw points in the batch
     int64_t m_kept;           // kept points
     int64_t nnz;              // neighbour entries
@@ -303,6 +303,16 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
                              int64_t m_cap, int64_t nbr_cap, bool dense_pass, DevStatus* st, const SearchWs& w,
                              const int32_t* off, int32_t* nbr, float* nrm, int64_t nrm_stride, uint8_t* flags,
                              int32_t* n_normal, hipStream_t s, int use_rn = 0, bool with_normals = true);
+// The list-first form of the grid build, search and normals (r_FPFH lists,
+// tables cleared beforehand): one search pass writes |N(q)| and each list
+// that fits a row of the pad (pad_cap entries shared evenly by the kept
+// points), the offsets follow from the degrees, the dense pass serves the
+// longer lists (listed in long_q, m_cap entries), and the normals pass copies
+// the pad rows into nbr.
+kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
+                              int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
+                              int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
+                              int64_t nrm_stride, uint8_t* flags, hipStream_t s);
 
 // ---- features.hip ---------------------------------------------------------
 // Row stride of the SPFH counts, in entries: 3H rounded up to a multiple of 8,
@@ -450,6 +460,7 @@ struct Tuning {
     int fuse_features = 0;    // 1: SPFH and FPFH in one persistent launch (per-cloud readiness counters)
     int xcd_split = 2;        // bit 0 SPFH, bit 1 FPFH: XCD-aware split of the points over the wavefronts
     int match_form = 0;       // 0: one-sided matching then the image back; 1: both directions in one pass
+    int search_form = 0;      // batches: 0 count pass then fill pass; 1 list-first (one search pass, a pad)
 };
 const Tuning& tuning();
 bool set_tuning(const Tuning& t);

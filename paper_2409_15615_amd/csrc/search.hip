@@ -9,7 +9,10 @@
 // whose lanes walk the flattened candidate list of the 27 cells.  The search
 // runs twice: a count pass (|N(q)|), then, after a prefix sum has placed
 // every list, a fill pass that collects the accepted indices in LDS and
-// writes them in ascending order (rank sort).  Normals are then estimated by
+// writes them in ascending order (rank sort).  Batches may instead search once
+// (the list-first form): each list goes to a row of a pad with its length,
+// the offsets follow from the lengths, and the normal estimation copies the
+// rows to their places while it reads them.  Normals are then estimated by
 // 16 lanes per point from the stored list: FP64 moments of the r_normal subset,
 // a cyclic Jacobi eigen-solver in FP64, the linearity test and viewpoint
 // orientation.
@@ -38,6 +41,13 @@ __device__ __forceinline__ int64_t cell_coord(float x, double inv_c) {
 
 __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
     return kept_cloud ? kept_cloud[q] : 0;
+}
+
+// List-first form: the fill pass writes each list of at most this many entries
+// into row q of a pad of pad_cap entries (the rows share the pad evenly among
+// the m kept points); longer lists are left to the dense pass.
+__device__ __forceinline__ int pad_stride(int64_t pad_cap, int64_t m) {
+    return m > 0 ? static_cast<int>(min<int64_t>(kListSmall, pad_cap / m)) : 0;
 }
 
 // Kept points in input order often share a cell: only the first lane of a run
@@ -149,14 +159,19 @@ constexpr int kNbrRounds = 4;   // neighbour-list entries in flight per lane (no
 // kFill = false: writes |N(q)| to deg[q].
 // kFill = true : writes N(q) ascending at nbr[off[q]..]; lists longer than
 //                kCap are skipped (dense = 0) or are the only ones served
-//                (dense = 1).
+//                (dense = 1: the lists longer than the common fill pass
+//                keeps, kListSmall, or in the list-first form (pad_cap > 0)
+//                longer than a pad row: then only the cell-sorted positions
+//                in long_q[0 .. st->n_long) are visited).
 template <bool kFill, int kCap, int kWaves>
 __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* __restrict__ cl, Grid g,
                                                                const int32_t* __restrict__ kept_cloud,
                                                                int64_t m_cap, int32_t* __restrict__ deg,
                                                                const int32_t* __restrict__ off,
                                                                int32_t* __restrict__ nbr, int64_t nbr_cap,
-                                                               int dense, int use_rn, DevStatus* st) {
+                                                               int dense, int use_rn, DevStatus* st,
+                                                               int64_t pad_cap = 0,
+                                                               const int32_t* __restrict__ long_q = nullptr) {
     __shared__ int32_t s_incl[kWaves][32];
     __shared__ int32_t s_start[kWaves][32];
     __shared__ int32_t s_list[kWaves][kFill ? kCap : 1];
@@ -168,15 +183,19 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
     // no search over a partial grid; no fill beyond the caller's list capacity
     if (st->err_range) return;
     if (kFill && st->nnz > nbr_cap) return;
-    if (kFill && dense && !(st->dense & 1)) return;  // no list exceeds the common LDS size
-    for (int64_t w = static_cast<int64_t>(blockIdx.x) * kWaves + wv; w < m;
-         w += static_cast<int64_t>(gridDim.x) * kWaves) {
+    if (kFill && dense && !(st->dense & 1)) return;  // no list exceeds the common LDS size (or a pad row)
+    const int served_above = pad_cap > 0 ? pad_stride(pad_cap, m) : kListSmall;
+    const int64_t n_visit = long_q ? clamp_count(st->n_long, m) : m;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWaves + wv; i < n_visit;
+         i += static_cast<int64_t>(gridDim.x) * kWaves) {
+        const int64_t w = long_q ? long_q[i] : i;
+        if (w < 0 || w >= m) continue;
         const float4 qp = g.pts[w];
         const int q = __float_as_int(qp.w);
         if (q < 0 || q >= m) continue;
         if (kFill) {
             const int d = off[q + 1] - off[q];
-            if (dense ? (d <= kListSmall) : (d > kCap)) continue;
+            if (dense ? (d <= served_above) : (d > kCap)) continue;
         }
         const int c = cloud_of(kept_cloud, q);
         const double inv_c = cl[c].inv_cell;
@@ -368,12 +387,19 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_count2(const CloudDev* _
 // per wavefront, one per half of 32 lanes: lookups and candidate tests as the
 // count pass, the found indices gathered in candidate order in the half's LDS
 // list, then sorted by the half and written ascending at nbr[off[q]..].
-template <int kWaves>
+// kFirst (the list-first form, no count pass before it): every query is
+// searched, |N(q)| goes to deg[q] and the list, if it fits a row of the pad
+// (nbr = pad of nbr_cap entries, row stride pad_stride), to row q, else the
+// query's cell-sorted position to long_q (m entries); the normals pass later
+// copies the rows to their CSR places.
+template <int kWaves, bool kFirst>
 __global__ __launch_bounds__(kWaves* kWave) void radius_fill2(const CloudDev* __restrict__ cl, Grid g,
                                                               const int32_t* __restrict__ kept_cloud, int64_t m_cap,
                                                               const int32_t* __restrict__ off,
                                                               int32_t* __restrict__ nbr, int64_t nbr_cap,
-                                                              int use_rn, DevStatus* st) {
+                                                              int32_t* __restrict__ deg,
+                                                              int32_t* __restrict__ long_q, int use_rn,
+                                                              DevStatus* st) {
     constexpr int kHalf = kWave / 2;
     __shared__ int32_t s_incl[kWaves][2][kHalf];
     __shared__ int32_t s_start[kWaves][2][kHalf];
@@ -382,17 +408,20 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_fill2(const CloudDev* __
     const int lane = lane_id();
     const int hf = lane / kHalf, hl = lane % kHalf;
     const int64_t m = clamp_count(st->m_kept, m_cap);
-    // lists that would overrun the caller's capacity are reported once
-    if (blockIdx.x == 0 && threadIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
-    // no search over a partial grid; no fill beyond the caller's list capacity
-    if (st->err_range || st->nnz > nbr_cap) return;
+    if (!kFirst) {
+        // lists that would overrun the caller's capacity are reported once
+        if (blockIdx.x == 0 && threadIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
+        if (st->nnz > nbr_cap) return;  // no fill beyond the caller's list capacity
+    }
+    if (st->err_range) return;  // no search over a partial grid
+    const int row = kFirst ? pad_stride(nbr_cap, m) : 0;
     for (int64_t pw = static_cast<int64_t>(blockIdx.x) * kWaves + wv; 2 * pw < m;
          pw += static_cast<int64_t>(gridDim.x) * kWaves) {
         const int64_t w = 2 * pw + hf;
         const float4 qp = w < m ? g.pts[w] : make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
         const int q = __float_as_int(qp.w);
         // longer lists are the dense pass's
-        const bool act = q >= 0 && q < m && off[q + 1] - off[q] <= kListSmall;
+        const bool act = q >= 0 && q < m && (kFirst || off[q + 1] - off[q] <= kListSmall);
         const int c = act ? cloud_of(kept_cloud, q) : 0;
         const double inv_c = cl[c].inv_cell;
         const RadiusTest rt = use_rn ? cl[c].rn : cl[c].rf;
@@ -453,9 +482,17 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_fill2(const CloudDev* __
             }
         }
         __builtin_amdgcn_wave_barrier();
-        const int nf = act ? min(found, kListSmall) : 0;
+        if (kFirst && act && hl == 0) {
+            deg[q] = found;
+            // lists beyond a pad row are listed (by cell-sorted position) for the dense pass
+            if (found > row) {
+                atomicOr(&st->dense, found > kMaxDegree ? 3 : 1);
+                long_q[atomicAdd(&st->n_long, 1)] = static_cast<int32_t>(w);
+            }
+        }
+        const int nf = act && (!kFirst || found <= row) ? min(found, kListSmall) : 0;
         const int nmax = max(nf, __shfl_xor(nf, kHalf, kWave));
-        int32_t* out = nbr + (act ? off[q] : 0);
+        int32_t* out = nbr + (act ? (kFirst ? static_cast<int64_t>(q) * row : off[q]) : 0);
         const int32_t* lst = s_list[wv][hf];
         if (nmax <= kHalf) {
             group_sort_write<1, kHalf>(lst, nf, out, hl);
@@ -510,12 +547,17 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
                                                          const float* __restrict__ xyz, int64_t stride,
                                                          const int32_t* __restrict__ kept_cloud, int64_t m_cap,
                                                          const int32_t* __restrict__ off,
-                                                         const int32_t* __restrict__ nbr, int64_t nbr_cap,
+                                                         int32_t* __restrict__ nbr, int64_t nbr_cap,
                                                          float* __restrict__ nrm, int64_t nrm_stride,
                                                          uint8_t* __restrict__ flags, int32_t* __restrict__ n_normal,
-                                                         DevStatus* st) {
+                                                         DevStatus* st, const int32_t* __restrict__ pad = nullptr,
+                                                         int64_t pad_cap = 0) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
+    // list-first form: this pass places the lists (those that fit a pad row)
+    // and reports a list volume beyond the caller's capacity
+    if (pad && blockIdx.x == 0 && threadIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
     if (st->err_range || st->nnz > nbr_cap) return;
+    const int row = pad ? pad_stride(pad_cap, m) : 0;
     // kNormalLanes lanes per point: each sums every kNormalLanes-th list entry, then
     // the group adds up its partial moments (every lane ends with the totals)
     const int sub = lane_id() % kNormalLanes;
@@ -525,6 +567,9 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
         const RadiusTest rn = cl[c].rn;
         const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[2 * stride + q];
         const int b = off[q], e = off[q + 1];
+        // the list: its pad row (copied to nbr on the way) or, if longer, nbr
+        const bool from_pad = pad && e - b <= row;
+        const int32_t* src = from_pad ? pad + static_cast<int64_t>(q) * row : nbr + b;
         int nn = 0;
         // moments of the r_normal subset, shifted to the query (FP64)
         double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
@@ -534,7 +579,8 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
 #pragma unroll
             for (int u = 0; u < kNbrRounds; ++u) {
                 const int k = k0 + u * kNormalLanes;
-                id[u] = k < e ? nbr[k] : -1;
+                id[u] = k < e ? src[k - b] : -1;
+                if (from_pad && k < e) nbr[k] = id[u];
             }
             float px[kNbrRounds], py[kNbrRounds], pz[kNbrRounds];
 #pragma unroll
@@ -657,21 +703,36 @@ kmg_status launch_count(int waves, int groups, const CloudDev* cl, Grid g, const
     }
 }
 
-template <int kWaves>
-kmg_status fill_as(const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap, const int32_t* off,
-                   int32_t* nbr, int64_t nbr_cap, int use_rn, DevStatus* st, hipStream_t s) {
-    radius_fill2<kWaves><<<grid_cap((m_cap + 1) / 2, kWaves), kWaves * kWave, 0, s>>>(cl, g, kept_cloud, m_cap, off,
-                                                                                     nbr, nbr_cap, use_rn, st);
+struct FillOut {
+    const int32_t* off;  // nullptr: the list-first pass
+    int32_t* nbr;        // the lists, or the pad of the list-first pass
+    int64_t nbr_cap;
+    int32_t* deg;        // list-first: |N(q)|
+    int32_t* long_q;     // list-first: positions of the lists beyond a pad row
+};
+
+template <int kWaves, bool kFirst>
+kmg_status fill_as(const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap, const FillOut& o,
+                   int use_rn, DevStatus* st, hipStream_t s) {
+    radius_fill2<kWaves, kFirst><<<grid_cap((m_cap + 1) / 2, kWaves), kWaves * kWave, 0, s>>>(
+        cl, g, kept_cloud, m_cap, o.off, o.nbr, o.nbr_cap, o.deg, o.long_q, use_rn, st);
     return launch_status();
 }
 
-kmg_status launch_fill(int waves, const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap,
-                       const int32_t* off, int32_t* nbr, int64_t nbr_cap, int use_rn, DevStatus* st, hipStream_t s) {
+template <bool kFirst>
+kmg_status fill_form(int waves, const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap,
+                     const FillOut& o, int use_rn, DevStatus* st, hipStream_t s) {
     switch (waves) {
-        case 2: return fill_as<2>(cl, g, kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st, s);
-        case 8: return fill_as<8>(cl, g, kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st, s);
-        default: return fill_as<4>(cl, g, kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st, s);
+        case 2: return fill_as<2, kFirst>(cl, g, kept_cloud, m_cap, o, use_rn, st, s);
+        case 8: return fill_as<8, kFirst>(cl, g, kept_cloud, m_cap, o, use_rn, st, s);
+        default: return fill_as<4, kFirst>(cl, g, kept_cloud, m_cap, o, use_rn, st, s);
     }
+}
+
+kmg_status launch_fill(int waves, const CloudDev* cl, Grid g, const int32_t* kept_cloud, int64_t m_cap,
+                       const FillOut& o, int use_rn, DevStatus* st, hipStream_t s) {
+    return o.off ? fill_form<false>(waves, cl, g, kept_cloud, m_cap, o, use_rn, st, s)
+                 : fill_form<true>(waves, cl, g, kept_cloud, m_cap, o, use_rn, st, s);
 }
 
 Grid grid_of(const SearchWs& w) {
@@ -700,28 +761,36 @@ SearchWs carve_search(Carver& c, int64_t m_cap) {
     return w;
 }
 
+namespace {
+
+kmg_status build_grid(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud, int64_t m_cap,
+                      DevStatus* st, const SearchWs& w, hipStream_t s, bool cleared) {
+    StageScope sc(ST_GRID, s);
+    if (!cleared) {
+        KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ccount), 0u, w.cap_table, s));
+        KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.cfill), 0u, w.cap_table, s));
+    }
+    if (m_cap > 0) {
+        cell_insert<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, w.keys,
+                                                              w.ccount, w.cap_table - 1, w.pslot, st);
+        KMG_TRY(launch_status());
+    }
+    KMG_TRY(scan_exclusive(w.ccount, w.cstart, w.cap_table, &st->n_cells, w.scan_tmp, s));
+    if (m_cap > 0) {
+        cell_scatter<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(xyz, stride, m_cap, w.pslot, w.cstart, w.cfill,
+                                                               w.pts, st);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
+}  // namespace
+
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
-                              bool build_grid, int use_rn, bool cleared) {
-    if (build_grid) {
-        StageScope sc(ST_GRID, s);
-        if (!cleared) {
-            KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
-            KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ccount), 0u, w.cap_table, s));
-            KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.cfill), 0u, w.cap_table, s));
-        }
-        if (m_cap > 0) {
-            cell_insert<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, w.keys,
-                                                                  w.ccount, w.cap_table - 1, w.pslot, st);
-            KMG_TRY(launch_status());
-        }
-        KMG_TRY(scan_exclusive(w.ccount, w.cstart, w.cap_table, &st->n_cells, w.scan_tmp, s));
-        if (m_cap > 0) {
-            cell_scatter<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(xyz, stride, m_cap, w.pslot, w.cstart, w.cfill,
-                                                                   w.pts, st);
-            KMG_TRY(launch_status());
-        }
-    }
+                              bool grid, int use_rn, bool cleared) {
+    if (grid) KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, cleared));
     {
         StageScope sc(ST_SEARCH_COUNT, s);
         if (!cleared) KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
@@ -735,6 +804,36 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
     return KMG_OK;
 }
 
+kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
+                              int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
+                              int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
+                              int64_t nrm_stride, uint8_t* flags, hipStream_t s) {
+    KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, true));
+    if (m_cap > 0) {
+        StageScope sc(ST_SEARCH_FILL, s);
+        KMG_TRY(launch_fill(tuning().search_waves, cl, grid_of(w), kept_cloud, m_cap,
+                            FillOut{nullptr, pad, pad_cap, w.deg, long_q}, 0, st, s));
+    }
+    {
+        StageScope sc(ST_SEARCH_COUNT, s);
+        KMG_TRY(scan_exclusive(w.deg, off, m_cap + 1, &st->nnz, w.scan_tmp, s));
+    }
+    if (m_cap <= 0) return KMG_OK;
+    {
+        StageScope sc(ST_SEARCH_FILL, s);
+        radius_search<true, kMaxDegree, 1><<<grid_cap(m_cap, 1), kWave, 0, s>>>(
+            cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 1, 0, st, pad_cap, long_q);
+        KMG_TRY(launch_status());
+    }
+    {
+        StageScope sc(ST_NORMALS, s);
+        normals_kernel<<<grid_cap(m_cap * kNormalLanes, kBlock), kBlock, 0, s>>>(
+            cl, xyz, stride, kept_cloud, m_cap, off, nbr, nbr_cap, nrm, nrm_stride, flags, nullptr, st, pad, pad_cap);
+        KMG_TRY(launch_status());
+    }
+    return KMG_OK;
+}
+
 kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                              int64_t m_cap, int64_t nbr_cap, bool dense_pass, DevStatus* st, const SearchWs& w,
                              const int32_t* off, int32_t* nbr, float* nrm, int64_t nrm_stride, uint8_t* flags,
@@ -742,8 +841,8 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
     if (m_cap <= 0) return KMG_OK;
     {
         StageScope sc(ST_SEARCH_FILL, s);
-        KMG_TRY(launch_fill(tuning().search_waves, cl, grid_of(w), kept_cloud, m_cap, off, nbr, nbr_cap, use_rn, st,
-                            s));
+        KMG_TRY(launch_fill(tuning().search_waves, cl, grid_of(w), kept_cloud, m_cap,
+                            FillOut{off, nbr, nbr_cap, nullptr, nullptr}, use_rn, st, s));
         if (dense_pass) {
             radius_search<true, kMaxDegree, 1><<<grid_cap(m_cap, 1), kWave, 0, s>>>(
                 cl, grid_of(w), kept_cloud, m_cap, nullptr, off, nbr, nbr_cap, 1, use_rn, st);

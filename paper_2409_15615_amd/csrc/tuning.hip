@@ -21,6 +21,7 @@ bool set_tuning(const Tuning& t) {
     if (t.fuse_features != 0 && t.fuse_features != 1) return false;
     if (t.xcd_split < 0 || t.xcd_split > 3) return false;
     if (t.match_form != 0 && t.match_form != 1) return false;
+    if (t.search_form != 0 && t.search_form != 1) return false;
     g_tuning = t;
     return true;
 }
@@ -40,6 +41,7 @@ __attribute__((visibility("default"))) kmg_status kmg_set_tuning(const kmg_tunin
         v.fuse_features = t->fuse_features;
         v.xcd_split = t->xcd_split;
         v.match_form = t->match_form;
+        v.search_form = t->search_form;
     }
     return kmg::set_tuning(v) ? KMG_OK : KMG_ERR_ARG;
 }
@@ -55,6 +57,7 @@ __attribute__((visibility("default"))) kmg_status kmg_get_tuning(kmg_tuning* t) 
     t->fuse_features = v.fuse_features;
     t->xcd_split = v.xcd_split;
     t->match_form = v.match_form;
+    t->search_form = v.search_form;
     return KMG_OK;
 }
 

@@ -56,11 +56,12 @@ class KmgTuning(C.Structure):
         ("fuse_features", C.c_int32),
         ("xcd_split", C.c_int32),
         ("match_form", C.c_int32),
+        ("search_form", C.c_int32),
     ]
 
 
 TUNING_FIELDS = ("search_waves", "count_queries", "spfh_pair_mean", "fpfh_rows", "band_tile", "fuse_features",
-                 "xcd_split", "match_form")
+                 "xcd_split", "match_form", "search_form")
 
 
 class KmgCloud(C.Structure):

@@ -33,6 +33,7 @@ SPACE = {
     "fuse_features": (0, 1),
     "xcd_split": (0, 1, 2, 3),
     "match_form": (0, 1),
+    "search_form": (0, 1),
 }
 
 

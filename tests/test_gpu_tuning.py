@@ -38,7 +38,7 @@ def settings():
     for f, vals in SPACE.items():
         out += [{f: v} for v in vals]
     out.append({"search_waves": 8, "count_queries": 4, "spfh_pair_mean": 0, "fpfh_rows": 16, "band_tile": 12,
-                "fuse_features": 1, "xcd_split": 0, "match_form": 1})
+                "fuse_features": 1, "xcd_split": 0, "match_form": 1, "search_form": 1})
     out.append({"search_waves": 2, "count_queries": 1, "spfh_pair_mean": 8192, "fpfh_rows": 4, "band_tile": 64,
                 "fuse_features": 0, "xcd_split": 2})
     return out
@@ -146,3 +146,71 @@ def test_match_forms_on_lidar_batch(K):
     for k in (0, 2, 3, 4):
         assert torch.equal(out[0][k], out[1][k]), k
     print("exact re-scans per pair: one-sided", out[0][1].tolist(), "both directions", out[1][1].tolist())
+
+
+def test_search_forms_same_lists_and_descriptors(K):
+    """The list-first radius search (search_form 1: one search pass into pad
+    rows, the normals pass placing them) and the count-then-fill form give
+    bit-identical results: every cloud's FPFH rows and J list, the counts
+    (neighbour entries included) and the correspondences.  A batch of two
+    small-cloud pairs leaves pad rows of 42 entries, so that most of their
+    lists (about 45 entries on average) are served by the dense pass instead;
+    the mixed batch has rows of about 96 entries; an empty cloud keeps row 0;
+    a neighbour capacity one entry short fails alike in both forms."""
+    empty = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
+    c0 = synth.c0_pair(0)
+    mixed = [synth.c0_pair(1), synth.indoor_pair(2, 101, 3000), synth.lidar_pair(2, 103, 0.6, n_az=900)]
+
+    def clouds_of(pairs, empty_src=False):
+        out = []
+        for i, d in enumerate(pairs):
+            p = d["params"]
+            src = empty if (empty_src and i == 0) else dev(d["src"])
+            out += [(src, K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins,
+                                        d["vp_src"])),
+                    (dev(d["tgt"]), K.make_params(p.voxel, p.r_normal, p.r_fpfh, p.tau_num, p.tau_lin, p.n_bins,
+                                                  d["vp_tgt"]))]
+        return out
+
+    for name, clouds in (("small", clouds_of([c0, c0])), ("mixed", clouds_of(mixed)),
+                         ("empty source", clouds_of([c0] + mixed[1:], empty_src=True))):
+        K.set_tuning(None)
+        _, probe = K.register_batch(clouds)
+        for short in (False, True):
+            cap = probe.nnz() - 1 if short else probe.nnz() + 4096
+            b = K.Batch(len(clouds) // 2, probe.raw_cap, cap, 11)
+            b.upload(clouds)
+            out = {}
+            for form in (0, 1):
+                K.set_tuning({"search_form": form})
+                b.counts.zero_()
+                b.pairs.fill_(-1)
+                b.d1.fill_(-1.0)
+                b.d2.fill_(-1.0)
+                b.run()
+                torch.cuda.synchronize()
+                cnt = b.counts.cpu().clone()
+                desc = []
+                if not short:
+                    for i in range(len(clouds) // 2):
+                        for side in (0, 1):
+                            n_kept, n_j = int(cnt[i, 1 + side]), int(cnt[i, 3 + side])
+                            fp, jj = b.descriptors(2 * i + side, n_kept, n_j)
+                            desc += [fp.cpu().clone(), jj.cpu().clone()]
+                out[form] = (cnt, b.pairs.cpu().clone(), b.d1.cpu().clone(), b.d2.cpu().clone(), desc)
+            K.set_tuning(None)
+            status = out[0][0][:, 6]
+            if short:
+                assert int(status.abs().sum()) > 0, name
+            else:
+                assert int(status[1:].abs().sum()) == 0, name
+                assert int(out[0][0][0, 7]) > 0, name
+            if short:  # the status and the list volume; nothing past the search is defined
+                assert torch.equal(out[0][0][:, 6:8], out[1][0][:, 6:8]), name
+            else:
+                assert torch.equal(out[0][0], out[1][0]), name
+                for k in (1, 2, 3):
+                    assert torch.equal(out[0][k], out[1][k]), (name, k)
+                assert len(out[0][4]) == len(out[1][4])
+                for x, y in zip(out[0][4], out[1][4]):
+                    assert torch.equal(x, y), name
