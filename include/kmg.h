@@ -179,7 +179,7 @@ const char* kmg_stage_name(int32_t stage);
  *   search_form     radius search (Eq. A1) of a batch (kmg_batch_run):
  *                   0 (default) a count pass, the offsets, then the fill
  *                   pass; 1 one search pass that writes |N(q)| and each list
- *                   into a row of a pad in the workspace (32 entries per raw
+ *                   into a row of a pad in the workspace (64 entries per raw
  *                   point, shared evenly by the kept points), the offsets,
  *                   then the rows are copied to their places by the normal
  *                   estimation (longer lists are searched again by the

@@ -12,9 +12,9 @@ namespace {
 // counts[i * 8 + k]: 0 correspondences, 1-2 kept points, 3-4 |J|, 5 exact
 // re-scans, 6 status, 7 neighbour entries of the batch.
 constexpr int kCountsStride = 8;
-// Pad entries per raw point for the list-first search (rows of about 120
+// Pad entries per raw point for the list-first search (rows of about 240
 // entries when a quarter of the points are kept).
-constexpr int64_t kPadPerRaw = 32;
+constexpr int64_t kPadPerRaw = 64;
 
 struct BatchWs {
     DevStatus* st;

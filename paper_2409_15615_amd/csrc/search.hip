@@ -45,9 +45,11 @@ __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
 
 // List-first form: the fill pass writes each list of at most this many entries
 // into row q of a pad of pad_cap entries (the rows share the pad evenly among
-// the m kept points); longer lists are left to the dense pass.
+// the m kept points, in whole 128-byte lines once a row holds one); longer
+// lists are left to the dense pass.
 __device__ __forceinline__ int pad_stride(int64_t pad_cap, int64_t m) {
-    return m > 0 ? static_cast<int>(min<int64_t>(kListSmall, pad_cap / m)) : 0;
+    const int r = m > 0 ? static_cast<int>(min<int64_t>(kListSmall, pad_cap / m)) : 0;
+    return r >= 32 ? (r & ~31) : r;
 }
 
 // Kept points in input order often share a cell: only the first lane of a run

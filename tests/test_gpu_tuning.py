@@ -152,14 +152,23 @@ def test_search_forms_same_lists_and_descriptors(K):
     """The list-first radius search (search_form 1: one search pass into pad
     rows, the normals pass placing them) and the count-then-fill form give
     bit-identical results: every cloud's FPFH rows and J list, the counts
-    (neighbour entries included) and the correspondences.  A batch of two
-    small-cloud pairs leaves pad rows of 42 entries, so that most of their
-    lists (about 45 entries on average) are served by the dense pass instead;
-    the mixed batch has rows of about 96 entries; an empty cloud keeps row 0;
-    a neighbour capacity one entry short fails alike in both forms."""
+    (neighbour entries included) and the correspondences.  In the grid batch
+    every point is kept, so the pad rows hold 64 entries while the inner
+    lists hold about 200: those are all served by the dense pass.  The small
+    batch (rows of 64 against lists of 30-67) sends a few lists there; an
+    empty cloud keeps row 0; a neighbour capacity one entry short fails alike
+    in both forms."""
     empty = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
     c0 = synth.c0_pair(0)
     mixed = [synth.c0_pair(1), synth.indoor_pair(2, 101, 3000), synth.lidar_pair(2, 103, 0.6, n_az=900)]
+    rng = np.random.default_rng(20260)
+    gx, gy = np.meshgrid(np.arange(40) * 0.1, np.arange(40) * 0.1)
+    plane = np.stack([gx.ravel(), gy.ravel(), 0.02 * np.sin(3.0 * gx.ravel())])
+    grid_src = (plane + rng.uniform(-0.01, 0.01, plane.shape)).astype(np.float32)
+    grid_tgt = (plane[[1, 0, 2]] + rng.uniform(-0.01, 0.01, plane.shape)).astype(np.float32)
+    vp = np.array([0.0, 0.0, 5.0])
+    grid = [(dev(grid_src), K.make_params(0.05, 0.3, 0.8, 3, 0.99, 11, vp)),
+            (dev(grid_tgt), K.make_params(0.05, 0.3, 0.8, 3, 0.99, 11, vp))]
 
     def clouds_of(pairs, empty_src=False):
         out = []
@@ -172,7 +181,7 @@ def test_search_forms_same_lists_and_descriptors(K):
                                                   d["vp_tgt"]))]
         return out
 
-    for name, clouds in (("small", clouds_of([c0, c0])), ("mixed", clouds_of(mixed)),
+    for name, clouds in (("grid", grid), ("small", clouds_of([c0, c0])), ("mixed", clouds_of(mixed)),
                          ("empty source", clouds_of([c0] + mixed[1:], empty_src=True))):
         K.set_tuning(None)
         _, probe = K.register_batch(clouds)
