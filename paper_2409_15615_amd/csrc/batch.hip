@@ -163,14 +163,16 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
     batch_init<<<static_cast<unsigned>(std::min<int64_t>((most + 255) / 256, 4096)), 256, 0, s>>>(w.st, w.cl, C,
                                                                                                   fills);
     KMG_TRY(launch_status());
+    // the kept points go into the cleared cell hash of the search as they are emitted
+    const GridInsert gi{w.srch.keys, w.srch.ccount, w.srch.cap_table - 1, w.srch.pslot, w.st};
     KMG_TRY(voxelize_batch(w.cl, C, raw_cap, w.st, w.vox, raw_cap, raw_cap, w.kept_idx, w.kept_xyz, w.kept_cloud,
-                           w.cs, s, true));
+                           w.cs, s, true, &gi));
     if (tuning().search_form == 1) {
         KMG_TRY(search_lists_first(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, w.st, w.srch, w.off,
-                                   w.nbr, w.pad, w.pad_cap, w.long_q, w.nrm, raw_cap, w.flags, s));
+                                   w.nbr, w.pad, w.pad_cap, w.long_q, w.nrm, raw_cap, w.flags, s, true));
     } else {
         KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s, true,
-                                   0, true));
+                                   0, true, true));
         KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch,
                                   w.off, w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
     }

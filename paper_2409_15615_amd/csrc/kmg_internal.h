@@ -271,9 +271,19 @@ VoxelWs carve_voxel(Carver& c, int64_t n_cap);
 // kept_idx and their cloud to kept_cloud (nullable); per-cloud ranges to cs
 // (nullable).  Nothing is written when the kept count exceeds out_cap.
 // cleared: the caller has already emptied the voxel table (keys, mins).
+// The cell hash of the radius search, filled by voxelize_batch as it emits the
+// kept points (the tables cleared beforehand); keys == nullptr: not filled.
+struct GridInsert {
+    uint64_t* keys = nullptr;
+    int32_t* cnt = nullptr;
+    uint32_t mask = 0;
+    int32_t* pslot = nullptr;
+    DevStatus* st = nullptr;
+};
 kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
                           int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
-                          int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared = false);
+                          int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared = false,
+                          const GridInsert* grid = nullptr);
 
 // ---- search.hip -----------------------------------------------------------
 struct SearchWs {
@@ -296,7 +306,7 @@ SearchWs carve_search(Carver& c, int64_t m_cap);
 // has already emptied the cell table (keys, ccount, cfill) and zeroed deg.
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
-                              bool build_grid = true, int use_rn = 0, bool cleared = false);
+                              bool build_grid = true, int use_rn = 0, bool cleared = false, bool inserted = false);
 // Fill pass (lists ascending) and normals.  Writes nothing into nbr when
 // st->nnz > nbr_cap (device-side check; st->err_capacity is set).
 kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
@@ -308,11 +318,11 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
 // that fits a row of the pad (pad_cap entries shared evenly by the kept
 // points), the offsets follow from the degrees, the dense pass serves the
 // longer lists (listed in long_q, m_cap entries), and the normals pass copies
-// the pad rows into nbr.
+// the pad rows into nbr.  inserted: the cell hash is filled already (voxelize_batch).
 kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
                               int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
-                              int64_t nrm_stride, uint8_t* flags, hipStream_t s);
+                              int64_t nrm_stride, uint8_t* flags, hipStream_t s, bool inserted = false);
 
 // ---- features.hip ---------------------------------------------------------
 // Row stride of the SPFH counts, in entries: 3H rounded up to a multiple of 8,

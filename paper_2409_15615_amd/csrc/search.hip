@@ -765,15 +765,17 @@ SearchWs carve_search(Carver& c, int64_t m_cap) {
 
 namespace {
 
+// inserted: the kept points are in the cell hash already (voxelize_batch put
+// them there as it emitted them); the counts are then scanned and scattered.
 kmg_status build_grid(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud, int64_t m_cap,
-                      DevStatus* st, const SearchWs& w, hipStream_t s, bool cleared) {
+                      DevStatus* st, const SearchWs& w, hipStream_t s, bool cleared, bool inserted) {
     StageScope sc(ST_GRID, s);
     if (!cleared) {
         KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
         KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.ccount), 0u, w.cap_table, s));
         KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.cfill), 0u, w.cap_table, s));
     }
-    if (m_cap > 0) {
+    if (m_cap > 0 && !inserted) {
         cell_insert<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, w.keys,
                                                               w.ccount, w.cap_table - 1, w.pslot, st);
         KMG_TRY(launch_status());
@@ -791,8 +793,8 @@ kmg_status build_grid(const CloudDev* cl, const float* xyz, int64_t stride, cons
 
 kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, DevStatus* st, const SearchWs& w, int32_t* off, hipStream_t s,
-                              bool grid, int use_rn, bool cleared) {
-    if (grid) KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, cleared));
+                              bool grid, int use_rn, bool cleared, bool inserted) {
+    if (grid) KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, cleared, inserted));
     {
         StageScope sc(ST_SEARCH_COUNT, s);
         if (!cleared) KMG_TRY(fill_u32(reinterpret_cast<uint32_t*>(w.deg), 0u, static_cast<size_t>(m_cap) + 1, s));
@@ -809,8 +811,8 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
 kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
                               int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
-                              int64_t nrm_stride, uint8_t* flags, hipStream_t s) {
-    KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, true));
+                              int64_t nrm_stride, uint8_t* flags, hipStream_t s, bool inserted) {
+    KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, true, inserted));
     if (m_cap > 0) {
         StageScope sc(ST_SEARCH_FILL, s);
         KMG_TRY(launch_fill(tuning().search_waves, cl, grid_of(w), kept_cloud, m_cap,

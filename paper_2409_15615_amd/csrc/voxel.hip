@@ -84,34 +84,82 @@ __global__ __launch_bounds__(kBlock) void voxel_mark(const int32_t* __restrict__
     }
 }
 
-// Kept point j = pos[t]; row stride `stride` (0: the kept count).
+// Kept point j = pos[t]; row stride `stride` (0: the kept count).  With
+// gi.keys, the kept points also go into the cell hash of the radius search
+// (what cell_insert does for the kept points in kept order).
 __global__ __launch_bounds__(kBlock) void voxel_emit(const CloudDev* __restrict__ cl, int n_clouds, int64_t n_cap,
                                                      const int32_t* __restrict__ flag,
                                                      const int32_t* __restrict__ pos, const DevStatus* st,
                                                      int64_t out_cap, int64_t out_stride,
                                                      int32_t* __restrict__ kept_idx, float* __restrict__ kept_xyz,
-                                                     int32_t* __restrict__ kept_cloud) {
+                                                     int32_t* __restrict__ kept_cloud, CloudState* cs,
+                                                     GridInsert gi) {
     const int64_t n = clamp_count(st->n_raw, n_cap);
     const int64_t m = st->m_kept;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    // per-cloud kept ranges (cs given): the exclusive scan at the cloud's first raw index
+    if (cs) {
+        for (int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; c < n_clouds; c += stride) {
+            const int64_t a = cl[c].raw_off;
+            const int64_t b = a + cl[c].n_raw;
+            const int64_t ka = a < n ? pos[a] : m;
+            const int64_t kb = b < n ? pos[b] : m;
+            cs[c].kept_off = static_cast<int32_t>(ka);
+            cs[c].kept_cnt = static_cast<int32_t>(kb - ka);
+        }
+    }
     if (m > out_cap) return;
     const int64_t ks = out_stride ? out_stride : m;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < n; t += stride) {
-        if (!flag[t]) continue;
-        const int c = cloud_of_raw(cl, n_clouds, t);
-        const int64_t i = t - cl[c].raw_off;
-        const int64_t nc = cl[c].n_raw;
-        const float* raw = cl[c].raw;
-        const int64_t j = pos[t];
-        kept_idx[j] = static_cast<int32_t>(i);
-        kept_xyz[j] = raw[i];
-        kept_xyz[ks + j] = raw[nc + i];
-        kept_xyz[2 * ks + j] = raw[2 * nc + i];
-        if (kept_cloud) kept_cloud[j] = c;
+    const int lane = lane_id();
+    // every lane of a wave runs the same rounds (the run detection of the cell insert shuffles)
+    for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~(kWave - 1)); t0 < n;
+         t0 += stride) {
+        const int64_t t = t0 + lane;
+        const bool kept = t < n && flag[t];
+        int64_t j = 0;
+        uint64_t key = kEmptyKey;
+        if (kept) {
+            const int c = cloud_of_raw(cl, n_clouds, t);
+            const int64_t i = t - cl[c].raw_off;
+            const int64_t nc = cl[c].n_raw;
+            const float* raw = cl[c].raw;
+            j = pos[t];
+            const float x = raw[i], y = raw[nc + i], z = raw[2 * nc + i];
+            kept_idx[j] = static_cast<int32_t>(i);
+            kept_xyz[j] = x;
+            kept_xyz[ks + j] = y;
+            kept_xyz[2 * ks + j] = z;
+            if (kept_cloud) kept_cloud[j] = c;
+            if (gi.keys) {
+                const double inv_c = cl[c].inv_cell;
+                const double kx = floor(static_cast<double>(x) * inv_c);
+                const double ky = floor(static_cast<double>(y) * inv_c);
+                const double kz = floor(static_cast<double>(z) * inv_c);
+                // one cell of headroom, so that the 27-cell stencil stays packable
+                if (!key_in_range(kx - 1) || !key_in_range(kx + 1) || !key_in_range(ky - 1) ||
+                    !key_in_range(ky + 1) || !key_in_range(kz - 1) || !key_in_range(kz + 1))
+                    atomicOr(&gi.st->err_range, 1);
+                else
+                    key = pack_key(c, static_cast<int64_t>(kx), static_cast<int64_t>(ky),
+                                   static_cast<int64_t>(kz));
+            }
+        }
+        if (gi.keys) {
+            // a run of kept points of one cell on consecutive lanes inserts once
+            const LaneRun run = lane_run(key);
+            int h = -1;
+            if (run.head && key != kEmptyKey) {
+                h = static_cast<int>(hash_insert(gi.keys, gi.mask, key));
+                atomicAdd(gi.cnt + h, run.len);
+            }
+            h = __shfl(h, run.lead, kWave);
+            if (kept) gi.pslot[j] = key == kEmptyKey ? -1 : h;
+        }
     }
 }
 
-// Per-cloud kept ranges: the exclusive scan at the cloud's first raw index.
+// Per-cloud kept ranges: the exclusive scan at the cloud's first raw index
+// (voxel_emit writes them itself when it runs).
 __global__ void cloud_ranges(const CloudDev* __restrict__ cl, int n_clouds, int64_t n_cap,
                              const int32_t* __restrict__ pos, const DevStatus* st, CloudState* cs) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,7 +190,8 @@ VoxelWs carve_voxel(Carver& c, int64_t n_cap) {
 
 kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
                           int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
-                          int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared) {
+                          int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared,
+                          const GridInsert* grid) {
     StageScope sc(ST_VOXELIZE, s);
     if (!cleared) {
         KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
@@ -159,10 +208,10 @@ kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevSt
     KMG_TRY(scan_exclusive_summed(w.flag, w.pos, n_cap, &st->m_kept, w.scan_tmp, s));
     if (n_cap > 0) {
         voxel_emit<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.flag, w.pos, st, out_cap,
-                                                             out_stride, kept_idx, kept_xyz, kept_cloud);
+                                                             out_stride, kept_idx, kept_xyz, kept_cloud, cs,
+                                                             grid ? *grid : GridInsert{});
         KMG_TRY(launch_status());
-    }
-    if (cs) {
+    } else if (cs) {
         cloud_ranges<<<grid_for(n_clouds, 256), 256, 0, s>>>(cl, n_clouds, n_cap, w.pos, st, cs);
         KMG_TRY(launch_status());
     }
