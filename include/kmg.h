@@ -180,10 +180,10 @@ const char* kmg_stage_name(int32_t stage);
  *                   0 (default) a count pass, the offsets, then the fill
  *                   pass; 1 one search pass that writes |N(q)| and each list
  *                   into a row of a pad in the workspace (64 entries per raw
- *                   point, shared evenly by the kept points), the offsets,
- *                   then the rows are copied to their places by the normal
- *                   estimation (longer lists are searched again by the
- *                   dense pass).  The same lists either way.
+ *                   point, shared evenly by the kept points) and the
+ *                   offsets, the longer lists searched again into their
+ *                   CSR places; the normal and feature passes read each
+ *                   list where it is.  The same lists either way.
  * kmg_set_tuning(NULL) restores the defaults; unsupported values give
  * KMG_ERR_ARG and leave the tuning unchanged.
  */

@@ -29,7 +29,7 @@ struct BatchWs {
     SearchWs srch;
     int32_t* off;
     int32_t* nbr;
-    int32_t* pad;     // list-first search: rows of the lists before they are placed
+    int32_t* pad;     // list-first search: the lists, a row per kept point
     int64_t pad_cap;
     int32_t* long_q;  // list-first search: the queries whose lists exceed a row
     float* nrm;
@@ -167,7 +167,8 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
     const GridInsert gi{w.srch.keys, w.srch.ccount, w.srch.cap_table - 1, w.srch.pslot, w.st};
     KMG_TRY(voxelize_batch(w.cl, C, raw_cap, w.st, w.vox, raw_cap, raw_cap, w.kept_idx, w.kept_xyz, w.kept_cloud,
                            w.cs, s, true, &gi));
-    if (tuning().search_form == 1) {
+    const bool list_first = tuning().search_form == 1;
+    if (list_first) {
         KMG_TRY(search_lists_first(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, w.st, w.srch, w.off,
                                    w.nbr, w.pad, w.pad_cap, w.long_q, w.nrm, raw_cap, w.flags, s, true));
     } else {
@@ -176,8 +177,10 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
         KMG_TRY(search_fill_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, true, w.st, w.srch,
                                   w.off, w.nbr, w.nrm, raw_cap, w.flags, nullptr, s));
     }
+    // the list-first search leaves the lists in the pad rows (the longer ones in nbr);
     // the J list emission also writes the clouds' J ranges and matching sets
-    KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, w.nbr,
+    const NbrLists nb = list_first ? NbrLists{w.nbr, w.pad, w.pad_cap} : NbrLists{w.nbr};
+    KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, nb,
                            w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, w.cs, s, true, w.sets));
     // the pair counts and statuses come with the correspondences
     KMG_TRY(match_batch(w.sets, C, D, prec, w.st, w.match, w.outs, counts, kCountsStride, s, w.cs, nnz_cap));

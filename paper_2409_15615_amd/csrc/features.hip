@@ -188,7 +188,7 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
                                            int64_t stride, const int32_t* __restrict__ kept_cloud, int64_t m,
                                            const float* __restrict__ nrm, int64_t nrm_stride,
                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
-                                           const int32_t* __restrict__ nbr, int H, uint16_t* __restrict__ cnt16,
+                                           NbrLists nb, int H, uint16_t* __restrict__ cnt16,
                                            float* __restrict__ spfh_out, int32_t* __restrict__ Pq,
                                            double* __restrict__ inv100, int32_t* __restrict__ jflag, int xcd,
                                            DevStatus* st, uint32_t* s_hist) {
@@ -198,6 +198,7 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
     uint32_t n64 = 0, nedge = 0;
+    const int prow = nb.pad ? pad_stride(nb.pad_cap, m) : 0;
     const XcdItems it = xcd ? xcd_items((m + 1) / 2, off[m] + kItemWork * m,
                                         [&](int64_t i) { return off[2 * i] + kItemWork * 2 * i; })
                             : cyclic_items((m + 1) / 2);
@@ -214,6 +215,7 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
             e = off[q + 1];
         }
         const int len = e - b;
+        const int32_t* lp = list_of(nb, prow, q, b, e);
         const int lmax = max(len, __shfl_xor(len, kHalf, kWave));
         int n_valid = 0;
         // the half's histogram in LDS (3H counters), one atomic per lane and feature
@@ -224,7 +226,7 @@ __device__ __forceinline__ void spfh_pairs_body(const CloudDev* __restrict__ cl,
             bool valid = false;
             int bn[3] = {-1, -1, -1};
             if (base + hl < len) {
-                const int k = nbr[b + base + hl];
+                const int k = lp[base + hl];
                 valid = (flags[k] & 1) != 0;
                 if (valid && k != q) {
                     const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
@@ -297,10 +299,10 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
                                            int64_t stride, const int32_t* __restrict__ kept_cloud,
                                            const float* __restrict__ nrm, int64_t nrm_stride,
                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
-                                           const int32_t* __restrict__ nbr, int H, uint16_t* __restrict__ cnt16,
+                                           NbrLists nb, int H, uint16_t* __restrict__ cnt16,
                                            float* __restrict__ spfh_out, int32_t* __restrict__ Pq,
                                            double* __restrict__ inv100, int32_t* __restrict__ jflag, DevStatus* st,
-                                           int64_t q, uint32_t* s_hist) {
+                                           int64_t q, uint32_t* s_hist, int prow) {
     const int lane = lane_id();
     const int D = 3 * H;
     const int64_t s2 = 2 * stride, n2 = 2 * nrm_stride;
@@ -320,6 +322,7 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
     const V3f pq = {xyz[q], xyz[stride + q], xyz[s2 + q]};
     const V3f nq = {nrm[q], nrm[nrm_stride + q], nrm[n2 + q]};
     const int b = off[q], e = off[q + 1];
+    const int32_t* lp = list_of(nb, prow, q, b, e);
     // the wavefront's histogram in LDS (3H counters), one atomic per lane and feature
     for (int t = lane; t < D; t += kWave) s_hist[t] = 0u;
     __builtin_amdgcn_wave_barrier();
@@ -330,7 +333,7 @@ __device__ __forceinline__ void spfh_point(const CloudDev* __restrict__ cl, cons
         bool valid = false;
         int bn[3] = {-1, -1, -1};
         if (t < e) {
-            const int k = nbr[t];
+            const int k = lp[t - b];
             valid = (flags[k] & 1) != 0;
             if (valid && k != q) {
                 const V3f pk = {xyz[k], xyz[stride + k], xyz[s2 + k]};
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
                                                      int64_t m_cap, const float* __restrict__ nrm,
                                                      int64_t nrm_stride, const uint8_t* __restrict__ flags,
                                                      const int32_t* __restrict__ off,
-                                                     const int32_t* __restrict__ nbr, int H,
+                                                     NbrLists nb, int H,
                                                      uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
                                                      int32_t* __restrict__ Pq, double* __restrict__ inv100,
                                                      int32_t* __restrict__ jflag, int pair_mean, int xcd,
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     if (st->nnz > pair_mean * m) return;            // long lists: spfh_kernel
     __shared__ uint32_t s_hist[kWaves][2 * 3 * kMaxBins];
-    spfh_pairs_body(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
+    spfh_pairs_body(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nb, H, cnt16, spfh_out, Pq, inv100,
                     jflag, xcd, st, s_hist[threadIdx.x / kWave]);
 }
 
@@ -406,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                                                       int64_t m_cap, const float* __restrict__ nrm,
                                                       int64_t nrm_stride, const uint8_t* __restrict__ flags,
                                                       const int32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ nbr, int H,
+                                                      NbrLists nb, int H,
                                                       uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out,
                                                       int32_t* __restrict__ Pq, double* __restrict__ inv100,
                                                       int32_t* __restrict__ jflag, int pair_mean, int xcd,
@@ -417,9 +420,10 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
     const XcdItems it = xcd ? xcd_items(m, off[m] + kItemWork * m, [&](int64_t i) { return off[i] + kItemWork * i; })
                             : cyclic_items(m);
     __shared__ uint32_t s_hist[kWaves][3 * kMaxBins];
+    const int prow = nb.pad ? pad_stride(nb.pad_cap, m) : 0;
     for (int64_t q = it.first; q < it.end; q += it.stride)
-        spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq, inv100,
-                   jflag, st, q, s_hist[threadIdx.x / kWave]);
+        spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nb, H, cnt16, spfh_out, Pq, inv100,
+                   jflag, st, q, s_hist[threadIdx.x / kWave], prow);
 }
 
 // FPFH of rows of at most 64 values over the J list, two points per
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
                                                      const int32_t* __restrict__ jflag,
                                                      const int32_t* __restrict__ j_list,
                                                      const int32_t* __restrict__ off,
-                                                     const int32_t* __restrict__ nbr, int H,
+                                                     NbrLists nb, int H,
                                                      const uint16_t* __restrict__ cnt16,
                                                      const int32_t* __restrict__ Pq,
                                                      const double* __restrict__ inv100, float* __restrict__ fpfh,
@@ -458,6 +462,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < m * D; t += gt)
         if (!jflag[t / D]) fpfh[t] = 0.0f;
     const int64_t n_j = clamp_count(st->n_j, m);
+    const int prow = nb.pad ? pad_stride(nb.pad_cap, m) : 0;
     const XcdItems it = xcd ? xcd_items((n_j + 1) / 2, off[m] + kItemWork * n_j,
                                         [&](int64_t i) { return off[j_list[2 * i]] + kItemWork * 2 * i; })
                             : cyclic_items((n_j + 1) / 2);
@@ -474,6 +479,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
             e = off[q + 1];
         }
         const int len = e - b;
+        const int32_t* lp = list_of(nb, prow, q, b, e);
         const int lmax = max(len, __shfl_xor(len, kHalf, kWave));
         // lanes own bins hl and hl + 32; lanes past D read bin D - 1 and are never stored
         const int lb0 = min(hl, D - 1), lb1 = min(hl + kHalf, D - 1);
@@ -483,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
             double w = 0.0;
             int k = 0;
             if (base + hl < len) {
-                k = nbr[b + base + hl];
+                k = lp[base + hl];
                 const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
                 use = (k != q) && (flags[k] & 1);
                 // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k]);
@@ -544,9 +550,10 @@ __global__ __launch_bounds__(kBlock) void fpfh_pairs(const float* __restrict__ x
 template <int kBatchNarrow>
 __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_t stride,
                                            const uint8_t* __restrict__ flags, const int32_t* __restrict__ off,
-                                           const int32_t* __restrict__ nbr, int H, const uint16_t* __restrict__ cnt16,
+                                           NbrLists nb, int H, const uint16_t* __restrict__ cnt16,
                                            const int32_t* __restrict__ Pq, const double* __restrict__ inv100,
-                                           float* __restrict__ fpfh, int32_t* s_k, double* s_w, int64_t q) {
+                                           float* __restrict__ fpfh, int32_t* s_k, double* s_w, int64_t q,
+                                           int prow) {
 #pragma clang fp contract(off)
     const int lane = lane_id();
     const int D = 3 * H;
@@ -555,13 +562,14 @@ __device__ __forceinline__ void fpfh_point(const float* __restrict__ xyz, int64_
     float* out = fpfh + q * D;
     const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[s2 + q];
     const int b = off[q], e = off[q + 1];
+    const int32_t* lp = list_of(nb, prow, q, b, e);
     // lanes own bins lane and lane + 64; lanes past D read bin D - 1 and are never stored
     const int lb0 = min(lane, D - 1), lb1 = min(lane + kWave, D - 1);
     double acc0 = 0.0, acc1 = 0.0;
     for (int base = b; base < e; base += kWave) {
         // every load is unconditional (indices clamped), the mask applies afterwards
         const int t = min(base + lane, e - 1);
-        const int k = nbr[t];
+        const int k = lp[t - b];
         const float kx = xyz[k], ky = xyz[stride + k], kz = xyz[s2 + k];
         const bool use = (base + lane < e) && (k != q) && (flags[k] & 1);
         // the weight of SPFH(k) = c (100 / P_k) folded with 1 / w_k (P_k >= 1: q is in M[k]);
@@ -631,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
                                                       const int32_t* __restrict__ jflag,
                                                       const int32_t* __restrict__ j_list,
                                                       const int32_t* __restrict__ off,
-                                                      const int32_t* __restrict__ nbr, int H,
+                                                      NbrLists nb, int H,
                                                       const uint16_t* __restrict__ cnt16,
                                                       const int32_t* __restrict__ Pq,
                                                       const double* __restrict__ inv100, float* __restrict__ fpfh,
@@ -649,9 +657,10 @@ __global__ __launch_bounds__(kBlock) void fpfh_kernel(const float* __restrict__ 
     const XcdItems it = xcd ? xcd_items(n_j, off[m] + kItemWork * n_j,
                                         [&](int64_t i) { return off[j_list[i]] + kItemWork * i; })
                             : cyclic_items(n_j);
+    const int prow = nb.pad ? pad_stride(nb.pad_cap, m) : 0;
     for (int64_t g = it.first; g < it.end; g += it.stride)
-        fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nbr, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
-                                 j_list[g]);
+        fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nb, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
+                                 j_list[g], prow);
 }
 
 // SPFH and FPFH in one persistent launch.  Wavefronts take work items from a
@@ -676,7 +685,7 @@ template <int kBatchNarrow>
 __global__ __launch_bounds__(kBlock) void features_fused(
     const CloudDev* __restrict__ cl, const float* __restrict__ xyz, int64_t stride,
     const int32_t* __restrict__ kept_cloud, int64_t m_cap, const float* __restrict__ nrm, int64_t nrm_stride,
-    uint8_t* __restrict__ flags, const int32_t* __restrict__ off, const int32_t* __restrict__ nbr, int H,
+    uint8_t* __restrict__ flags, const int32_t* __restrict__ off, NbrLists nb, int H,
     uint16_t* __restrict__ cnt16, float* __restrict__ spfh_out, int32_t* __restrict__ Pq, double* __restrict__ inv100,
     int32_t* __restrict__ jflag, float* __restrict__ fpfh, const CloudState* __restrict__ cs, uint32_t* queue,
     int32_t* ready, DevStatus* st) {
@@ -688,6 +697,7 @@ __global__ __launch_bounds__(kBlock) void features_fused(
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
     const int D = 3 * H;
+    const int prow = nb.pad ? pad_stride(nb.pad_cap, m) : 0;
     const int64_t n_chunks = (m + kFuseChunk - 1) / kFuseChunk;
     int known = -1;  // a cloud whose SPFH this wavefront has seen complete (and acquired)
     while (true) {
@@ -699,8 +709,8 @@ __global__ __launch_bounds__(kBlock) void features_fused(
             const int64_t p0 = static_cast<int64_t>(item) * kFuseChunk;
             const int64_t p1 = min(p0 + kFuseChunk, m);
             for (int64_t q = p0; q < p1; ++q)
-                spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nbr, H, cnt16, spfh_out, Pq,
-                           inv100, jflag, st, q, s_hist[wv]);
+                spfh_point(cl, xyz, stride, kept_cloud, nrm, nrm_stride, flags, off, nb, H, cnt16, spfh_out, Pq,
+                           inv100, jflag, st, q, s_hist[wv], prow);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (lane == 0) {
                 // the chunk's points by cloud (a chunk rarely crosses a cloud boundary)
@@ -739,8 +749,8 @@ __global__ __launch_bounds__(kBlock) void features_fused(
                 if (ok) known = c;
             }
             if (jflag[q]) {
-                fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nbr, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
-                                         q);
+                fpfh_point<kBatchNarrow>(xyz, stride, flags, off, nb, H, cnt16, Pq, inv100, fpfh, s_k[wv], s_w[wv],
+                                         q, prow);
             } else {
                 for (int t = lane; t < D; t += kWave) fpfh[q * D + t] = 0.0f;
             }
@@ -752,17 +762,17 @@ __global__ __launch_bounds__(kBlock) void features_fused(
 // accumulation order, ascending neighbours, is the same for every choice).
 template <bool kPairs, int kRows>
 kmg_status fpfh_as(const float* xyz, int64_t stride, int64_t m_cap, const uint8_t* flags, const int32_t* jflag,
-                   const int32_t* j_idx, const int32_t* off, const int32_t* nbr, int H, const uint16_t* cnt16,
+                   const int32_t* j_idx, const int32_t* off, NbrLists nb, int H, const uint16_t* cnt16,
                    const int32_t* Pq, const double* inv100, float* fpfh_out, const DevStatus* st, hipStream_t s) {
     if (kPairs) {
         // dynamic LDS: one SPFH row per lane of the block
         const size_t rows_lds = static_cast<size_t>(kBlock) * spfh_row(H) * sizeof(uint16_t);
         fpfh_pairs<kRows><<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, rows_lds, s>>>(xyz, stride, m_cap, flags, jflag, j_idx,
-                                                                              off, nbr, H, cnt16, Pq, inv100, fpfh_out,
+                                                                              off, nb, H, cnt16, Pq, inv100, fpfh_out,
                                                                               (tuning().xcd_split >> 1) & 1, st);
     } else {
         fpfh_kernel<kRows><<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(xyz, stride, m_cap, flags, jflag, j_idx, off,
-                                                                     nbr, H, cnt16, Pq, inv100, fpfh_out,
+                                                                     nb, H, cnt16, Pq, inv100, fpfh_out,
                                                                      (tuning().xcd_split >> 1) & 1, st);
     }
     return launch_status();
@@ -770,24 +780,24 @@ kmg_status fpfh_as(const float* xyz, int64_t stride, int64_t m_cap, const uint8_
 
 template <bool kPairs>
 kmg_status launch_fpfh(int rows, const float* xyz, int64_t stride, int64_t m_cap, const uint8_t* flags,
-                       const int32_t* jflag, const int32_t* j_idx, const int32_t* off, const int32_t* nbr, int H,
+                       const int32_t* jflag, const int32_t* j_idx, const int32_t* off, NbrLists nb, int H,
                        const uint16_t* cnt16, const int32_t* Pq, const double* inv100, float* fpfh_out,
                        const DevStatus* st, hipStream_t s) {
     switch (rows) {
         case 1:
-            return fpfh_as<kPairs, 1>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+            return fpfh_as<kPairs, 1>(xyz, stride, m_cap, flags, jflag, j_idx, off, nb, H, cnt16, Pq, inv100,
                                       fpfh_out, st, s);
         case 2:
-            return fpfh_as<kPairs, 2>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+            return fpfh_as<kPairs, 2>(xyz, stride, m_cap, flags, jflag, j_idx, off, nb, H, cnt16, Pq, inv100,
                                       fpfh_out, st, s);
         case 4:
-            return fpfh_as<kPairs, 4>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+            return fpfh_as<kPairs, 4>(xyz, stride, m_cap, flags, jflag, j_idx, off, nb, H, cnt16, Pq, inv100,
                                       fpfh_out, st, s);
         case 16:
-            return fpfh_as<kPairs, 16>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+            return fpfh_as<kPairs, 16>(xyz, stride, m_cap, flags, jflag, j_idx, off, nb, H, cnt16, Pq, inv100,
                                        fpfh_out, st, s);
         default:
-            return fpfh_as<kPairs, 8>(xyz, stride, m_cap, flags, jflag, j_idx, off, nbr, H, cnt16, Pq, inv100,
+            return fpfh_as<kPairs, 8>(xyz, stride, m_cap, flags, jflag, j_idx, off, nb, H, cnt16, Pq, inv100,
                                       fpfh_out, st, s);
     }
 }
@@ -859,7 +869,7 @@ FeatWs carve_feat(Carver& c, int64_t m_cap, int H) {
 }
 
 kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
-                      int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, const int32_t* nbr,
+                      int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, NbrLists nb,
                       const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s,
                       bool cleared) {
     if (!cleared)
@@ -869,11 +879,11 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
         StageScope sc(ST_SPFH, s);
         const int pair_mean = tuning().spfh_pair_mean;
         spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
-                                                              flags, off, nbr, H, w.cnt16, spfh_out, w.Pq, w.inv100,
+                                                              flags, off, nb, H, w.cnt16, spfh_out, w.Pq, w.inv100,
                                                               w.jflag, pair_mean, tuning().xcd_split & 1, st);
         KMG_TRY(launch_status());
         spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
-                                                                       nrm_stride, flags, off, nbr, H, w.cnt16,
+                                                                       nrm_stride, flags, off, nb, H, w.cnt16,
                                                                        spfh_out, w.Pq, w.inv100, w.jflag, pair_mean,
                                                                        tuning().xcd_split & 1, st);
         KMG_TRY(launch_status());
@@ -882,7 +892,7 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
 }
 
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
-                      const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
+                      const FeatWs& w, const int32_t* off, NbrLists nb, uint8_t* flags, float* fpfh_out,
                       int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets) {
     if (sets && !cs) return KMG_ERR_ARG;
     {
@@ -902,10 +912,10 @@ kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_
     if (m_cap > 0) {
         StageScope sc(ST_FPFH, s);
         if (3 * H <= kWave) {
-            KMG_TRY(launch_fpfh<true>(tuning().fpfh_rows, xyz, stride, m_cap, flags, w.jflag, j_idx, off, nbr, H,
+            KMG_TRY(launch_fpfh<true>(tuning().fpfh_rows, xyz, stride, m_cap, flags, w.jflag, j_idx, off, nb, H,
                                       w.cnt16, w.Pq, w.inv100, fpfh_out, st, s));
         } else {
-            KMG_TRY(launch_fpfh<false>(tuning().fpfh_rows, xyz, stride, m_cap, flags, w.jflag, j_idx, off, nbr, H,
+            KMG_TRY(launch_fpfh<false>(tuning().fpfh_rows, xyz, stride, m_cap, flags, w.jflag, j_idx, off, nb, H,
                                        w.cnt16, w.Pq, w.inv100, fpfh_out, st, s));
         }
     }
@@ -915,18 +925,18 @@ kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_
 // SPFH and FPFH in the fused persistent launch, then the J list.
 template <int kRows>
 void launch_fused(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud, int64_t m_cap,
-                  const float* nrm, int64_t nrm_stride, uint8_t* flags, const int32_t* off, const int32_t* nbr, int H,
+                  const float* nrm, int64_t nrm_stride, uint8_t* flags, const int32_t* off, NbrLists nb, int H,
                   const FeatWs& w, float* spfh_out, float* fpfh_out, const CloudState* cs, DevStatus* st,
                   hipStream_t s) {
     features_fused<kRows><<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
-                                                                      nrm_stride, flags, off, nbr, H, w.cnt16, spfh_out,
+                                                                      nrm_stride, flags, off, nb, H, w.cnt16, spfh_out,
                                                                       w.Pq, w.inv100, w.jflag, fpfh_out, cs, w.queue,
                                                                       w.ready, st);
 }
 
 kmg_status features_fused_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
                                 const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
-                                const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                                const int32_t* off, NbrLists nb, const float* nrm, int64_t nrm_stride,
                                 uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
                                 hipStream_t s, bool cleared, MatchSet* sets) {
     if (sets && !cs) return KMG_ERR_ARG;
@@ -938,11 +948,11 @@ kmg_status features_fused_batch(const CloudDev* cl, int n_clouds, const float* x
     if (m_cap > 0) {
         StageScope sc(ST_SPFH, s);  // SPFH and FPFH together
         switch (tuning().fpfh_rows) {
-            case 4: launch_fused<4>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nbr, H, w,
+            case 4: launch_fused<4>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nb, H, w,
                                     spfh_out, fpfh_out, cs, st, s); break;
-            case 16: launch_fused<16>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nbr, H, w,
+            case 16: launch_fused<16>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nb, H, w,
                                       spfh_out, fpfh_out, cs, st, s); break;
-            default: launch_fused<8>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nbr, H, w,
+            default: launch_fused<8>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride, flags, off, nb, H, w,
                                      spfh_out, fpfh_out, cs, st, s); break;
         }
         KMG_TRY(launch_status());
@@ -963,15 +973,15 @@ kmg_status features_fused_batch(const CloudDev* cl, int n_clouds, const float* x
 
 kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
-                          const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                          const int32_t* off, NbrLists nb, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
                           hipStream_t s, bool cleared, MatchSet* sets) {
     if (tuning().fuse_features)
-        return features_fused_batch(cl, n_clouds, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm,
+        return features_fused_batch(cl, n_clouds, xyz, stride, kept_cloud, m_cap, H, st, w, off, nb, nrm,
                                     nrm_stride, flags, spfh_out, fpfh_out, j_idx, cs, s, cleared, sets);
-    KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nbr, nrm, nrm_stride, flags, spfh_out, s,
+    KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nb, nrm, nrm_stride, flags, spfh_out, s,
                        cleared));
-    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nbr, flags, fpfh_out, j_idx, cs, s, sets);
+    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nb, flags, fpfh_out, j_idx, cs, s, sets);
 }
 
 }  // namespace kmg

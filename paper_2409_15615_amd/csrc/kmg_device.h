@@ -175,6 +175,20 @@ __device__ __forceinline__ int cloud_of_raw(const CloudDev* cl, int n_clouds, in
 
 __device__ __forceinline__ int64_t clamp_count(int64_t v, int64_t cap) { return v < cap ? v : cap; }
 
+// List-first radius search: each list of at most this many entries sits in
+// row q of a pad of pad_cap entries (the rows share the pad evenly among the
+// m kept points, in whole 128-byte lines once a row holds one); longer lists
+// sit at their CSR places.
+__device__ __forceinline__ int pad_stride(int64_t pad_cap, int64_t m) {
+    const int r = m > 0 ? static_cast<int>(min<int64_t>(kListSmall, pad_cap / m)) : 0;
+    return r >= 32 ? (r & ~31) : r;
+}
+
+// First entry of point q's list (CSR range [b, e)); row = pad_stride(...).
+__device__ __forceinline__ const int32_t* list_of(const NbrLists& L, int row, int64_t q, int b, int e) {
+    return (L.pad && e - b <= row) ? L.pad + q * row : L.nbr + b;
+}
+
 // Runs of equal keys on consecutive lanes (a lane with key kEmptyKey is a run
 // of its own).  The whole wavefront must be active.  head: this lane starts a
 // run; lead: the first lane of this lane's run; len: the run's lane count

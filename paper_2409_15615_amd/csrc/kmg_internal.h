@@ -286,6 +286,15 @@ kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevSt
                           const GridInsert* grid = nullptr);
 
 // ---- search.hip -----------------------------------------------------------
+// The neighbour lists as the feature passes read them: the CSR lists, or
+// (pad != nullptr) the pad rows of the list-first search (pad_cap entries)
+// with the lists longer than a row at their CSR places.
+struct NbrLists {
+    const int32_t* nbr = nullptr;
+    const int32_t* pad = nullptr;
+    int64_t pad_cap = 0;
+};
+
 struct SearchWs {
     uint64_t* keys;
     int32_t* ccount;
@@ -317,8 +326,9 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
 // tables cleared beforehand): one search pass writes |N(q)| and each list
 // that fits a row of the pad (pad_cap entries shared evenly by the kept
 // points), the offsets follow from the degrees, the dense pass serves the
-// longer lists (listed in long_q, m_cap entries), and the normals pass copies
-// the pad rows into nbr.  inserted: the cell hash is filled already (voxelize_batch).
+// longer lists (listed in long_q, m_cap entries) into their CSR places in
+// nbr, and the normals pass reads the lists where they are (NbrLists).
+// inserted: the cell hash is filled already (voxelize_batch).
 kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
                               int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
@@ -346,17 +356,17 @@ FeatWs carve_feat(Carver& c, int64_t m_cap, int H);
 // each cloud's matching set.  cleared: jflag is zero already.
 kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, int64_t stride,
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
-                          const int32_t* off, const int32_t* nbr, const float* nrm, int64_t nrm_stride,
+                          const int32_t* off, NbrLists nb, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
                           hipStream_t s, bool cleared = false, MatchSet* sets = nullptr);
-// The two halves of features_batch: SPFH (and J) over (off, nbr); then the
-// FPFH sum over (off, nbr) and the J list.
+// The two halves of features_batch: SPFH (and J) over (off, nb); then the
+// FPFH sum over (off, nb) and the J list.
 kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
-                      int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, const int32_t* nbr,
+                      int64_t m_cap, int H, DevStatus* st, const FeatWs& w, const int32_t* off, NbrLists nb,
                       const float* nrm, int64_t nrm_stride, uint8_t* flags, float* spfh_out, hipStream_t s,
                       bool cleared = false);
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
-                      const FeatWs& w, const int32_t* off, const int32_t* nbr, uint8_t* flags, float* fpfh_out,
+                      const FeatWs& w, const int32_t* off, NbrLists nb, uint8_t* flags, float* fpfh_out,
                       int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets = nullptr);
 
 // ---- match.hip ------------------------------------------------------------

@@ -11,8 +11,9 @@
 // every list, a fill pass that collects the accepted indices in LDS and
 // writes them in ascending order (rank sort).  Batches may instead search once
 // (the list-first form): each list goes to a row of a pad with its length,
-// the offsets follow from the lengths, and the normal estimation copies the
-// rows to their places while it reads them.  Normals are then estimated by
+// the offsets follow from the lengths, and the later passes read the lists
+// from their rows (the longer lists, searched again, from their CSR places).
+// Normals are then estimated by
 // 16 lanes per point from the stored list: FP64 moments of the r_normal subset,
 // a cyclic Jacobi eigen-solver in FP64, the linearity test and viewpoint
 // orientation.
@@ -41,15 +42,6 @@ __device__ __forceinline__ int64_t cell_coord(float x, double inv_c) {
 
 __device__ __forceinline__ int cloud_of(const int32_t* kept_cloud, int64_t q) {
     return kept_cloud ? kept_cloud[q] : 0;
-}
-
-// List-first form: the fill pass writes each list of at most this many entries
-// into row q of a pad of pad_cap entries (the rows share the pad evenly among
-// the m kept points, in whole 128-byte lines once a row holds one); longer
-// lists are left to the dense pass.
-__device__ __forceinline__ int pad_stride(int64_t pad_cap, int64_t m) {
-    const int r = m > 0 ? static_cast<int>(min<int64_t>(kListSmall, pad_cap / m)) : 0;
-    return r >= 32 ? (r & ~31) : r;
 }
 
 // Kept points in input order often share a cell: only the first lane of a run
@@ -392,8 +384,8 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_count2(const CloudDev* _
 // kFirst (the list-first form, no count pass before it): every query is
 // searched, |N(q)| goes to deg[q] and the list, if it fits a row of the pad
 // (nbr = pad of nbr_cap entries, row stride pad_stride), to row q, else the
-// query's cell-sorted position to long_q (m entries); the normals pass later
-// copies the rows to their CSR places.
+// query's cell-sorted position to long_q (m entries); the later passes read
+// the lists from the rows.
 template <int kWaves, bool kFirst>
 __global__ __launch_bounds__(kWaves* kWave) void radius_fill2(const CloudDev* __restrict__ cl, Grid g,
                                                               const int32_t* __restrict__ kept_cloud, int64_t m_cap,
@@ -549,17 +541,18 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
                                                          const float* __restrict__ xyz, int64_t stride,
                                                          const int32_t* __restrict__ kept_cloud, int64_t m_cap,
                                                          const int32_t* __restrict__ off,
-                                                         int32_t* __restrict__ nbr, int64_t nbr_cap,
+                                                         const int32_t* __restrict__ nbr, int64_t nbr_cap,
                                                          float* __restrict__ nrm, int64_t nrm_stride,
                                                          uint8_t* __restrict__ flags, int32_t* __restrict__ n_normal,
                                                          DevStatus* st, const int32_t* __restrict__ pad = nullptr,
                                                          int64_t pad_cap = 0) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
-    // list-first form: this pass places the lists (those that fit a pad row)
-    // and reports a list volume beyond the caller's capacity
+    // list-first form: the lists stay in their pad rows; a list volume beyond
+    // the caller's capacity is reported here
     if (pad && blockIdx.x == 0 && threadIdx.x == 0 && st->nnz > nbr_cap) st->err_capacity = 1;
     if (st->err_range || st->nnz > nbr_cap) return;
     const int row = pad ? pad_stride(pad_cap, m) : 0;
+    const NbrLists lists{nbr, pad, pad_cap};
     // kNormalLanes lanes per point: each sums every kNormalLanes-th list entry, then
     // the group adds up its partial moments (every lane ends with the totals)
     const int sub = lane_id() % kNormalLanes;
@@ -569,9 +562,7 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
         const RadiusTest rn = cl[c].rn;
         const float qx = xyz[q], qy = xyz[stride + q], qz = xyz[2 * stride + q];
         const int b = off[q], e = off[q + 1];
-        // the list: its pad row (copied to nbr on the way) or, if longer, nbr
-        const bool from_pad = pad && e - b <= row;
-        const int32_t* src = from_pad ? pad + static_cast<int64_t>(q) * row : nbr + b;
+        const int32_t* src = list_of(lists, row, q, b, e);
         int nn = 0;
         // moments of the r_normal subset, shifted to the query (FP64)
         double sx = 0, sy = 0, sz = 0, sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
@@ -582,7 +573,6 @@ __global__ __launch_bounds__(kBlock) void normals_kernel(const CloudDev* __restr
             for (int u = 0; u < kNbrRounds; ++u) {
                 const int k = k0 + u * kNormalLanes;
                 id[u] = k < e ? src[k - b] : -1;
-                if (from_pad && k < e) nbr[k] = id[u];
             }
             float px[kNbrRounds], py[kNbrRounds], pz[kNbrRounds];
 #pragma unroll

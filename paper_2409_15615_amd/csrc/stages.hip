@@ -179,11 +179,11 @@ kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_
     if (!c.fits()) return KMG_ERR_WORKSPACE;
     KMG_TRY(init(st, cl, make_cloud(p, nullptr, 0, 0), 0, m, s));
     if (!classic) {
-        KMG_TRY(features_batch(cl, 1, xyz, m, nullptr, m, H, st, w, off, nbr, nrm, m, flags, spfh_out, fpfh_out,
-                               j_idx, nullptr, s));
+        KMG_TRY(features_batch(cl, 1, xyz, m, nullptr, m, H, st, w, off, NbrLists{nbr}, nrm, m, flags, spfh_out,
+                               fpfh_out, j_idx, nullptr, s));
     } else {
         // SPFH over the lists of search 2; search 3 (r_FPFH again) for the FPFH sum
-        KMG_TRY(spfh_batch(cl, xyz, m, nullptr, m, H, st, w, off, nbr, nrm, m, flags, spfh_out, s));
+        KMG_TRY(spfh_batch(cl, xyz, m, nullptr, m, H, st, w, off, NbrLists{nbr}, nrm, m, flags, spfh_out, s));
         KMG_TRY(search_count_batch(cl, xyz, m, nullptr, m, st, sw, off3, s, true, 0));
         DevStatus h3;
         KMG_TRY(read_status(st, &h3, s));
@@ -191,7 +191,7 @@ kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_
         if (h3.nnz > nnz3_cap) return KMG_ERR_WORKSPACE;
         KMG_TRY(search_fill_batch(cl, xyz, m, nullptr, m, nnz3_cap, (h3.dense & 1) != 0, st, sw, off3, nbr3, nullptr,
                                   m, flags, nullptr, s, 0, false));
-        KMG_TRY(fpfh_batch(1, xyz, m, m, H, st, w, off3, nbr3, flags, fpfh_out, j_idx, nullptr, s));
+        KMG_TRY(fpfh_batch(1, xyz, m, m, H, st, w, off3, NbrLists{nbr3}, flags, fpfh_out, j_idx, nullptr, s));
     }
     DevStatus h;
     KMG_TRY(read_status(st, &h, s));
