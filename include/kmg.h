@@ -145,7 +145,8 @@ const char* kmg_stage_name(int32_t stage);
  * in force at capture time.  Not synchronised with concurrent calls.
  *   search_waves    waves per block of the radius count and fill passes
  *                   (Eq. A1): 2, 4 (default) or 8.
- *   count_queries   queries per wavefront in the count pass: 1, 2 (default)
+ *   count_queries   queries per wavefront in the count pass (the per-stage
+ *                   calls, and batches under search_form 0): 1, 2 (default)
  *                   or 4.
  *   spfh_pair_mean  mean neighbour-list length up to which the SPFH pass
  *                   (Eq. A2-A4) takes two points per wavefront (default 24;
@@ -177,8 +178,8 @@ const char* kmg_stage_name(int32_t stage);
  *                   distance tiles, fewer launches).  The same
  *                   correspondences, d1 and d2 either way.
  *   search_form     radius search (Eq. A1) of a batch (kmg_batch_run):
- *                   0 (default) a count pass, the offsets, then the fill
- *                   pass; 1 one search pass that writes |N(q)| and each list
+ *                   0 a count pass, the offsets, then the fill pass;
+ *                   1 (default) one search pass that writes |N(q)| and each list
  *                   into a row of a pad in the workspace (64 entries per raw
  *                   point, shared evenly by the kept points) and the
  *                   offsets, the longer lists searched again into their

@@ -480,7 +480,7 @@ struct Tuning {
     int fuse_features = 0;    // 1: SPFH and FPFH in one persistent launch (per-cloud readiness counters)
     int xcd_split = 2;        // bit 0 SPFH, bit 1 FPFH: XCD-aware split of the points over the wavefronts
     int match_form = 0;       // 0: one-sided matching then the image back; 1: both directions in one pass
-    int search_form = 0;      // batches: 0 count pass then fill pass; 1 list-first (one search pass, a pad)
+    int search_form = 1;      // batches: 0 count pass then fill pass; 1 list-first (one search pass, a pad)
 };
 const Tuning& tuning();
 bool set_tuning(const Tuning& t);

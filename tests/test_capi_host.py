@@ -130,7 +130,7 @@ def test_tuning_set_get_and_validation(kmg):
     kmg.set_tuning(None)
     d = kmg.get_tuning()
     assert d == {"search_waves": 4, "count_queries": 2, "spfh_pair_mean": 24, "fpfh_rows": 2, "band_tile": 0,
-                 "fuse_features": 0, "xcd_split": 2, "match_form": 0, "search_form": 0}
+                 "fuse_features": 0, "xcd_split": 2, "match_form": 0, "search_form": 1}
     kmg.set_tuning({"search_waves": 8, "band_tile": 20})
     assert kmg.get_tuning()["search_waves"] == 8 and kmg.get_tuning()["band_tile"] == 20
     for bad in ({"search_waves": 3}, {"count_queries": 8}, {"fpfh_rows": 5}, {"band_tile": 65},
