@@ -52,7 +52,7 @@ PEAK_HBM_GBS = 8000.0
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
     "sha256": "b740fe305887ed50e1d6288e9537764500bb6db324ba52f2ae072391727c0263",
-    "fetch_kib": 67821.3,
+    "fetch_kib": 67687.5,
     "fetch_scale": 262144.0 / 131085.2,
     "write_kib": 11850.6,
     "write_scale": 262144.0 / 262144.0,
