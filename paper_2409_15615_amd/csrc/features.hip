@@ -893,12 +893,15 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
 
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
                       const FeatWs& w, const int32_t* off, NbrLists nb, uint8_t* flags, float* fpfh_out,
-                      int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets) {
+                      int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets, uint64_t* j_scan_status) {
     if (sets && !cs) return KMG_ERR_ARG;
     {
         // the J list first: the FPFH sums run over it
         StageScope sc(ST_J_COMPACT, s);
-        KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
+        if (j_scan_status)
+            KMG_TRY(scan_exclusive_onepass(w.jflag, w.pos, m_cap, &st->n_j, j_scan_status, &st->err_sync, s));
+        else
+            KMG_TRY(scan_exclusive(w.jflag, w.pos, m_cap, &st->n_j, w.scan_tmp, s));
         if (m_cap > 0 || sets) {
             j_emit<<<std::max(grid_cap(m_cap, kBlock), 1u), kBlock, 0, s>>>(w.jflag, w.pos, m_cap, flags, j_idx, st,
                                                                           cs, n_clouds, fpfh_out, sets);
@@ -975,13 +978,14 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, NbrLists nb, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s, bool cleared, MatchSet* sets) {
+                          hipStream_t s, bool cleared, MatchSet* sets, uint64_t* j_scan_status) {
     if (tuning().fuse_features)
         return features_fused_batch(cl, n_clouds, xyz, stride, kept_cloud, m_cap, H, st, w, off, nb, nrm,
                                     nrm_stride, flags, spfh_out, fpfh_out, j_idx, cs, s, cleared, sets);
     KMG_TRY(spfh_batch(cl, xyz, stride, kept_cloud, m_cap, H, st, w, off, nb, nrm, nrm_stride, flags, spfh_out, s,
                        cleared));
-    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nb, flags, fpfh_out, j_idx, cs, s, sets);
+    return fpfh_batch(n_clouds, xyz, stride, m_cap, H, st, w, off, nb, flags, fpfh_out, j_idx, cs, s, sets,
+                      j_scan_status);
 }
 
 }  // namespace kmg

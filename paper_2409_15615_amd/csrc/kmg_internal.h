@@ -228,6 +228,13 @@ kmg_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int64_t* t
 // temp[b] = the sum of in[b kScanTile .. (b + 1) kScanTile) for every tile b.
 kmg_status scan_exclusive_summed(const int32_t* in, int32_t* out, int64_t n, int64_t* total, int64_t* temp,
                                  hipStream_t s);
+// One launch: each block publishes its tile's sum in status[tile] and adds up
+// those of the tiles before it (decoupled look-back).  status holds
+// scan_temp_elems(n) words, all zero at the launch (the scan leaves them
+// nonzero); a wait that gives up (never expected) sets *err.
+kmg_status scan_exclusive_onepass(const int32_t* in, int32_t* out, int64_t n, int64_t* total, uint64_t* status,
+                                  int32_t* err, hipStream_t s, const int32_t* live = nullptr,
+                                  int32_t* list = nullptr);
 kmg_status fill_u8(uint8_t* p, uint8_t v, size_t n, hipStream_t s);
 // Up to kMaxFillJobs fills (4- or 8-byte elements) done by one grid-stride pass.
 struct FillJob {
@@ -236,7 +243,7 @@ struct FillJob {
     int64_t n;
     int32_t bytes;
 };
-constexpr int kMaxFillJobs = 8;
+constexpr int kMaxFillJobs = 10;
 struct FillJobs {
     FillJob job[kMaxFillJobs];
     int32_t n_jobs;
@@ -328,11 +335,15 @@ kmg_status search_fill_batch(const CloudDev* cl, const float* xyz, int64_t strid
 // points), the offsets follow from the degrees, the dense pass serves the
 // longer lists (listed in long_q, m_cap entries) into their CSR places in
 // nbr, and the normals pass reads the lists where they are (NbrLists).
-// inserted: the cell hash is filled already (voxelize_batch).
+// inserted: the cell hash is filled already (voxelize_batch).  scan_status
+// (optional): zeroed look-back words for the two scans (cell counts, then
+// degrees), search_scan_status_elems(w, m_cap) of them.
 kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
                               int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
-                              int64_t nrm_stride, uint8_t* flags, hipStream_t s, bool inserted = false);
+                              int64_t nrm_stride, uint8_t* flags, hipStream_t s, bool inserted = false,
+                              uint64_t* scan_status = nullptr);
+size_t search_scan_status_elems(const SearchWs& w, int64_t m_cap);
 
 // ---- features.hip ---------------------------------------------------------
 // Row stride of the SPFH counts, in entries: 3H rounded up to a multiple of 8,
@@ -358,7 +369,8 @@ kmg_status features_batch(const CloudDev* cl, int n_clouds, const float* xyz, in
                           const int32_t* kept_cloud, int64_t m_cap, int H, DevStatus* st, const FeatWs& w,
                           const int32_t* off, NbrLists nb, const float* nrm, int64_t nrm_stride,
                           uint8_t* flags, float* spfh_out, float* fpfh_out, int32_t* j_idx, CloudState* cs,
-                          hipStream_t s, bool cleared = false, MatchSet* sets = nullptr);
+                          hipStream_t s, bool cleared = false, MatchSet* sets = nullptr,
+                          uint64_t* j_scan_status = nullptr);
 // The two halves of features_batch: SPFH (and J) over (off, nb); then the
 // FPFH sum over (off, nb) and the J list.
 kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
@@ -367,7 +379,8 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
                       bool cleared = false);
 kmg_status fpfh_batch(int n_clouds, const float* xyz, int64_t stride, int64_t m_cap, int H, DevStatus* st,
                       const FeatWs& w, const int32_t* off, NbrLists nb, uint8_t* flags, float* fpfh_out,
-                      int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets = nullptr);
+                      int32_t* j_idx, CloudState* cs, hipStream_t s, MatchSet* sets = nullptr,
+                      uint64_t* j_scan_status = nullptr);
 
 // ---- match.hip ------------------------------------------------------------
 constexpr int kLpMaxDim = 64;  // descriptor length of the FP16 / BF16 tiles (two K = 32 steps)

@@ -758,7 +758,8 @@ namespace {
 // inserted: the kept points are in the cell hash already (voxelize_batch put
 // them there as it emitted them); the counts are then scanned and scattered.
 kmg_status build_grid(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud, int64_t m_cap,
-                      DevStatus* st, const SearchWs& w, hipStream_t s, bool cleared, bool inserted) {
+                      DevStatus* st, const SearchWs& w, hipStream_t s, bool cleared, bool inserted,
+                      uint64_t* scan_status = nullptr) {
     StageScope sc(ST_GRID, s);
     if (!cleared) {
         KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
@@ -770,7 +771,10 @@ kmg_status build_grid(const CloudDev* cl, const float* xyz, int64_t stride, cons
                                                               w.ccount, w.cap_table - 1, w.pslot, st);
         KMG_TRY(launch_status());
     }
-    KMG_TRY(scan_exclusive(w.ccount, w.cstart, w.cap_table, &st->n_cells, w.scan_tmp, s));
+    if (scan_status)
+        KMG_TRY(scan_exclusive_onepass(w.ccount, w.cstart, w.cap_table, &st->n_cells, scan_status, &st->err_sync, s));
+    else
+        KMG_TRY(scan_exclusive(w.ccount, w.cstart, w.cap_table, &st->n_cells, w.scan_tmp, s));
     if (m_cap > 0) {
         cell_scatter<<<grid_cap(m_cap, kBlock), kBlock, 0, s>>>(xyz, stride, m_cap, w.pslot, w.cstart, w.cfill,
                                                                w.pts, st);
@@ -798,11 +802,16 @@ kmg_status search_count_batch(const CloudDev* cl, const float* xyz, int64_t stri
     return KMG_OK;
 }
 
+size_t search_scan_status_elems(const SearchWs& w, int64_t m_cap) {
+    return scan_temp_elems(w.cap_table) + scan_temp_elems(m_cap + 1);
+}
+
 kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stride, const int32_t* kept_cloud,
                               int64_t m_cap, int64_t nbr_cap, DevStatus* st, const SearchWs& w, int32_t* off,
                               int32_t* nbr, int32_t* pad, int64_t pad_cap, int32_t* long_q, float* nrm,
-                              int64_t nrm_stride, uint8_t* flags, hipStream_t s, bool inserted) {
-    KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, true, inserted));
+                              int64_t nrm_stride, uint8_t* flags, hipStream_t s, bool inserted,
+                              uint64_t* scan_status) {
+    KMG_TRY(build_grid(cl, xyz, stride, kept_cloud, m_cap, st, w, s, true, inserted, scan_status));
     if (m_cap > 0) {
         StageScope sc(ST_SEARCH_FILL, s);
         KMG_TRY(launch_fill(tuning().search_waves, cl, grid_of(w), kept_cloud, m_cap,
@@ -810,7 +819,11 @@ kmg_status search_lists_first(const CloudDev* cl, const float* xyz, int64_t stri
     }
     {
         StageScope sc(ST_SEARCH_COUNT, s);
-        KMG_TRY(scan_exclusive(w.deg, off, m_cap + 1, &st->nnz, w.scan_tmp, s));
+        if (scan_status)
+            KMG_TRY(scan_exclusive_onepass(w.deg, off, m_cap + 1, &st->nnz, scan_status + scan_temp_elems(w.cap_table),
+                                           &st->err_sync, s));
+        else
+            KMG_TRY(scan_exclusive(w.deg, off, m_cap + 1, &st->nnz, w.scan_tmp, s));
     }
     if (m_cap <= 0) return KMG_OK;
     {
