@@ -333,7 +333,9 @@ kmg_status kmg_match(const float* desc_p, const int32_t* rows_p, int64_t np, con
  * 5 queries re-scanned exactly (a work statistic: it depends on the matching
  * form of the launch tuning, the other entries do not), 6 status (a kmg_status; KMG_ERR_WORKSPACE
  * when the batch's neighbour entries exceed nnz_cap, KMG_ERR_CAPACITY when
- * outs[i].cap is too small), 7 neighbour entries of the whole batch.
+ * outs[i].cap is too small, KMG_ERR_DEVICE if a bounded wait between the
+ * blocks of a kernel gave up, which is never expected), 7 neighbour entries
+ * of the whole batch.
  *
  * Capacities: raw_cap >= total raw points of the batch; nnz_cap = neighbour
  * entries reserved for the batch; at most 511 pairs.  The batch matches the

@@ -957,7 +957,8 @@ __global__ __launch_bounds__(kBlock) void emit_pairs(const MatchSet* __restrict_
             o[4] = cs[2 * i + 1].j_cnt;
             o[7] = st->nnz;
             int64_t status = KMG_OK;
-            if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
+            if (st->err_sync) status = KMG_ERR_DEVICE;  // a bounded wait gave up (never expected)
+            else if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
             else if (st->err_capacity || st->nnz > nnz_cap) status = KMG_ERR_WORKSPACE;
             else if (o[0] > outs[i].cap) status = KMG_ERR_CAPACITY;
             o[6] = status;
@@ -1553,7 +1554,8 @@ __global__ __launch_bounds__(kBlock) void emit_both(const MatchSet* __restrict__
             o[4] = cs[2 * i + 1].j_cnt;
             o[7] = st->nnz;
             int64_t status = KMG_OK;
-            if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
+            if (st->err_sync) status = KMG_ERR_DEVICE;  // a bounded wait gave up (never expected)
+            else if (st->err_range || (st->dense & 2)) status = KMG_ERR_RANGE;
             else if (st->err_capacity || st2->err_capacity || st->nnz > nnz_cap) status = KMG_ERR_WORKSPACE;
             else if (o[0] > outs[i].cap) status = KMG_ERR_CAPACITY;
             o[6] = status;
