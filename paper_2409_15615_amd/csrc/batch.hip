@@ -75,8 +75,9 @@ BatchWs carve_batch(Carver& c, int n_pairs, int64_t raw_cap, int64_t nnz_cap, in
 }
 
 // Clears the status (block 0) and does every fill the step needs before its
-// first stage: the count table, the voxel and cell tables, the degrees and the
-// J flags (the stages are told that they come in cleared).
+// first stage: the count table, the voxel and cell tables, the degrees, the J
+// flags and the look-back words of the one-launch scans (the stages are told
+// that they come in cleared).
 __global__ __launch_bounds__(256) void batch_init(DevStatus* st, const CloudDev* cl, int n_clouds, FillJobs fills) {
     if (blockIdx.x == 0) {
         uint32_t* w = reinterpret_cast<uint32_t*>(st);

@@ -5,18 +5,17 @@
 // r_FPFH of a query lies in the 27 cells around the query's cell.  Cell keys
 // carry the cloud id, so one table serves the batch and a query only ever
 // sees its own cloud.  Points are counting-sorted by cell into an AoS float4
-// array (x, y, z, kept index), and each query is served by one wavefront
-// whose lanes walk the flattened candidate list of the 27 cells.  The search
-// runs twice: a count pass (|N(q)|), then, after a prefix sum has placed
-// every list, a fill pass that collects the accepted indices in LDS and
-// writes them in ascending order (rank sort).  Batches may instead search once
-// (the list-first form): each list goes to a row of a pad with its length,
-// the offsets follow from the lengths, and the later passes read the lists
-// from their rows (the longer lists, searched again, from their CSR places).
-// Normals are then estimated by
-// 16 lanes per point from the stored list: FP64 moments of the r_normal subset,
-// a cyclic Jacobi eigen-solver in FP64, the linearity test and viewpoint
-// orientation.
+// array (x, y, z, kept index), and each query is served by half a wavefront
+// (a whole one for the longest lists) whose lanes walk the flattened candidate
+// list of the 27 cells.  The search runs twice: a count pass (|N(q)|), then,
+// after a prefix sum has placed every list, a fill pass that collects the
+// accepted indices in LDS and writes them in ascending order.  Batches may
+// instead search once (the list-first form): each list goes to a row of a pad
+// with its length, the offsets follow from the lengths, and the later passes
+// read the lists from their rows (the longer lists, searched again, from
+// their CSR places).  Normals are then estimated by four lanes per point from
+// the stored list: FP64 moments of the r_normal subset, a cyclic Jacobi
+// eigen-solver in FP64, the linearity test and viewpoint orientation.
 #include <climits>
 
 #include "kmg_device.h"
