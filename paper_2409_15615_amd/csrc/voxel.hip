@@ -111,6 +111,8 @@ __global__ __launch_bounds__(kBlock) void voxel_emit(const CloudDev* __restrict_
     if (m > out_cap) return;
     const int64_t ks = out_stride ? out_stride : m;
     const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    __shared__ int s_src[kBlock / kWave][kWave];  // packed lane -> kept lane
     // every lane of a wave runs the same rounds (the run detection of the cell insert shuffles)
     for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * kBlock + (threadIdx.x & ~(kWave - 1)); t0 < n;
          t0 += stride) {
@@ -145,15 +147,27 @@ __global__ __launch_bounds__(kBlock) void voxel_emit(const CloudDev* __restrict_
             }
         }
         if (gi.keys) {
-            // a run of kept points of one cell on consecutive lanes inserts once
-            const LaneRun run = lane_run(key);
+            // the kept lanes' keys packed to the front of the wave in lane order, so
+            // that the lanes of dropped points do not break up the runs of one cell;
+            // a run inserts once
+            const uint64_t live = ballot(key != kEmptyKey);
+            const int n_live = __popcll(live);
+            const int rank = __popcll(live & ((1ull << lane) - 1ull));
+            if (key != kEmptyKey) s_src[wv][rank] = lane;
+            __builtin_amdgcn_wave_barrier();
+            const int src = lane < n_live ? s_src[wv][lane] : lane;
+            const uint64_t packed = __shfl(key, src, kWave);
+            const uint64_t ckey = lane < n_live ? packed : kEmptyKey;
+            const LaneRun run = lane_run(ckey);
             int h = -1;
-            if (run.head && key != kEmptyKey) {
-                h = static_cast<int>(hash_insert(gi.keys, gi.mask, key));
+            if (run.head && ckey != kEmptyKey) {
+                h = static_cast<int>(hash_insert(gi.keys, gi.mask, ckey));
                 atomicAdd(gi.cnt + h, run.len);
             }
-            h = __shfl(h, run.lead, kWave);
+            h = __shfl(h, run.lead, kWave);  // the run's slot, in packed lanes
+            h = __shfl(h, rank, kWave);      // back to the kept lane
             if (kept) gi.pslot[j] = key == kEmptyKey ? -1 : h;
+            __builtin_amdgcn_wave_barrier();  // s_src is free for the next round
         }
     }
 }
