@@ -32,7 +32,8 @@ struct BatchWs {
     int32_t* pad;     // list-first search: the lists, a row per kept point
     int64_t pad_cap;
     int32_t* long_q;  // list-first search: the queries whose lists exceed a row
-    uint64_t* scan_status;  // look-back words of the search's two scans, then of the J scan
+    uint64_t* scan_status;  // look-back words: the voxel numbering, the search's two scans, the J scan
+    size_t n_vox_status;
     size_t n_search_status;
     size_t n_scan_status;
     float* nrm;
@@ -62,8 +63,9 @@ BatchWs carve_batch(Carver& c, int n_pairs, int64_t raw_cap, int64_t nnz_cap, in
     w.pad_cap = static_cast<int64_t>(rc) * kPadPerRaw;
     w.pad = c.take<int32_t>(static_cast<size_t>(w.pad_cap));
     w.long_q = c.take<int32_t>(rc);
+    w.n_vox_status = scan_temp_elems(raw_cap);
     w.n_search_status = search_scan_status_elems(w.srch, raw_cap);
-    w.n_scan_status = w.n_search_status + scan_temp_elems(raw_cap);
+    w.n_scan_status = w.n_vox_status + w.n_search_status + scan_temp_elems(raw_cap);
     w.scan_status = c.take<uint64_t>(w.n_scan_status);
     w.nrm = c.take<float>(3 * rc);
     w.flags = c.take<uint8_t>(rc);
@@ -174,12 +176,12 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
     // the kept points go into the cleared cell hash of the search as they are emitted
     const GridInsert gi{w.srch.keys, w.srch.ccount, w.srch.cap_table - 1, w.srch.pslot, w.st};
     KMG_TRY(voxelize_batch(w.cl, C, raw_cap, w.st, w.vox, raw_cap, raw_cap, w.kept_idx, w.kept_xyz, w.kept_cloud,
-                           w.cs, s, true, &gi));
+                           w.cs, s, true, &gi, w.scan_status));
     const bool list_first = tuning().search_form == 1;
     if (list_first) {
         KMG_TRY(search_lists_first(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, nnz_cap, w.st, w.srch, w.off,
                                    w.nbr, w.pad, w.pad_cap, w.long_q, w.nrm, raw_cap, w.flags, s, true,
-                                   w.scan_status));
+                                   w.scan_status + w.n_vox_status));
     } else {
         KMG_TRY(search_count_batch(w.cl, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, w.st, w.srch, w.off, s, true,
                                    0, true, true));
@@ -191,7 +193,7 @@ kmg_status batch_run(int n_pairs, int64_t raw_cap, int64_t nnz_cap, int H, int p
     const NbrLists nb = list_first ? NbrLists{w.nbr, w.pad, w.pad_cap} : NbrLists{w.nbr};
     KMG_TRY(features_batch(w.cl, C, w.kept_xyz, raw_cap, w.kept_cloud, raw_cap, H, w.st, w.feat, w.off, nb,
                            w.nrm, raw_cap, w.flags, nullptr, w.fpfh, w.jlist, w.cs, s, true, w.sets,
-                           w.scan_status + w.n_search_status));
+                           w.scan_status + w.n_vox_status + w.n_search_status));
     // the pair counts and statuses come with the correspondences
     KMG_TRY(match_batch(w.sets, C, D, prec, w.st, w.match, w.outs, counts, kCountsStride, s, w.cs, nnz_cap));
     timer_collect();  // waits for the stream only while timing is enabled

@@ -212,4 +212,80 @@ __device__ __forceinline__ LaneRun lane_run(uint64_t key) {
     return r;
 }
 
+// Decoupled look-back for one-launch prefix sums over tiles.  status[t] of
+// tile t: 0 until the tile's block publishes its own sum (kAggregate) and then
+// the sum of every tile up to and including it (kInclusive), in the low 62
+// bits; status[nt] hands out the tiles in launch order (look_back_ticket), so
+// a block only ever waits on tiles whose blocks are running already.  The
+// caller zeroes status[0 .. nt] before the launch.
+constexpr uint64_t kAggregate = 1ull << 62;
+constexpr uint64_t kInclusive = 2ull << 62;
+constexpr uint64_t kScanValue = (1ull << 62) - 1;
+constexpr uint32_t kLookSpinLimit = 1u << 18;  // a bounded wait (never reached in practice)
+constexpr int kLookBack = 4;                    // 64-tile slots per lane and look-back window
+
+__device__ __forceinline__ int look_back_ticket(uint64_t* status, int64_t nt) {
+    return static_cast<int>(atomicAdd(reinterpret_cast<unsigned long long*>(status + nt), 1ull));
+}
+
+// Called by one whole wavefront of the tile's block: publishes the tile's sum,
+// returns (to every lane) the sum of the tiles before it and publishes the
+// inclusive sum.  The predecessors are read kLookBack x 64 at a time, nearest
+// first (lane l, slot u: tile hi - l - 64 u), down to the nearest inclusive
+// sum; tiles before 0 count as an inclusive 0.  A wait that gives up (never
+// expected) sets *err and counts the tile as 0.
+__device__ __forceinline__ int64_t look_back(uint64_t* status, int64_t tile, int64_t tile_total, int32_t* err) {
+    const int lane = lane_id();
+    if (lane == 0)
+        __hip_atomic_store(status + tile, static_cast<uint64_t>(tile_total) | (tile == 0 ? kInclusive : kAggregate),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t prefix = 0;
+    for (int64_t hi = tile - 1; hi >= 0; hi -= kLookBack * kWave) {
+        uint64_t w[kLookBack];
+#pragma unroll
+        for (int u = 0; u < kLookBack; ++u) {
+            const int64_t j = hi - lane - u * kWave;
+            w[u] = j >= 0 ? __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kInclusive;
+        }
+        for (uint32_t spins = 0;; ++spins) {
+            bool pending = false;
+#pragma unroll
+            for (int u = 0; u < kLookBack; ++u) pending |= (w[u] >> 62) == 0;
+            if (!pending) break;
+            if (spins > kLookSpinLimit) {
+                atomicOr(err, 1);
+#pragma unroll
+                for (int u = 0; u < kLookBack; ++u)
+                    if ((w[u] >> 62) == 0) w[u] = kInclusive;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+            for (int u = 0; u < kLookBack; ++u)
+                if ((w[u] >> 62) == 0)
+                    w[u] = __hip_atomic_load(status + (hi - lane - u * kWave), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+        int found = kLookBack, last = kWave - 1;
+#pragma unroll
+        for (int u = kLookBack - 1; u >= 0; --u) {
+            const uint64_t incl = ballot((w[u] >> 62) == 2);
+            if (incl) {
+                found = u;
+                last = __ffsll(static_cast<unsigned long long>(incl)) - 1;
+            }
+        }
+        int64_t add = 0;
+#pragma unroll
+        for (int u = 0; u < kLookBack; ++u)
+            if (u < found || (u == found && lane <= last)) add += static_cast<int64_t>(w[u] & kScanValue);
+        prefix += wave_sum(add);
+        if (found < kLookBack) break;
+    }
+    if (lane == 0 && tile > 0)
+        __hip_atomic_store(status + tile, static_cast<uint64_t>(prefix + tile_total) | kInclusive, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return prefix;
+}
+
 }  // namespace kmg

@@ -287,10 +287,12 @@ struct GridInsert {
     int32_t* pslot = nullptr;
     DevStatus* st = nullptr;
 };
+// scan_status (optional): scan_temp_elems(n_cap) zeroed look-back words, for
+// numbering the kept points in one launch.
 kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
                           int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
                           int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared = false,
-                          const GridInsert* grid = nullptr);
+                          const GridInsert* grid = nullptr, uint64_t* scan_status = nullptr);
 
 // ---- search.hip -----------------------------------------------------------
 // The neighbour lists as the feature passes read them: the CSR lists, or

@@ -87,17 +87,6 @@ __global__ __launch_bounds__(kScanThreads) void tile_scan(const int32_t* in, int
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = prefix + tile_total;
 }
 
-// One-launch form (decoupled look-back).  status[t] of tile t: 0 until the
-// tile's block publishes its own sum (kAggregate) and then the sum of every
-// tile up to and including it (kInclusive), in the low 62 bits; status[nt]
-// hands out the tiles in launch order, so a block only ever waits on tiles
-// whose blocks are running already.  The caller zeroes status[0 .. nt].
-constexpr uint64_t kAggregate = 1ull << 62;
-constexpr uint64_t kInclusive = 2ull << 62;
-constexpr uint64_t kScanValue = (1ull << 62) - 1;
-constexpr uint32_t kLookSpinLimit = 1u << 18;  // a bounded wait (never reached in practice)
-constexpr int kLookBack = 4;                    // 64-tile slots per lane and look-back window
-
 __global__ __launch_bounds__(kScanThreads) void scan_onepass(const int32_t* in, int32_t* out, int64_t n,
                                                              const int32_t* live, uint64_t* status, int64_t* total,
                                                              int32_t* list, int32_t* err) {
@@ -105,8 +94,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_onepass(const int32_t* in, 
     __shared__ int s_tile;
     __shared__ int64_t s_prefix;
     const int64_t nt = gridDim.x;
-    if (threadIdx.x == 0)
-        s_tile = static_cast<int>(atomicAdd(reinterpret_cast<unsigned long long*>(status + nt), 1ull));
+    if (threadIdx.x == 0) s_tile = look_back_ticket(status, nt);
     __syncthreads();
     const int64_t tile = s_tile;
     const int64_t nl = live_count(n, live);
@@ -122,63 +110,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_onepass(const int32_t* in, 
     int64_t excl;
     const int64_t tile_total = block_excl_scan(acc, smem, excl);
     if (threadIdx.x < kWave) {
-        const int lane = lane_id();
-        if (lane == 0)
-            __hip_atomic_store(status + tile, static_cast<uint64_t>(tile_total) | (tile == 0 ? kInclusive : kAggregate),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // look back over windows of kLookBack x 64 tiles, nearest first (lane
-        // l, slot u: tile hi - l - 64 u), down to the nearest inclusive sum;
-        // tiles before 0 count as an inclusive 0.  The window's loads are all
-        // in flight before the first wait.
-        int64_t prefix = 0;
-        for (int64_t hi = tile - 1; hi >= 0; hi -= kLookBack * kWave) {
-            uint64_t w[kLookBack];
-#pragma unroll
-            for (int u = 0; u < kLookBack; ++u) {
-                const int64_t j = hi - lane - u * kWave;
-                w[u] = j >= 0 ? __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kInclusive;
-            }
-            for (uint32_t spins = 0;; ++spins) {
-                bool pending = false;
-#pragma unroll
-                for (int u = 0; u < kLookBack; ++u) pending |= (w[u] >> 62) == 0;
-                if (!pending) break;
-                if (spins > kLookSpinLimit) {  // gives up: the result is flagged wrong
-                    atomicOr(err, 1);
-#pragma unroll
-                    for (int u = 0; u < kLookBack; ++u)
-                        if ((w[u] >> 62) == 0) w[u] = kInclusive;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-                for (int u = 0; u < kLookBack; ++u)
-                    if ((w[u] >> 62) == 0)
-                        w[u] = __hip_atomic_load(status + (hi - lane - u * kWave), __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            }
-            int found = kLookBack, last = kWave - 1;
-#pragma unroll
-            for (int u = kLookBack - 1; u >= 0; --u) {
-                const uint64_t incl = ballot((w[u] >> 62) == 2);
-                if (incl) {
-                    found = u;
-                    last = __ffsll(static_cast<unsigned long long>(incl)) - 1;
-                }
-            }
-            int64_t add = 0;
-#pragma unroll
-            for (int u = 0; u < kLookBack; ++u)
-                if (u < found || (u == found && lane <= last)) add += static_cast<int64_t>(w[u] & kScanValue);
-            prefix += wave_sum(add);
-            if (found < kLookBack) break;
-        }
-        if (lane == 0) {
-            s_prefix = prefix;
-            if (tile > 0)
-                __hip_atomic_store(status + tile, static_cast<uint64_t>(prefix + tile_total) | kInclusive,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        const int64_t prefix = look_back(status, tile, tile_total, err);
+        if (threadIdx.x == 0) s_prefix = prefix;
     }
     __syncthreads();
     int64_t run = s_prefix + excl;

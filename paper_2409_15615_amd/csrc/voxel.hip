@@ -84,6 +84,62 @@ __global__ __launch_bounds__(kBlock) void voxel_mark(const int32_t* __restrict__
     }
 }
 
+// voxel_mark and the scan in one launch: the kept flags of a tile of
+// kScanTile raw points (eight per thread, in order), the tile's exclusive
+// scan (each kept point's index) and the kept count, the tiles chained through
+// the look-back words `status` (zeroed beforehand).
+__global__ __launch_bounds__(kBlock) void voxel_number(const int32_t* __restrict__ slot, const int32_t* mins,
+                                                       int64_t n_cap, int32_t* __restrict__ flag,
+                                                       int32_t* __restrict__ pos, uint64_t* status, DevStatus* st) {
+    constexpr int kItems = kScanTile / kBlock;
+    static_assert(kItems * kBlock == kScanTile, "whole tiles per block");
+    __shared__ int64_t s_wave[kBlock / kWave];
+    __shared__ int s_tile;
+    __shared__ int64_t s_prefix;
+    const int64_t nt = gridDim.x;
+    if (threadIdx.x == 0) s_tile = look_back_ticket(status, nt);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kScanTile + static_cast<int64_t>(threadIdx.x) * kItems;
+    int f[kItems];
+    int64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t t = base + k;
+        f[k] = 0;
+        if (t < n_cap) {
+            const int h = slot[t];
+            f[k] = (h >= 0 && mins[h] == t) ? 1 : 0;
+            flag[t] = f[k];
+        }
+        acc += f[k];
+    }
+    const int wv = threadIdx.x / kWave;
+    const int64_t incl = wave_incl_scan(acc);
+    if (lane_id() == kWave - 1) s_wave[wv] = incl;
+    __syncthreads();
+    int64_t before = 0, tile_total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        const int64_t t = s_wave[w];
+        if (w < wv) before += t;
+        tile_total += t;
+    }
+    if (threadIdx.x < kWave) {
+        const int64_t prefix = look_back(status, tile, tile_total, &st->err_sync);
+        if (threadIdx.x == 0) s_prefix = prefix;
+    }
+    __syncthreads();
+    int64_t run = s_prefix + before + incl - acc;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t t = base + k;
+        if (t < n_cap) pos[t] = static_cast<int32_t>(run);
+        run += f[k];
+    }
+    if (tile == nt - 1 && threadIdx.x == 0) st->m_kept = s_prefix + tile_total;
+}
+
 // Kept point j = pos[t]; row stride `stride` (0: the kept count).  With
 // gi.keys, the kept points also go into the cell hash of the radius search
 // (what cell_insert does for the kept points in kept order).
@@ -205,7 +261,7 @@ VoxelWs carve_voxel(Carver& c, int64_t n_cap) {
 kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevStatus* st, const VoxelWs& w,
                           int64_t out_cap, int64_t out_stride, int32_t* kept_idx, float* kept_xyz,
                           int32_t* kept_cloud, CloudState* cs, hipStream_t s, bool cleared,
-                          const GridInsert* grid) {
+                          const GridInsert* grid, uint64_t* scan_status) {
     StageScope sc(ST_VOXELIZE, s);
     if (!cleared) {
         KMG_TRY(fill_u64(w.keys, kEmptyKey, w.cap_table, s));
@@ -215,11 +271,16 @@ kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevSt
         voxel_insert<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.keys, w.mins,
                                                                w.cap_table - 1, w.slot, st);
         KMG_TRY(launch_status());
-        voxel_mark<<<static_cast<unsigned>((n_cap + kScanTile - 1) / kScanTile), kBlock, 0, s>>>(
-            w.slot, w.mins, n_cap, w.flag, w.scan_tmp);
+        const unsigned nt = static_cast<unsigned>((n_cap + kScanTile - 1) / kScanTile);
+        if (scan_status) {
+            voxel_number<<<nt, kBlock, 0, s>>>(w.slot, w.mins, n_cap, w.flag, w.pos, scan_status, st);
+        } else {
+            voxel_mark<<<nt, kBlock, 0, s>>>(w.slot, w.mins, n_cap, w.flag, w.scan_tmp);
+        }
         KMG_TRY(launch_status());
     }
-    KMG_TRY(scan_exclusive_summed(w.flag, w.pos, n_cap, &st->m_kept, w.scan_tmp, s));
+    if (!scan_status || n_cap <= 0)
+        KMG_TRY(scan_exclusive_summed(w.flag, w.pos, n_cap, &st->m_kept, w.scan_tmp, s));
     if (n_cap > 0) {
         voxel_emit<<<grid_cap(n_cap, kBlock), kBlock, 0, s>>>(cl, n_clouds, n_cap, w.flag, w.pos, st, out_cap,
                                                              out_stride, kept_idx, kept_xyz, kept_cloud, cs,
