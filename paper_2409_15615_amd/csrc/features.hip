@@ -395,7 +395,8 @@ __global__ __launch_bounds__(kBlock) void spfh_pairs(const CloudDev* __restrict_
                                                      DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz > pair_mean * m) return;            // long lists: spfh_kernel
+    // long lists: spfh_kernel (0 = always spfh_kernel, kMaxDegree = always this pass)
+    if (pair_mean < kMaxDegree && (pair_mean == 0 || st->nnz > pair_mean * m)) return;
     __shared__ uint32_t s_hist[kWaves][2 * 3 * kMaxBins];
     spfh_pairs_body(cl, xyz, stride, kept_cloud, m, nrm, nrm_stride, flags, off, nb, H, cnt16, spfh_out, Pq, inv100,
                     jflag, xcd, st, s_hist[threadIdx.x / kWave]);
@@ -416,7 +417,8 @@ __global__ __launch_bounds__(kBlock) void spfh_kernel(const CloudDev* __restrict
                                                       DevStatus* st) {
     const int64_t m = clamp_count(st->m_kept, m_cap);
     if (st->err_range || st->err_capacity) return;  // the neighbour lists are incomplete
-    if (st->nnz <= pair_mean * m) return;           // short lists: spfh_pairs
+    // short lists: spfh_pairs (0 = always this pass, kMaxDegree = always spfh_pairs)
+    if (pair_mean >= kMaxDegree || (pair_mean > 0 && st->nnz <= pair_mean * m)) return;
     const XcdItems it = xcd ? xcd_items(m, off[m] + kItemWork * m, [&](int64_t i) { return off[i] + kItemWork * i; })
                             : cyclic_items(m);
     __shared__ uint32_t s_hist[kWaves][3 * kMaxBins];
@@ -878,15 +880,23 @@ kmg_status spfh_batch(const CloudDev* cl, const float* xyz, int64_t stride, cons
     if (m_cap > 0) {
         StageScope sc(ST_SPFH, s);
         const int pair_mean = tuning().spfh_pair_mean;
-        spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm, nrm_stride,
-                                                              flags, off, nb, H, w.cnt16, spfh_out, w.Pq, w.inv100,
-                                                              w.jflag, pair_mean, tuning().xcd_split & 1, st);
-        KMG_TRY(launch_status());
-        spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
-                                                                       nrm_stride, flags, off, nb, H, w.cnt16,
-                                                                       spfh_out, w.Pq, w.inv100, w.jflag, pair_mean,
-                                                                       tuning().xcd_split & 1, st);
-        KMG_TRY(launch_status());
+        // the two forms split on the mean list length on the device; at the ends of
+        // the range (0: one point per wavefront, kMaxDegree: two) the choice is made
+        // here, and only that form is launched
+        if (pair_mean < kMaxDegree) {
+            spfh_kernel<<<grid_cap(m_cap, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
+                                                                  nrm_stride, flags, off, nb, H, w.cnt16, spfh_out,
+                                                                  w.Pq, w.inv100, w.jflag, pair_mean,
+                                                                  tuning().xcd_split & 1, st);
+            KMG_TRY(launch_status());
+        }
+        if (pair_mean > 0) {
+            spfh_pairs<<<grid_cap((m_cap + 1) / 2, kWaves), kBlock, 0, s>>>(cl, xyz, stride, kept_cloud, m_cap, nrm,
+                                                                           nrm_stride, flags, off, nb, H, w.cnt16,
+                                                                           spfh_out, w.Pq, w.inv100, w.jflag,
+                                                                           pair_mean, tuning().xcd_split & 1, st);
+            KMG_TRY(launch_status());
+        }
     }
     return KMG_OK;
 }

@@ -105,7 +105,7 @@ struct PairOutDev {
 
 // Device status block carved at the start of every workspace.
 struct DevStatus {
-    int32_t err_range;        // a key left the packable range
+    int32_t err_range;        // a key left the packable range, or a list exceeds kMaxDegree
     int32_t dense;            // bit 0: some |N(q)| > kListSmall; bit 1: some |N(q)| > kMaxDegree
     int32_t err_capacity;     // a capacity bound was exceeded (CSR or partials)
     int32_t n_long;           // list-first search: lists longer than a pad row

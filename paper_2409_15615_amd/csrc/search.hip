@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_search(const CloudDev* _
                 deg[q] = found;
                 // rare events only: no contended atomic per query
                 if (found > kListSmall) atomicOr(&st->dense, found > kMaxDegree ? 3 : 1);
+                if (found > kMaxDegree) atomicOr(&st->err_range, 1);  // a list beyond the supported length
             }
             continue;
         }
@@ -371,6 +372,7 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_count2(const CloudDev* _
             deg[q] = found;
             // rare events only: no contended atomic per query
             if (found > kListSmall) atomicOr(&st->dense, found > kMaxDegree ? 3 : 1);
+            if (found > kMaxDegree) atomicOr(&st->err_range, 1);  // a list beyond the supported length
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -480,6 +482,7 @@ __global__ __launch_bounds__(kWaves* kWave) void radius_fill2(const CloudDev* __
             // lists beyond a pad row are listed (by cell-sorted position) for the dense pass
             if (found > row) {
                 atomicOr(&st->dense, found > kMaxDegree ? 3 : 1);
+                if (found > kMaxDegree) atomicOr(&st->err_range, 1);  // a list beyond the supported length
                 long_q[atomicAdd(&st->n_long, 1)] = static_cast<int32_t>(w);
             }
         }

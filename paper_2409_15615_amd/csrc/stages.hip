@@ -6,7 +6,10 @@ namespace kmg {
 
 namespace {
 
-__global__ void init_single(DevStatus* st, CloudDev* cl, CloudDev v, int64_t n_raw, int64_t m_kept) {
+// off (optional): the caller's neighbour lists, whose volume off[m_kept] goes
+// to st->nnz.
+__global__ void init_single(DevStatus* st, CloudDev* cl, CloudDev v, int64_t n_raw, int64_t m_kept,
+                            const int32_t* off) {
     const int i = threadIdx.x;
     uint32_t* w = reinterpret_cast<uint32_t*>(st);
     for (int k = i; k < static_cast<int>(sizeof(DevStatus) / 4); k += blockDim.x) w[k] = 0u;
@@ -14,12 +17,14 @@ __global__ void init_single(DevStatus* st, CloudDev* cl, CloudDev v, int64_t n_r
     if (i == 0) {
         st->n_raw = n_raw;
         st->m_kept = m_kept;
+        if (off) st->nnz = off[m_kept];
         cl[0] = v;
     }
 }
 
-kmg_status init(DevStatus* st, CloudDev* cl, const CloudDev& v, int64_t n_raw, int64_t m_kept, hipStream_t s) {
-    init_single<<<1, 64, 0, s>>>(st, cl, v, n_raw, m_kept);
+kmg_status init(DevStatus* st, CloudDev* cl, const CloudDev& v, int64_t n_raw, int64_t m_kept, hipStream_t s,
+                const int32_t* off = nullptr) {
+    init_single<<<1, 64, 0, s>>>(st, cl, v, n_raw, m_kept, off);
     return launch_status();
 }
 
@@ -177,7 +182,7 @@ kmg_status fpfh(const float* xyz, const float* nrm, uint8_t* flags, const int32_
         nbr3 = c.take<int32_t>(static_cast<size_t>(std::max<int64_t>(nnz3_cap, 1)));
     }
     if (!c.fits()) return KMG_ERR_WORKSPACE;
-    KMG_TRY(init(st, cl, make_cloud(p, nullptr, 0, 0), 0, m, s));
+    KMG_TRY(init(st, cl, make_cloud(p, nullptr, 0, 0), 0, m, s, off));
     if (!classic) {
         KMG_TRY(features_batch(cl, 1, xyz, m, nullptr, m, H, st, w, off, NbrLists{nbr}, nrm, m, flags, spfh_out,
                                fpfh_out, j_idx, nullptr, s));

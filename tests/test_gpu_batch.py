@@ -270,3 +270,27 @@ def test_uneven_batch_sizes_against_oracle(K, orc):
     got = register_batch_direct(K, [c for d in pairs for c in clouds_of(K, d)], "fp32")
     check_against_oracle(orc, pairs, got, grid=True)
     print("uneven batch items", items, "kept", [g[3] for g in got], "correspondences", [len(g[0]) for g in got])
+
+
+def test_list_beyond_supported_length_is_a_range_error(K):
+    """A point with more than 8,192 neighbours within r_FPFH (every point of a
+    dense 25^3 lattice, all kept, lies within r_FPFH of the centre) is outside
+    the supported range: the batch reports KMG_ERR_RANGE for its pairs in
+    either search form, and the per-stage normal estimation raises it."""
+    g = np.arange(25, dtype=np.float64) * 0.1
+    cube = np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    rng = np.random.default_rng(7)
+    src = (cube + rng.uniform(-0.01, 0.01, cube.shape)).astype(np.float32)
+    tgt = (cube + rng.uniform(-0.01, 0.01, cube.shape)).astype(np.float32)
+    prm = K.make_params(0.05, 0.3, 2.0, 3, 0.99, 11, (5.0, 5.0, 5.0))
+    clouds = [(dev(src), prm), (dev(tgt), prm)]
+    for form in (0, 1):
+        K.set_tuning({"search_form": form})
+        res, _ = K.register_batch(clouds)
+        assert res[0].status == K.KMG_ERR_RANGE, form
+    K.set_tuning(None)
+    kept, xyz = K.voxelize(dev(src), 0.05)
+    assert kept.numel() == cube.shape[1]
+    with pytest.raises(K.KmgError) as e:
+        K.normals(xyz.contiguous(), prm)
+    assert e.value.status == K.KMG_ERR_RANGE
