@@ -231,7 +231,10 @@ kmg_status scan_exclusive_summed(const int32_t* in, int32_t* out, int64_t n, int
 // One launch: each block publishes its tile's sum in status[tile] and adds up
 // those of the tiles before it (decoupled look-back).  status holds
 // scan_temp_elems(n) words, all zero at the launch (the scan leaves them
-// nonzero); a wait that gives up (never expected) sets *err.
+// nonzero); a wait that gives up (never expected) sets *err.  Beyond
+// kOnePassMaxTiles tiles the two-launch form runs instead (the words as its
+// temp).
+constexpr int64_t kOnePassMaxTiles = 512;
 kmg_status scan_exclusive_onepass(const int32_t* in, int32_t* out, int64_t n, int64_t* total, uint64_t* status,
                                   int32_t* err, hipStream_t s, const int32_t* live = nullptr,
                                   int32_t* list = nullptr);

@@ -168,6 +168,10 @@ kmg_status scan_exclusive_onepass(const int32_t* in, int32_t* out, int64_t n, in
                                   int32_t* err, hipStream_t s, const int32_t* live, int32_t* list) {
     const int64_t nt = (n + kScanTile - 1) / kScanTile;
     if (nt == 0) return fill_u64(reinterpret_cast<uint64_t*>(total), 0ull, 1, s);
+    // past kOnePassMaxTiles the look-back chains cost more than the second launch:
+    // the two-launch form, with the words as its tile sums
+    if (nt > kOnePassMaxTiles)
+        return scan_exclusive(in, out, n, total, reinterpret_cast<int64_t*>(status), s, live, list);
     scan_onepass<<<static_cast<unsigned>(nt), kScanThreads, 0, s>>>(in, out, n, live, status, total, list, err);
     return launch_status();
 }

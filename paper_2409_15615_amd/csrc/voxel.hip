@@ -272,6 +272,7 @@ kmg_status voxelize_batch(const CloudDev* cl, int n_clouds, int64_t n_cap, DevSt
                                                                w.cap_table - 1, w.slot, st);
         KMG_TRY(launch_status());
         const unsigned nt = static_cast<unsigned>((n_cap + kScanTile - 1) / kScanTile);
+        if (nt > kOnePassMaxTiles) scan_status = nullptr;  // long look-back chains: two launches
         if (scan_status) {
             voxel_number<<<nt, kBlock, 0, s>>>(w.slot, w.mins, n_cap, w.flag, w.pos, scan_status, st);
         } else {
