@@ -52,7 +52,7 @@ PEAK_HBM_GBS = 8000.0
 TILE_TRAFFIC = {
     "source": "paper_2409_15615_amd/csrc/match.hip",
     "sha256": "c19c40ba7b1c6146f86b83e53969efbe83c0ec5e5319a86bd9b15fd011006aeb",
-    "fetch_kib": 67569.5,
+    "fetch_kib": 67735.5,
     "fetch_scale": 262144.0 / 131085.2,
     "write_kib": 11850.6,
     "write_scale": 262144.0 / 262144.0,
